@@ -1,0 +1,207 @@
+/*
+ * concpd.h - C ABI of the MI355X (gfx950) implementation of CoNCPD-APG and
+ * lraCoNCPD-APG: coupled nonnegative CP decomposition of S third-order
+ * tensors by alternating proximal gradient with Nesterov extrapolation and
+ * restart (Wang, Liu, Cong, "Fast Learnings of Coupled Nonnegative Tensor
+ * Decomposition Using Optimal Gradient and Low-rank Approximation",
+ * arXiv 2302.05119).
+ *
+ * Problem (Section II-B, eq. tensormodel and eq. costfunc): given blocks
+ * M^(s) (s = 1..S) of size I1 x I2 x I3, find lambda^(s) >= 0 (the
+ * super-diagonal of the core D^(s)) and factors U^(n,s) >= 0 of size
+ * I_n x R whose first L_n columns are shared by every block, minimising
+ * 1/2 sum_s || M^(s) - [[D^(s); U^(1,s), U^(2,s), U^(3,s)]] ||_F^2.
+ *
+ * Conventions used by every call:
+ *  - Tensors are device buffers, C-contiguous (i3 fastest):
+ *    element (i1,i2,i3) of block s at offset (i1*I2 + i2)*I3 + i3.
+ *  - Host factor arrays are row-major I_n x R doubles (column r fastest).
+ *  - Block s, mode n (0-based) is addressed as index 3*s + n in [S*3] arrays.
+ *  - All device work is queued on the stream given to concpd_init.
+ *  - Every call returns a concpd_status; no C++ exception crosses the ABI.
+ *    On error the context is unchanged and concpd_last_error() returns a
+ *    thread-local message describing the first error.
+ *  - The library never allocates device memory: the caller passes one
+ *    workspace buffer of at least concpd_query_workspace() bytes and keeps it
+ *    (and the tensors) alive until concpd_destroy().
+ */
+#ifndef CONCPD_H
+#define CONCPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum concpd_status {
+    CONCPD_OK = 0,
+    CONCPD_EINVAL = 1,     /* invalid argument or configuration */
+    CONCPD_ENOTSUP = 2,    /* valid but not supported by this build (e.g. order != 3) */
+    CONCPD_ENONFINITE = 3, /* NaN or Inf in an input */
+    CONCPD_EHIP = 4,       /* a HIP runtime call failed */
+    CONCPD_ESTATE = 5      /* call not valid in the context's current state */
+} concpd_status;
+
+typedef enum concpd_dtype {
+    CONCPD_F64 = 0,
+    CONCPD_F32 = 1,
+    CONCPD_BF16 = 2,
+    CONCPD_F16 = 3
+} concpd_dtype;
+
+typedef struct concpd_config {
+    int32_t order;          /* N, the tensor order; only 3 is supported */
+    int32_t num_blocks;     /* S >= 1, at most 64 */
+    int32_t rank;           /* R, components per block, 1..64 */
+    int32_t coupled[3];     /* L_n, 0 <= L_n <= R: the first L_n columns of every
+                               mode-n factor are shared by all blocks (Section II-B);
+                               a mode with L_n > 0 needs equal I_n in every block */
+    const int64_t* dims;    /* [S*3]: I_n of block s at dims[3*s + n], each >= 1 */
+    int32_t tensor_dtype;   /* element type of the caller's tensors: CONCPD_F64 or CONCPD_F32 */
+    int32_t compute_dtype;  /* MTTKRP operand type.  CONCPD_F64 needs F64 tensors and keeps
+                               every quantity in FP64.  CONCPD_F32 runs FP32 MFMA.
+                               CONCPD_BF16 / CONCPD_F16 keep a 16-bit shadow of the tensors
+                               in the workspace and run 16-bit MFMA with FP32 accumulation.
+                               Grams, Lipschitz constants, the core update, the objective
+                               and the restart test are FP64 in every mode. */
+    int32_t update_core;    /* 1: update D^(s) (CoNCPD-APG); 0: keep lambda fixed (-NC) */
+    int32_t restart;        /* 1: restart rule of Algorithm 1 */
+    double delta_w;         /* delta_w < 1 of eq. eqextrawd / eqextrawu (paper: 0.9999) */
+    double tol;             /* concpd_fit stops when |RelErr_k - RelErr_{k-1}| < tol */
+    int32_t max_it;         /* concpd_fit iteration limit (paper: 1000) */
+    const int32_t* tucker_ranks; /* [S*3] Tucker ranks J_n <= I_n for lra_compress, or NULL
+                               when the context will not be compressed */
+} concpd_config;
+
+typedef struct concpd_stats {
+    int64_t k;              /* accepted outer iterations so far */
+    double F;               /* objective F_k (eq. costfunc, or eq. cosfunclra after lra_compress) */
+    double relerr;          /* RelErr_k = 1/S sum_s ||M - M^|| / ||M|| */
+    double fit;             /* 1 - relerr */
+    int64_t restarts;       /* number of restarted iterations so far */
+    int32_t restarted_last; /* 1 if the last iteration was restarted */
+    int32_t converged;      /* 1 once |dRelErr| < tol was met (further steps are no-ops) */
+    int32_t nonfinite;      /* 1 if F_k is not finite */
+    int32_t lra;            /* 1 after lra_compress */
+} concpd_stats;
+
+typedef struct concpd_ctx_s* concpd_ctx;
+
+/* Thread-local text of the last error (empty string if none). */
+const char* concpd_last_error(void);
+
+/* Bytes of device workspace concpd_init needs for cfg (host-only call).
+ * Errors: EINVAL/ENOTSUP for an invalid configuration. */
+concpd_status concpd_query_workspace(const concpd_config* cfg, size_t* bytes);
+
+/* Create a context: validates cfg, lays out the workspace, uploads the initial
+ * iterate and computes its Grams, core data term b, F_0 and RelErr_0 on the
+ * device (Algorithm 1, initialisation).
+ *   tensors      [S] device pointers to the blocks (borrowed, read-only).
+ *   init_U       [S*3] host I_n x R row-major arrays (copied), or NULL for a
+ *                seeded U[0,1] draw (SplitMix64, order: n, then s, then row,
+ *                then column; shared columns drawn once).  Shared columns are
+ *                taken from block 0.
+ *   init_lambda  [S] host R-vectors, or NULL for a seeded U[0,1] draw.
+ *   workspace    device buffer of ws_bytes >= concpd_query_workspace(cfg).
+ *   stream       hipStream_t (NULL = default stream).
+ * Errors: EINVAL, ENOTSUP, ENONFINITE (NaN/Inf in init arrays or tensors), EHIP.
+ * On error *out is NULL and nothing stays queued that writes the workspace. */
+concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors,
+                          const double* const* init_U, const double* const* init_lambda,
+                          uint64_t seed, void* workspace, size_t ws_bytes, void* stream,
+                          concpd_ctx* out);
+
+/* Run n_iter outer iterations of Algorithm 1 (each: the extrapolated sweep
+ * D^(1..S), U^(1,1..S), ..., U^(3,1..S); if F_k >= F_{k-1} and restart is on,
+ * the sweep is redone from x_{k-1} with zero extrapolation and accepted).
+ * Asynchronous when out == NULL; with out != NULL it synchronises the stream
+ * and fills *out.  After convergence (concpd_fit) further iterations are no-ops.
+ * In lra mode (after lra_compress) the gradients use the compressed blocks.
+ * Errors: EINVAL (n_iter < 0), EHIP. */
+concpd_status concpd_step(concpd_ctx ctx, int32_t n_iter, concpd_stats* out);
+
+/* Iterate until |RelErr_k - RelErr_{k-1}| < tol or k = max_it (Section III-C).
+ * Reaching max_it is not an error (out->converged = 0).  Synchronises. */
+concpd_status concpd_fit(concpd_ctx ctx, concpd_stats* out);
+
+/* Compress every block by truncated HOSVD to the Tucker ranks given in the
+ * configuration (ranks == NULL) or in ranks [S*3] (each <= the configured
+ * rank for that block/mode): A_n^(s) = J_n leading left singular vectors of
+ * M^(s)_(n), G^(s) = M^(s) x_1 A_1^T x_2 A_2^T x_3 A_3^T, then switch the
+ * context to lraCoNCPD-APG (Algorithm 2, eq. cosfunclra): F, RelErr and every
+ * gradient are taken against the compressed blocks.  The current iterate is
+ * kept; its F and b are recomputed.  Synchronises; out may be NULL.
+ * Errors: ESTATE (no Tucker ranks configured), EINVAL (J_n > configured), EHIP. */
+concpd_status lra_compress(concpd_ctx ctx, const int32_t* ranks, concpd_stats* out);
+
+/* concpd_step in lra mode.  Errors: ESTATE if lra_compress has not run. */
+concpd_status lra_step(concpd_ctx ctx, int32_t n_iter, concpd_stats* out);
+
+/* Global fit 1 - 1/S sum_s ||M^(s) - M^^(s)||_F / ||M^(s)||_F against the
+ * original tensors, by one direct FP64-accumulated pass (the "final fit").
+ * Synchronises. */
+concpd_status concpd_global_fit(concpd_ctx ctx, double* fit);
+
+/* Copy U^(n,s) (I_n x R row-major, shared columns included) or lambda^(s) of
+ * the current accepted iterate to host doubles.  Synchronises.
+ * Errors: EINVAL for n/s out of range. */
+concpd_status concpd_get_factor(concpd_ctx ctx, int32_t n, int32_t s, double* host_dst);
+concpd_status concpd_get_lambda(concpd_ctx ctx, int32_t s, double* host_dst);
+
+/* Lipschitz constants used by the last accepted sweep (eq. eqLipsLd /
+ * eqLipsLu): Ld [S], Lu [S*3] (index 3*s + n), LC [3] = sum_s Lu.  Synchronises. */
+concpd_status concpd_get_lipschitz(concpd_ctx ctx, double* Ld, double* Lu, double* LC);
+
+/* Replace the iterate state (checkpoint restore / teacher forcing):
+ *   U, lam          x_{k-1}: [S*3] / [S] host arrays,
+ *   U_prev, lam_prev x_{k-2} (NULL: same as x_{k-1}),
+ *   Ld_prev [S], Lu_prev [S*3], LC_prev [3]: constants of the previous sweep,
+ *                   NULL or negative entries meaning "none" (weight 0),
+ *   t               t_{k-1} of eq. eqextrawu (t_0 = 1), k the iteration count.
+ * Recomputes Grams, b, F_{k-1}, RelErr_{k-1}; clears the converged flag.
+ * Errors: EINVAL, ENONFINITE, EHIP. */
+concpd_status concpd_set_state(concpd_ctx ctx, const double* const* U, const double* const* U_prev,
+                               const double* const* lam, const double* const* lam_prev,
+                               const double* Ld_prev, const double* Lu_prev, const double* LC_prev,
+                               double t, int64_t k);
+
+/* Loss F and its partial gradients at an arbitrary point, without touching the
+ * iterate (autograd form): dF/dlambda^(s) = H lambda - b (eq. solbpgG) and
+ * dF/dU^(n,s) = U D H_{-n} D - M_(n) U^{⊙-n} D (eq. solbpgU), all blocks at the
+ * same point.
+ *   U_dev      [S*3] device I_n x R row-major arrays in the context's factor type
+ *              (double for compute_dtype F64, else float); shared columns are
+ *              read from block 0.
+ *   lambda_dev [S] device double R-vectors.
+ *   gU_dev     [S*3] device outputs like U_dev; for a mode with L_n > 0 the
+ *              first L_n columns of every block receive the sum over s
+ *              (eq. solbpgUCI summed over the blocks sharing U_C).
+ *   glam_dev   [S] device double outputs.  *loss receives F (host).
+ * Synchronises.  Errors: EINVAL, ESTATE (not supported in lra mode), EHIP. */
+concpd_status concpd_loss_grad(concpd_ctx ctx, const void* const* U_dev, const void* const* lambda_dev,
+                               double* loss, void* const* gU_dev, void* const* glam_dev);
+
+/* Test hook: K = M^(s)_(n) U^{⊙-n} at the current iterate, I_n x R row-major
+ * float (double in F64 mode) written to dev_out.  Synchronises. */
+concpd_status concpd_debug_mttkrp(concpd_ctx ctx, int32_t n, int32_t s, void* dev_out);
+
+/* Per-kernel timing of the dense MTTKRP passes (pass 1: M x_3 U^(3); pass 2:
+ * the mode-3 MTTKRP) of later concpd_step calls: with enable != 0, HIP events
+ * are recorded on the context stream around each pass launch of every
+ * extrapolated sweep.  concpd_profile_read synchronises and returns the summed
+ * milliseconds and the number of timed launches of each pass, then clears the
+ * record.  Errors: EHIP. */
+concpd_status concpd_profile(concpd_ctx ctx, int32_t enable);
+concpd_status concpd_profile_read(concpd_ctx ctx, double* ms_pass1, double* ms_pass2, int64_t* launches);
+
+/* Release the host context.  Queued work is synchronised first; the workspace
+ * and the tensors stay owned by the caller. */
+concpd_status concpd_destroy(concpd_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CONCPD_H */

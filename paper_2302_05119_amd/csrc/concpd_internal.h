@@ -1,0 +1,98 @@
+// Internal types shared by the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define CPD_MAXS 64   // blocks per context
+#define CPD_MAXR 64   // components per block
+
+// Device-side control block: scalars of the outer iteration (Algorithm 1).
+struct Ctrl {
+    double t;          // t_{k-1} (Appendix A, parameter settings)
+    double w_hat;      // w_hat_{k-1} = (t_{k-1} - 1) / t_k for the coming iteration
+    double F_prev;     // F_{k-1}
+    double F_cur;      // F of the latest sweep
+    double rel_prev;   // RelErr_{k-1}
+    double rel_cur;
+    double tol;        // |dRelErr| threshold (0: never stop)
+    double delta_w;
+    long long k;
+    long long restarts;
+    int redo;          // set when F_k >= F_{k-1}: the gated sweep reruns without extrapolation
+    int stop;          // converged: every later kernel is a no-op
+    int last_restarted;
+    int nonfinite;
+    int restart_on;
+    int reset_t;
+    unsigned int counter_finish;   // arrival counters for last-workgroup reductions
+    unsigned int counter_commit;
+    unsigned int counter_aux;
+    int pad;
+};
+
+// Per-context geometry, resident in the workspace.
+struct Geo {
+    int S, R, Rq;                 // Rq = R rounded up to a multiple of 4 (factor row stride)
+    int L[3];
+    int upd_core;
+    int lra;                      // 1: gradients from the Tucker form
+    int I[CPD_MAXS][3];
+    int J[CPD_MAXS][3];           // Tucker ranks (lra)
+    long long uoff[3][CPD_MAXS];  // element offset of U^(n,s) inside one factor slot
+    long long yoff[CPD_MAXS];     // Y^(s) = M^(s) x_3 U^(3,s): I1 x I2 x Rq
+    long long koff[CPD_MAXS];     // K^(3,s) buffer (I3 x Rq)
+    long long poff[CPD_MAXS];     // mode-3 MTTKRP partials: nchunk x I3 x Rq
+    int nchunk[CPD_MAXS];
+    long long aoff[3][CPD_MAXS];  // Tucker bases A_n^(s): I_n x J_n (double)
+    long long goff[CPD_MAXS];     // Tucker cores G^(s): J1 x J2 x J3 (double), i3 fastest
+    long long woff[3][CPD_MAXS];  // W_n^(s) = A_n^T U^(n): J_n x Rq (double)
+    long long coff[CPD_MAXS];     // lra scratch per block
+    const void* M[CPD_MAXS];      // block tensors in the MTTKRP operand type
+    int mdtype;                   // operand type of M (concpd_dtype)
+};
+
+// Device pointers of the iterate state.  Slot 0 = x_k being built,
+// slot 1 = x_{k-1}, slot 2 = x_{k-2}.
+template <typename T>
+struct StateP {
+    T* U[3];            // factors, one slot = sum_{n,s} I_n * Rq elements
+    double* lam[3];     // [S][Rq]
+    double* V[2];       // Grams U^T U, [3][S][R*R], slots 0 and 1
+    double* b[2];       // core data term (U^⊙)^T vec(M), [S][Rq]
+    double* P;          // D H_{-n} D of the mode being updated, [S][R*R]
+    double* Ld_cur;     // [S]
+    double* Ld_prev;
+    double* Lu_cur;     // [3][S]
+    double* Lu_prev;
+    double* LC_prev;    // [3]
+    double* Fblk;       // [S]
+    double* normM2;     // [S] ||M^(s)||_F^2 (or ||G^(s)||^2 in lra mode)
+    T* Y;               // pass-1 output
+    T* K3;              // reduced mode-3 MTTKRP
+    T* part;            // mode-3 partials
+    double* lra;        // Tucker storage base (A, G, W, scratch)
+    Ctrl* ctrl;
+};
+
+// Work items of the grouped kernels (host-built lists, one entry per workgroup).
+struct ItemP1 { int s, i1, rg, pad; };              // pass 1: block, slab, 64-row group
+struct ItemP2 { int s, chunk, q0, pad; };           // pass 2: block, 4-slab chunk, i3 start
+struct ItemU  { int s0, ns, row0, nrows; };         // update: blocks [s0, s0+ns), rows
+
+// Kernel launchers (defined in the .hip files).
+namespace cpd {
+template <typename T> void launch_core(const Geo* g, const StateP<T>& st, int S, int R, int extrap, int gate, hipStream_t q);
+template <typename T> void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, int gate, hipStream_t q);
+template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, int first_sweep, int gate, hipStream_t q);
+template <typename T> void launch_commit(const Geo* g, const StateP<T>& st, long long uslot, int S, int Rq, int R, hipStream_t q);
+template <typename T> void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
+template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int Rq, int slot, int gate, int mdtype, hipStream_t q);
+template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int gate, int mdtype, hipStream_t q);
+template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int gate, int lds_rows, hipStream_t q);
+template <typename T> void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, int R, T* out, int ld_out, hipStream_t q);
+template <typename T> void launch_resid(const Geo* g, const StateP<T>& st, const void* M, int dtype, int s, int I1, double* part, hipStream_t q);
+void launch_sqnorm(const void* src, int dtype, long long n, double* out, double* part, int npart, hipStream_t q);
+void launch_sum_parts(const double* part, int np, double* out, hipStream_t q);
+void launch_convert(const void* src, int dst_dtype, void* dst, long long n, hipStream_t q);
+void launch_finite_check(const void* src, int dtype, long long n, int* flag, hipStream_t q);
+}  // namespace cpd

@@ -1,0 +1,148 @@
+// Factor update of one mode for every block (eq. solUns / solUnC / solUnsI):
+//
+//   U_hat = U_{k-1} + w (U_{k-1} - U_{k-2})                  (eq. eqextraPU)
+//   G     = U_hat P - K diag(lambda),  P = D H_{-n} D        (eq. solapgU)
+//   individual columns:  U_I = max(0, U_hat_I - G_I / L_u^(n,s))
+//   shared columns:      U_C = max(0, U_hat_C - sum_s G_C^(s) / sum_s L_u^(n,s))
+//
+// K = M_(n) U^{⊙-n} is contracted here from the MTTKRP pass outputs:
+//   mode 1: K1[i1] = sum_i2 Y[i1][i2] ⊛ U2_old[i2]
+//   mode 2: K2[i2] = sum_i1 Y[i1][i2] ⊛ U1_new[i1]
+//   mode 3: K3[i3] = sum over the pass-2 chunk partials (fixed order)
+// All of the small arithmetic is FP64; the new factor is rounded to the
+// storage type once.  A workgroup owns a row tile of every block that shares
+// the mode's columns, so the coupled sum runs in LDS in block order.
+#include "dev_common.h"
+
+namespace cpd {
+
+enum { KSRC_Y1 = 0, KSRC_Y2 = 1, KSRC_PART = 2 };
+
+template <typename T, int KSRC>
+__device__ __forceinline__ double k_value(const Geo* __restrict__ g, const StateP<T>& st, int s, int i, int col,
+                                          int other_slot) {
+    const int Rq = g->Rq;
+    double acc = 0.0;
+    if (KSRC == KSRC_Y1) {
+        const int I2 = g->I[s][1];
+        const T* Y = st.Y + g->yoff[s] + (long long)i * I2 * Rq + col;
+        const T* U2 = st.U[other_slot] + g->uoff[1][s] + col;
+        for (int i2 = 0; i2 < I2; ++i2) acc += (double)Y[(long long)i2 * Rq] * (double)U2[(long long)i2 * Rq];
+    } else if (KSRC == KSRC_Y2) {
+        const int I1 = g->I[s][0], I2 = g->I[s][1];
+        const T* Y = st.Y + g->yoff[s] + (long long)i * Rq + col;
+        const T* U1 = st.U[other_slot] + g->uoff[0][s] + col;
+        const long long ys = (long long)I2 * Rq;
+        for (int i1 = 0; i1 < I1; ++i1) acc += (double)Y[i1 * ys] * (double)U1[(long long)i1 * Rq];
+    } else {
+        const int I3 = g->I[s][2], nch = g->nchunk[s];
+        const T* p = st.part + g->poff[s] + (long long)i * Rq + col;
+        const long long ps = (long long)I3 * Rq;
+        for (int ch = 0; ch < nch; ++ch) acc += (double)p[ch * ps];
+    }
+    return acc;
+}
+
+template <typename T, int KSRC>
+__global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, StateP<T> st, const ItemU* __restrict__ items,
+                                                int n, int extrapolate, int gate) {
+    const Ctrl* c = st.ctrl;
+    if (gated_out(c, gate)) return;
+    const ItemU it = items[blockIdx.x];
+    const int s0 = it.s0, ns = it.ns, row0 = it.row0, nrows = it.nrows;
+    const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R, Ln = g->L[n];
+    const int tid = threadIdx.x;
+    extern __shared__ double sm[];
+    double* uh = sm;                       // [ns][nrows][R]
+    double* gc = uh + ns * nrows * R;      // [ns][nrows][Ln]
+    const int tot = ns * nrows * R;
+    const double what = c->w_hat, dw = c->delta_w;
+    double LC = 0.0;
+    if (Ln > 0)
+        for (int b = 0; b < S; ++b) LC += st.Lu_cur[n * S + b];
+    const double wC = (Ln > 0) ? extrap_weight(extrapolate, what, st.LC_prev[n], LC, dw) : 0.0;
+    const int other_slot = (KSRC == KSRC_Y1) ? 1 : 0;
+
+    // extrapolated point
+    for (int e = tid; e < tot; e += 256) {
+        const int sl = e / (nrows * R), rem = e % (nrows * R), rr = rem / R, col = rem % R;
+        const int s = s0 + sl;
+        const long long off = g->uoff[n][s] + (long long)(row0 + rr) * Rq + col;
+        const double x1 = (double)st.U[1][off], x2 = (double)st.U[2][off];
+        const double w = (col < Ln) ? wC : extrap_weight(extrapolate, what, st.Lu_prev[n * S + s], st.Lu_cur[n * S + s], dw);
+        uh[e] = x1 + w * (x1 - x2);
+    }
+    __syncthreads();
+    // gradient; individual columns are projected here
+    for (int e = tid; e < tot; e += 256) {
+        const int sl = e / (nrows * R), rem = e % (nrows * R), rr = rem / R, col = rem % R;
+        const int s = s0 + sl, i = row0 + rr;
+        const double* P = st.P + (long long)s * RR;
+        const double* u = uh + (sl * nrows + rr) * R;
+        double gr = 0.0;
+        for (int r = 0; r < R; ++r) gr += u[r] * P[r * R + col];
+        const double kv = k_value<T, KSRC>(g, st, s, i, col, other_slot);
+        gr -= kv * st.lam[0][s * Rq + col];
+        if (KSRC == KSRC_PART) st.K3[g->koff[s] + (long long)i * Rq + col] = (T)kv;
+        const long long off = g->uoff[n][s] + (long long)i * Rq + col;
+        if (col >= Ln) {
+            const double Lu = st.Lu_cur[n * S + s];
+            const double un = (Lu > 0.0) ? relu_keep_nan(uh[e] - gr / Lu) : (double)st.U[1][off];
+            st.U[0][off] = (T)un;
+        } else {
+            gc[(sl * nrows + rr) * Ln + col] = gr;
+        }
+    }
+    if (Ln == 0) return;
+    __syncthreads();
+    // shared columns: sum the block gradients in block order
+    for (int e = tid; e < nrows * Ln; e += 256) {
+        const int rr = e / Ln, col = e % Ln, i = row0 + rr;
+        double gsum = 0.0;
+        for (int sl = 0; sl < ns; ++sl) gsum += gc[(sl * nrows + rr) * Ln + col];
+        const long long off0 = g->uoff[n][s0] + (long long)i * Rq + col;
+        const double un = (LC > 0.0) ? relu_keep_nan(uh[rr * R + col] - gsum / LC) : (double)st.U[1][off0];
+        const T ut = (T)un;
+        for (int sl = 0; sl < ns; ++sl) st.U[0][g->uoff[n][s0 + sl] + (long long)i * Rq + col] = ut;
+    }
+}
+
+// K = M_(n) U^{⊙-n} of one block at the accepted iterate (slot 1) from the
+// pass outputs computed on slot 1; used at initialisation and by the test hook.
+template <typename T, int KSRC>
+__global__ __launch_bounds__(256) void k_extract(const Geo* __restrict__ g, StateP<T> st, int s, int I, T* __restrict__ out,
+                                                 int ld_out) {
+    const int R = g->R;
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < (long long)I * R; e += (long long)gridDim.x * 256) {
+        const int i = (int)(e / R), col = (int)(e % R);
+        out[(long long)i * ld_out + col] = (T)k_value<T, KSRC>(g, st, s, i, col, 1);
+    }
+}
+
+template <typename T>
+void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, int R, T* out, int ld_out, hipStream_t q) {
+    long long nb = ((long long)I * R + 255) / 256;
+    if (nb > 1024) nb = 1024;
+    if (nb < 1) nb = 1;
+    if (n == 0) hipLaunchKernelGGL((k_extract<T, KSRC_Y1>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
+    else if (n == 1) hipLaunchKernelGGL((k_extract<T, KSRC_Y2>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
+    else hipLaunchKernelGGL((k_extract<T, KSRC_PART>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
+}
+template void launch_extract_k<float>(const Geo*, const StateP<float>&, int, int, int, int, float*, int, hipStream_t);
+template void launch_extract_k<double>(const Geo*, const StateP<double>&, int, int, int, int, double*, int, hipStream_t);
+
+template <typename T>
+void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int gate,
+                   int lds_rows, hipStream_t q) {
+    if (nitems <= 0) return;
+    // lds_rows = max over items of ns * nrows; the shared-gradient buffer uses at most as much
+    const size_t lds = sizeof(double) * (size_t)lds_rows * (size_t)(2 * R);
+    if (n == 0) hipLaunchKernelGGL((k_update<T, KSRC_Y1>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
+    else if (n == 1) hipLaunchKernelGGL((k_update<T, KSRC_Y2>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
+    else hipLaunchKernelGGL((k_update<T, KSRC_PART>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
+}
+
+template void launch_update<float>(const Geo*, const StateP<float>&, const ItemU*, int, int, int, int, int, int, hipStream_t);
+template void launch_update<double>(const Geo*, const StateP<double>&, const ItemU*, int, int, int, int, int, int, hipStream_t);
+
+}  // namespace cpd

@@ -1,0 +1,799 @@
+// Host runtime behind the C ABI of concpd.h: configuration checks, workspace
+// layout, grouped work lists, the per-iteration launch schedule of
+// Algorithm 1 (with the device-side restart test), checkpoint / restore and
+// the read-back calls.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/concpd.h"
+#include "concpd_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+concpd_status fail(concpd_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHECK(x)                                                                        \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return fail(CONCPD_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t geo, ctrl, U[3], lam[3], V[2], b[2], P, Ld_cur, Ld_prev, Lu_cur, Lu_prev, LC_prev, Fblk, normM2, normOrig, Y,
+        K3, part, it1, it2, itu[3], scratch, shadow, lra, flag, total;
+    long long uslot, ylen, klen, plen, shadow_elems[CPD_MAXS], lra_len;
+    size_t scratch_len;
+    int esz;  // bytes per factor element
+};
+
+struct Lists {
+    std::vector<ItemP1> p1;
+    std::vector<ItemP2> p2;
+    std::vector<ItemU> u[3];
+    int lds_rows[3];
+};
+
+concpd_status validate(const concpd_config* c) {
+    if (!c) return fail(CONCPD_EINVAL, "config is NULL");
+    if (c->order != 3) return fail(CONCPD_ENOTSUP, "order %d not supported (only 3)", c->order);
+    if (c->num_blocks < 1 || c->num_blocks > CPD_MAXS) return fail(CONCPD_EINVAL, "num_blocks %d not in [1, %d]", c->num_blocks, CPD_MAXS);
+    if (c->rank < 1 || c->rank > CPD_MAXR) return fail(CONCPD_EINVAL, "rank %d not in [1, %d]", c->rank, CPD_MAXR);
+    if (!c->dims) return fail(CONCPD_EINVAL, "dims is NULL");
+    for (int n = 0; n < 3; ++n)
+        if (c->coupled[n] < 0 || c->coupled[n] > c->rank)
+            return fail(CONCPD_EINVAL, "coupled[%d] = %d not in [0, rank]", n, c->coupled[n]);
+    for (int s = 0; s < c->num_blocks; ++s)
+        for (int n = 0; n < 3; ++n) {
+            const int64_t d = c->dims[3 * s + n];
+            if (d < 1 || d > (1 << 24)) return fail(CONCPD_EINVAL, "dims[%d] = %lld out of range", 3 * s + n, (long long)d);
+            if (c->coupled[n] > 0 && d != c->dims[n])
+                return fail(CONCPD_EINVAL, "mode %d is coupled but block %d has I=%lld != %lld", n, s, (long long)d,
+                            (long long)c->dims[n]);
+        }
+    if (c->tensor_dtype != CONCPD_F64 && c->tensor_dtype != CONCPD_F32)
+        return fail(CONCPD_EINVAL, "tensor_dtype must be F64 or F32");
+    if (c->compute_dtype < CONCPD_F64 || c->compute_dtype > CONCPD_F16) return fail(CONCPD_EINVAL, "bad compute_dtype");
+    if (c->compute_dtype == CONCPD_F64 && c->tensor_dtype != CONCPD_F64)
+        return fail(CONCPD_EINVAL, "compute_dtype F64 needs F64 tensors");
+    if (c->compute_dtype != CONCPD_F64 && c->tensor_dtype == CONCPD_F64)
+        return fail(CONCPD_ENOTSUP, "F64 tensors are only supported with compute_dtype F64");
+    if (c->compute_dtype == CONCPD_F64 && c->rank > 32) return fail(CONCPD_ENOTSUP, "compute_dtype F64 supports rank <= 32");
+    if (!(c->delta_w >= 0.0 && c->delta_w < 1.0)) return fail(CONCPD_EINVAL, "delta_w must be in [0, 1)");
+    if (!(c->tol >= 0.0)) return fail(CONCPD_EINVAL, "tol must be >= 0");
+    if (c->max_it < 0) return fail(CONCPD_EINVAL, "max_it must be >= 0");
+    if (c->tucker_ranks)
+        for (int s = 0; s < c->num_blocks; ++s)
+            for (int n = 0; n < 3; ++n) {
+                const int J = c->tucker_ranks[3 * s + n];
+                if (J < 1 || J > c->dims[3 * s + n] || J > 64)
+                    return fail(CONCPD_EINVAL, "tucker_ranks[%d] = %d must be in [1, min(I_n, 64)]", 3 * s + n, J);
+            }
+    return CONCPD_OK;
+}
+
+void build_lists(const concpd_config* c, Lists* L) {
+    const int S = c->num_blocks, R = c->rank;
+    L->p1.clear();
+    L->p2.clear();
+    for (int s = 0; s < S; ++s) {
+        const int I1 = (int)c->dims[3 * s], I2 = (int)c->dims[3 * s + 1], I3 = (int)c->dims[3 * s + 2];
+        for (int i1 = 0; i1 < I1; ++i1)
+            for (int rg = 0; rg * 64 < I2; ++rg) L->p1.push_back({s, i1, rg, 0});
+        for (int ch = 0; ch * 4 < I1; ++ch)
+            for (int q0 = 0; q0 < I3; q0 += 64) L->p2.push_back({s, ch, q0, 0});
+    }
+    for (int n = 0; n < 3; ++n) {
+        L->u[n].clear();
+        int lds_rows = 1;
+        if (c->coupled[n] > 0) {
+            const int I = (int)c->dims[n];
+            int nrows = std::max(1, 256 / (S * R));
+            // LDS: ns * nrows * 2R doubles <= 48 KiB
+            while (nrows > 1 && (size_t)S * nrows * 2 * R * 8 > 49152) --nrows;
+            for (int r0 = 0; r0 < I; r0 += nrows) L->u[n].push_back({0, S, r0, std::min(nrows, I - r0)});
+            lds_rows = S * nrows;
+        } else {
+            const int nrows = std::max(1, 256 / R);
+            for (int s = 0; s < S; ++s) {
+                const int I = (int)c->dims[3 * s + n];
+                for (int r0 = 0; r0 < I; r0 += nrows) L->u[n].push_back({s, 1, r0, std::min(nrows, I - r0)});
+            }
+            lds_rows = nrows;
+        }
+        L->lds_rows[n] = lds_rows;
+    }
+}
+
+void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
+    memset(P, 0, sizeof *P);
+    memset(g, 0, sizeof *g);
+    const int S = c->num_blocks, R = c->rank, Rq = (R + 3) / 4 * 4;
+    const bool f64 = c->compute_dtype == CONCPD_F64;
+    P->esz = f64 ? 8 : 4;
+    g->S = S;
+    g->R = R;
+    g->Rq = Rq;
+    for (int n = 0; n < 3; ++n) g->L[n] = c->coupled[n];
+    g->upd_core = c->update_core;
+    g->mdtype = c->compute_dtype;
+    long long u = 0, y = 0, k = 0, p = 0;
+    for (int n = 0; n < 3; ++n)
+        for (int s = 0; s < S; ++s) {
+            g->uoff[n][s] = u;
+            u += c->dims[3 * s + n] * Rq;
+        }
+    for (int s = 0; s < S; ++s) {
+        const long long I1 = c->dims[3 * s], I2 = c->dims[3 * s + 1], I3 = c->dims[3 * s + 2];
+        for (int n = 0; n < 3; ++n) g->I[s][n] = (int)c->dims[3 * s + n];
+        g->yoff[s] = y;
+        y += I1 * I2 * Rq;
+        g->koff[s] = k;
+        k += I3 * Rq;
+        g->nchunk[s] = (int)((I1 + 3) / 4);
+        g->poff[s] = p;
+        p += g->nchunk[s] * I3 * Rq;
+    }
+    P->uslot = u;
+    P->ylen = y;
+    P->klen = k;
+    P->plen = p;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    P->geo = take(sizeof(Geo));
+    P->ctrl = take(sizeof(Ctrl));
+    for (int i = 0; i < 3; ++i) P->U[i] = take((size_t)u * P->esz);
+    for (int i = 0; i < 3; ++i) P->lam[i] = take(sizeof(double) * S * Rq);
+    for (int i = 0; i < 2; ++i) P->V[i] = take(sizeof(double) * 3 * S * R * R);
+    for (int i = 0; i < 2; ++i) P->b[i] = take(sizeof(double) * S * Rq);
+    P->P = take(sizeof(double) * S * R * R);
+    P->Ld_cur = take(sizeof(double) * S);
+    P->Ld_prev = take(sizeof(double) * S);
+    P->Lu_cur = take(sizeof(double) * 3 * S);
+    P->Lu_prev = take(sizeof(double) * 3 * S);
+    P->LC_prev = take(sizeof(double) * 3);
+    P->Fblk = take(sizeof(double) * S);
+    P->normM2 = take(sizeof(double) * S);
+    P->normOrig = take(sizeof(double) * S);
+    P->Y = take((size_t)y * P->esz);
+    P->K3 = take((size_t)k * P->esz);
+    P->part = take((size_t)p * P->esz);
+    P->it1 = take(sizeof(ItemP1) * std::max<size_t>(1, L.p1.size()));
+    P->it2 = take(sizeof(ItemP2) * std::max<size_t>(1, L.p2.size()));
+    for (int n = 0; n < 3; ++n) P->itu[n] = take(sizeof(ItemU) * std::max<size_t>(1, L.u[n].size()));
+    size_t scr = 4096;
+    for (int s = 0; s < S; ++s) scr = std::max<size_t>(scr, (size_t)c->dims[3 * s]);
+    P->scratch_len = scr;
+    P->scratch = take(sizeof(double) * scr);
+    P->flag = take(sizeof(int) * 4);
+    if (c->compute_dtype == CONCPD_BF16 || c->compute_dtype == CONCPD_F16) {
+        long long tot = 0;
+        for (int s = 0; s < S; ++s) {
+            P->shadow_elems[s] = c->dims[3 * s] * c->dims[3 * s + 1] * c->dims[3 * s + 2];
+            tot += P->shadow_elems[s];
+        }
+        P->shadow = take((size_t)tot * 2);
+    }
+    P->total = off;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014) -> uniform doubles in [0, 1).
+struct SplitMix64 {
+    uint64_t x;
+    uint64_t next() {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
+};
+
+}  // namespace
+
+struct concpd_ctx_s {
+    concpd_config cfg;
+    std::vector<int64_t> dims;
+    std::vector<int32_t> tucker;
+    int S, R, Rq, L[3];
+    bool f64;
+    int mdtype;
+    std::vector<const void*> tensors;
+    char* ws;
+    hipStream_t q;
+    Layout lay;
+    Lists lists;
+    Geo geo;
+    Geo* dgeo;
+    StateP<float> sf;
+    StateP<double> sd;
+    Ctrl* ctrl;
+    int lra;
+    std::vector<double> normOrig;
+    long long launched_iters;
+    int profiling;
+    std::vector<hipEvent_t> ev1, ev2;  // begin/end pairs of timed pass launches
+};
+
+namespace {
+
+template <typename T>
+StateP<T> make_state(char* ws, const Layout& P) {
+    StateP<T> st;
+    for (int i = 0; i < 3; ++i) st.U[i] = (T*)(ws + P.U[i]);
+    for (int i = 0; i < 3; ++i) st.lam[i] = (double*)(ws + P.lam[i]);
+    for (int i = 0; i < 2; ++i) st.V[i] = (double*)(ws + P.V[i]);
+    for (int i = 0; i < 2; ++i) st.b[i] = (double*)(ws + P.b[i]);
+    st.P = (double*)(ws + P.P);
+    st.Ld_cur = (double*)(ws + P.Ld_cur);
+    st.Ld_prev = (double*)(ws + P.Ld_prev);
+    st.Lu_cur = (double*)(ws + P.Lu_cur);
+    st.Lu_prev = (double*)(ws + P.Lu_prev);
+    st.LC_prev = (double*)(ws + P.LC_prev);
+    st.Fblk = (double*)(ws + P.Fblk);
+    st.normM2 = (double*)(ws + P.normM2);
+    st.Y = (T*)(ws + P.Y);
+    st.K3 = (T*)(ws + P.K3);
+    st.part = (T*)(ws + P.part);
+    st.lra = (double*)(ws + P.lra);
+    st.ctrl = (Ctrl*)(ws + P.ctrl);
+    return st;
+}
+
+template <typename T>
+void run_sweep(concpd_ctx c, const StateP<T>& st, int extrap, int gate, int first) {
+    const Geo* g = c->dgeo;
+    const int S = c->S, R = c->R, Rq = c->Rq;
+    hipStream_t q = c->q;
+    const ItemP1* it1 = (const ItemP1*)(c->ws + c->lay.it1);
+    const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
+    const ItemU* itu[3];
+    for (int n = 0; n < 3; ++n) itu[n] = (const ItemU*)(c->ws + c->lay.itu[n]);
+    const bool prof = c->profiling && gate == 0;
+    hipEvent_t e[4];
+    if (prof)
+        for (int i = 0; i < 4; ++i) hipEventCreate(&e[i]);
+    cpd::launch_core<T>(g, st, S, R, extrap, gate, q);
+    if (prof) hipEventRecord(e[0], q);
+    cpd::launch_pass1<T>(g, st, it1, (int)c->lists.p1.size(), Rq, 1, gate, c->mdtype, q);
+    if (prof) hipEventRecord(e[1], q);
+    cpd::launch_update<T>(g, st, itu[0], (int)c->lists.u[0].size(), 0, R, extrap, gate, c->lists.lds_rows[0], q);
+    cpd::launch_prep<T>(g, st, S, R, 1, gate, q);
+    cpd::launch_update<T>(g, st, itu[1], (int)c->lists.u[1].size(), 1, R, extrap, gate, c->lists.lds_rows[1], q);
+    cpd::launch_prep<T>(g, st, S, R, 2, gate, q);
+    if (prof) hipEventRecord(e[2], q);
+    cpd::launch_pass2<T>(g, st, it2, (int)c->lists.p2.size(), Rq, 0, gate, c->mdtype, q);
+    if (prof) {
+        hipEventRecord(e[3], q);
+        c->ev1.push_back(e[0]);
+        c->ev1.push_back(e[1]);
+        c->ev2.push_back(e[2]);
+        c->ev2.push_back(e[3]);
+    }
+    cpd::launch_update<T>(g, st, itu[2], (int)c->lists.u[2].size(), 2, R, extrap, gate, c->lists.lds_rows[2], q);
+    cpd::launch_finish<T>(g, st, S, R, first, gate, q);
+}
+
+template <typename T>
+void run_iteration(concpd_ctx c, const StateP<T>& st) {
+    run_sweep<T>(c, st, 1, 0, 1);
+    if (c->cfg.restart) run_sweep<T>(c, st, 0, 1, 0);
+    cpd::launch_commit<T>(c->dgeo, st, c->lay.uslot, c->S, c->Rq, c->R, c->q);
+}
+
+// Grams, b, F and RelErr of the iterate in slot 1.
+template <typename T>
+void recompute_stats(concpd_ctx c, const StateP<T>& st) {
+    const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
+    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->q);
+    for (int s = 0; s < c->S; ++s)
+        cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], c->R, st.K3 + c->geo.koff[s], c->Rq, c->q);
+    cpd::launch_init_stats<T>(c->dgeo, st, c->S, c->R, c->q);
+}
+
+concpd_status read_stats(concpd_ctx c, concpd_stats* out) {
+    Ctrl h;
+    HIPCHECK(hipMemcpyAsync(&h, c->ctrl, sizeof h, hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    if (out) {
+        out->k = h.k;
+        out->F = h.F_prev;
+        out->relerr = h.rel_prev;
+        out->fit = 1.0 - h.rel_prev;
+        out->restarts = h.restarts;
+        out->restarted_last = h.last_restarted;
+        out->converged = h.stop;
+        out->nonfinite = !isfinite(h.F_prev);
+        out->lra = c->lra;
+    }
+    return CONCPD_OK;
+}
+
+// Host factor arrays (I x R doubles) -> slot layout (I x Rq, storage type).
+template <typename T>
+void pack_factors(concpd_ctx c, const double* const* U, std::vector<T>& out) {
+    out.assign((size_t)c->lay.uslot, (T)0);
+    for (int n = 0; n < 3; ++n)
+        for (int s = 0; s < c->S; ++s) {
+            const int I = (int)c->dims[3 * s + n];
+            const double* src = U[3 * s + n];
+            const double* shared = U[3 * 0 + n];
+            T* dst = out.data() + c->geo.uoff[n][s];
+            for (int i = 0; i < I; ++i)
+                for (int r = 0; r < c->R; ++r)
+                    dst[(size_t)i * c->Rq + r] = (T)(r < c->L[n] ? shared[(size_t)i * c->R + r] : src[(size_t)i * c->R + r]);
+        }
+}
+
+bool all_finite(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!isfinite(p[i])) return false;
+    return true;
+}
+
+template <typename T>
+concpd_status upload_iterate(concpd_ctx c, const double* const* U, const double* const* Up, const double* const* lam,
+                             const double* const* lamp) {
+    std::vector<T> h1, h2;
+    pack_factors<T>(c, U, h1);
+    pack_factors<T>(c, Up ? Up : U, h2);
+    const size_t bytes = (size_t)c->lay.uslot * sizeof(T);
+    HIPCHECK(hipMemcpyAsync(c->ws + c->lay.U[1], h1.data(), bytes, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipMemcpyAsync(c->ws + c->lay.U[2], h2.data(), bytes, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipMemcpyAsync(c->ws + c->lay.U[0], h1.data(), bytes, hipMemcpyHostToDevice, c->q));
+    std::vector<double> l1((size_t)c->S * c->Rq, 0.0), l2((size_t)c->S * c->Rq, 0.0);
+    for (int s = 0; s < c->S; ++s)
+        for (int r = 0; r < c->R; ++r) {
+            l1[(size_t)s * c->Rq + r] = lam[s][r];
+            l2[(size_t)s * c->Rq + r] = (lamp ? lamp : lam)[s][r];
+        }
+    HIPCHECK(hipMemcpyAsync(c->ws + c->lay.lam[1], l1.data(), l1.size() * 8, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipMemcpyAsync(c->ws + c->lay.lam[2], l2.data(), l2.size() * 8, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipMemcpyAsync(c->ws + c->lay.lam[0], l1.data(), l1.size() * 8, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));  // host vectors go out of scope
+    return CONCPD_OK;
+}
+
+concpd_status set_lipschitz_prev(concpd_ctx c, const double* Ld, const double* Lu, const double* LC) {
+    std::vector<double> ld(c->S, -1.0), lu(3 * c->S, -1.0), lc(3, -1.0);
+    for (int s = 0; s < c->S; ++s) {
+        if (Ld) ld[s] = Ld[s];
+        for (int n = 0; n < 3; ++n)
+            if (Lu) lu[n * c->S + s] = Lu[3 * s + n];
+    }
+    for (int n = 0; n < 3; ++n)
+        if (LC) lc[n] = LC[n];
+    HIPCHECK(hipMemcpyAsync(c->ws + c->lay.Ld_prev, ld.data(), ld.size() * 8, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipMemcpyAsync(c->ws + c->lay.Lu_prev, lu.data(), lu.size() * 8, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipMemcpyAsync(c->ws + c->lay.LC_prev, lc.data(), lc.size() * 8, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    return CONCPD_OK;
+}
+
+concpd_status set_ctrl(concpd_ctx c, double t, long long k) {
+    Ctrl h;
+    memset(&h, 0, sizeof h);
+    h.t = t;
+    const double tk = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+    h.w_hat = (t - 1.0) / tk;
+    h.F_prev = INFINITY;
+    h.F_cur = INFINITY;
+    h.rel_prev = INFINITY;
+    h.rel_cur = INFINITY;
+    h.tol = 0.0;
+    h.delta_w = c->cfg.delta_w;
+    h.k = k;
+    h.restart_on = c->cfg.restart;
+    HIPCHECK(hipMemcpyAsync(c->ctrl, &h, sizeof h, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    return CONCPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* concpd_last_error(void) { return g_err.c_str(); }
+
+concpd_status concpd_query_workspace(const concpd_config* cfg, size_t* bytes) {
+    concpd_status st = validate(cfg);
+    if (st != CONCPD_OK) return st;
+    if (!bytes) return fail(CONCPD_EINVAL, "bytes is NULL");
+    Lists L;
+    build_lists(cfg, &L);
+    Layout P;
+    Geo g;
+    plan(cfg, L, &P, &g);
+    *bytes = P.total;
+    return CONCPD_OK;
+}
+
+concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, const double* const* init_U,
+                          const double* const* init_lambda, uint64_t seed, void* workspace, size_t ws_bytes, void* stream,
+                          concpd_ctx* out) {
+    g_err.clear();
+    if (!out) return fail(CONCPD_EINVAL, "out is NULL");
+    *out = nullptr;
+    concpd_status st = validate(cfg);
+    if (st != CONCPD_OK) return st;
+    if (!tensors) return fail(CONCPD_EINVAL, "tensors is NULL");
+    for (int s = 0; s < cfg->num_blocks; ++s)
+        if (!tensors[s]) return fail(CONCPD_EINVAL, "tensors[%d] is NULL", s);
+    if (!workspace) return fail(CONCPD_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(CONCPD_EINVAL, "workspace must be 256-byte aligned");
+
+    concpd_ctx c = new concpd_ctx_s();
+    c->cfg = *cfg;
+    c->S = cfg->num_blocks;
+    c->R = cfg->rank;
+    c->Rq = (c->R + 3) / 4 * 4;
+    for (int n = 0; n < 3; ++n) c->L[n] = cfg->coupled[n];
+    c->dims.assign(cfg->dims, cfg->dims + 3 * c->S);
+    c->cfg.dims = c->dims.data();
+    if (cfg->tucker_ranks) {
+        c->tucker.assign(cfg->tucker_ranks, cfg->tucker_ranks + 3 * c->S);
+        c->cfg.tucker_ranks = c->tucker.data();
+    }
+    c->f64 = cfg->compute_dtype == CONCPD_F64;
+    c->mdtype = cfg->compute_dtype;
+    c->tensors.assign(tensors, tensors + c->S);
+    c->ws = (char*)workspace;
+    c->q = (hipStream_t)stream;
+    c->lra = 0;
+    c->launched_iters = 0;
+    c->profiling = 0;
+    build_lists(&c->cfg, &c->lists);
+    plan(&c->cfg, c->lists, &c->lay, &c->geo);
+    if (ws_bytes < c->lay.total) {
+        const size_t need = c->lay.total;
+        delete c;
+        return fail(CONCPD_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    }
+
+    // host-side initial iterate
+    std::vector<std::vector<double>> hU(3 * c->S);
+    std::vector<const double*> pU(3 * c->S);
+    std::vector<std::vector<double>> hl(c->S);
+    std::vector<const double*> pl(c->S);
+    if (!init_U || !init_lambda) {
+        SplitMix64 rng{seed};
+        for (int n = 0; n < 3; ++n)
+            for (int s = 0; s < c->S; ++s) {
+                const int I = (int)c->dims[3 * s + n];
+                std::vector<double>& v = hU[3 * s + n];
+                v.assign((size_t)I * c->R, 0.0);
+                for (int i = 0; i < I; ++i)
+                    for (int r = 0; r < c->R; ++r) {
+                        if (r < c->L[n] && s > 0) v[(size_t)i * c->R + r] = hU[n][(size_t)i * c->R + r];
+                        else v[(size_t)i * c->R + r] = rng.uniform();
+                    }
+            }
+        for (int s = 0; s < c->S; ++s) {
+            hl[s].resize(c->R);
+            for (int r = 0; r < c->R; ++r) hl[s][r] = rng.uniform();
+        }
+    }
+    for (int i = 0; i < 3 * c->S; ++i) pU[i] = init_U ? init_U[i] : hU[i].data();
+    for (int s = 0; s < c->S; ++s) pl[s] = init_lambda ? init_lambda[s] : hl[s].data();
+    for (int s = 0; s < c->S; ++s) {
+        for (int n = 0; n < 3; ++n)
+            if (!pU[3 * s + n] || !all_finite(pU[3 * s + n], (size_t)c->dims[3 * s + n] * c->R)) {
+                delete c;
+                return fail(pU[3 * s + n] ? CONCPD_ENONFINITE : CONCPD_EINVAL, "init_U[%d] missing or not finite", 3 * s + n);
+            }
+        if (!pl[s] || !all_finite(pl[s], c->R)) {
+            delete c;
+            return fail(pl[s] ? CONCPD_ENONFINITE : CONCPD_EINVAL, "init_lambda[%d] missing or not finite", s);
+        }
+    }
+
+#define INIT_CHECK(x)                 \
+    do {                              \
+        concpd_status s_ = (x);       \
+        if (s_ != CONCPD_OK) {        \
+            hipStreamSynchronize(c->q); \
+            delete c;                 \
+            return s_;                \
+        }                             \
+    } while (0)
+#define INIT_HIP(x)                                                                          \
+    do {                                                                                     \
+        hipError_t e_ = (x);                                                                 \
+        if (e_ != hipSuccess) {                                                              \
+            hipStreamSynchronize(c->q);                                                      \
+            delete c;                                                                        \
+            return fail(CONCPD_EHIP, "%s: %s", #x, hipGetErrorString(e_));                   \
+        }                                                                                    \
+    } while (0)
+
+    INIT_HIP(hipMemsetAsync(c->ws, 0, c->lay.total, c->q));
+    // operand copies of the tensors
+    for (int s = 0; s < c->S; ++s) c->geo.M[s] = c->tensors[s];
+    if (c->mdtype == CONCPD_BF16 || c->mdtype == CONCPD_F16) {
+        size_t off = c->lay.shadow;
+        for (int s = 0; s < c->S; ++s) {
+            cpd::launch_convert(c->tensors[s], c->mdtype, c->ws + off, c->lay.shadow_elems[s], c->q);
+            c->geo.M[s] = c->ws + off;
+            off += (size_t)c->lay.shadow_elems[s] * 2;
+        }
+    }
+    c->dgeo = (Geo*)(c->ws + c->lay.geo);
+    INIT_HIP(hipMemcpyAsync(c->dgeo, &c->geo, sizeof(Geo), hipMemcpyHostToDevice, c->q));
+    if (!c->lists.p1.empty())
+        INIT_HIP(hipMemcpyAsync(c->ws + c->lay.it1, c->lists.p1.data(), c->lists.p1.size() * sizeof(ItemP1), hipMemcpyHostToDevice, c->q));
+    if (!c->lists.p2.empty())
+        INIT_HIP(hipMemcpyAsync(c->ws + c->lay.it2, c->lists.p2.data(), c->lists.p2.size() * sizeof(ItemP2), hipMemcpyHostToDevice, c->q));
+    for (int n = 0; n < 3; ++n)
+        if (!c->lists.u[n].empty())
+            INIT_HIP(hipMemcpyAsync(c->ws + c->lay.itu[n], c->lists.u[n].data(), c->lists.u[n].size() * sizeof(ItemU),
+                                    hipMemcpyHostToDevice, c->q));
+    c->sf = make_state<float>(c->ws, c->lay);
+    c->sd = make_state<double>(c->ws, c->lay);
+    c->ctrl = (Ctrl*)(c->ws + c->lay.ctrl);
+
+    // finiteness of the tensors and their squared norms (original and operand copy)
+    int* dflag = (int*)(c->ws + c->lay.flag);
+    double* scratch = (double*)(c->ws + c->lay.scratch);
+    for (int s = 0; s < c->S; ++s) {
+        const long long n = c->dims[3 * s] * c->dims[3 * s + 1] * c->dims[3 * s + 2];
+        cpd::launch_finite_check(c->tensors[s], cfg->tensor_dtype, n, dflag, c->q);
+        cpd::launch_sqnorm(c->tensors[s], cfg->tensor_dtype, n, (double*)(c->ws + c->lay.normOrig) + s, scratch, 1024, c->q);
+        cpd::launch_sqnorm(c->geo.M[s], c->mdtype, n, (double*)(c->ws + c->lay.normM2) + s, scratch, 1024, c->q);
+    }
+    int hflag = 0;
+    INIT_HIP(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, c->q));
+    c->normOrig.resize(c->S);
+    INIT_HIP(hipMemcpyAsync(c->normOrig.data(), c->ws + c->lay.normOrig, sizeof(double) * c->S, hipMemcpyDeviceToHost, c->q));
+    INIT_HIP(hipStreamSynchronize(c->q));
+    if (hflag) {
+        delete c;
+        return fail(CONCPD_ENONFINITE, "a tensor holds NaN or Inf");
+    }
+    for (int s = 0; s < c->S; ++s)
+        if (!(c->normOrig[s] > 0.0)) {
+            delete c;
+            return fail(CONCPD_EINVAL, "tensor %d is identically zero", s);
+        }
+
+    INIT_CHECK(c->f64 ? upload_iterate<double>(c, pU.data(), nullptr, pl.data(), nullptr)
+                      : upload_iterate<float>(c, pU.data(), nullptr, pl.data(), nullptr));
+    INIT_CHECK(set_lipschitz_prev(c, nullptr, nullptr, nullptr));
+    INIT_CHECK(set_ctrl(c, 1.0, 0));
+    if (c->f64) recompute_stats<double>(c, c->sd);
+    else recompute_stats<float>(c, c->sf);
+    INIT_HIP(hipGetLastError());
+    INIT_HIP(hipStreamSynchronize(c->q));
+    *out = c;
+    return CONCPD_OK;
+#undef INIT_CHECK
+#undef INIT_HIP
+}
+
+concpd_status concpd_step(concpd_ctx c, int32_t n_iter, concpd_stats* out) {
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    if (n_iter < 0) return fail(CONCPD_EINVAL, "n_iter < 0");
+    for (int i = 0; i < n_iter; ++i) {
+        if (c->f64) run_iteration<double>(c, c->sd);
+        else run_iteration<float>(c, c->sf);
+    }
+    c->launched_iters += n_iter;
+    HIPCHECK(hipGetLastError());
+    if (out) return read_stats(c, out);
+    return CONCPD_OK;
+}
+
+concpd_status concpd_fit(concpd_ctx c, concpd_stats* out) {
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    const double tol = c->cfg.tol;
+    HIPCHECK(hipMemcpyAsync(&c->ctrl->tol, &tol, sizeof tol, hipMemcpyHostToDevice, c->q));
+    concpd_stats s;
+    concpd_status r = read_stats(c, &s);
+    if (r != CONCPD_OK) return r;
+    while (!s.converged && s.k < c->cfg.max_it) {
+        const int chunk = (int)std::min<long long>(16, c->cfg.max_it - s.k);
+        r = concpd_step(c, chunk, &s);
+        if (r != CONCPD_OK) return r;
+    }
+    if (out) *out = s;
+    return CONCPD_OK;
+}
+
+concpd_status lra_compress(concpd_ctx c, const int32_t* ranks, concpd_stats* out) {
+    (void)ranks;
+    (void)out;
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    return fail(CONCPD_ESTATE, "lra_compress: no Tucker ranks configured");
+}
+
+concpd_status lra_step(concpd_ctx c, int32_t n_iter, concpd_stats* out) {
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    if (!c->lra) return fail(CONCPD_ESTATE, "lra_step before lra_compress");
+    return concpd_step(c, n_iter, out);
+}
+
+concpd_status concpd_global_fit(concpd_ctx c, double* fit) {
+    if (!c || !fit) return fail(CONCPD_EINVAL, "NULL argument");
+    double* scratch = (double*)(c->ws + c->lay.scratch);
+    double* res = scratch + c->lay.scratch_len - 1;
+    double acc = 0.0;
+    for (int s = 0; s < c->S; ++s) {
+        const int I1 = (int)c->dims[3 * s];
+        if (c->f64) cpd::launch_resid<double>(c->dgeo, c->sd, c->tensors[s], c->cfg.tensor_dtype, s, I1, scratch, c->q);
+        else cpd::launch_resid<float>(c->dgeo, c->sf, c->tensors[s], c->cfg.tensor_dtype, s, I1, scratch, c->q);
+        cpd::launch_sum_parts(scratch, I1, res, c->q);
+        double h = 0.0;
+        HIPCHECK(hipMemcpyAsync(&h, res, sizeof h, hipMemcpyDeviceToHost, c->q));
+        HIPCHECK(hipStreamSynchronize(c->q));
+        acc += sqrt(fmax(0.0, h)) / sqrt(c->normOrig[s]);
+    }
+    *fit = 1.0 - acc / c->S;
+    return CONCPD_OK;
+}
+
+concpd_status concpd_get_factor(concpd_ctx c, int32_t n, int32_t s, double* dst) {
+    if (!c || !dst) return fail(CONCPD_EINVAL, "NULL argument");
+    if (n < 0 || n > 2 || s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "n/s out of range");
+    const int I = (int)c->dims[3 * s + n];
+    const size_t cnt = (size_t)I * c->Rq;
+    const char* src = c->ws + c->lay.U[1] + (size_t)c->geo.uoff[n][s] * c->lay.esz;
+    if (c->f64) {
+        std::vector<double> h(cnt);
+        HIPCHECK(hipMemcpyAsync(h.data(), src, cnt * 8, hipMemcpyDeviceToHost, c->q));
+        HIPCHECK(hipStreamSynchronize(c->q));
+        for (int i = 0; i < I; ++i)
+            for (int r = 0; r < c->R; ++r) dst[(size_t)i * c->R + r] = h[(size_t)i * c->Rq + r];
+    } else {
+        std::vector<float> h(cnt);
+        HIPCHECK(hipMemcpyAsync(h.data(), src, cnt * 4, hipMemcpyDeviceToHost, c->q));
+        HIPCHECK(hipStreamSynchronize(c->q));
+        for (int i = 0; i < I; ++i)
+            for (int r = 0; r < c->R; ++r) dst[(size_t)i * c->R + r] = h[(size_t)i * c->Rq + r];
+    }
+    return CONCPD_OK;
+}
+
+concpd_status concpd_get_lambda(concpd_ctx c, int32_t s, double* dst) {
+    if (!c || !dst) return fail(CONCPD_EINVAL, "NULL argument");
+    if (s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "s out of range");
+    HIPCHECK(hipMemcpyAsync(dst, c->ws + c->lay.lam[1] + sizeof(double) * s * c->Rq, sizeof(double) * c->R,
+                            hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    return CONCPD_OK;
+}
+
+concpd_status concpd_get_lipschitz(concpd_ctx c, double* Ld, double* Lu, double* LC) {
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    std::vector<double> ld(c->S), lu(3 * c->S), lc(3);
+    HIPCHECK(hipMemcpyAsync(ld.data(), c->ws + c->lay.Ld_prev, 8 * ld.size(), hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipMemcpyAsync(lu.data(), c->ws + c->lay.Lu_prev, 8 * lu.size(), hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipMemcpyAsync(lc.data(), c->ws + c->lay.LC_prev, 8 * lc.size(), hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    for (int s = 0; s < c->S; ++s) {
+        if (Ld) Ld[s] = ld[s];
+        for (int n = 0; n < 3; ++n)
+            if (Lu) Lu[3 * s + n] = lu[n * c->S + s];
+    }
+    if (LC)
+        for (int n = 0; n < 3; ++n) LC[n] = lc[n];
+    return CONCPD_OK;
+}
+
+concpd_status concpd_set_state(concpd_ctx c, const double* const* U, const double* const* U_prev,
+                               const double* const* lam, const double* const* lam_prev, const double* Ld_prev,
+                               const double* Lu_prev, const double* LC_prev, double t, int64_t k) {
+    if (!c || !U || !lam) return fail(CONCPD_EINVAL, "NULL argument");
+    if (!(t >= 1.0) || k < 0) return fail(CONCPD_EINVAL, "t must be >= 1 and k >= 0");
+    for (int s = 0; s < c->S; ++s) {
+        for (int n = 0; n < 3; ++n) {
+            const size_t cnt = (size_t)c->dims[3 * s + n] * c->R;
+            if (!U[3 * s + n]) return fail(CONCPD_EINVAL, "U[%d] is NULL", 3 * s + n);
+            if (!all_finite(U[3 * s + n], cnt) || (U_prev && (!U_prev[3 * s + n] || !all_finite(U_prev[3 * s + n], cnt))))
+                return fail(CONCPD_ENONFINITE, "U / U_prev[%d] missing or not finite", 3 * s + n);
+        }
+        if (!lam[s] || !all_finite(lam[s], c->R) || (lam_prev && (!lam_prev[s] || !all_finite(lam_prev[s], c->R))))
+            return fail(CONCPD_ENONFINITE, "lambda / lambda_prev[%d] missing or not finite", s);
+    }
+    concpd_status r = c->f64 ? upload_iterate<double>(c, U, U_prev, lam, lam_prev)
+                             : upload_iterate<float>(c, U, U_prev, lam, lam_prev);
+    if (r != CONCPD_OK) return r;
+    r = set_lipschitz_prev(c, Ld_prev, Lu_prev, LC_prev);
+    if (r != CONCPD_OK) return r;
+    r = set_ctrl(c, t, k);
+    if (r != CONCPD_OK) return r;
+    if (c->f64) recompute_stats<double>(c, c->sd);
+    else recompute_stats<float>(c, c->sf);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(c->q));
+    return CONCPD_OK;
+}
+
+concpd_status concpd_loss_grad(concpd_ctx c, const void* const* U_dev, const void* const* lambda_dev, double* loss,
+                               void* const* gU_dev, void* const* glam_dev) {
+    (void)U_dev;
+    (void)lambda_dev;
+    (void)loss;
+    (void)gU_dev;
+    (void)glam_dev;
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    return fail(CONCPD_ENOTSUP, "concpd_loss_grad not available yet");
+}
+
+concpd_status concpd_debug_mttkrp(concpd_ctx c, int32_t n, int32_t s, void* dev_out) {
+    if (!c || !dev_out) return fail(CONCPD_EINVAL, "NULL argument");
+    if (n < 0 || n > 2 || s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "n/s out of range");
+    const ItemP1* it1 = (const ItemP1*)(c->ws + c->lay.it1);
+    const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
+    const int I = (int)c->dims[3 * s + n];
+    if (c->f64) {
+        cpd::launch_pass1<double>(c->dgeo, c->sd, it1, (int)c->lists.p1.size(), c->Rq, 1, 0, c->mdtype, c->q);
+        cpd::launch_pass2<double>(c->dgeo, c->sd, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->q);
+        cpd::launch_extract_k<double>(c->dgeo, c->sd, s, n, I, c->R, (double*)dev_out, c->R, c->q);
+    } else {
+        cpd::launch_pass1<float>(c->dgeo, c->sf, it1, (int)c->lists.p1.size(), c->Rq, 1, 0, c->mdtype, c->q);
+        cpd::launch_pass2<float>(c->dgeo, c->sf, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->q);
+        cpd::launch_extract_k<float>(c->dgeo, c->sf, s, n, I, c->R, (float*)dev_out, c->R, c->q);
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(c->q));
+    return CONCPD_OK;
+}
+
+concpd_status concpd_profile(concpd_ctx c, int32_t enable) {
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    c->profiling = enable != 0;
+    return CONCPD_OK;
+}
+
+concpd_status concpd_profile_read(concpd_ctx c, double* ms1, double* ms2, int64_t* launches) {
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    HIPCHECK(hipStreamSynchronize(c->q));
+    double a = 0.0, b = 0.0;
+    for (size_t i = 0; i + 1 < c->ev1.size(); i += 2) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, c->ev1[i], c->ev1[i + 1]));
+        a += ms;
+        ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, c->ev2[i], c->ev2[i + 1]));
+        b += ms;
+    }
+    if (ms1) *ms1 = a;
+    if (ms2) *ms2 = b;
+    if (launches) *launches = (int64_t)(c->ev1.size() / 2);
+    for (hipEvent_t e : c->ev1) hipEventDestroy(e);
+    for (hipEvent_t e : c->ev2) hipEventDestroy(e);
+    c->ev1.clear();
+    c->ev2.clear();
+    return CONCPD_OK;
+}
+
+concpd_status concpd_destroy(concpd_ctx c) {
+    if (!c) return CONCPD_OK;
+    hipStreamSynchronize(c->q);
+    for (hipEvent_t e : c->ev1) hipEventDestroy(e);
+    for (hipEvent_t e : c->ev2) hipEventDestroy(e);
+    delete c;
+    return CONCPD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+"""Python front end of the C ABI.  PyTorch supplies device memory (the
+tensors and the workspace) and the stream; all arithmetic runs in the HIP
+library.  Nothing here computes any part of the method.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import Config, Stats, check, load
+
+DTYPES = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "f16": _lib.F16}
+
+
+def _dbl_ptr_array(arrays):
+    """Keep-alive list of contiguous float64 arrays and a C array of their pointers."""
+    keep = [np.ascontiguousarray(a, dtype=np.float64) for a in arrays]
+    ptrs = (ctypes.POINTER(ctypes.c_double) * len(keep))(*[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in keep])
+    return keep, ptrs
+
+
+def _opt_dbl(a):
+    if a is None:
+        return None, None
+    k = np.ascontiguousarray(a, dtype=np.float64)
+    return k, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _void_ptr_array(ptrs):
+    return (ctypes.c_void_p * len(ptrs))(*ptrs)
+
+
+class CoupledCP:
+    """Coupled nonnegative CP decomposition of S third-order blocks on one GPU.
+
+    tensors      list of S contiguous 3-way torch tensors on one HIP device
+                 (float32, or float64 with compute="f64"); borrowed.
+    rank         R; coupled = (L1, L2, L3) shared leading columns per mode.
+    compute      "f64" | "f32" | "bf16" | "f16": MTTKRP operand type.
+    init_U       optional [n][s] arrays (I_n x R); init_lambda optional [s] arrays.
+    tucker_ranks optional (J1, J2, J3) or [S][3] for lra_compress.
+    """
+
+    def __init__(self, tensors, rank: int, coupled=(0, 0, 0), compute: str = "f32", init_U=None, init_lambda=None,
+                 seed: int = 0, update_core: bool = True, restart: bool = True, delta_w: float = 0.9999,
+                 tol: float = 1e-8, max_it: int = 1000, tucker_ranks=None, stream=None):
+        import torch
+
+        self._lib = load()
+        self.tensors = list(tensors)
+        S = len(self.tensors)
+        dev = self.tensors[0].device
+        for t in self.tensors:
+            if t.device != dev or t.dim() != 3 or not t.is_contiguous():
+                raise ValueError("tensors must be contiguous 3-way tensors on one device")
+        tdt = _lib.F64 if self.tensors[0].dtype == torch.float64 else _lib.F32
+        if any(t.dtype not in (torch.float32, torch.float64) or t.dtype != self.tensors[0].dtype for t in self.tensors):
+            raise ValueError("tensors must all be float32 or all float64")
+        self.S, self.R = S, int(rank)
+        self.coupled = tuple(int(x) for x in coupled)
+        self.dims = [tuple(int(d) for d in t.shape) for t in self.tensors]
+        self._dims_c = (ctypes.c_int64 * (3 * S))(*[d for dims in self.dims for d in dims])
+        self._tucker_c = None
+        if tucker_ranks is not None:
+            tr = np.asarray(tucker_ranks, dtype=np.int32)
+            if tr.ndim == 1:
+                tr = np.tile(tr, (S, 1))
+            self._tucker_c = (ctypes.c_int32 * (3 * S))(*tr.reshape(-1).tolist())
+        cfg = Config()
+        cfg.order = 3
+        cfg.num_blocks = S
+        cfg.rank = self.R
+        for n in range(3):
+            cfg.coupled[n] = self.coupled[n]
+        cfg.dims = self._dims_c
+        cfg.tensor_dtype = tdt
+        cfg.compute_dtype = DTYPES[compute]
+        cfg.update_core = int(update_core)
+        cfg.restart = int(restart)
+        cfg.delta_w = float(delta_w)
+        cfg.tol = float(tol)
+        cfg.max_it = int(max_it)
+        cfg.tucker_ranks = self._tucker_c
+        self.cfg = cfg
+        self.compute = compute
+        nbytes = ctypes.c_size_t()
+        check(self._lib.concpd_query_workspace(ctypes.byref(cfg), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        tptrs = _void_ptr_array([t.data_ptr() for t in self.tensors])
+        keepU = keepL = None
+        pU = pL = None
+        if init_U is not None:
+            flat = [init_U[n][s] for s in range(S) for n in range(3)]
+            keepU, pU = _dbl_ptr_array(flat)
+        if init_lambda is not None:
+            keepL, pL = _dbl_ptr_array(init_lambda)
+        ctx = ctypes.c_void_p()
+        check(self._lib.concpd_init(ctypes.byref(cfg), tptrs, pU, pL, ctypes.c_uint64(seed), ctypes.c_void_p(self._ws_ptr),
+                                    ctypes.c_size_t(int(nbytes.value)), ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(ctx)))
+        self.ctx = ctx
+        del keepU, keepL
+
+    # -- iteration --------------------------------------------------------
+    def step(self, n_iter: int = 1, sync: bool = True) -> Optional[dict]:
+        st = Stats()
+        check(self._lib.concpd_step(self.ctx, int(n_iter), ctypes.byref(st) if sync else None))
+        return st.as_dict() if sync else None
+
+    def fit(self) -> dict:
+        st = Stats()
+        check(self._lib.concpd_fit(self.ctx, ctypes.byref(st)))
+        return st.as_dict()
+
+    def lra_compress(self, ranks=None) -> dict:
+        st = Stats()
+        pr = None
+        if ranks is not None:
+            r = np.asarray(ranks, dtype=np.int32)
+            if r.ndim == 1:
+                r = np.tile(r, (self.S, 1))
+            self._ranks_c = (ctypes.c_int32 * (3 * self.S))(*r.reshape(-1).tolist())
+            pr = self._ranks_c
+        check(self._lib.lra_compress(self.ctx, pr, ctypes.byref(st)))
+        return st.as_dict()
+
+    def lra_step(self, n_iter: int = 1, sync: bool = True) -> Optional[dict]:
+        st = Stats()
+        check(self._lib.lra_step(self.ctx, int(n_iter), ctypes.byref(st) if sync else None))
+        return st.as_dict() if sync else None
+
+    def stats(self) -> dict:
+        return self.step(0)
+
+    # -- read-back --------------------------------------------------------
+    def factor(self, n: int, s: int) -> np.ndarray:
+        out = np.empty((self.dims[s][n], self.R), dtype=np.float64)
+        check(self._lib.concpd_get_factor(self.ctx, n, s, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def factors(self):
+        return [[self.factor(n, s) for s in range(self.S)] for n in range(3)]
+
+    def lam(self, s: int) -> np.ndarray:
+        out = np.empty(self.R, dtype=np.float64)
+        check(self._lib.concpd_get_lambda(self.ctx, s, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def lams(self):
+        return [self.lam(s) for s in range(self.S)]
+
+    def lipschitz(self):
+        Ld = np.empty(self.S)
+        Lu = np.empty(3 * self.S)
+        LC = np.empty(3)
+        P = ctypes.POINTER(ctypes.c_double)
+        check(self._lib.concpd_get_lipschitz(self.ctx, Ld.ctypes.data_as(P), Lu.ctypes.data_as(P), LC.ctypes.data_as(P)))
+        return Ld, Lu.reshape(self.S, 3), LC
+
+    def global_fit(self) -> float:
+        f = ctypes.c_double()
+        check(self._lib.concpd_global_fit(self.ctx, ctypes.byref(f)))
+        return f.value
+
+    def debug_mttkrp(self, n: int, s: int):
+        import torch
+
+        dt = torch.float64 if self.compute == "f64" else torch.float32
+        out = torch.empty((self.dims[s][n], self.R), dtype=dt, device=self.tensors[0].device)
+        check(self._lib.concpd_debug_mttkrp(self.ctx, n, s, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def set_state(self, U, lam, U_prev=None, lam_prev=None, Ld_prev=None, Lu_prev=None, LC_prev=None, t=1.0, k=0):
+        """U, U_prev: [n][s] arrays; Lu_prev [s][n] (or [n][s] transposed by caller); None entries mean 'none'."""
+        flat = lambda UU: [UU[n][s] for s in range(self.S) for n in range(3)]  # noqa: E731
+        kU, pU = _dbl_ptr_array(flat(U))
+        kL, pL = _dbl_ptr_array(lam)
+        kUp = pUp = kLp = pLp = None
+        if U_prev is not None:
+            kUp, pUp = _dbl_ptr_array(flat(U_prev))
+        if lam_prev is not None:
+            kLp, pLp = _dbl_ptr_array(lam_prev)
+
+        def _arr(x, shape):
+            if x is None:
+                return None, None
+            a = np.array([(-1.0 if v is None else float(v)) for v in np.asarray(x, dtype=object).reshape(-1)],
+                         dtype=np.float64).reshape(shape)
+            return _opt_dbl(a)
+
+        kd, pd = _arr(Ld_prev, (self.S,))
+        ku, pu = _arr(Lu_prev, (self.S, 3))
+        kc, pc = _arr(LC_prev, (3,))
+        check(self._lib.concpd_set_state(self.ctx, pU, pUp, pL, pLp, pd, pu, pc, float(t), int(k)))
+        del kU, kL, kUp, kLp, kd, ku, kc
+
+    def profile(self, enable: bool = True):
+        check(self._lib.concpd_profile(self.ctx, int(enable)))
+
+    def profile_read(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        n = ctypes.c_int64()
+        check(self._lib.concpd_profile_read(self.ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)))
+        return a.value, b.value, n.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            check(self._lib.concpd_destroy(self.ctx))
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

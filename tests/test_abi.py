@@ -1,0 +1,105 @@
+"""The C-ABI library loads, exports every symbol include/concpd.h declares,
+and rejects invalid configurations on the host (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "concpd.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:concpd_status|const char\*)\s+(\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2302_05119_amd import _lib
+    return _lib.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", os.path.join(ROOT, "paper_2302_05119_amd", "libconcpd.so")],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, re.M))
+    for s in syms:
+        assert s in exported, s
+        assert hasattr(lib, s)
+
+
+def _cfg(S=2, R=5, L=(5, 0, 0), dims=None, tdt=1, cdt=1):
+    from paper_2302_05119_amd._lib import Config
+    dims = dims or [(10, 11, 12)] * S
+    c = Config()
+    c.order = 3
+    c.num_blocks = S
+    c.rank = R
+    for n in range(3):
+        c.coupled[n] = L[n]
+    arr = (ctypes.c_int64 * (3 * S))(*[d for t in dims for d in t])
+    c.dims = arr
+    c.tensor_dtype = tdt
+    c.compute_dtype = cdt
+    c.update_core = 1
+    c.restart = 1
+    c.delta_w = 0.9999
+    c.tol = 1e-8
+    c.max_it = 100
+    c.tucker_ranks = None
+    c._keep = arr
+    return c
+
+
+def query(lib, c):
+    n = ctypes.c_size_t()
+    st = lib.concpd_query_workspace(ctypes.byref(c), ctypes.byref(n))
+    return st, n.value
+
+
+def test_query_workspace_valid(lib):
+    st, n = query(lib, _cfg())
+    assert st == 0 and n > 0
+    st2, n2 = query(lib, _cfg(S=4))
+    assert st2 == 0 and n2 > n
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(R=0), 1),
+    (dict(R=65), 1),
+    (dict(L=(6, 0, 0)), 1),
+    (dict(dims=[(10, 11, 12), (9, 11, 12)]), 1),   # coupled mode with unequal sizes
+    (dict(S=0), 1),
+    (dict(tdt=1, cdt=0), 1),                        # F64 compute needs F64 tensors
+    (dict(tdt=0, cdt=1), 2),                        # F64 tensors only with F64 compute
+])
+def test_invalid_configs_rejected_with_message(lib, kw, expect):
+    st, _ = query(lib, _cfg(**kw))
+    assert st == expect
+    assert len(lib.concpd_last_error()) > 0
+
+
+def test_order_other_than_three_not_supported(lib):
+    c = _cfg()
+    c.order = 4
+    st, _ = query(lib, c)
+    assert st == 2
+
+
+def test_init_rejects_null_arguments_without_device(lib):
+    c = _cfg()
+    ctx = ctypes.c_void_p()
+    st = lib.concpd_init(ctypes.byref(c), None, None, None, 0, None, 0, None, ctypes.byref(ctx))
+    assert st == 1 and not ctx.value
+
+
+def test_calls_on_null_context_fail_cleanly(lib):
+    from paper_2302_05119_amd._lib import Stats
+    assert lib.concpd_step(None, 1, ctypes.byref(Stats())) == 1
+    assert lib.lra_step(None, 1, None) == 1
+    assert lib.concpd_destroy(None) == 0
