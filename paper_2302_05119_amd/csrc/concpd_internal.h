@@ -47,6 +47,9 @@ struct Geo {
     long long goff[CPD_MAXS];     // Tucker cores G^(s): J1 x J2 x J3 (double), i3 fastest
     long long woff[3][CPD_MAXS];  // W_n^(s) = A_n^T U^(n): J_n x Rq (double)
     long long coff[CPD_MAXS];     // lra scratch per block
+    long long k1off[CPD_MAXS];    // mode-1 MTTKRP partials per 64-row group: I1 x nrg x Rq
+    long long k2off[CPD_MAXS];    // mode-2 MTTKRP: I2 x Rq
+    int nrg[CPD_MAXS];            // ceil(I2 / 64)
     const void* M[CPD_MAXS];      // block tensors in the MTTKRP operand type
     int mdtype;                   // operand type of M (concpd_dtype)
 };
@@ -70,6 +73,8 @@ struct StateP {
     T* Y;               // pass-1 output
     T* K3;              // reduced mode-3 MTTKRP
     T* part;            // mode-3 partials
+    T* K1p;             // mode-1 partials
+    T* K2;              // mode-2 MTTKRP
     double* lra;        // Tucker storage base (A, G, W, scratch)
     Ctrl* ctrl;
 };
@@ -78,6 +83,7 @@ struct StateP {
 struct ItemP1 { int s, i1, rg, pad; };              // pass 1: block, slab, 64-row group
 struct ItemP2 { int s, chunk, q0, pad; };           // pass 2: block, 4-slab chunk, i3 start
 struct ItemU  { int s0, ns, row0, nrows; };         // update: blocks [s0, s0+ns), rows
+struct ItemK2 { int s, row0, pad0, pad1; };         // mode-2 contraction: block, 64-row start
 
 // Kernel launchers (defined in the .hip files).
 namespace cpd {
@@ -87,7 +93,8 @@ template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int 
 template <typename T> void launch_commit(const Geo* g, const StateP<T>& st, long long uslot, int S, int Rq, int R, hipStream_t q);
 template <typename T> void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
 template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int Rq, int slot, int gate, int mdtype, hipStream_t q);
-template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int gate, int mdtype, hipStream_t q);
+template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int gate, int mdtype, int maxI2, hipStream_t q);
+template <typename T> void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, int gate, hipStream_t q);
 template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int gate, int lds_rows, hipStream_t q);
 template <typename T> void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, int R, T* out, int ld_out, hipStream_t q);
 template <typename T> void launch_resid(const Geo* g, const StateP<T>& st, const void* M, int dtype, int s, int I1, double* part, hipStream_t q);

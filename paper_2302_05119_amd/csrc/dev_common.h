@@ -11,6 +11,12 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 namespace cpd {
 
+// Global-address-space view of a pointer read from a struct (such pointers
+// are generic otherwise, and generic accesses serialise with LDS traffic).
+#define CPD_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ const CPD_GLOBAL T* gptr(const T* p) { return (const CPD_GLOBAL T*)p; }
+template <typename T> __device__ __forceinline__ CPD_GLOBAL T* gptr_w(T* p) { return (CPD_GLOBAL T*)p; }
+
 // Orders LDS traffic of one wavefront (lanes of a wave exchanging data
 // through LDS without a workgroup barrier).
 __device__ __forceinline__ void wave_sync() {

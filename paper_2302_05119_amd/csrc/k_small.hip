@@ -1,271 +1,122 @@
-// Small FP64 kernels of the sweep: Hadamard products of Grams, exact spectral
-// norms, the core (lambda) update, the objective / restart test and the
-// commit of an accepted iterate.  One workgroup per block for the R x R work.
-#include "dev_common.h"
+// Small FP64 kernels of the sweep: the core (lambda) update, Grams and step
+// matrices with their exact spectral norms, the objective with the restart
+// test, and the commit of an accepted iterate.  One workgroup per block for
+// the R x R work.
+#include "small_dev.h"
 
 namespace cpd {
 
-// ---------------------------------------------------------------------------
-// Largest eigenvalue of a symmetric n x n matrix (n <= 64) held row-major in
-// LDS (row stride ld).  Executed by one wavefront: Householder reduction to
-// tridiagonal form, then Sturm-count multisection (64 shifts per round) on the
-// tridiagonal.  This is the spectral norm of eq. eqLipsLd / eqLipsLu for the
-// PSD matrices used there; A is overwritten.  `w` is >= 320 doubles of LDS.
-// ---------------------------------------------------------------------------
-__device__ double wave_sym_lmax(double* A, int n, int ld, double* w) {
-    const int lane = threadIdx.x & 63;
-    double* v = w;
-    double* q = w + 64;
-    double* d = w + 128;
-    double* e2 = w + 192;
-    double* ea = w + 256;
-
-    int bad = 0;
-    for (int i = lane; i < n * n; i += 64) {
-        double x = A[(i / n) * ld + (i % n)];
-        bad |= !isfinite(x);
-    }
-    if (__ballot(bad)) return __longlong_as_double(0x7ff8000000000000LL);
-    if (n == 1) return A[0];
-
-    for (int k = 0; k + 2 < n; ++k) {
-        const double x = (lane > k && lane < n) ? A[lane * ld + k] : 0.0;
-        const double sig = wave_sum(x * x);
-        const double dk = A[k * ld + k];
-        if (sig == 0.0) {
-            if (lane == 0) { d[k] = dk; e2[k] = 0.0; ea[k] = 0.0; }
-            wave_sync();
-            continue;
-        }
-        const double x0 = __shfl(x, k + 1, 64);
-        const double alpha = (x0 >= 0.0) ? -sqrt(sig) : sqrt(sig);
-        const double vn = sqrt(2.0 * (sig - alpha * x0));
-        const double vi = (x - ((lane == k + 1) ? alpha : 0.0)) / vn;
-        v[lane] = vi;
-        wave_sync();
-        double p = 0.0;
-        if (lane > k && lane < n) {
-            const double* row = A + lane * ld;
-            for (int j = k + 1; j < n; ++j) p += row[j] * v[j];
-        }
-        const double K = wave_sum(vi * p);
-        const double qi = p - K * vi;
-        q[lane] = qi;
-        wave_sync();
-        if (lane > k && lane < n) {
-            double* row = A + lane * ld;
-            for (int j = k + 1; j < n; ++j) row[j] -= 2.0 * (vi * q[j] + qi * v[j]);
-        }
-        if (lane == 0) { d[k] = dk; e2[k] = alpha * alpha; ea[k] = fabs(alpha); }
-        wave_sync();
-    }
-    if (lane == 0) {
-        d[n - 2] = A[(n - 2) * ld + n - 2];
-        d[n - 1] = A[(n - 1) * ld + n - 1];
-        const double e = A[(n - 1) * ld + n - 2];
-        e2[n - 2] = e * e;
-        ea[n - 2] = fabs(e);
-    }
-    wave_sync();
-
-    // Gershgorin interval of the tridiagonal
-    double lo = INFINITY, hi = -INFINITY;
-    if (lane < n) {
-        const double r = (lane > 0 ? ea[lane - 1] : 0.0) + (lane < n - 1 ? ea[lane] : 0.0);
-        lo = d[lane] - r;
-        hi = d[lane] + r;
-    }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    for (int it = 0; it < 64; ++it) {
-        if (!(hi - lo > 4.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
-        const double x = lo + (hi - lo) * ((double)(lane + 1) / 65.0);
-        // number of eigenvalues below x = negative pivots of T - x I = L D L^T
-        double piv = d[0] - x;
-        int cnt = piv < 0.0;
-        for (int i = 1; i < n; ++i) {
-            if (piv == 0.0) piv = -DBL_MIN;
-            piv = (d[i] - x) - e2[i - 1] / piv;
-            cnt += piv < 0.0;
-        }
-        const unsigned long long above = __ballot(cnt >= n);
-        if (above == 0ull) {
-            lo = __shfl(x, 63, 64);
-        } else {
-            const int f = __ffsll((long long)above) - 1;
-            const double xf = __shfl(x, f, 64);
-            const double xp = __shfl(x, f > 0 ? f - 1 : 0, 64);
-            hi = xf;
-            if (f > 0) lo = xp;
-        }
-    }
-    return 0.5 * (lo + hi);
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_core(const Geo* __restrict__ g, StateP<T> st, int extrapolate, int gate) {
+    if (gated_out(st.ctrl, gate)) return;
+    extern __shared__ char smraw[];
+    core_block<T, NMAX>(g, st, blockIdx.x, extrapolate, smraw);
 }
 
-// ---------------------------------------------------------------------------
-// Core tensor update (eq. solD with the gradient of eq. solapgG at the
-// extrapolated point of eq. eqextraPG) and the mode-1 step matrix
-// P = D H_{-1} D with its spectral norm.  One 64-thread workgroup per block.
-// b (the data term (U^⊙)^T vec(M)) is the value kept from the previous sweep.
-// ---------------------------------------------------------------------------
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_prep(const Geo* __restrict__ g, StateP<T> st, int n, int gate) {
+    if (gated_out(st.ctrl, gate)) return;
+    extern __shared__ char smraw[];
+    prep_block<T, NMAX>(g, st, blockIdx.x, n, smraw);
+}
+
+// b = colsum(K3 ⊛ U^(3)) and the Gram of U^(3) from LDS-staged rows.
 template <typename T>
-__global__ __launch_bounds__(64) void k_core(const Geo* __restrict__ g, StateP<T> st, int extrapolate, int gate) {
-    const Ctrl* c = st.ctrl;
-    if (gated_out(c, gate)) return;
-    const int s = blockIdx.x, lane = threadIdx.x;
-    const int S = g->S, R = g->R, Rq = g->Rq, ld = R | 1, RR = R * R;
-    extern __shared__ double sm[];
-    double* A = sm;
-    double* w = A + R * ld;
-    double* lh = w + 320;
-    double* ln = lh + 64;
-
-    const double* V0 = st.V[1] + (0 * S + s) * RR;
-    const double* V1 = st.V[1] + (1 * S + s) * RR;
-    const double* V2 = st.V[1] + (2 * S + s) * RR;
-    for (int i = lane; i < RR; i += 64) A[(i / R) * ld + i % R] = V0[i] * V1[i] * V2[i];
-    wave_sync();
-    const double Ld = wave_sym_lmax(A, R, ld, w);
-
-    const double* l1 = st.lam[1] + s * Rq;
-    const double* l2 = st.lam[2] + s * Rq;
-    const double wd = extrap_weight(extrapolate, c->w_hat, st.Ld_prev[s], Ld, c->delta_w);
-    if (lane < R) lh[lane] = l1[lane] + wd * (l1[lane] - l2[lane]);
-    wave_sync();
-    double nl = (lane < R) ? l1[lane] : 0.0;
-    if (g->upd_core && Ld > 0.0 && lane < R) {
-        double gr = -st.b[1][s * Rq + lane];
-        for (int r = 0; r < R; ++r) {
-            const int i = lane * R + r;
-            gr += V0[i] * V1[i] * V2[i] * lh[r];
+__device__ __forceinline__ void gram_and_b(const T* __restrict__ U3, const T* __restrict__ K3, int I3, int R, int Rq, double* __restrict__ V,
+                           double* __restrict__ b, char* lds) {
+    T* tile = (T*)(lds + ((gram_acc_bytes(R) + 255) & ~(size_t)255));
+    block_gram<T>(U3, I3, R, Rq, V, tile, 128, (double*)lds);
+    // b: 256 threads = 4 row phases x 64 columns; tiles of 64 rows of K3 and U3 in LDS
+    __shared__ double bp[4][CPD_MAXR];
+    const int tid = threadIdx.x, c = tid & 63, ph = tid >> 6;
+    T* tk = tile;
+    T* tu = tile + 64 * Rq;
+    double acc = 0.0;
+    for (int r0 = 0; r0 < I3; r0 += 64) {
+        const int nr = min(64, I3 - r0);
+        for (int e = tid; e < nr * Rq; e += 256) {
+            tk[e] = K3[(long long)r0 * Rq + e];
+            tu[e] = U3[(long long)r0 * Rq + e];
         }
-        nl = relu_keep_nan(lh[lane] - gr / Ld);
+        __syncthreads();
+        if (c < R)
+            for (int i = ph; i < nr; i += 4) acc += (double)tk[i * Rq + c] * (double)tu[i * Rq + c];
+        __syncthreads();
     }
-    if (lane < Rq) st.lam[0][s * Rq + lane] = (lane < R) ? nl : 0.0;
-    if (lane < 64) ln[lane] = (lane < R) ? nl : 0.0;
-    if (lane == 0) st.Ld_cur[s] = Ld;
-    wave_sync();
-    for (int i = lane; i < RR; i += 64) {
-        const int r = i / R, cc = i % R;
-        const double p = ln[r] * ln[cc] * V1[i] * V2[i];
-        st.P[s * RR + i] = p;
-        A[r * ld + cc] = p;
-    }
-    wave_sync();
-    const double Lu = wave_sym_lmax(A, R, ld, w);
-    if (lane == 0) st.Lu_cur[0 * S + s] = Lu;
-}
-
-// Gram V = U^T U of one factor (I rows, row stride Rq) into LDS/global, FP64.
-template <typename T>
-__device__ void block_gram(const T* __restrict__ U, int I, int R, int Rq, double* __restrict__ out) {
-    const int npair = R * (R + 1) / 2;
-    for (int p = threadIdx.x; p < npair; p += blockDim.x) {
-        // (a, b) with a <= b from the packed index
-        int a = 0, rem = p;
-        while (rem >= R - a) { rem -= R - a; ++a; }
-        const int b = a + rem;
-        double acc = 0.0;
-        for (int i = 0; i < I; ++i) acc += (double)U[(long long)i * Rq + a] * (double)U[(long long)i * Rq + b];
-        out[a * R + b] = acc;
-        out[b * R + a] = acc;
-    }
-}
-
-// Gram of the mode just updated, then P = D H_{-n} D and its spectral norm for
-// mode n.  Modes before n take slot 0 (this sweep), after n slot 1.
-template <typename T>
-__global__ __launch_bounds__(256) void k_prep(const Geo* __restrict__ g, StateP<T> st, int n, int gate) {
-    const Ctrl* c = st.ctrl;
-    if (gated_out(c, gate)) return;
-    const int s = blockIdx.x;
-    const int S = g->S, R = g->R, Rq = g->Rq, ld = R | 1, RR = R * R;
-    extern __shared__ double sm[];
-    double* A = sm;
-    double* w = A + R * ld;
-    const int m = n - 1;
-    double* Vm = st.V[0] + (m * S + s) * RR;
-    block_gram<T>(st.U[0] + g->uoff[m][s], g->I[s][m], R, Rq, Vm);
+    if (c < R) bp[ph][c] = acc;
     __syncthreads();
-    if (threadIdx.x >= 64) return;
-    const int lane = threadIdx.x;
-    const double* lam = st.lam[0] + s * Rq;
-    const double* Va = st.V[0] + (0 * S + s) * RR;           // mode 0: updated
-    const double* Vb = (n == 1) ? st.V[1] + (2 * S + s) * RR  // mode 2: not yet
-                                : st.V[0] + (1 * S + s) * RR; // mode 1: updated
-    for (int i = lane; i < RR; i += 64) {
-        const int r = i / R, cc = i % R;
-        const double p = lam[r] * lam[cc] * Va[i] * Vb[i];
-        st.P[s * RR + i] = p;
-        A[r * ld + cc] = p;
-    }
-    wave_sync();
-    const double Lu = wave_sym_lmax(A, R, ld, w);
-    if (lane == 0) st.Lu_cur[n * S + s] = Lu;
+    if (tid < R) b[tid] = bp[0][tid] + bp[1][tid] + bp[2][tid] + bp[3][tid];
+    __syncthreads();
 }
 
-// After the mode-3 update: Gram of U^(3), b = colsum(K3 ⊛ U^(3)) (the data term
-// (U^⊙)^T vec(M) of eq. solapgG, reused by the next core update), and
-// F^(s) = 1/2 (||M||^2 - 2 lam^T b + lam^T H lam) (eq. costfunc expanded).  The
-// last workgroup sums F over the blocks in block order and, for the
-// extrapolated sweep, raises the restart flag when F_k >= F_{k-1} (Algorithm 1).
+// F^(s) = 1/2 (||M||^2 - 2 lam^T b + lam^T H lam), H = V0 ⊛ V1 ⊛ V2 (eq. costfunc
+// expanded with the Hadamard-of-Grams identity of Appendix A).
+__device__ __forceinline__ double block_objective(const double* lam, const double* V0, const double* V1, const double* V2,
+                                  const double* b, double normM2, int R) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x, RR = R * R;
+    double part = 0.0;
+    for (int i = tid; i < RR; i += 256) part += lam[i / R] * lam[i % R] * V0[i] * V1[i] * V2[i];
+    if (tid < R) part -= 2.0 * lam[tid] * b[tid];
+    red[tid] = part;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    return 0.5 * (normM2 + red[0]);
+}
+
+// After the mode-3 update: Gram of U^(3), b (the data term (U^⊙)^T vec(M) of
+// eq. solapgG, reused by the next core update) and F^(s).  The last workgroup
+// sums F over the blocks in block order and, for the extrapolated sweep,
+// raises the restart flag when F_k >= F_{k-1} (Algorithm 1).
 template <typename T>
 __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, StateP<T> st, int first_sweep, int gate) {
     Ctrl* c = st.ctrl;
     if (gated_out(c, gate)) return;
     const int s = blockIdx.x, tid = threadIdx.x;
     const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R;
-    __shared__ double bsh[CPD_MAXR];
-    __shared__ double red[256];
+    extern __shared__ char smraw[];
     __shared__ int last;
+    __shared__ double fb[CPD_MAXS], nb[CPD_MAXS];
     double* V2 = st.V[0] + (2 * S + s) * RR;
-    const T* U3 = st.U[0] + g->uoff[2][s];
-    const int I3 = g->I[s][2];
-    block_gram<T>(U3, I3, R, Rq, V2);
-    const T* K3 = st.K3 + g->koff[s];
-    if (tid < R) {
-        double acc = 0.0;
-        for (int i = 0; i < I3; ++i) acc += (double)K3[(long long)i * Rq + tid] * (double)U3[(long long)i * Rq + tid];
-        bsh[tid] = acc;
-        st.b[0][s * Rq + tid] = acc;
-    }
+    double* b = st.b[0] + s * Rq;
+    gram_and_b<T>(st.U[0] + g->uoff[2][s], st.K3 + g->koff[s], g->I[s][2], R, Rq, V2, b, smraw);
+    __threadfence_block();
     __syncthreads();
-    const double* lam = st.lam[0] + s * Rq;
-    const double* V0 = st.V[0] + (0 * S + s) * RR;
-    const double* V1 = st.V[0] + (1 * S + s) * RR;
-    double part = 0.0;
-    for (int i = tid; i < RR; i += 256) part += lam[i / R] * lam[i % R] * V0[i] * V1[i] * V2[i];
-    red[tid] = part;
-    __syncthreads();
+    const double F = block_objective(st.lam[0] + s * Rq, st.V[0] + (0 * S + s) * RR, st.V[0] + (1 * S + s) * RR, V2, b,
+                                     st.normM2[s], R);
     if (tid == 0) {
-        double quad = 0.0;
-        for (int i = 0; i < 256; ++i) quad += red[i];
-        double lb = 0.0;
-        for (int r = 0; r < R; ++r) lb += lam[r] * bsh[r];
-        st.Fblk[s] = 0.5 * (st.normM2[s] - 2.0 * lb + quad);
+        st.Fblk[s] = F;
         __threadfence();
         last = (atomicAdd(&c->counter_finish, 1u) == (unsigned)(gridDim.x - 1));
     }
     __syncthreads();
-    if (!last || tid != 0) return;
+    if (!last) return;
     __threadfence();
-    double F = 0.0, rel = 0.0;
-    for (int b = 0; b < S; ++b) {
-        const double fb = load_agent(&st.Fblk[b]);
-        F += fb;
-        rel += sqrt(fmax(0.0, 2.0 * fb)) / sqrt(st.normM2[b]);
+    if (tid < S) {
+        fb[tid] = load_agent(&st.Fblk[tid]);
+        nb[tid] = st.normM2[tid];
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    double Fs = 0.0, rel = 0.0;
+    for (int q = 0; q < S; ++q) {
+        Fs += fb[q];
+        rel += sqrt(fmax(0.0, 2.0 * fb[q])) / sqrt(nb[q]);
     }
     rel /= S;
-    c->F_cur = F;
+    c->F_cur = Fs;
     c->rel_cur = rel;
-    c->nonfinite = !isfinite(F);
-    if (first_sweep) c->redo = (c->restart_on && F >= c->F_prev) ? 1 : 0;
+    c->nonfinite = !isfinite(Fs);
+    if (first_sweep) c->redo = (c->restart_on && Fs >= c->F_prev) ? 1 : 0;
     c->counter_finish = 0u;
 }
 
 // Accept the sweep: x_{k-2} <- x_{k-1}, x_{k-1} <- x_k for factors and lambda,
-// Grams and b to slot 1.  The last workgroup advances k and t, keeps the
-// Lipschitz constants of the accepted sweep and applies the stopping rule.
+// Grams and b to slot 1.  The last workgroup keeps the Lipschitz constants of
+// the accepted sweep, advances k and t and applies the stopping rule.
 template <typename T>
 __global__ __launch_bounds__(256) void k_commit(const Geo* __restrict__ g, StateP<T> st, long long uslot) {
     Ctrl* c = st.ctrl;
@@ -296,8 +147,23 @@ __global__ __launch_bounds__(256) void k_commit(const Geo* __restrict__ g, State
         last = (atomicAdd(&c->counter_commit, 1u) == (unsigned)(gridDim.x - 1));
     }
     __syncthreads();
-    if (!last || threadIdx.x != 0) return;
+    if (!last) return;
     __threadfence();
+    const int tid = threadIdx.x;
+    __shared__ double lu[3 * CPD_MAXS];
+    if (tid < S) st.Ld_prev[tid] = st.Ld_cur[tid];
+    if (tid < 3 * S) {
+        const double v = st.Lu_cur[tid];
+        st.Lu_prev[tid] = v;
+        lu[tid] = v;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double LC = 0.0;
+        for (int b = 0; b < S; ++b) LC += lu[tid * S + b];
+        st.LC_prev[tid] = LC;
+    }
+    if (tid != 0) return;
     const int redo = c->redo;
     c->restarts += redo;
     c->last_restarted = redo;
@@ -309,94 +175,86 @@ __global__ __launch_bounds__(256) void k_commit(const Geo* __restrict__ g, State
     if (redo && c->reset_t) t_k = 1.0;
     c->t = t_k;
     c->w_hat = (t_k - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * t_k * t_k)));
-    for (int b = 0; b < S; ++b) st.Ld_prev[b] = st.Ld_cur[b];
-    for (int n = 0; n < 3; ++n) {
-        double LC = 0.0;
-        for (int b = 0; b < S; ++b) {
-            st.Lu_prev[n * S + b] = st.Lu_cur[n * S + b];
-            LC += st.Lu_cur[n * S + b];
-        }
-        st.LC_prev[n] = LC;
-    }
     if (c->tol > 0.0 && fabs(c->rel_cur - rel_old) < c->tol) c->stop = 1;
     c->redo = 0;
     c->counter_commit = 0u;
 }
 
-// Initial (or restored) iterate in slot 1: Grams of every factor, b from the
+// Iterate in slot 1 (initial or restored): Grams of every factor, b from the
 // reduced mode-3 MTTKRP, F and RelErr; sets F_prev / rel_prev.
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_stats(const Geo* __restrict__ g, StateP<T> st) {
     Ctrl* c = st.ctrl;
     const int s = blockIdx.x, tid = threadIdx.x;
     const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R;
-    __shared__ double bsh[CPD_MAXR];
-    __shared__ double red[256];
+    extern __shared__ char smraw[];
     __shared__ int last;
-    for (int m = 0; m < 3; ++m) block_gram<T>(st.U[1] + g->uoff[m][s], g->I[s][m], R, Rq, st.V[1] + (m * S + s) * RR);
-    const T* U3 = st.U[1] + g->uoff[2][s];
-    const T* K3 = st.K3 + g->koff[s];
-    const int I3 = g->I[s][2];
-    if (tid < R) {
-        double acc = 0.0;
-        for (int i = 0; i < I3; ++i) acc += (double)K3[(long long)i * Rq + tid] * (double)U3[(long long)i * Rq + tid];
-        bsh[tid] = acc;
-        st.b[1][s * Rq + tid] = acc;
-    }
+    __shared__ double fb[CPD_MAXS], nb[CPD_MAXS];
+    for (int m = 0; m < 2; ++m)
+        block_gram<T>(st.U[1] + g->uoff[m][s], g->I[s][m], R, Rq, st.V[1] + (m * S + s) * RR,
+                      (T*)(smraw + ((gram_acc_bytes(R) + 255) & ~(size_t)255)), 128, (double*)smraw);
+    double* V2 = st.V[1] + (2 * S + s) * RR;
+    double* b = st.b[1] + s * Rq;
+    gram_and_b<T>(st.U[1] + g->uoff[2][s], st.K3 + g->koff[s], g->I[s][2], R, Rq, V2, b, smraw);
+    __threadfence_block();
     __syncthreads();
-    const double* lam = st.lam[1] + s * Rq;
-    const double* V0 = st.V[1] + (0 * S + s) * RR;
-    const double* V1 = st.V[1] + (1 * S + s) * RR;
-    const double* V2 = st.V[1] + (2 * S + s) * RR;
-    double part = 0.0;
-    for (int i = tid; i < RR; i += 256) part += lam[i / R] * lam[i % R] * V0[i] * V1[i] * V2[i];
-    red[tid] = part;
-    __syncthreads();
+    const double F = block_objective(st.lam[1] + s * Rq, st.V[1] + (0 * S + s) * RR, st.V[1] + (1 * S + s) * RR, V2, b,
+                                     st.normM2[s], R);
     if (tid == 0) {
-        double quad = 0.0;
-        for (int i = 0; i < 256; ++i) quad += red[i];
-        double lb = 0.0;
-        for (int r = 0; r < R; ++r) lb += lam[r] * bsh[r];
-        st.Fblk[s] = 0.5 * (st.normM2[s] - 2.0 * lb + quad);
+        st.Fblk[s] = F;
         __threadfence();
         last = (atomicAdd(&c->counter_aux, 1u) == (unsigned)(gridDim.x - 1));
     }
     __syncthreads();
-    if (!last || tid != 0) return;
+    if (!last) return;
     __threadfence();
-    double F = 0.0, rel = 0.0;
-    for (int b = 0; b < S; ++b) {
-        const double fb = load_agent(&st.Fblk[b]);
-        F += fb;
-        rel += sqrt(fmax(0.0, 2.0 * fb)) / sqrt(st.normM2[b]);
+    if (tid < S) {
+        fb[tid] = load_agent(&st.Fblk[tid]);
+        nb[tid] = st.normM2[tid];
     }
-    c->F_prev = F;
-    c->F_cur = F;
+    __syncthreads();
+    if (tid != 0) return;
+    double Fs = 0.0, rel = 0.0;
+    for (int q = 0; q < S; ++q) {
+        Fs += fb[q];
+        rel += sqrt(fmax(0.0, 2.0 * fb[q])) / sqrt(nb[q]);
+    }
+    c->F_prev = Fs;
+    c->F_cur = Fs;
     c->rel_prev = rel / S;
     c->rel_cur = rel / S;
-    c->nonfinite = !isfinite(F);
+    c->nonfinite = !isfinite(Fs);
     c->counter_aux = 0u;
 }
-
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static size_t eig_lds(int R) { return sizeof(double) * ((size_t)R * (R | 1) + 320); }
+#define CPD_NMAX_DISPATCH(R, CALL) \
+    do {                              \
+        if ((R) <= 16) { CALL(16); }  \
+        else if ((R) <= 32) { CALL(32); } \
+        else if ((R) <= 48) { CALL(48); } \
+        else { CALL(64); }            \
+    } while (0)
 
 template <typename T>
 void launch_core(const Geo* g, const StateP<T>& st, int S, int R, int extrap, int gate, hipStream_t q) {
-    const size_t lds = eig_lds(R) + sizeof(double) * 128;
-    hipLaunchKernelGGL(k_core<T>, dim3(S), dim3(64), lds, q, g, st, extrap, gate);
+#define CPD_CORE(N) hipLaunchKernelGGL((k_core<T, N>), dim3(S), dim3(256), eig_lds_bytes(R), q, g, st, extrap, gate)
+    CPD_NMAX_DISPATCH(R, CPD_CORE);
+#undef CPD_CORE
 }
 template <typename T>
 void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, int gate, hipStream_t q) {
-    hipLaunchKernelGGL(k_prep<T>, dim3(S), dim3(256), eig_lds(R), q, g, st, n, gate);
+    const int Rq = (R + 3) / 4 * 4;
+#define CPD_PREP(N) hipLaunchKernelGGL((k_prep<T, N>), dim3(S), dim3(256), prep_lds_bytes<T>(R, Rq), q, g, st, n, gate)
+    CPD_NMAX_DISPATCH(R, CPD_PREP);
+#undef CPD_PREP
 }
 template <typename T>
 void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, int first_sweep, int gate, hipStream_t q) {
-    (void)R;
-    hipLaunchKernelGGL(k_finish<T>, dim3(S), dim3(256), 0, q, g, st, first_sweep, gate);
+    const int Rq = (R + 3) / 4 * 4;
+    hipLaunchKernelGGL(k_finish<T>, dim3(S), dim3(256), gram_lds_bytes<T>(R, Rq, 128), q, g, st, first_sweep, gate);
 }
 template <typename T>
 void launch_commit(const Geo* g, const StateP<T>& st, long long uslot, int S, int Rq, int R, hipStream_t q) {
@@ -408,8 +266,8 @@ void launch_commit(const Geo* g, const StateP<T>& st, long long uslot, int S, in
 }
 template <typename T>
 void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q) {
-    (void)R;
-    hipLaunchKernelGGL(k_init_stats<T>, dim3(S), dim3(256), 0, q, g, st);
+    const int Rq = (R + 3) / 4 * 4;
+    hipLaunchKernelGGL(k_init_stats<T>, dim3(S), dim3(256), gram_lds_bytes<T>(R, Rq, 128), q, g, st);
 }
 
 #define CPD_INST_SMALL(T)                                                                                  \

@@ -5,10 +5,9 @@
 //   individual columns:  U_I = max(0, U_hat_I - G_I / L_u^(n,s))
 //   shared columns:      U_C = max(0, U_hat_C - sum_s G_C^(s) / sum_s L_u^(n,s))
 //
-// K = M_(n) U^{⊙-n} is contracted here from the MTTKRP pass outputs:
-//   mode 1: K1[i1] = sum_i2 Y[i1][i2] ⊛ U2_old[i2]
-//   mode 2: K2[i2] = sum_i1 Y[i1][i2] ⊛ U1_new[i1]
-//   mode 3: K3[i3] = sum over the pass-2 chunk partials (fixed order)
+// K = M_(n) U^{⊙-n} comes from the MTTKRP kernels: the mode-1 partials of
+// pass 1 (one per 64 rows of i2), the mode-2 contraction, and the pass-2 chunk
+// partials for mode 3, each summed here in fixed order.
 // All of the small arithmetic is FP64; the new factor is rounded to the
 // storage type once.  A workgroup owns a row tile of every block that shares
 // the mode's columns, so the coupled sum runs in LDS in block order.
@@ -16,28 +15,24 @@
 
 namespace cpd {
 
-enum { KSRC_Y1 = 0, KSRC_Y2 = 1, KSRC_PART = 2 };
+enum { KSRC_K1P = 0, KSRC_K2 = 1, KSRC_PART = 2 };
 
+// K[i][col] of block s from the MTTKRP pass outputs (FP64 sums in fixed order).
 template <typename T, int KSRC>
-__device__ __forceinline__ double k_value(const Geo* __restrict__ g, const StateP<T>& st, int s, int i, int col,
-                                          int other_slot) {
+__device__ __forceinline__ double k_value(const Geo* __restrict__ g, const StateP<T>& st, int s, int i, int col) {
     const int Rq = g->Rq;
     double acc = 0.0;
-    if (KSRC == KSRC_Y1) {
-        const int I2 = g->I[s][1];
-        const T* Y = st.Y + g->yoff[s] + (long long)i * I2 * Rq + col;
-        const T* U2 = st.U[other_slot] + g->uoff[1][s] + col;
-        for (int i2 = 0; i2 < I2; ++i2) acc += (double)Y[(long long)i2 * Rq] * (double)U2[(long long)i2 * Rq];
-    } else if (KSRC == KSRC_Y2) {
-        const int I1 = g->I[s][0], I2 = g->I[s][1];
-        const T* Y = st.Y + g->yoff[s] + (long long)i * Rq + col;
-        const T* U1 = st.U[other_slot] + g->uoff[0][s] + col;
-        const long long ys = (long long)I2 * Rq;
-        for (int i1 = 0; i1 < I1; ++i1) acc += (double)Y[i1 * ys] * (double)U1[(long long)i1 * Rq];
+    if (KSRC == KSRC_K1P) {
+        const int nrg = g->nrg[s];
+        const T* p = st.K1p + g->k1off[s] + (long long)i * nrg * Rq + col;
+        for (int r = 0; r < nrg; ++r) acc += (double)p[r * Rq];
+    } else if (KSRC == KSRC_K2) {
+        acc = (double)st.K2[g->k2off[s] + (long long)i * Rq + col];
     } else {
         const int I3 = g->I[s][2], nch = g->nchunk[s];
         const T* p = st.part + g->poff[s] + (long long)i * Rq + col;
         const long long ps = (long long)I3 * Rq;
+#pragma unroll 8
         for (int ch = 0; ch < nch; ++ch) acc += (double)p[ch * ps];
     }
     return acc;
@@ -61,7 +56,6 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
     if (Ln > 0)
         for (int b = 0; b < S; ++b) LC += st.Lu_cur[n * S + b];
     const double wC = (Ln > 0) ? extrap_weight(extrapolate, what, st.LC_prev[n], LC, dw) : 0.0;
-    const int other_slot = (KSRC == KSRC_Y1) ? 1 : 0;
 
     // extrapolated point
     for (int e = tid; e < tot; e += 256) {
@@ -81,7 +75,7 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
         const double* u = uh + (sl * nrows + rr) * R;
         double gr = 0.0;
         for (int r = 0; r < R; ++r) gr += u[r] * P[r * R + col];
-        const double kv = k_value<T, KSRC>(g, st, s, i, col, other_slot);
+        const double kv = k_value<T, KSRC>(g, st, s, i, col);
         gr -= kv * st.lam[0][s * Rq + col];
         if (KSRC == KSRC_PART) st.K3[g->koff[s] + (long long)i * Rq + col] = (T)kv;
         const long long off = g->uoff[n][s] + (long long)i * Rq + col;
@@ -107,15 +101,15 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
     }
 }
 
-// K = M_(n) U^{⊙-n} of one block at the accepted iterate (slot 1) from the
-// pass outputs computed on slot 1; used at initialisation and by the test hook.
+// K = M_(n) U^{⊙-n} of one block from the pass outputs (computed by the caller
+// on the iterate of interest); used at initialisation and by the test hook.
 template <typename T, int KSRC>
 __global__ __launch_bounds__(256) void k_extract(const Geo* __restrict__ g, StateP<T> st, int s, int I, T* __restrict__ out,
                                                  int ld_out) {
     const int R = g->R;
     for (long long e = blockIdx.x * 256LL + threadIdx.x; e < (long long)I * R; e += (long long)gridDim.x * 256) {
         const int i = (int)(e / R), col = (int)(e % R);
-        out[(long long)i * ld_out + col] = (T)k_value<T, KSRC>(g, st, s, i, col, 1);
+        out[(long long)i * ld_out + col] = (T)k_value<T, KSRC>(g, st, s, i, col);
     }
 }
 
@@ -124,8 +118,8 @@ void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, in
     long long nb = ((long long)I * R + 255) / 256;
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
-    if (n == 0) hipLaunchKernelGGL((k_extract<T, KSRC_Y1>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
-    else if (n == 1) hipLaunchKernelGGL((k_extract<T, KSRC_Y2>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
+    if (n == 0) hipLaunchKernelGGL((k_extract<T, KSRC_K1P>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
+    else if (n == 1) hipLaunchKernelGGL((k_extract<T, KSRC_K2>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
     else hipLaunchKernelGGL((k_extract<T, KSRC_PART>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
 }
 template void launch_extract_k<float>(const Geo*, const StateP<float>&, int, int, int, int, float*, int, hipStream_t);
@@ -137,8 +131,8 @@ void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int ni
     if (nitems <= 0) return;
     // lds_rows = max over items of ns * nrows; the shared-gradient buffer uses at most as much
     const size_t lds = sizeof(double) * (size_t)lds_rows * (size_t)(2 * R);
-    if (n == 0) hipLaunchKernelGGL((k_update<T, KSRC_Y1>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
-    else if (n == 1) hipLaunchKernelGGL((k_update<T, KSRC_Y2>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
+    if (n == 0) hipLaunchKernelGGL((k_update<T, KSRC_K1P>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
+    else if (n == 1) hipLaunchKernelGGL((k_update<T, KSRC_K2>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
     else hipLaunchKernelGGL((k_update<T, KSRC_PART>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
 }
 

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -38,7 +39,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t geo, ctrl, U[3], lam[3], V[2], b[2], P, Ld_cur, Ld_prev, Lu_cur, Lu_prev, LC_prev, Fblk, normM2, normOrig, Y,
-        K3, part, it1, it2, itu[3], scratch, shadow, lra, flag, total;
+        K3, part, K1p, K2, it1, it2, itk2, itu[3], scratch, shadow, lra, flag, total;
     long long uslot, ylen, klen, plen, shadow_elems[CPD_MAXS], lra_len;
     size_t scratch_len;
     int esz;  // bytes per factor element
@@ -47,7 +48,9 @@ struct Layout {
 struct Lists {
     std::vector<ItemP1> p1;
     std::vector<ItemP2> p2;
+    std::vector<ItemK2> k2;
     std::vector<ItemU> u[3];
+    int maxI2;
     int lds_rows[3];
 };
 
@@ -93,8 +96,12 @@ void build_lists(const concpd_config* c, Lists* L) {
     const int S = c->num_blocks, R = c->rank;
     L->p1.clear();
     L->p2.clear();
+    L->k2.clear();
+    L->maxI2 = 1;
     for (int s = 0; s < S; ++s) {
         const int I1 = (int)c->dims[3 * s], I2 = (int)c->dims[3 * s + 1], I3 = (int)c->dims[3 * s + 2];
+        L->maxI2 = std::max(L->maxI2, I2);
+        for (int r0 = 0; r0 < I2; r0 += 64) L->k2.push_back({s, r0, 0, 0});
         for (int i1 = 0; i1 < I1; ++i1)
             for (int rg = 0; rg * 64 < I2; ++rg) L->p1.push_back({s, i1, rg, 0});
         for (int ch = 0; ch * 4 < I1; ++ch)
@@ -134,7 +141,7 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     for (int n = 0; n < 3; ++n) g->L[n] = c->coupled[n];
     g->upd_core = c->update_core;
     g->mdtype = c->compute_dtype;
-    long long u = 0, y = 0, k = 0, p = 0;
+    long long u = 0, y = 0, k = 0, p = 0, k1 = 0, k2 = 0;
     for (int n = 0; n < 3; ++n)
         for (int s = 0; s < S; ++s) {
             g->uoff[n][s] = u;
@@ -150,6 +157,11 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
         g->nchunk[s] = (int)((I1 + 3) / 4);
         g->poff[s] = p;
         p += g->nchunk[s] * I3 * Rq;
+        g->nrg[s] = (int)((I2 + 63) / 64);
+        g->k1off[s] = k1;
+        k1 += I1 * g->nrg[s] * Rq;
+        g->k2off[s] = k2;
+        k2 += I2 * Rq;
     }
     P->uslot = u;
     P->ylen = y;
@@ -179,8 +191,11 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     P->Y = take((size_t)y * P->esz);
     P->K3 = take((size_t)k * P->esz);
     P->part = take((size_t)p * P->esz);
+    P->K1p = take((size_t)k1 * P->esz);
+    P->K2 = take((size_t)k2 * P->esz);
     P->it1 = take(sizeof(ItemP1) * std::max<size_t>(1, L.p1.size()));
     P->it2 = take(sizeof(ItemP2) * std::max<size_t>(1, L.p2.size()));
+    P->itk2 = take(sizeof(ItemK2) * std::max<size_t>(1, L.k2.size()));
     for (int n = 0; n < 3; ++n) P->itu[n] = take(sizeof(ItemU) * std::max<size_t>(1, L.u[n].size()));
     size_t scr = 4096;
     for (int s = 0; s < S; ++s) scr = std::max<size_t>(scr, (size_t)c->dims[3 * s]);
@@ -233,6 +248,7 @@ struct concpd_ctx_s {
     std::vector<double> normOrig;
     long long launched_iters;
     int profiling;
+    int fuse;  // run the small FP64 work inside the MTTKRP launches (CONCPD_NO_FUSE=1 turns it off)
     std::vector<hipEvent_t> ev1, ev2;  // begin/end pairs of timed pass launches
 };
 
@@ -256,6 +272,8 @@ StateP<T> make_state(char* ws, const Layout& P) {
     st.Y = (T*)(ws + P.Y);
     st.K3 = (T*)(ws + P.K3);
     st.part = (T*)(ws + P.part);
+    st.K1p = (T*)(ws + P.K1p);
+    st.K2 = (T*)(ws + P.K2);
     st.lra = (double*)(ws + P.lra);
     st.ctrl = (Ctrl*)(ws + P.ctrl);
     return st;
@@ -268,24 +286,29 @@ void run_sweep(concpd_ctx c, const StateP<T>& st, int extrap, int gate, int firs
     hipStream_t q = c->q;
     const ItemP1* it1 = (const ItemP1*)(c->ws + c->lay.it1);
     const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
+    const ItemK2* itk = (const ItemK2*)(c->ws + c->lay.itk2);
     const ItemU* itu[3];
     for (int n = 0; n < 3; ++n) itu[n] = (const ItemU*)(c->ws + c->lay.itu[n]);
     const bool prof = c->profiling && gate == 0;
     hipEvent_t e[4];
     if (prof)
-        for (int i = 0; i < 4; ++i) hipEventCreate(&e[i]);
+        for (int i = 0; i < 4; ++i) (void)hipEventCreate(&e[i]);
+    // core update beside pass 1 (Y from the old U^(3), mode-1 partials)
     cpd::launch_core<T>(g, st, S, R, extrap, gate, q);
-    if (prof) hipEventRecord(e[0], q);
+    if (prof) (void)hipEventRecord(e[0], q);
     cpd::launch_pass1<T>(g, st, it1, (int)c->lists.p1.size(), Rq, 1, gate, c->mdtype, q);
-    if (prof) hipEventRecord(e[1], q);
+    if (prof) (void)hipEventRecord(e[1], q);
     cpd::launch_update<T>(g, st, itu[0], (int)c->lists.u[0].size(), 0, R, extrap, gate, c->lists.lds_rows[0], q);
+    // mode-2 step matrix beside the mode-2 contraction (new U^(1))
     cpd::launch_prep<T>(g, st, S, R, 1, gate, q);
+    cpd::launch_k2<T>(g, st, itk, (int)c->lists.k2.size(), 0, gate, q);
     cpd::launch_update<T>(g, st, itu[1], (int)c->lists.u[1].size(), 1, R, extrap, gate, c->lists.lds_rows[1], q);
+    // mode-3 step matrix beside pass 2 (new U^(1), U^(2))
     cpd::launch_prep<T>(g, st, S, R, 2, gate, q);
-    if (prof) hipEventRecord(e[2], q);
-    cpd::launch_pass2<T>(g, st, it2, (int)c->lists.p2.size(), Rq, 0, gate, c->mdtype, q);
+    if (prof) (void)hipEventRecord(e[2], q);
+    cpd::launch_pass2<T>(g, st, it2, (int)c->lists.p2.size(), Rq, 0, gate, c->mdtype, c->lists.maxI2, q);
     if (prof) {
-        hipEventRecord(e[3], q);
+        (void)hipEventRecord(e[3], q);
         c->ev1.push_back(e[0]);
         c->ev1.push_back(e[1]);
         c->ev2.push_back(e[2]);
@@ -306,7 +329,7 @@ void run_iteration(concpd_ctx c, const StateP<T>& st) {
 template <typename T>
 void recompute_stats(concpd_ctx c, const StateP<T>& st) {
     const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
-    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->q);
+    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->lists.maxI2, c->q);
     for (int s = 0; s < c->S; ++s)
         cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], c->R, st.K3 + c->geo.koff[s], c->Rq, c->q);
     cpd::launch_init_stats<T>(c->dgeo, st, c->S, c->R, c->q);
@@ -410,6 +433,16 @@ concpd_status set_ctrl(concpd_ctx c, double t, long long k) {
     return CONCPD_OK;
 }
 
+template <typename T>
+void debug_passes(concpd_ctx c, const StateP<T>& st) {
+    const ItemP1* it1 = (const ItemP1*)(c->ws + c->lay.it1);
+    const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
+    const ItemK2* itk = (const ItemK2*)(c->ws + c->lay.itk2);
+    cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->Rq, 1, 0, c->mdtype, c->q);
+    cpd::launch_k2<T>(c->dgeo, st, itk, (int)c->lists.k2.size(), 1, 0, c->q);
+    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->lists.maxI2, c->q);
+}
+
 }  // namespace
 
 extern "C" {
@@ -463,6 +496,10 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
     c->lra = 0;
     c->launched_iters = 0;
     c->profiling = 0;
+    {
+        const char* nf = getenv("CONCPD_NO_FUSE");
+        c->fuse = !(nf && nf[0] == '1');
+    }
     build_lists(&c->cfg, &c->lists);
     plan(&c->cfg, c->lists, &c->lay, &c->geo);
     if (ws_bytes < c->lay.total) {
@@ -544,6 +581,8 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
         INIT_HIP(hipMemcpyAsync(c->ws + c->lay.it1, c->lists.p1.data(), c->lists.p1.size() * sizeof(ItemP1), hipMemcpyHostToDevice, c->q));
     if (!c->lists.p2.empty())
         INIT_HIP(hipMemcpyAsync(c->ws + c->lay.it2, c->lists.p2.data(), c->lists.p2.size() * sizeof(ItemP2), hipMemcpyHostToDevice, c->q));
+    if (!c->lists.k2.empty())
+        INIT_HIP(hipMemcpyAsync(c->ws + c->lay.itk2, c->lists.k2.data(), c->lists.k2.size() * sizeof(ItemK2), hipMemcpyHostToDevice, c->q));
     for (int n = 0; n < 3; ++n)
         if (!c->lists.u[n].empty())
             INIT_HIP(hipMemcpyAsync(c->ws + c->lay.itu[n], c->lists.u[n].data(), c->lists.u[n].size() * sizeof(ItemU),
@@ -742,16 +781,12 @@ concpd_status concpd_loss_grad(concpd_ctx c, const void* const* U_dev, const voi
 concpd_status concpd_debug_mttkrp(concpd_ctx c, int32_t n, int32_t s, void* dev_out) {
     if (!c || !dev_out) return fail(CONCPD_EINVAL, "NULL argument");
     if (n < 0 || n > 2 || s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "n/s out of range");
-    const ItemP1* it1 = (const ItemP1*)(c->ws + c->lay.it1);
-    const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
     const int I = (int)c->dims[3 * s + n];
     if (c->f64) {
-        cpd::launch_pass1<double>(c->dgeo, c->sd, it1, (int)c->lists.p1.size(), c->Rq, 1, 0, c->mdtype, c->q);
-        cpd::launch_pass2<double>(c->dgeo, c->sd, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->q);
+        debug_passes<double>(c, c->sd);
         cpd::launch_extract_k<double>(c->dgeo, c->sd, s, n, I, c->R, (double*)dev_out, c->R, c->q);
     } else {
-        cpd::launch_pass1<float>(c->dgeo, c->sf, it1, (int)c->lists.p1.size(), c->Rq, 1, 0, c->mdtype, c->q);
-        cpd::launch_pass2<float>(c->dgeo, c->sf, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->q);
+        debug_passes<float>(c, c->sf);
         cpd::launch_extract_k<float>(c->dgeo, c->sf, s, n, I, c->R, (float*)dev_out, c->R, c->q);
     }
     HIPCHECK(hipGetLastError());
@@ -780,8 +815,8 @@ concpd_status concpd_profile_read(concpd_ctx c, double* ms1, double* ms2, int64_
     if (ms1) *ms1 = a;
     if (ms2) *ms2 = b;
     if (launches) *launches = (int64_t)(c->ev1.size() / 2);
-    for (hipEvent_t e : c->ev1) hipEventDestroy(e);
-    for (hipEvent_t e : c->ev2) hipEventDestroy(e);
+    for (hipEvent_t e : c->ev1) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev2) (void)hipEventDestroy(e);
     c->ev1.clear();
     c->ev2.clear();
     return CONCPD_OK;
@@ -789,9 +824,9 @@ concpd_status concpd_profile_read(concpd_ctx c, double* ms1, double* ms2, int64_
 
 concpd_status concpd_destroy(concpd_ctx c) {
     if (!c) return CONCPD_OK;
-    hipStreamSynchronize(c->q);
-    for (hipEvent_t e : c->ev1) hipEventDestroy(e);
-    for (hipEvent_t e : c->ev2) hipEventDestroy(e);
+    (void)hipStreamSynchronize(c->q);
+    for (hipEvent_t e : c->ev1) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev2) (void)hipEventDestroy(e);
     delete c;
     return CONCPD_OK;
 }
