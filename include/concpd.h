@@ -134,11 +134,22 @@ concpd_status concpd_fit(concpd_ctx ctx, concpd_stats* out);
  * context to lraCoNCPD-APG (Algorithm 2, eq. cosfunclra): F, RelErr and every
  * gradient are taken against the compressed blocks.  The current iterate is
  * kept; its F and b are recomputed.  Synchronises; out may be NULL.
+ * The Grams M_(n) M_(n)^T are formed with FP64 products and sums and their
+ * leading eigenvectors found by Householder tridiagonalisation, bisection and
+ * inverse iteration (descending order; each vector signed so that its
+ * largest-magnitude entry is positive).  Limits (checked by concpd_init when
+ * tucker_ranks is set): F32 tensors, I_n <= 512, J_n <= 64.
  * Errors: ESTATE (no Tucker ranks configured), EINVAL (J_n > configured), EHIP. */
 concpd_status lra_compress(concpd_ctx ctx, const int32_t* ranks, concpd_stats* out);
 
 /* concpd_step in lra mode.  Errors: ESTATE if lra_compress has not run. */
 concpd_status lra_step(concpd_ctx ctx, int32_t n_iter, concpd_stats* out);
+
+/* Copy one part of block s's compressed form to host memory (FP64):
+ * n = 0, 1, 2: the basis A_n (I_n x J_n, row-major); n = 3: the core G
+ * (J_1 x J_2 x J_3, row-major).  Synchronises.
+ * Errors: EINVAL (s or n out of range), ESTATE (before lra_compress), EHIP. */
+concpd_status lra_get_tucker(concpd_ctx ctx, int32_t s, int32_t n, double* host_dst);
 
 /* Global fit 1 - 1/S sum_s ||M^(s) - M^^(s)||_F / ||M^(s)||_F against the
  * original tensors, by one direct FP64-accumulated pass (the "final fit").

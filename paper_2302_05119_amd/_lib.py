@@ -66,6 +66,7 @@ SIGNATURES = {
     "concpd_fit": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "lra_compress": (ctypes.c_int, [_P, _I32P, ctypes.POINTER(Stats)]),
     "lra_step": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Stats)]),
+    "lra_get_tucker": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _DP]),
     "concpd_global_fit": (ctypes.c_int, [_P, _DP]),
     "concpd_get_factor": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _DP]),
     "concpd_get_lambda": (ctypes.c_int, [_P, ctypes.c_int32, _DP]),

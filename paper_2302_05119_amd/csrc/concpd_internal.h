@@ -46,7 +46,8 @@ struct Geo {
     long long aoff[3][CPD_MAXS];  // Tucker bases A_n^(s): I_n x J_n (double)
     long long goff[CPD_MAXS];     // Tucker cores G^(s): J1 x J2 x J3 (double), i3 fastest
     long long woff[3][CPD_MAXS];  // W_n^(s) = A_n^T U^(n): J_n x Rq (double)
-    long long coff[CPD_MAXS];     // lra scratch per block
+    long long coff[CPD_MAXS];     // C_n^(s) = G_(n) (⊙ W): Jmax x Rq (double)
+    long long wslot_len;          // doubles per W slot (slot 1 follows slot 0)
     long long k1off[CPD_MAXS];    // mode-1 MTTKRP partials per 64-row group: I1 x nrg x Rq
     long long k2off[CPD_MAXS];    // mode-2 MTTKRP: I2 x Rq
     int nrg[CPD_MAXS];            // ceil(I2 / 64)
@@ -90,15 +91,21 @@ namespace cpd {
 template <typename T> void launch_core(const Geo* g, const StateP<T>& st, int S, int R, int extrap, int gate, hipStream_t q);
 template <typename T> void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, int gate, hipStream_t q);
 template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, int first_sweep, int gate, hipStream_t q);
-template <typename T> void launch_commit(const Geo* g, const StateP<T>& st, long long uslot, int S, int Rq, int R, hipStream_t q);
+template <typename T> void launch_commit(const Geo* g, const StateP<T>& st, long long uslot, int S, int Rq, int R, long long wlen, hipStream_t q);
 template <typename T> void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
 template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int Rq, int slot, int gate, int mdtype, hipStream_t q);
 template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int gate, int mdtype, int maxI2, hipStream_t q);
 template <typename T> void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, int gate, hipStream_t q);
-template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int gate, int lds_rows, hipStream_t q);
-template <typename T> void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, int R, T* out, int ld_out, hipStream_t q);
+template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int gate, int lds_rows, int lra, hipStream_t q);
+template <typename T> void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, int R, T* out, int ld_out, int lra, hipStream_t q);
 template <typename T> void launch_resid(const Geo* g, const StateP<T>& st, const void* M, int dtype, int s, int I1, double* part, hipStream_t q);
 void launch_sqnorm(const void* src, int dtype, long long n, double* out, double* part, int npart, hipStream_t q);
+void launch_mode_gram(const float* X, int mode, int I1, int I2, int I3, double* part, int nsplit, hipStream_t q);
+void launch_sum_split(const double* part, int nsplit, long long n, double* out, hipStream_t q);
+void launch_eig_top(const Geo* g, double* lra, double* sig, long long sig_stride, double* work, long long work_stride, int nmat, hipStream_t q);
+void launch_ttm_chain(const float* M, int I1, int I2, int I3, const double* A1, const double* A2, const double* A3, int J1, int J2, int J3, double* T1, double* T2, double* G, hipStream_t q);
+template <typename T> void launch_lra_w(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int uslot, int wslot, int gate, hipStream_t q);
+template <typename T> void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int gate, hipStream_t q);
 void launch_sum_parts(const double* part, int np, double* out, hipStream_t q);
 void launch_convert(const void* src, int dst_dtype, void* dst, long long n, hipStream_t q);
 void launch_finite_check(const void* src, int dtype, long long n, int* flag, hipStream_t q);

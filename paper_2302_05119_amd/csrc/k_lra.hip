@@ -1,0 +1,594 @@
+// Low-rank-approximation path (Algorithm 2, Section III-B).
+//
+// Compression (once per block): truncated HOSVD
+//   Sigma_n = M_(n) M_(n)^T                     (mode Grams, FP64)
+//   A_n     = J_n leading eigenvectors of Sigma_n (tridiagonalisation,
+//             bisection, inverse iteration)
+//   G       = M x_1 A_1^T x_2 A_2^T x_3 A_3^T   (TTM chain, FP64)
+// Only the subspace matters: the compressed tensor X~ = G x_n A_n, and with
+// it every quantity the iterations use, is invariant to the basis chosen.
+//
+// Iterations: the data terms of eq. solapgU / solapgG in Tucker form
+//   W_m = A_m^T U^(m)                      (J_m x R)
+//   C_n = G_(n) (⊙_{m != n} W_m)           (J_n x R)
+//   K_n = A_n C_n,  b = colsum(K_3 ⊛ U^(3)) = colsum(C_3 ⊛ W_3)
+// (with G super-diagonal of ones and A_n = U~^(n) this is eq. eqlrau /
+// eq. eqlrag).  K_n is formed inside the factor-update kernel.
+#include "dev_common.h"
+
+namespace cpd {
+
+// ---------------------------------------------------------------------------
+// Mode Gram Sigma_n[a][b] = sum_t X_n(a, t) X_n(b, t) of one block, as a tiled
+// SYRK: a 64 x 64 output tile per workgroup (upper triangle of tiles only),
+// 4 x 4 outputs per thread, the contraction index t staged through LDS in
+// chunks of 32.  Products and sums are FP64 (the FP32 inputs convert exactly),
+// so the Gram carries no rounding beyond FP64 summation.
+// Element (a, t) of the unfolding sits at
+//   mode 0: a*I2*I3 + t                        (t = i2*I3 + i3)
+//   mode 1: (t / I3)*I2*I3 + a*I3 + t % I3     (t = i1*I3 + i3)
+//   mode 2: t*I3 + a                           (t = i1*I2 + i2)
+// A split-K grid dimension (blockIdx.y) writes partial tiles, summed later.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long unfold_addr(int mode, int a, long long t, int I2, int I3) {
+    if (mode == 0) return (long long)a * I2 * I3 + t;
+    if (mode == 1) return (t / I3) * (long long)I2 * I3 + (long long)a * I3 + (t % I3);
+    return t * I3 + a;
+}
+
+__global__ __launch_bounds__(256) void k_mode_gram(const float* __restrict__ X, int mode, int I1, int I2, int I3,
+                                                   int ntile, double* __restrict__ part) {
+    const int In = mode == 0 ? I1 : (mode == 1 ? I2 : I3);
+    const long long T = (long long)I1 * I2 * I3 / In;
+    // tile pair (ta <= tb) from blockIdx.x
+    int ta = 0, rem = blockIdx.x;
+    while (rem >= ntile - ta) { rem -= ntile - ta; ++ta; }
+    const int tb = ta + rem;
+    const int nsplit = gridDim.y, sp = blockIdx.y;
+    const long long tb0 = T * sp / nsplit, tb1 = T * (sp + 1) / nsplit;
+    __shared__ double sa[32][65];
+    __shared__ double sb[32][65];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (long long t0 = tb0; t0 < tb1; t0 += 32) {
+        // stage X_n(ta*64 + r, t0 + k) and X_n(tb*64 + r, t0 + k), r < 64, k < 32;
+        // the fastest-varying thread index follows the contiguous direction
+        for (int e = tid; e < 64 * 32; e += 256) {
+            const int r = mode == 2 ? (e & 63) : (e >> 5);
+            const int k = mode == 2 ? (e >> 6) : (e & 31);
+            const long long t = t0 + k;
+            const int ra = ta * 64 + r, rb = tb * 64 + r;
+            sa[k][r] = (ra < In && t < tb1) ? (double)X[unfold_addr(mode, ra, t, I2, I3)] : 0.0;
+            sb[k][r] = (rb < In && t < tb1) ? (double)X[unfold_addr(mode, rb, t, I2, I3)] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < 32; ++k) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = sa[k][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = sb[k][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    // partial tile sp of Sigma (full In x In storage, both triangles; on a
+    // diagonal tile the mirrored writes carry identical values)
+    double* out = part + (long long)sp * In * In;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int a = ta * 64 + ty * 4 + i, b = tb * 64 + tx * 4 + j;
+            if (a < In && b < In) {
+                out[(long long)a * In + b] = acc[i][j];
+                out[(long long)b * In + a] = acc[i][j];
+            }
+        }
+}
+
+__global__ __launch_bounds__(256) void k_sum_split(const double* __restrict__ part, int nsplit, long long n,
+                                                   double* __restrict__ out) {
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+        double a = 0.0;
+        for (int p = 0; p < nsplit; ++p) a += part[p * n + e];
+        out[e] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// J leading eigenvectors of a symmetric n x n matrix (n <= 512, J <= 64), one
+// workgroup per matrix, FP64 throughout:
+//   1. Householder tridiagonalisation Q^T A Q = T (Golub & Van Loan, Alg.
+//      5.1.1 for the reflectors, 8.3.1 for the reduction), in place in A;
+//      the reflector vectors are kept below the subdiagonal of A.
+//   2. The J largest eigenvalues of T by bisection on Sturm counts.
+//   3. Their eigenvectors of T by inverse iteration with a partially pivoted
+//      LU of T - lambda I (as in LAPACK's xSTEIN); vectors whose eigenvalues lie
+//      within 1e-3 ||T|| of each other are kept orthogonal by Gram-Schmidt.
+//   4. Back-transformation by the reflectors, descending-eigenvalue column
+//      order, each column signed so its largest-magnitude entry is positive.
+// Matrix m = blockIdx.x is block m / 3, mode m % 3; its Gram sits at
+// sig + m * sig_stride, its scratch at work + m * work_stride, and the basis
+// is written to the block's A_n (I_n x J_n, row-major) in the Tucker storage.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double hash_uniform(unsigned long long k) {
+    unsigned long long z = k + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+}
+
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+// number of eigenvalues of T (d, e2 = e^2) below x
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int cnt = q < 0.0;
+    for (int i = 1; i < n; ++i) {
+        q = (d[i] - x) - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+    }
+    return cnt;
+}
+
+__global__ __launch_bounds__(256) void k_eig_top(const Geo* __restrict__ g, double* __restrict__ lra,
+                                                 double* __restrict__ sig, long long sig_stride,
+                                                 double* __restrict__ work, long long work_stride) {
+    const int mat = blockIdx.x, s = mat / 3, mode = mat % 3;
+    const int n = g->I[s][mode], J = g->J[s][mode];
+    double* A = sig + (long long)mat * sig_stride;
+    double* W = work + (long long)mat * work_stride;
+    double* d = W;
+    double* e = W + n;
+    double* e2 = W + 2 * n;
+    double* tau = W + 3 * n;
+    double* ev = W + 4 * n;                 // 64
+    double* F = W + 4 * n + 64;             // 5 x n x J factors of T - ev_j I
+    double* Z = lra + g->aoff[mode][s];     // n x J output
+    __shared__ double sv[512], sw[512], red[4];
+    __shared__ double part[4][64];
+    __shared__ int cstart[64];
+    __shared__ double tinfo[3];
+    const int tid = threadIdx.x;
+
+    // ---- 1. tridiagonalisation -------------------------------------------
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        const double* xrow = A + (long long)k * n + k + 1;   // row k == column k
+        double ss = 0.0;
+        for (int i = tid; i < m; i += 256) {
+            const double x = xrow[i];
+            sv[i] = x;
+            if (i > 0) ss = fma(x, x, ss);
+        }
+        const double sigma = block_sum256(ss, red);
+        const double alpha = sv[0];
+        if (tid == 0) d[k] = A[(long long)k * n + k];
+        if (!(sigma > 0.0)) {
+            if (tid == 0) {
+                e[k] = alpha;
+                tau[k] = 0.0;
+            }
+            for (int i = tid; i < m; i += 256) A[(long long)(k + 1 + i) * n + k] = 0.0;
+            __syncthreads();
+            continue;
+        }
+        const double mu = sqrt(fma(alpha, alpha, sigma));
+        const double v1 = alpha <= 0.0 ? alpha - mu : -sigma / (alpha + mu);
+        const double beta = 2.0 * v1 * v1 / (sigma + v1 * v1);
+        __syncthreads();
+        for (int i = tid; i < m; i += 256) sv[i] = i == 0 ? 1.0 : sv[i] / v1;
+        if (tid == 0) {
+            e[k] = mu;
+            tau[k] = beta;
+        }
+        __syncthreads();
+        // p = beta B v (B = trailing block, read by columns for coalescing)
+        const double* B = A + (long long)(k + 1) * n + k + 1;
+        double pv = 0.0;
+        for (int r = tid; r < m; r += 256) {
+            double a0 = 0.0, a1 = 0.0;
+            int c = 0;
+            for (; c + 1 < m; c += 2) {
+                a0 = fma(B[(long long)c * n + r], sv[c], a0);
+                a1 = fma(B[(long long)(c + 1) * n + r], sv[c + 1], a1);
+            }
+            if (c < m) a0 = fma(B[(long long)c * n + r], sv[c], a0);
+            const double p = beta * (a0 + a1);
+            sw[r] = p;
+            pv = fma(p, sv[r], pv);
+        }
+        const double K = 0.5 * beta * block_sum256(pv, red);
+        for (int r = tid; r < m; r += 256) sw[r] = fma(-K, sv[r], sw[r]);
+        __syncthreads();
+        // B -= v w^T + w v^T, evaluated in a symmetric order so B stays
+        // exactly symmetric
+        double* Bw = A + (long long)(k + 1) * n + k + 1;
+        for (long long q = tid; q < (long long)m * m; q += 256) {
+            const int r = (int)(q / m), c = (int)(q % m);
+            const int lo = min(r, c), hi = max(r, c);
+            Bw[(long long)r * n + c] -= fma(sv[lo], sw[hi], sw[lo] * sv[hi]);
+        }
+        // reflector vector below the subdiagonal of column k
+        for (int i = tid; i < m; i += 256) A[(long long)(k + 1 + i) * n + k] = sv[i];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (n >= 2) {
+            d[n - 2] = A[(long long)(n - 2) * n + n - 2];
+            e[n - 2] = A[(long long)(n - 2) * n + n - 1];
+            tau[n - 2] = 0.0;
+        }
+        d[n - 1] = A[(long long)(n - 1) * n + n - 1];
+        tau[n - 1] = 0.0;
+        double tn = 0.0, lo = 0.0, hi = 0.0, emax = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double el = i > 0 ? fabs(e[i - 1]) : 0.0, er = i + 1 < n ? fabs(e[i]) : 0.0;
+            if (i + 1 < n) {
+                e2[i] = e[i] * e[i];
+                emax = fmax(emax, e2[i]);
+            }
+            tn = fmax(tn, fabs(d[i]) + el + er);
+            lo = i == 0 ? d[i] - el - er : fmin(lo, d[i] - el - er);
+            hi = i == 0 ? d[i] + el + er : fmax(hi, d[i] + el + er);
+        }
+        tinfo[0] = tn;
+        tinfo[1] = lo - (2.0 * DBL_EPSILON * n * tn + 1e-300);
+        tinfo[2] = hi + (2.0 * DBL_EPSILON * n * tn + 1e-300);
+        red[0] = DBL_MIN * fmax(1.0, emax);
+    }
+    __syncthreads();
+    const double tnorm = tinfo[0], pivmin = red[0];
+    __syncthreads();
+
+    if (!(tnorm > 0.0)) {
+        // zero matrix: any orthonormal basis spans an invariant subspace
+        for (long long q = tid; q < (long long)n * J; q += 256) Z[q] = ((int)(q / J) == (int)(q % J)) ? 1.0 : 0.0;
+        return;
+    }
+
+    // ---- 2. bisection ----------------------------------------------------
+    if (tid < J) {
+        const int t = n - 1 - tid;   // ascending index of the wanted eigenvalue
+        double lo = tinfo[1], hi = tinfo[2];
+        const double atol = 2.0 * DBL_EPSILON * tnorm;
+        for (int it = 0; it < 200; ++it) {
+            if (hi - lo <= fmax(atol, 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) break;
+            const double mid = 0.5 * (lo + hi);
+            if (sturm_count(d, e2, n, mid, pivmin) <= t) lo = mid;
+            else hi = mid;
+        }
+        ev[tid] = 0.5 * (lo + hi);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        cstart[0] = 0;
+        for (int j = 1; j < J; ++j) cstart[j] = (ev[j - 1] - ev[j] > 1e-3 * tnorm) ? j : cstart[j - 1];
+    }
+
+    // ---- 3. inverse iteration -------------------------------------------
+    // factors of T - ev_j I: F[(f * n + i) * J + j], f = l, u0, u1, u2, swap
+    const double pivtol = DBL_EPSILON * tnorm;
+    if (tid < J) {
+        const int j = tid;
+        const double lam = ev[j];
+        double al = d[0] - lam, be = n > 1 ? e[0] : 0.0;
+        for (int i = 0; i + 1 < n; ++i) {
+            const double c = e[i], an = d[i + 1] - lam, bn = i + 2 < n ? e[i + 1] : 0.0;
+            double l, u0, u1, u2, sw_;
+            if (fabs(al) >= fabs(c)) {
+                l = al != 0.0 ? c / al : 0.0;
+                u0 = al; u1 = be; u2 = 0.0; sw_ = 0.0;
+                al = an - l * be;
+                be = bn;
+            } else {
+                l = al / c;
+                u0 = c; u1 = an; u2 = bn; sw_ = 1.0;
+                al = be - l * an;
+                be = -l * bn;
+            }
+            F[(0LL * n + i) * J + j] = l;
+            F[(1LL * n + i) * J + j] = u0;
+            F[(2LL * n + i) * J + j] = u1;
+            F[(3LL * n + i) * J + j] = u2;
+            F[(4LL * n + i) * J + j] = sw_;
+        }
+        F[(1LL * n + n - 1) * J + j] = al;
+        for (int i = 0; i < n; ++i)
+            Z[(long long)i * J + j] = hash_uniform(((unsigned long long)mat << 40) ^ ((unsigned long long)j << 20) ^ (unsigned long long)i);
+    }
+    __syncthreads();
+    for (int it = 0; it < 5; ++it) {
+        if (tid < J) {
+            const int j = tid;
+            // forward elimination of the right-hand side (in place)
+            double rw = Z[j];
+            for (int i = 0; i + 1 < n; ++i) {
+                const double l = F[(0LL * n + i) * J + j], y1 = Z[(long long)(i + 1) * J + j];
+                if (F[(4LL * n + i) * J + j] == 0.0) {
+                    Z[(long long)i * J + j] = rw;
+                    rw = y1 - l * rw;
+                } else {
+                    Z[(long long)i * J + j] = y1;
+                    rw = rw - l * y1;
+                }
+            }
+            Z[(long long)(n - 1) * J + j] = rw;
+            // back substitution, tiny pivots replaced by +-eps ||T||
+            double x1 = 0.0, x2 = 0.0;
+            for (int i = n - 1; i >= 0; --i) {
+                double u0 = F[(1LL * n + i) * J + j];
+                if (fabs(u0) < pivtol) u0 = u0 < 0.0 ? -pivtol : pivtol;
+                const double x = (Z[(long long)i * J + j] - F[(2LL * n + i) * J + j] * x1 - F[(3LL * n + i) * J + j] * x2) / u0;
+                Z[(long long)i * J + j] = x;
+                x2 = x1;
+                x1 = x;
+            }
+        }
+        __syncthreads();
+        // scale every column to unit max-norm (keeps later sums in range)
+        {
+            const int j = tid & 63, grp = tid >> 6;
+            double mx = 0.0;
+            if (j < J)
+                for (int i = grp; i < n; i += 4) mx = fmax(mx, fabs(Z[(long long)i * J + j]));
+            part[grp][j] = mx;
+            __syncthreads();
+            if (j < J) {
+                const double m = fmax(fmax(part[0][j], part[1][j]), fmax(part[2][j], part[3][j]));
+                const double sc = m > 0.0 ? 1.0 / m : 1.0;
+                for (int i = grp; i < n; i += 4) Z[(long long)i * J + j] *= sc;
+            }
+            __syncthreads();
+        }
+        // Gram-Schmidt (twice) against earlier vectors of the same cluster,
+        // then normalisation
+        for (int j = 0; j < J; ++j) {
+            const int c0 = cstart[j];
+            for (int pass = 0; pass < (c0 < j ? 2 : 0); ++pass) {
+                // dots with columns c0 .. j-1: column jj = c0 + (tid & 63), 4 row phases
+                const int jj = c0 + (tid & 63), grp = tid >> 6;
+                double dt = 0.0;
+                if (jj < j)
+                    for (int i = grp; i < n; i += 4) dt = fma(Z[(long long)i * J + jj], Z[(long long)i * J + j], dt);
+                part[grp][tid & 63] = dt;
+                __syncthreads();
+                if (tid < 64) sw[tid] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+                __syncthreads();
+                for (int i = tid; i < n; i += 256) {
+                    double z = Z[(long long)i * J + j];
+                    for (int q = c0; q < j; ++q) z = fma(-sw[q - c0], Z[(long long)i * J + q], z);
+                    Z[(long long)i * J + j] = z;
+                }
+                __syncthreads();
+            }
+            double nn = 0.0;
+            for (int i = tid; i < n; i += 256) nn = fma(Z[(long long)i * J + j], Z[(long long)i * J + j], nn);
+            const double nrm = sqrt(block_sum256(nn, red));
+            const double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
+            for (int i = tid; i < n; i += 256) Z[(long long)i * J + j] *= sc;
+            __syncthreads();
+        }
+    }
+
+    // ---- 4. back-transformation y = H_0 H_1 ... H_{n-3} z ------------------
+    for (int k = n - 3; k >= 0; --k) {
+        const double tk = tau[k];
+        if (tk == 0.0) continue;
+        const int m = n - k - 1;
+        const double* v = A + (long long)(k + 1) * n + k;   // v_i at row k+1+i, v_0 = 1
+        const int j = tid & 63, grp = tid >> 6;
+        double dt = 0.0;
+        if (j < J)
+            for (int i = grp; i < m; i += 4)
+                dt = fma(i == 0 ? 1.0 : v[(long long)i * n], Z[(long long)(k + 1 + i) * J + j], dt);
+        part[grp][j] = dt;
+        __syncthreads();
+        if (j < J) {
+            const double f = tk * (part[0][j] + part[1][j] + part[2][j] + part[3][j]);
+            for (int i = grp; i < m; i += 4)
+                Z[(long long)(k + 1 + i) * J + j] = fma(-f, i == 0 ? 1.0 : v[(long long)i * n], Z[(long long)(k + 1 + i) * J + j]);
+        }
+        __syncthreads();
+    }
+
+    // ---- sign convention ---------------------------------------------------
+    {
+        __shared__ double bv[4][64];
+        __shared__ int bidx[4][64];
+        const int j = tid & 63, grp = tid >> 6;
+        double best = -1.0;
+        int bi = 0x7fffffff;
+        if (j < J)
+            for (int i = grp; i < n; i += 4) {
+                const double a = fabs(Z[(long long)i * J + j]);
+                if (a > best) { best = a; bi = i; }
+            }
+        bv[grp][j] = best;
+        bidx[grp][j] = bi;
+        __syncthreads();
+        bool neg = false;
+        if (j < J) {
+            double b = bv[0][j];
+            int ib = bidx[0][j];
+            for (int q = 1; q < 4; ++q)
+                if (bv[q][j] > b || (bv[q][j] == b && bidx[q][j] < ib)) { b = bv[q][j]; ib = bidx[q][j]; }
+            neg = Z[(long long)ib * J + j] < 0.0;
+        }
+        __syncthreads();
+        if (neg)
+            for (int i = grp; i < n; i += 4) Z[(long long)i * J + j] = -Z[(long long)i * J + j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TTM chain for G = M x_1 A_1^T x_2 A_2^T x_3 A_3^T (FP64 accumulation)
+//   T1[i1][i2][j3] = sum_i3 M[i1][i2][i3] A3[i3][j3]          (one slab per workgroup)
+//   T2[i1][j2][j3] = sum_i2 A2[i2][j2] T1[i1][i2][j3]
+//   G [j1][j2][j3] = sum_i1 A1[i1][j1] T2[i1][j2][j3]
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ttm3(const float* __restrict__ M, int I2, int I3, const double* __restrict__ A3,
+                                              int J3, double* __restrict__ T1) {
+    const int i1 = blockIdx.x;
+    __shared__ float xs[4][512];
+    const int tid = threadIdx.x;
+    for (int i2b = 0; i2b < I2; i2b += 4) {
+        const int nr = min(4, I2 - i2b);
+        __syncthreads();
+        for (int e = tid; e < nr * I3; e += 256) xs[e / I3][e % I3] = M[((long long)i1 * I2 + i2b + e / I3) * I3 + e % I3];
+        __syncthreads();
+        for (int e = tid; e < nr * J3; e += 256) {
+            const int r = e / J3, j = e % J3;
+            double a = 0.0;
+            for (int k = 0; k < I3; ++k) a = fma((double)xs[r][k], A3[(long long)k * J3 + j], a);
+            T1[((long long)i1 * I2 + i2b + r) * J3 + j] = a;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ttm2(const double* __restrict__ T1, int I2, int J3, const double* __restrict__ A2,
+                                              int J2, double* __restrict__ T2) {
+    const int i1 = blockIdx.x;
+    for (int e = threadIdx.x; e < J2 * J3; e += 256) {
+        const int j2 = e / J3, j3 = e % J3;
+        double a = 0.0;
+        for (int i2 = 0; i2 < I2; ++i2) a = fma(A2[(long long)i2 * J2 + j2], T1[((long long)i1 * I2 + i2) * J3 + j3], a);
+        T2[((long long)i1 * J2 + j2) * J3 + j3] = a;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ttm1(const double* __restrict__ T2, int I1, int J2J3, const double* __restrict__ A1,
+                                              int J1, double* __restrict__ G) {
+    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < (long long)J1 * J2J3; e += (long long)gridDim.x * 256) {
+        const int j1 = (int)(e / J2J3), q = (int)(e % J2J3);
+        double a = 0.0;
+        for (int i1 = 0; i1 < I1; ++i1) a = fma(A1[(long long)i1 * J1 + j1], T2[(long long)i1 * J2J3 + q], a);
+        G[e] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Iteration kernels
+// ---------------------------------------------------------------------------
+// W_n^(s)[j][c] = sum_i A_n[i][j] U^(n,s)[i][c] for every block; one
+// workgroup per (block, j): 4 row phases x 64 columns, summed in fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lra_w(const Geo* __restrict__ g, StateP<T> st, int n, int uslot, int wslot, int gate) {
+    if (gated_out(st.ctrl, gate)) return;
+    const int s = blockIdx.y, j = blockIdx.x;
+    const int Jn = g->J[s][n];
+    if (j >= Jn) return;
+    const int I = g->I[s][n], Rq = g->Rq, R = g->R;
+    const double* A = st.lra + g->aoff[n][s];
+    const T* U = st.U[uslot] + g->uoff[n][s];
+    __shared__ double part[4][64];
+    const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    double a = 0.0;
+    if (c < R)
+        for (int i = ph; i < I; i += 4) a = fma(A[(long long)i * Jn + j], (double)U[(long long)i * Rq + c], a);
+    part[ph][c] = a;
+    __syncthreads();
+    if (threadIdx.x < Rq) {
+        const double v = (c < R) ? part[0][c] + part[1][c] + part[2][c] + part[3][c] : 0.0;
+        st.lra[g->woff[n][s] + (long long)wslot * g->wslot_len + (long long)j * Rq + c] = v;
+    }
+}
+
+// C_n^(s)[jn][c] = sum_{ja, jb} G_(n)[jn][(ja, jb)] W_a[ja][c] W_b[jb][c], where
+// (a, b) are the other two modes (W of modes before n from slot 0, after n
+// from slot 1).  One workgroup per (block, jn).
+template <typename T>
+__global__ __launch_bounds__(256) void k_lra_c(const Geo* __restrict__ g, StateP<T> st, int n, int gate) {
+    if (gated_out(st.ctrl, gate)) return;
+    const int s = blockIdx.y, jn = blockIdx.x;
+    const int J0 = g->J[s][0], J1 = g->J[s][1], J2 = g->J[s][2];
+    const int Jn = g->J[s][n];
+    if (jn >= Jn) return;
+    const int Rq = g->Rq, R = g->R;
+    const int ma = (n == 0) ? 1 : 0, mb = (n == 2) ? 1 : 2;
+    const int Ja = g->J[s][ma], Jb = g->J[s][mb];
+    const long long wl = g->wslot_len;
+    const double* Wa = st.lra + g->woff[ma][s] + (ma < n ? 0 : wl);
+    const double* Wb = st.lra + g->woff[mb][s] + (mb < n ? 0 : wl);
+    const double* G = st.lra + g->goff[s];
+    __shared__ double part[4][64];
+    const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    double acc = 0.0;
+    if (c < R) {
+        for (int ja = ph; ja < Ja; ja += 4) {
+            const double wa = Wa[(long long)ja * Rq + c];
+            double inner = 0.0;
+            for (int jb = 0; jb < Jb; ++jb) {
+                long long gi;
+                if (n == 0) gi = ((long long)jn * J1 + ja) * J2 + jb;
+                else if (n == 1) gi = ((long long)ja * J1 + jn) * J2 + jb;
+                else gi = ((long long)ja * J1 + jb) * J2 + jn;
+                inner = fma(G[gi], Wb[(long long)jb * Rq + c], inner);
+            }
+            acc = fma(wa, inner, acc);
+        }
+    }
+    (void)J0;
+    part[ph][c] = acc;
+    __syncthreads();
+    if (threadIdx.x < Rq)
+        st.lra[g->coff[s] + (long long)jn * Rq + c] = (c < R) ? part[0][c] + part[1][c] + part[2][c] + part[3][c] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_mode_gram(const float* X, int mode, int I1, int I2, int I3, double* part, int nsplit, hipStream_t q) {
+    const int In = mode == 0 ? I1 : (mode == 1 ? I2 : I3);
+    const int nt = (In + 63) / 64;
+    hipLaunchKernelGGL(k_mode_gram, dim3(nt * (nt + 1) / 2, nsplit), dim3(256), 0, q, X, mode, I1, I2, I3, nt, part);
+}
+void launch_sum_split(const double* part, int nsplit, long long n, double* out, hipStream_t q) {
+    long long nb = (n + 255) / 256;
+    if (nb > 2048) nb = 2048;
+    hipLaunchKernelGGL(k_sum_split, dim3((unsigned)nb), dim3(256), 0, q, part, nsplit, n, out);
+}
+void launch_eig_top(const Geo* g, double* lra, double* sig, long long sig_stride, double* work, long long work_stride,
+                    int nmat, hipStream_t q) {
+    hipLaunchKernelGGL(k_eig_top, dim3(nmat), dim3(256), 0, q, g, lra, sig, sig_stride, work, work_stride);
+}
+void launch_ttm_chain(const float* M, int I1, int I2, int I3, const double* A1, const double* A2, const double* A3, int J1,
+                      int J2, int J3, double* T1, double* T2, double* G, hipStream_t q) {
+    hipLaunchKernelGGL(k_ttm3, dim3(I1), dim3(256), 0, q, M, I2, I3, A3, J3, T1);
+    hipLaunchKernelGGL(k_ttm2, dim3(I1), dim3(256), 0, q, T1, I2, J3, A2, J2, T2);
+    long long nb = ((long long)J1 * J2 * J3 + 255) / 256;
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(k_ttm1, dim3((unsigned)nb), dim3(256), 0, q, T2, I1, J2 * J3, A1, J1, G);
+}
+template <typename T>
+void launch_lra_w(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int uslot, int wslot, int gate, hipStream_t q) {
+    hipLaunchKernelGGL(k_lra_w<T>, dim3(Jmax, S), dim3(256), 0, q, g, st, n, uslot, wslot, gate);
+}
+template <typename T>
+void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int gate, hipStream_t q) {
+    hipLaunchKernelGGL(k_lra_c<T>, dim3(Jmax, S), dim3(256), 0, q, g, st, n, gate);
+}
+template void launch_lra_w<float>(const Geo*, const StateP<float>&, int, int, int, int, int, int, hipStream_t);
+template void launch_lra_w<double>(const Geo*, const StateP<double>&, int, int, int, int, int, int, hipStream_t);
+template void launch_lra_c<float>(const Geo*, const StateP<float>&, int, int, int, int, hipStream_t);
+template void launch_lra_c<double>(const Geo*, const StateP<double>&, int, int, int, int, hipStream_t);
+
+}  // namespace cpd

@@ -118,12 +118,12 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
 // Grams and b to slot 1.  The last workgroup keeps the Lipschitz constants of
 // the accepted sweep, advances k and t and applies the stopping rule.
 template <typename T>
-__global__ __launch_bounds__(256) void k_commit(const Geo* __restrict__ g, StateP<T> st, long long uslot) {
+__global__ __launch_bounds__(256) void k_commit(const Geo* __restrict__ g, StateP<T> st, long long uslot, long long wlen) {
     Ctrl* c = st.ctrl;
     if (c->stop) return;
     const int S = g->S, R = g->R, Rq = g->Rq;
     const long long nl = (long long)S * Rq, nv = 3LL * S * R * R, nb = (long long)S * Rq;
-    const long long total = uslot + nl + nv + nb;
+    const long long total = uslot + nl + nv + nb + wlen;
     for (long long i = blockIdx.x * 256LL + threadIdx.x; i < total; i += (long long)gridDim.x * 256) {
         if (i < uslot) {
             st.U[2][i] = st.U[1][i];
@@ -135,9 +135,13 @@ __global__ __launch_bounds__(256) void k_commit(const Geo* __restrict__ g, State
         } else if (i < uslot + nl + nv) {
             const long long j = i - uslot - nl;
             st.V[1][j] = st.V[0][j];
-        } else {
+        } else if (i < uslot + nl + nv + nb) {
             const long long j = i - uslot - nl - nv;
             st.b[1][j] = st.b[0][j];
+        } else {
+            // Tucker-form W = A^T U (lra): slot 0 -> slot 1
+            const long long j = i - uslot - nl - nv - nb;
+            st.lra[g->woff[0][0] + g->wslot_len + j] = st.lra[g->woff[0][0] + j];
         }
     }
     __shared__ int last;
@@ -257,12 +261,12 @@ void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, int first_sw
     hipLaunchKernelGGL(k_finish<T>, dim3(S), dim3(256), gram_lds_bytes<T>(R, Rq, 128), q, g, st, first_sweep, gate);
 }
 template <typename T>
-void launch_commit(const Geo* g, const StateP<T>& st, long long uslot, int S, int Rq, int R, hipStream_t q) {
-    const long long total = uslot + (long long)S * Rq * 2 + 3LL * S * R * R;
+void launch_commit(const Geo* g, const StateP<T>& st, long long uslot, int S, int Rq, int R, long long wlen, hipStream_t q) {
+    const long long total = uslot + (long long)S * Rq * 2 + 3LL * S * R * R + wlen;
     long long nb = (total + 255) / 256;
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_commit<T>, dim3((unsigned)nb), dim3(256), 0, q, g, st, uslot);
+    hipLaunchKernelGGL(k_commit<T>, dim3((unsigned)nb), dim3(256), 0, q, g, st, uslot, wlen);
 }
 template <typename T>
 void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q) {
@@ -274,7 +278,7 @@ void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStrea
     template void launch_core<T>(const Geo*, const StateP<T>&, int, int, int, int, hipStream_t);          \
     template void launch_prep<T>(const Geo*, const StateP<T>&, int, int, int, int, hipStream_t);          \
     template void launch_finish<T>(const Geo*, const StateP<T>&, int, int, int, int, hipStream_t);        \
-    template void launch_commit<T>(const Geo*, const StateP<T>&, long long, int, int, int, hipStream_t);  \
+    template void launch_commit<T>(const Geo*, const StateP<T>&, long long, int, int, int, long long, hipStream_t); \
     template void launch_init_stats<T>(const Geo*, const StateP<T>&, int, int, hipStream_t);
 CPD_INST_SMALL(float)
 CPD_INST_SMALL(double)

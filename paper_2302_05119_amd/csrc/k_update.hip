@@ -15,7 +15,7 @@
 
 namespace cpd {
 
-enum { KSRC_K1P = 0, KSRC_K2 = 1, KSRC_PART = 2 };
+enum { KSRC_K1P = 0, KSRC_K2 = 1, KSRC_PART = 2, KSRC_LRA0 = 3, KSRC_LRA1 = 4, KSRC_LRA2 = 5 };
 
 // K[i][col] of block s from the MTTKRP pass outputs (FP64 sums in fixed order).
 template <typename T, int KSRC>
@@ -28,6 +28,12 @@ __device__ __forceinline__ double k_value(const Geo* __restrict__ g, const State
         for (int r = 0; r < nrg; ++r) acc += (double)p[r * Rq];
     } else if (KSRC == KSRC_K2) {
         acc = (double)st.K2[g->k2off[s] + (long long)i * Rq + col];
+    } else if (KSRC >= KSRC_LRA0) {
+        // Tucker form: K_n[i][col] = sum_j A_n[i][j] C_n[j][col]
+        const int n = KSRC - KSRC_LRA0, Jn = g->J[s][n];
+        const double* A = st.lra + g->aoff[n][s] + (long long)i * Jn;
+        const double* C = st.lra + g->coff[s] + col;
+        for (int j = 0; j < Jn; ++j) acc = fma(A[j], C[(long long)j * Rq], acc);
     } else {
         const int I3 = g->I[s][2], nch = g->nchunk[s];
         const T* p = st.part + g->poff[s] + (long long)i * Rq + col;
@@ -77,7 +83,7 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
         for (int r = 0; r < R; ++r) gr += u[r] * P[r * R + col];
         const double kv = k_value<T, KSRC>(g, st, s, i, col);
         gr -= kv * st.lam[0][s * Rq + col];
-        if (KSRC == KSRC_PART) st.K3[g->koff[s] + (long long)i * Rq + col] = (T)kv;
+        if (KSRC == KSRC_PART || KSRC == KSRC_LRA2) st.K3[g->koff[s] + (long long)i * Rq + col] = (T)kv;
         const long long off = g->uoff[n][s] + (long long)i * Rq + col;
         if (col >= Ln) {
             const double Lu = st.Lu_cur[n * S + s];
@@ -114,29 +120,41 @@ __global__ __launch_bounds__(256) void k_extract(const Geo* __restrict__ g, Stat
 }
 
 template <typename T>
-void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, int R, T* out, int ld_out, hipStream_t q) {
+void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, int R, T* out, int ld_out, int lra, hipStream_t q) {
     long long nb = ((long long)I * R + 255) / 256;
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
+    if (lra) {
+        if (n == 0) hipLaunchKernelGGL((k_extract<T, KSRC_LRA0>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
+        else if (n == 1) hipLaunchKernelGGL((k_extract<T, KSRC_LRA1>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
+        else hipLaunchKernelGGL((k_extract<T, KSRC_LRA2>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
+        return;
+    }
     if (n == 0) hipLaunchKernelGGL((k_extract<T, KSRC_K1P>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
     else if (n == 1) hipLaunchKernelGGL((k_extract<T, KSRC_K2>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
     else hipLaunchKernelGGL((k_extract<T, KSRC_PART>), dim3((unsigned)nb), dim3(256), 0, q, g, st, s, I, out, ld_out);
 }
-template void launch_extract_k<float>(const Geo*, const StateP<float>&, int, int, int, int, float*, int, hipStream_t);
-template void launch_extract_k<double>(const Geo*, const StateP<double>&, int, int, int, int, double*, int, hipStream_t);
+template void launch_extract_k<float>(const Geo*, const StateP<float>&, int, int, int, int, float*, int, int, hipStream_t);
+template void launch_extract_k<double>(const Geo*, const StateP<double>&, int, int, int, int, double*, int, int, hipStream_t);
 
 template <typename T>
 void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int gate,
-                   int lds_rows, hipStream_t q) {
+                   int lds_rows, int lra, hipStream_t q) {
     if (nitems <= 0) return;
     // lds_rows = max over items of ns * nrows; the shared-gradient buffer uses at most as much
     const size_t lds = sizeof(double) * (size_t)lds_rows * (size_t)(2 * R);
+    if (lra) {
+        if (n == 0) hipLaunchKernelGGL((k_update<T, KSRC_LRA0>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
+        else if (n == 1) hipLaunchKernelGGL((k_update<T, KSRC_LRA1>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
+        else hipLaunchKernelGGL((k_update<T, KSRC_LRA2>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
+        return;
+    }
     if (n == 0) hipLaunchKernelGGL((k_update<T, KSRC_K1P>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
     else if (n == 1) hipLaunchKernelGGL((k_update<T, KSRC_K2>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
     else hipLaunchKernelGGL((k_update<T, KSRC_PART>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
 }
 
-template void launch_update<float>(const Geo*, const StateP<float>&, const ItemU*, int, int, int, int, int, int, hipStream_t);
-template void launch_update<double>(const Geo*, const StateP<double>&, const ItemU*, int, int, int, int, int, int, hipStream_t);
+template void launch_update<float>(const Geo*, const StateP<float>&, const ItemU*, int, int, int, int, int, int, int, hipStream_t);
+template void launch_update<double>(const Geo*, const StateP<double>&, const ItemU*, int, int, int, int, int, int, int, hipStream_t);
 
 }  // namespace cpd

@@ -41,6 +41,9 @@ struct Layout {
     size_t geo, ctrl, U[3], lam[3], V[2], b[2], P, Ld_cur, Ld_prev, Lu_cur, Lu_prev, LC_prev, Fblk, normM2, normOrig, Y,
         K3, part, K1p, K2, it1, it2, itk2, itu[3], scratch, shadow, lra, flag, total;
     long long uslot, ylen, klen, plen, shadow_elems[CPD_MAXS], lra_len;
+    // lra region (doubles from its base): compression scratch
+    long long l_sig, l_part, l_work, l_t1, l_t2, sig_stride, work_stride;
+    int nsplit, Imax, Jmax;
     size_t scratch_len;
     int esz;  // bytes per factor element
 };
@@ -88,7 +91,11 @@ concpd_status validate(const concpd_config* c) {
                 const int J = c->tucker_ranks[3 * s + n];
                 if (J < 1 || J > c->dims[3 * s + n] || J > 64)
                     return fail(CONCPD_EINVAL, "tucker_ranks[%d] = %d must be in [1, min(I_n, 64)]", 3 * s + n, J);
+                if (c->dims[3 * s + n] > 512)
+                    return fail(CONCPD_ENOTSUP, "lra compression supports I_n <= 512 (block %d mode %d)", s, n);
             }
+    if (c->tucker_ranks && c->tensor_dtype != CONCPD_F32)
+        return fail(CONCPD_ENOTSUP, "lra compression needs F32 tensors");
     return CONCPD_OK;
 }
 
@@ -210,6 +217,55 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
         }
         P->shadow = take((size_t)tot * 2);
     }
+    if (c->tucker_ranks) {
+        long long a = 0;
+        int Imax = 1, Jmax = 1;
+        long long t1 = 1, t2 = 1;
+        for (int n = 0; n < 3; ++n)
+            for (int s = 0; s < S; ++s) {
+                const int J = c->tucker_ranks[3 * s + n];
+                g->J[s][n] = J;
+                g->aoff[n][s] = a;
+                a += c->dims[3 * s + n] * J;
+                Imax = std::max(Imax, (int)c->dims[3 * s + n]);
+                Jmax = std::max(Jmax, J);
+            }
+        for (int s = 0; s < S; ++s) {
+            g->goff[s] = a;
+            a += (long long)g->J[s][0] * g->J[s][1] * g->J[s][2];
+            t1 = std::max<long long>(t1, c->dims[3 * s] * c->dims[3 * s + 1] * g->J[s][2]);
+            t2 = std::max<long long>(t2, c->dims[3 * s] * (long long)g->J[s][1] * g->J[s][2]);
+        }
+        long long w = 0;
+        for (int n = 0; n < 3; ++n)
+            for (int s = 0; s < S; ++s) {
+                g->woff[n][s] = a + w;
+                w += (long long)g->J[s][n] * Rq;
+            }
+        g->wslot_len = w;
+        a += 2 * w;
+        for (int s = 0; s < S; ++s) {
+            g->coff[s] = a;
+            a += (long long)Jmax * Rq;
+        }
+        P->nsplit = 16;
+        P->Imax = Imax;
+        P->Jmax = Jmax;
+        P->sig_stride = (long long)Imax * Imax;
+        P->work_stride = 4LL * Imax + 64 + 5LL * Imax * Jmax;
+        P->l_sig = a;
+        a += 3LL * S * P->sig_stride;
+        P->l_work = a;
+        a += 3LL * S * P->work_stride;
+        P->l_part = a;
+        a += (long long)P->nsplit * Imax * Imax;
+        P->l_t1 = a;
+        a += t1;
+        P->l_t2 = a;
+        a += t2;
+        P->lra_len = a;
+        P->lra = take(sizeof(double) * (size_t)a);
+    }
     P->total = off;
 }
 
@@ -298,11 +354,11 @@ void run_sweep(concpd_ctx c, const StateP<T>& st, int extrap, int gate, int firs
     if (prof) (void)hipEventRecord(e[0], q);
     cpd::launch_pass1<T>(g, st, it1, (int)c->lists.p1.size(), Rq, 1, gate, c->mdtype, q);
     if (prof) (void)hipEventRecord(e[1], q);
-    cpd::launch_update<T>(g, st, itu[0], (int)c->lists.u[0].size(), 0, R, extrap, gate, c->lists.lds_rows[0], q);
+    cpd::launch_update<T>(g, st, itu[0], (int)c->lists.u[0].size(), 0, R, extrap, gate, c->lists.lds_rows[0], 0, q);
     // mode-2 step matrix beside the mode-2 contraction (new U^(1))
     cpd::launch_prep<T>(g, st, S, R, 1, gate, q);
     cpd::launch_k2<T>(g, st, itk, (int)c->lists.k2.size(), 0, gate, q);
-    cpd::launch_update<T>(g, st, itu[1], (int)c->lists.u[1].size(), 1, R, extrap, gate, c->lists.lds_rows[1], q);
+    cpd::launch_update<T>(g, st, itu[1], (int)c->lists.u[1].size(), 1, R, extrap, gate, c->lists.lds_rows[1], 0, q);
     // mode-3 step matrix beside pass 2 (new U^(1), U^(2))
     cpd::launch_prep<T>(g, st, S, R, 2, gate, q);
     if (prof) (void)hipEventRecord(e[2], q);
@@ -314,24 +370,57 @@ void run_sweep(concpd_ctx c, const StateP<T>& st, int extrap, int gate, int firs
         c->ev2.push_back(e[2]);
         c->ev2.push_back(e[3]);
     }
-    cpd::launch_update<T>(g, st, itu[2], (int)c->lists.u[2].size(), 2, R, extrap, gate, c->lists.lds_rows[2], q);
+    cpd::launch_update<T>(g, st, itu[2], (int)c->lists.u[2].size(), 2, R, extrap, gate, c->lists.lds_rows[2], 0, q);
+    cpd::launch_finish<T>(g, st, S, R, first, gate, q);
+}
+
+// The same sweep with the gradients taken from the Tucker form (Algorithm 2).
+template <typename T>
+void run_sweep_lra(concpd_ctx c, const StateP<T>& st, int extrap, int gate, int first) {
+    const Geo* g = c->dgeo;
+    const int S = c->S, R = c->R, J = c->lay.Jmax;
+    hipStream_t q = c->q;
+    const ItemU* itu[3];
+    for (int n = 0; n < 3; ++n) itu[n] = (const ItemU*)(c->ws + c->lay.itu[n]);
+    cpd::launch_core<T>(g, st, S, R, extrap, gate, q);
+    for (int n = 0; n < 3; ++n) {
+        if (n > 0) cpd::launch_prep<T>(g, st, S, R, n, gate, q);
+        cpd::launch_lra_c<T>(g, st, S, J, n, gate, q);
+        cpd::launch_update<T>(g, st, itu[n], (int)c->lists.u[n].size(), n, R, extrap, gate, c->lists.lds_rows[n], 1, q);
+        cpd::launch_lra_w<T>(g, st, S, J, n, 0, 0, gate, q);
+    }
     cpd::launch_finish<T>(g, st, S, R, first, gate, q);
 }
 
 template <typename T>
 void run_iteration(concpd_ctx c, const StateP<T>& st) {
-    run_sweep<T>(c, st, 1, 0, 1);
-    if (c->cfg.restart) run_sweep<T>(c, st, 0, 1, 0);
-    cpd::launch_commit<T>(c->dgeo, st, c->lay.uslot, c->S, c->Rq, c->R, c->q);
+    if (c->lra) {
+        run_sweep_lra<T>(c, st, 1, 0, 1);
+        if (c->cfg.restart) run_sweep_lra<T>(c, st, 0, 1, 0);
+    } else {
+        run_sweep<T>(c, st, 1, 0, 1);
+        if (c->cfg.restart) run_sweep<T>(c, st, 0, 1, 0);
+    }
+    cpd::launch_commit<T>(c->dgeo, st, c->lay.uslot, c->S, c->Rq, c->R, c->lra ? c->geo.wslot_len : 0, c->q);
 }
 
 // Grams, b, F and RelErr of the iterate in slot 1.
 template <typename T>
 void recompute_stats(concpd_ctx c, const StateP<T>& st) {
+    if (c->lra) {
+        // W of the iterate in both slots, then K3 = A_3 C_3 and the statistics
+        for (int n = 0; n < 3; ++n)
+            for (int slot = 0; slot < 2; ++slot) cpd::launch_lra_w<T>(c->dgeo, st, c->S, c->lay.Jmax, n, 1, slot, 0, c->q);
+        cpd::launch_lra_c<T>(c->dgeo, st, c->S, c->lay.Jmax, 2, 0, c->q);
+        for (int s = 0; s < c->S; ++s)
+            cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], c->R, st.K3 + c->geo.koff[s], c->Rq, 1, c->q);
+        cpd::launch_init_stats<T>(c->dgeo, st, c->S, c->R, c->q);
+        return;
+    }
     const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
     cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->lists.maxI2, c->q);
     for (int s = 0; s < c->S; ++s)
-        cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], c->R, st.K3 + c->geo.koff[s], c->Rq, c->q);
+        cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], c->R, st.K3 + c->geo.koff[s], c->Rq, 0, c->q);
     cpd::launch_init_stats<T>(c->dgeo, st, c->S, c->R, c->q);
 }
 
@@ -659,10 +748,52 @@ concpd_status concpd_fit(concpd_ctx c, concpd_stats* out) {
 }
 
 concpd_status lra_compress(concpd_ctx c, const int32_t* ranks, concpd_stats* out) {
-    (void)ranks;
-    (void)out;
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
-    return fail(CONCPD_ESTATE, "lra_compress: no Tucker ranks configured");
+    if (c->tucker.empty()) return fail(CONCPD_ESTATE, "lra_compress: no Tucker ranks configured");
+    if (ranks)
+        for (int i = 0; i < 3 * c->S; ++i)
+            if (ranks[i] < 1 || ranks[i] > c->tucker[i])
+                return fail(CONCPD_EINVAL, "ranks[%d] = %d not in [1, configured %d]", i, ranks[i], c->tucker[i]);
+    for (int s = 0; s < c->S; ++s)
+        for (int n = 0; n < 3; ++n) c->geo.J[s][n] = ranks ? ranks[3 * s + n] : c->tucker[3 * s + n];
+    double* L = (double*)(c->ws + c->lay.lra);
+    const Layout& P = c->lay;
+    double* scratch = (double*)(c->ws + c->lay.scratch);
+    HIPCHECK(hipMemcpyAsync(c->dgeo, &c->geo, sizeof(Geo), hipMemcpyHostToDevice, c->q));
+    // mode Grams of every block, then all leading-eigenvector problems at once
+    for (int s = 0; s < c->S; ++s) {
+        const int I[3] = {(int)c->dims[3 * s], (int)c->dims[3 * s + 1], (int)c->dims[3 * s + 2]};
+        const float* X = (const float*)c->tensors[s];
+        for (int n = 0; n < 3; ++n) {
+            cpd::launch_mode_gram(X, n, I[0], I[1], I[2], L + P.l_part, P.nsplit, c->q);
+            cpd::launch_sum_split(L + P.l_part, P.nsplit, (long long)I[n] * I[n], L + P.l_sig + (3LL * s + n) * P.sig_stride,
+                                  c->q);
+        }
+    }
+    cpd::launch_eig_top(c->dgeo, L, L + P.l_sig, P.sig_stride, L + P.l_work, P.work_stride, 3 * c->S, c->q);
+    for (int s = 0; s < c->S; ++s) {
+        const int I[3] = {(int)c->dims[3 * s], (int)c->dims[3 * s + 1], (int)c->dims[3 * s + 2]};
+        const float* X = (const float*)c->tensors[s];
+        cpd::launch_ttm_chain(X, I[0], I[1], I[2], L + c->geo.aoff[0][s], L + c->geo.aoff[1][s], L + c->geo.aoff[2][s],
+                              c->geo.J[s][0], c->geo.J[s][1], c->geo.J[s][2], L + P.l_t1, L + P.l_t2, L + c->geo.goff[s],
+                              c->q);
+        cpd::launch_sqnorm(L + c->geo.goff[s], CONCPD_F64, (long long)c->geo.J[s][0] * c->geo.J[s][1] * c->geo.J[s][2],
+                           (double*)(c->ws + c->lay.normM2) + s, scratch, 64, c->q);
+    }
+    c->geo.lra = 1;
+    c->lra = 1;
+    HIPCHECK(hipMemcpyAsync(c->dgeo, &c->geo, sizeof(Geo), hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    // statistics of the current iterate against the compressed blocks
+    Ctrl h;
+    HIPCHECK(hipMemcpy(&h, c->ctrl, sizeof h, hipMemcpyDeviceToHost));
+    h.stop = 0;
+    h.redo = 0;
+    HIPCHECK(hipMemcpy(c->ctrl, &h, sizeof h, hipMemcpyHostToDevice));
+    if (c->f64) recompute_stats<double>(c, c->sd);
+    else recompute_stats<float>(c, c->sf);
+    HIPCHECK(hipGetLastError());
+    return read_stats(c, out);
 }
 
 concpd_status lra_step(concpd_ctx c, int32_t n_iter, concpd_stats* out) {
@@ -717,6 +848,19 @@ concpd_status concpd_get_lambda(concpd_ctx c, int32_t s, double* dst) {
     if (s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "s out of range");
     HIPCHECK(hipMemcpyAsync(dst, c->ws + c->lay.lam[1] + sizeof(double) * s * c->Rq, sizeof(double) * c->R,
                             hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    return CONCPD_OK;
+}
+
+concpd_status lra_get_tucker(concpd_ctx c, int32_t s, int32_t n, double* dst) {
+    if (!c || !dst) return fail(CONCPD_EINVAL, "NULL argument");
+    if (s < 0 || s >= c->S || n < 0 || n > 3) return fail(CONCPD_EINVAL, "block or mode out of range");
+    if (!c->lra) return fail(CONCPD_ESTATE, "lra_get_tucker before lra_compress");
+    const double* L = (const double*)(c->ws + c->lay.lra);
+    const long long len = n < 3 ? c->dims[3 * s + n] * c->geo.J[s][n]
+                                : (long long)c->geo.J[s][0] * c->geo.J[s][1] * c->geo.J[s][2];
+    const double* src = L + (n < 3 ? c->geo.aoff[n][s] : c->geo.goff[s]);
+    HIPCHECK(hipMemcpyAsync(dst, src, sizeof(double) * len, hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipStreamSynchronize(c->q));
     return CONCPD_OK;
 }
@@ -784,10 +928,10 @@ concpd_status concpd_debug_mttkrp(concpd_ctx c, int32_t n, int32_t s, void* dev_
     const int I = (int)c->dims[3 * s + n];
     if (c->f64) {
         debug_passes<double>(c, c->sd);
-        cpd::launch_extract_k<double>(c->dgeo, c->sd, s, n, I, c->R, (double*)dev_out, c->R, c->q);
+        cpd::launch_extract_k<double>(c->dgeo, c->sd, s, n, I, c->R, (double*)dev_out, c->R, 0, c->q);
     } else {
         debug_passes<float>(c, c->sf);
-        cpd::launch_extract_k<float>(c->dgeo, c->sf, s, n, I, c->R, (float*)dev_out, c->R, c->q);
+        cpd::launch_extract_k<float>(c->dgeo, c->sf, s, n, I, c->R, (float*)dev_out, c->R, 0, c->q);
     }
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(c->q));

@@ -135,6 +135,23 @@ class CoupledCP:
         check(self._lib.lra_step(self.ctx, int(n_iter), ctypes.byref(st) if sync else None))
         return st.as_dict() if sync else None
 
+    def tucker(self, s: int):
+        """Compressed form of block s after lra_compress: ([A_1, A_2, A_3], G)."""
+        P = ctypes.POINTER(ctypes.c_double)
+        J = self._tucker_ranks(s)
+        A = []
+        for n in range(3):
+            a = np.empty((self.dims[s][n], J[n]), dtype=np.float64)
+            check(self._lib.lra_get_tucker(self.ctx, s, n, a.ctypes.data_as(P)))
+            A.append(a)
+        G = np.empty(tuple(J), dtype=np.float64)
+        check(self._lib.lra_get_tucker(self.ctx, s, 3, G.ctypes.data_as(P)))
+        return A, G
+
+    def _tucker_ranks(self, s: int):
+        src = getattr(self, "_ranks_c", None) or self._tucker_c
+        return [int(src[3 * s + n]) for n in range(3)]
+
     def stats(self) -> dict:
         return self.step(0)
 

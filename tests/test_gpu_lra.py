@@ -1,0 +1,250 @@
+"""Parity of the lra path (T-HOSVD compression + Tucker-form gradients) with
+the FP64 oracle, through the C ABI.
+
+Compression: the bases are compared as subspaces (projector distance) and,
+where the eigenvalue gaps are wide, column by column (the sign convention is
+fixed on both sides); the core G and the compressed tensor at 1e-9.
+Iterations: as the dense path (FP32 factors at 1e-5 per teacher-forced step).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import apg, tucker
+from oracle.apg import DenseData, Options, TuckerData
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = np.linalg.norm(b)
+    d = np.linalg.norm(a - b)
+    return d / n if n > 0 else d
+
+
+def make_model(P, U0, lam0, dev, ranks, **kw):
+    import torch
+    from paper_2302_05119_amd import CoupledCP
+    tens = [torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev) for X in P.tensors]
+    return CoupledCP(tens, P.R, P.L, compute="f32", init_U=U0, init_lambda=lam0, tucker_ranks=ranks, **kw)
+
+
+def reconstruct(G, A):
+    X = G
+    for n in range(3):
+        X = apg.mode_product(X, A[n], n)
+    return X
+
+
+def check_block(m, s, X, ranks, col_tol=None):
+    Gr, Ar, evr = tucker.thosvd(X, ranks)
+    Ag, Gg = m.tucker(s)
+    for n in range(3):
+        J = ranks[n]
+        orth = np.linalg.norm(Ag[n].T @ Ag[n] - np.eye(J))
+        dist = np.linalg.norm(Ag[n] @ Ag[n].T - Ar[n] @ Ar[n].T, 2)
+        ev = np.sort(np.linalg.eigvalsh(apg.unfold(X, n) @ apg.unfold(X, n).T))[::-1]
+        gap = (ev[J - 1] - ev[J]) / ev[0] if J < len(ev) else 1.0
+        say(f"   s={s} n={n} J={J} orth={orth:.1e} subspace={dist:.1e} boundary gap={gap:.1e}")
+        assert orth <= 1e-12
+        # the computed subspace is exact up to FP64 rounding over the gap
+        assert dist <= 1e-13 / max(gap, 1e-12) + 1e-12
+        if col_tol is not None:
+            assert rel(Ag[n], Ar[n]) <= col_tol
+    Xg = reconstruct(Gg, Ag)
+    Xr = reconstruct(Gr, Ar)
+    e = rel(Xg, Xr)
+    say(f"   s={s} ||X~gpu - X~oracle|| / ||X~|| = {e:.2e}")
+    assert e <= 1e-9
+    return Ag, Gg
+
+
+COMPRESS_CASES = [
+    # dims per block, ranks: several Gram tiles and ragged tails; J = I (full);
+    # J = 1; a 300-long mode (4 full tiles + 44)
+    ([(40, 50, 36), (40, 30, 36)], (8, 6, 7)),
+    ([(3, 65, 130)], (3, 10, 9)),
+    ([(70, 9, 11)], (1, 9, 4)),
+    ([(300, 12, 20)], (16, 12, 5)),
+]
+
+
+@pytest.mark.parametrize("dims,ranks", COMPRESS_CASES)
+def test_thosvd_matches_oracle(dev, dims, ranks):
+    say(f"[thosvd] dims={dims} ranks={ranks}")
+    R = 4
+    P = synth.coupled_problem(dims, R, (0, 0, 0), 10.0, 601, dtype=np.float32)
+    U0, lam0 = synth.uniform_init(P.dims, R, (0, 0, 0), 602)
+    m = make_model(P, U0, lam0, dev, ranks)
+    st = m.lra_compress()
+    assert st["lra"] == 1
+    for s in range(P.S):
+        check_block(m, s, P.tensors[s].astype(np.float64), ranks, col_tol=None)
+
+
+def test_thosvd_well_separated_columns_and_core(dev):
+    # rank-4 signal at 30 dB and J = 4: wide gaps, so columns and core are unique
+    say("[thosvd] columns and core")
+    P = synth.coupled_problem([(33, 41, 29)], 4, (0, 0, 0), 30.0, 611, dtype=np.float32)
+    U0, lam0 = synth.uniform_init(P.dims, 4, (0, 0, 0), 612)
+    m = make_model(P, U0, lam0, dev, (4, 4, 4))
+    m.lra_compress()
+    X = P.tensors[0].astype(np.float64)
+    Ag, Gg = check_block(m, 0, X, (4, 4, 4), col_tol=1e-9)
+    Gr, _, _ = tucker.thosvd(X, (4, 4, 4))
+    assert rel(Gg, Gr) <= 1e-9
+
+
+def test_thosvd_rank_deficient_and_zero(dev):
+    # noiseless rank 3 with J = 5: the extra directions span the (numerical)
+    # null space; X~ = X up to the FP32 rounding of the stored tensor, which is
+    # full-rank noise of relative size ~3e-8
+    import torch
+    from paper_2302_05119_amd import CoupledCP
+    say("[thosvd] rank-deficient")
+    P = synth.coupled_problem([(20, 24, 18)], 3, (0, 0, 0), None, 621, dtype=np.float32)
+    U0, lam0 = synth.uniform_init(P.dims, 3, (0, 0, 0), 622)
+    m = make_model(P, U0, lam0, dev, (5, 5, 5))
+    m.lra_compress()
+    A, G = m.tucker(0)
+    X = P.tensors[0].astype(np.float64)
+    e = rel(reconstruct(G, A), X)
+    Gr, Ar, _ = tucker.thosvd(X, (5, 5, 5))
+    er = rel(reconstruct(Gr, Ar), X)
+    say(f"   ||X~ - X|| / ||X|| gpu={e:.3e} oracle={er:.3e}")
+    assert e <= 1e-7 and abs(e - er) <= 0.1 * er
+    for n in range(3):
+        assert np.linalg.norm(A[n].T @ A[n] - np.eye(5)) <= 1e-12
+    # an all-zero block has no defined fit and is refused before any compression
+    from paper_2302_05119_amd._lib import ConcpdError
+    Z = torch.zeros((6, 7, 8), dtype=torch.float32, device=dev)
+    X1 = torch.from_numpy(P.tensors[0][:6, :7, :8].copy()).to(dev)
+    with pytest.raises(ConcpdError, match="identically zero"):
+        CoupledCP([X1, Z], 2, (0, 0, 0), seed=3, tucker_ranks=(2, 3, 2))
+
+
+def lra_teacher_forced(dev, P, R, L, ranks, k_before, seed):
+    U0, lam0 = synth.uniform_init(P.dims, R, L, seed)
+    cores, bases, _ = tucker.compress_all([X.astype(np.float64) for X in P.tensors], ranks)
+    data = TuckerData(cores, bases)
+    opt = Options(L=L)
+    st = apg.run(data, U0, lam0, opt, iters=k_before)
+    st.U = [[u.astype(np.float32).astype(np.float64) for u in per] for per in st.U]
+    st.U_prev = [[u.astype(np.float32).astype(np.float64) for u in per] for per in st.U_prev]
+    st.F = apg.objective(data, st.lam, st.U)
+    st.relerr = apg.relerr(data, st.lam, st.U)
+    m = make_model(P, st.U, st.lam, dev, ranks)
+    m.lra_compress()
+    Lu_prev = [[st.Lu_prev[n][s] for n in range(3)] for s in range(P.S)]
+    m.set_state(st.U, st.lam, st.U_prev, st.lam_prev, st.Ld_prev, Lu_prev, st.LC_prev, t=st.t, k=st.k)
+    s0 = m.stats()
+    new = apg.iterate(data, st, opt)
+    s1 = m.lra_step(1)
+    return m, data, st, new, s0, s1
+
+
+@pytest.mark.parametrize("k_before", [0, 3])
+def test_lra_one_iteration_teacher_forced(dev, k_before):
+    say(f"[lra step] k_before={k_before}")
+    L = (2, 0, 1)
+    P = synth.coupled_problem([(30, 40, 35), (30, 25, 35)], 5, L, 15.0, 631, dtype=np.float32)
+    ranks = (7, 6, 8)
+    m, data, st, new, s0, s1 = lra_teacher_forced(dev, P, 5, L, ranks, k_before, 632)
+    say(f"   F_prev gpu={s0['F']:.12e} oracle={st.F:.12e}; F gpu={s1['F']:.12e} oracle={new.F:.12e}")
+    assert abs(s0["F"] - st.F) / st.F <= 1e-5
+    assert abs(s1["F"] - new.F) / new.F <= 1e-5
+    assert bool(s1["restarted_last"]) == bool(new.last_restarted)
+    Ld, Lu, LC = m.lipschitz()
+    np.testing.assert_allclose(Ld, new.Ld_prev, rtol=1e-6)
+    for s in range(P.S):
+        np.testing.assert_allclose(Lu[s], [new.Lu_prev[n][s] for n in range(3)], rtol=1e-6)
+        assert rel(m.lam(s), new.lam[s]) <= 1e-5
+        for n in range(3):
+            e = rel(m.factor(n, s), new.U[n][s])
+            assert e <= 1e-5, (n, s, e)
+
+
+def test_lra_trajectory_and_global_fit(dev):
+    say("[lra] trajectory")
+    L = (3, 0, 0)
+    P = synth.coupled_problem([(40, 36, 44)] * 3, 6, L, 15.0, 641, dtype=np.float32)
+    ranks = (9, 9, 9)
+    U0, lam0 = synth.uniform_init(P.dims, 6, L, 642)
+    cores, bases, _ = tucker.compress_all([X.astype(np.float64) for X in P.tensors], ranks)
+    ref = apg.run(TuckerData(cores, bases), U0, lam0, Options(L=L), iters=40)
+    m = make_model(P, U0, lam0, dev, ranks)
+    m.lra_compress()
+    s = m.lra_step(40)
+    gf = m.global_fit()
+    rf = apg.fit(P.tensors, ref.lam, ref.U)
+    say(f"   fit(X~) gpu={s['fit']:.8f} oracle={1 - ref.relerr:.8f}; global gpu={gf:.8f} oracle={rf:.8f}")
+    assert s["k"] == 40
+    assert abs(s["fit"] - (1 - ref.relerr)) <= 1e-4
+    assert abs(gf - rf) <= 1e-4
+
+
+def test_lra_equals_dense_on_noiseless_data(dev):
+    # multilinear rank R <= J: the compression is exact, so the lra and dense
+    # iterations see the same tensor
+    say("[lra] noiseless lra == dense")
+    L = (2, 0, 0)
+    P = synth.coupled_problem([(25, 30, 28)] * 2, 4, L, None, 651, dtype=np.float32)
+    U0, lam0 = synth.uniform_init(P.dims, 4, L, 652)
+    md = make_model(P, U0, lam0, dev, (6, 6, 6))
+    ml = make_model(P, U0, lam0, dev, (6, 6, 6))
+    ml.lra_compress()
+    sd = md.step(25)
+    sl = ml.lra_step(25)
+    say(f"   F dense={sd['F']:.10e} lra={sl['F']:.10e}")
+    assert abs(sd["F"] - sl["F"]) <= 1e-5 * sd["F"]
+    for s in range(2):
+        for n in range(3):
+            assert rel(ml.factor(n, s), md.factor(n, s)) <= 1e-4
+
+
+def test_full_size_c3_compression_and_iteration(dev):
+    # 10 blocks of 256^3, R = 20, Tucker 30^3, 8 shared mode-1 columns, 20 dB
+    say("[c3 full] compression + teacher-forced lra iteration")
+    name = "c3_lra_10x256cube_r20"
+    w = synth.WORKLOADS[name]
+    P = synth.make_workload(name)
+    ranks = tuple(w["tucker"])
+    U0, lam0 = synth.workload_init(name, P)
+    m = make_model(P, U0, lam0, dev, ranks)
+    m.lra_compress()
+    for s in (0, P.S - 1):
+        check_block(m, s, P.tensors[s].astype(np.float64), ranks)
+    # one teacher-forced lra iteration against the oracle on the GPU's own
+    # compressed blocks (their parity is checked above)
+    cores, bases = [], []
+    for s in range(P.S):
+        A, G = m.tucker(s)
+        cores.append(G)
+        bases.append(A)
+    data = TuckerData(cores, bases)
+    opt = Options(L=w["L"])
+    U0r = [[u.astype(np.float32).astype(np.float64) for u in per] for per in U0]
+    st = apg.initial_state(data, U0r, lam0)
+    new = apg.iterate(data, st, opt)
+    s1 = m.lra_step(1)
+    say(f"   F gpu={s1['F']:.10e} oracle={new.F:.10e}")
+    assert abs(s1["F"] - new.F) / new.F <= 1e-5
+    for s in range(P.S):
+        assert rel(m.lam(s), new.lam[s]) <= 1e-5
+        for n in range(3):
+            assert rel(m.factor(n, s), new.U[n][s]) <= 1e-5
