@@ -51,13 +51,68 @@ def cpu_baseline(P, U0, lam0, budget_s=12.0):
             "sample": f"{n} oracle iterations (NumPy FP64) of the same 10x100^3 R=20 workload from the same init"}
 
 
+LRA_WORKLOAD = "c3_lra_10x256cube_r20"
+
+
+def lra_leg(steps: int, warmup: int):
+    """lraCoNCPD-APG on 10 blocks of 256^3 (Tucker 30^3): compression time and
+    iterations/s of the compressed iterations (step 2)."""
+    import torch
+
+    import synth
+    from paper_2302_05119_amd import CoupledCP
+
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS[LRA_WORKLOAD]
+    P = synth.make_workload(LRA_WORKLOAD)
+    U0, lam0 = synth.workload_init(LRA_WORKLOAD, P)
+    tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
+    del P
+    m = CoupledCP(tens, w["R"], w["L"], compute="f32", init_U=U0, init_lambda=lam0, tucker_ranks=w["tucker"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.lra_compress()
+    t1 = time.perf_counter()
+    m.lra_step(warmup, sync=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    m.lra_step(steps, sync=False)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    st = m.stats()
+    return {"workload": LRA_WORKLOAD, "compress_s": t1 - t0, "iter_per_s": steps / (t3 - t2), "steps": steps,
+            "warmup": warmup, "fit_compressed": st["fit"], "global_fit": m.global_fit(), "iterations": st["k"],
+            "restarts": st["restarts"]}
+
+
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
+    """Plain device copies of known size: the HBM byte counters read on these
+    calibrate the counters read on the path's kernels."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                                           "copies": reps}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lra-steps", type=int, default=300, help="iterations of the lra leg (0: skip it)")
+    ap.add_argument("--copy-calibration", action="store_true", help="only run the copy kernels used to "
+                    "calibrate HBM byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU path is a design, "
                                    "not built (see the design notes)", "n_gpus": args.gpus}))
@@ -131,6 +186,8 @@ def main():
         "fit": {"after_steps": st["fit"], "global": gfit, "initial": s_init["fit"], "restarts": st["restarts"],
                 "iterations": st["k"]},
     }
+    if args.lra_steps > 0:
+        out["lra"] = lra_leg(args.lra_steps, max(1, args.warmup // 2))
     if not args.no_cpu_baseline:
         U0r = [[m_u.astype(np.float32).astype(np.float64) for m_u in per] for per in U0]
         out["cpu_baseline"] = cpu_baseline(P, U0r, lam0)

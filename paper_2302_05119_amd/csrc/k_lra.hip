@@ -490,9 +490,9 @@ __global__ __launch_bounds__(256) void k_ttm1(const double* __restrict__ T2, int
 // ---------------------------------------------------------------------------
 // W_n^(s)[j][c] = sum_i A_n[i][j] U^(n,s)[i][c] for every block; one
 // workgroup per (block, j): 4 row phases x 64 columns, summed in fixed order.
-template <typename T>
-__global__ __launch_bounds__(256) void k_lra_w(const Geo* __restrict__ g, StateP<T> st, int n, int uslot, int wslot, int gate) {
-    if (gated_out(st.ctrl, gate)) return;
+template <typename T, int GATE>
+__global__ __launch_bounds__(256) void k_lra_w(const Geo* __restrict__ g, StateP<T> st, int n, int uslot, int wslot) {
+    if (gated_out(st.ctrl, GATE)) return;
     const int s = blockIdx.y, j = blockIdx.x;
     const int Jn = g->J[s][n];
     if (j >= Jn) return;
@@ -515,9 +515,9 @@ __global__ __launch_bounds__(256) void k_lra_w(const Geo* __restrict__ g, StateP
 // C_n^(s)[jn][c] = sum_{ja, jb} G_(n)[jn][(ja, jb)] W_a[ja][c] W_b[jb][c], where
 // (a, b) are the other two modes (W of modes before n from slot 0, after n
 // from slot 1).  One workgroup per (block, jn).
-template <typename T>
-__global__ __launch_bounds__(256) void k_lra_c(const Geo* __restrict__ g, StateP<T> st, int n, int gate) {
-    if (gated_out(st.ctrl, gate)) return;
+template <typename T, int GATE>
+__global__ __launch_bounds__(256) void k_lra_c(const Geo* __restrict__ g, StateP<T> st, int n) {
+    if (gated_out(st.ctrl, GATE)) return;
     const int s = blockIdx.y, jn = blockIdx.x;
     const int J0 = g->J[s][0], J1 = g->J[s][1], J2 = g->J[s][2];
     const int Jn = g->J[s][n];
@@ -580,11 +580,13 @@ void launch_ttm_chain(const float* M, int I1, int I2, int I3, const double* A1, 
 }
 template <typename T>
 void launch_lra_w(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int uslot, int wslot, int gate, hipStream_t q) {
-    hipLaunchKernelGGL(k_lra_w<T>, dim3(Jmax, S), dim3(256), 0, q, g, st, n, uslot, wslot, gate);
+    if (gate) hipLaunchKernelGGL((k_lra_w<T, 1>), dim3(Jmax, S), dim3(256), 0, q, g, st, n, uslot, wslot);
+    else hipLaunchKernelGGL((k_lra_w<T, 0>), dim3(Jmax, S), dim3(256), 0, q, g, st, n, uslot, wslot);
 }
 template <typename T>
 void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int gate, hipStream_t q) {
-    hipLaunchKernelGGL(k_lra_c<T>, dim3(Jmax, S), dim3(256), 0, q, g, st, n, gate);
+    if (gate) hipLaunchKernelGGL((k_lra_c<T, 1>), dim3(Jmax, S), dim3(256), 0, q, g, st, n);
+    else hipLaunchKernelGGL((k_lra_c<T, 0>), dim3(Jmax, S), dim3(256), 0, q, g, st, n);
 }
 template void launch_lra_w<float>(const Geo*, const StateP<float>&, int, int, int, int, int, int, hipStream_t);
 template void launch_lra_w<double>(const Geo*, const StateP<double>&, int, int, int, int, int, int, hipStream_t);

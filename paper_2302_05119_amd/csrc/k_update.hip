@@ -44,11 +44,11 @@ __device__ __forceinline__ double k_value(const Geo* __restrict__ g, const State
     return acc;
 }
 
-template <typename T, int KSRC>
+template <typename T, int KSRC, int GATE>
 __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, StateP<T> st, const ItemU* __restrict__ items,
-                                                int n, int extrapolate, int gate) {
+                                                int n, int extrapolate) {
     const Ctrl* c = st.ctrl;
-    if (gated_out(c, gate)) return;
+    if (gated_out(c, GATE)) return;
     const ItemU it = items[blockIdx.x];
     const int s0 = it.s0, ns = it.ns, row0 = it.row0, nrows = it.nrows;
     const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R, Ln = g->L[n];
@@ -137,23 +137,28 @@ void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, in
 template void launch_extract_k<float>(const Geo*, const StateP<float>&, int, int, int, int, float*, int, int, hipStream_t);
 template void launch_extract_k<double>(const Geo*, const StateP<double>&, int, int, int, int, double*, int, int, hipStream_t);
 
+template <typename T, int GATE>
+static void update_k(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int extrap, size_t lds, int lra,
+                     hipStream_t q) {
+    const int ks = lra ? KSRC_LRA0 + n : (n == 0 ? KSRC_K1P : (n == 1 ? KSRC_K2 : KSRC_PART));
+#define CPD_UPD(KS) \
+    case KS: hipLaunchKernelGGL((k_update<T, KS, GATE>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap); break;
+    switch (ks) {
+        CPD_UPD(KSRC_K1P) CPD_UPD(KSRC_K2) CPD_UPD(KSRC_PART) CPD_UPD(KSRC_LRA0) CPD_UPD(KSRC_LRA1) CPD_UPD(KSRC_LRA2)
+        default: break;
+    }
+#undef CPD_UPD
+}
+
 template <typename T>
 void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int gate,
                    int lds_rows, int lra, hipStream_t q) {
     if (nitems <= 0) return;
     // lds_rows = max over items of ns * nrows; the shared-gradient buffer uses at most as much
     const size_t lds = sizeof(double) * (size_t)lds_rows * (size_t)(2 * R);
-    if (lra) {
-        if (n == 0) hipLaunchKernelGGL((k_update<T, KSRC_LRA0>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
-        else if (n == 1) hipLaunchKernelGGL((k_update<T, KSRC_LRA1>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
-        else hipLaunchKernelGGL((k_update<T, KSRC_LRA2>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
-        return;
-    }
-    if (n == 0) hipLaunchKernelGGL((k_update<T, KSRC_K1P>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
-    else if (n == 1) hipLaunchKernelGGL((k_update<T, KSRC_K2>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
-    else hipLaunchKernelGGL((k_update<T, KSRC_PART>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap, gate);
+    if (gate) update_k<T, 1>(g, st, items, nitems, n, extrap, lds, lra, q);
+    else update_k<T, 0>(g, st, items, nitems, n, extrap, lds, lra, q);
 }
-
 template void launch_update<float>(const Geo*, const StateP<float>&, const ItemU*, int, int, int, int, int, int, int, hipStream_t);
 template void launch_update<double>(const Geo*, const StateP<double>&, const ItemU*, int, int, int, int, int, int, int, hipStream_t);
 
