@@ -114,11 +114,16 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors,
                           uint64_t seed, void* workspace, size_t ws_bytes, void* stream,
                           concpd_ctx* out);
 
-/* Run n_iter outer iterations of Algorithm 1 (each: the extrapolated sweep
+/* Run outer iterations of Algorithm 1 (each: the extrapolated sweep
  * D^(1..S), U^(1,1..S), ..., U^(3,1..S); if F_k >= F_{k-1} and restart is on,
  * the sweep is redone from x_{k-1} with zero extrapolation and accepted).
- * Asynchronous when out == NULL; with out != NULL it synchronises the stream
- * and fills *out.  After convergence (concpd_fit) further iterations are no-ops.
+ * Every decision is taken on the device, so a rejected sweep is simply
+ * followed by its redo in the next sweep launched.
+ * With out != NULL: exactly n_iter iterations are accepted (fewer once
+ * converged); synchronises the stream and fills *out.
+ * With out == NULL: asynchronous; queues n_iter sweeps, so each restart in
+ * them leaves one iteration fewer accepted (the stats give k).
+ * After convergence (concpd_fit) further sweeps are no-ops.
  * In lra mode (after lra_compress) the gradients use the compressed blocks.
  * Errors: EINVAL (n_iter < 0), EHIP. */
 concpd_status concpd_step(concpd_ctx ctx, int32_t n_iter, concpd_stats* out);

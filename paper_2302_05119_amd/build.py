@@ -18,7 +18,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libconcpd.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["runtime.cpp", "k_small.hip", "k_small_redo.hip", "k_mttkrp.hip", "k_mttkrp_redo.hip", "k_update.hip",
+SOURCES = ["runtime.cpp", "k_small.hip", "k_mttkrp.hip", "k_update.hip",
            "k_misc.hip", "k_lra.hip", "k_grad.hip"]
 ARCH = os.environ.get("CONCPD_ARCH", "gfx950")
 FLAGS = [

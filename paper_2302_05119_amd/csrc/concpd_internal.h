@@ -7,6 +7,8 @@
 #define CPD_MAXR 64   // components per block
 
 // Device-side control block: scalars of the outer iteration (Algorithm 1).
+#define CPD_K2ROWS 16   // i1 rows per mode-2 contraction chunk
+
 struct Ctrl {
     double t;          // t_{k-1} (Appendix A, parameter settings)
     double w_hat;      // w_hat_{k-1} = (t_{k-1} - 1) / t_k for the coming iteration
@@ -18,14 +20,14 @@ struct Ctrl {
     double delta_w;
     long long k;
     long long restarts;
-    int redo;          // set when F_k >= F_{k-1}: the gated sweep reruns without extrapolation
+    int rot3, rot2;    // slot rotation: factors/lambda (3 slots), Grams/b/W (2 slots)
+    int redo;          // set when F_k >= F_{k-1}: the next sweep redoes it from x_{k-1} without extrapolation
     int stop;          // converged: every later kernel is a no-op
     int last_restarted;
     int nonfinite;
     int restart_on;
     int reset_t;
     unsigned int counter_finish;   // arrival counters for last-workgroup reductions
-    unsigned int counter_commit;
     unsigned int counter_aux;
     int pad;
 };
@@ -49,7 +51,8 @@ struct Geo {
     long long coff[CPD_MAXS];     // C_n^(s) = G_(n) (⊙ W): Jmax x Rq (double)
     long long wslot_len;          // doubles per W slot (slot 1 follows slot 0)
     long long k1off[CPD_MAXS];    // mode-1 MTTKRP partials per 64-row group: I1 x nrg x Rq
-    long long k2off[CPD_MAXS];    // mode-2 MTTKRP: I2 x Rq
+    long long k2off[CPD_MAXS];    // mode-2 MTTKRP partials per chunk of CPD_K2ROWS i1 rows: nk2 x I2 x Rq
+    int nk2[CPD_MAXS];            // ceil(I1 / CPD_K2ROWS)
     int nrg[CPD_MAXS];            // ceil(I2 / 64)
     const void* M[CPD_MAXS];      // block tensors in the MTTKRP operand type
     int mdtype;                   // operand type of M (concpd_dtype)
@@ -84,19 +87,18 @@ struct StateP {
 struct ItemP1 { int s, i1, rg, pad; };              // pass 1: block, slab, 64-row group
 struct ItemP2 { int s, chunk, q0, pad; };           // pass 2: block, 4-slab chunk, i3 start
 struct ItemU  { int s0, ns, row0, nrows; };         // update: blocks [s0, s0+ns), rows
-struct ItemK2 { int s, row0, pad0, pad1; };         // mode-2 contraction: block, 64-row start
+struct ItemK2 { int s, col0, chunk, pad; };         // mode-2 contraction: block, column tile start, i1 chunk
 
 // Kernel launchers (defined in the .hip files).
 namespace cpd {
-template <typename T> void launch_core(const Geo* g, const StateP<T>& st, int S, int R, int extrap, int gate, hipStream_t q);
-template <typename T> void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, int gate, hipStream_t q);
-template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, int first_sweep, int gate, hipStream_t q);
-template <typename T> void launch_commit(const Geo* g, const StateP<T>& st, long long uslot, int S, int Rq, int R, long long wlen, hipStream_t q);
+template <typename T> void launch_core(const Geo* g, const StateP<T>& st, int S, int R, int extrap, hipStream_t q);
+template <typename T> void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, hipStream_t q);
+template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
 template <typename T> void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
-template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int Rq, int slot, int gate, int mdtype, hipStream_t q);
-template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int gate, int mdtype, int maxI2, hipStream_t q);
-template <typename T> void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, int gate, hipStream_t q);
-template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int gate, int lds_rows, int lra, hipStream_t q);
+template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int Rq, int slot, int mdtype, hipStream_t q);
+template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int mdtype, int maxI2, hipStream_t q);
+template <typename T> void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, hipStream_t q);
+template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int lds_rows, int lra, hipStream_t q);
 template <typename T> void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, int R, T* out, int ld_out, int lra, hipStream_t q);
 template <typename T> void launch_resid(const Geo* g, const StateP<T>& st, const void* M, int dtype, int s, int I1, double* part, hipStream_t q);
 void launch_sqnorm(const void* src, int dtype, long long n, double* out, double* part, int npart, hipStream_t q);
@@ -104,8 +106,8 @@ void launch_mode_gram(const float* X, int mode, int I1, int I2, int I3, double* 
 void launch_sum_split(const double* part, int nsplit, long long n, double* out, hipStream_t q);
 void launch_eig_top(const Geo* g, double* lra, double* sig, long long sig_stride, double* work, long long work_stride, int nmat, hipStream_t q);
 void launch_ttm_chain(const float* M, int I1, int I2, int I3, const double* A1, const double* A2, const double* A3, int J1, int J2, int J3, double* T1, double* T2, double* G, hipStream_t q);
-template <typename T> void launch_lra_w(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int uslot, int wslot, int gate, hipStream_t q);
-template <typename T> void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int gate, hipStream_t q);
+template <typename T> void launch_lra_w(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int uslot, int wslot, hipStream_t q);
+template <typename T> void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, hipStream_t q);
 void launch_sum_parts(const double* part, int np, double* out, hipStream_t q);
 void launch_convert(const void* src, int dst_dtype, void* dst, long long n, hipStream_t q);
 void launch_finite_check(const void* src, int dtype, long long n, int* flag, hipStream_t q);

@@ -490,15 +490,17 @@ __global__ __launch_bounds__(256) void k_ttm1(const double* __restrict__ T2, int
 // ---------------------------------------------------------------------------
 // W_n^(s)[j][c] = sum_i A_n[i][j] U^(n,s)[i][c] for every block; one
 // workgroup per (block, j): 4 row phases x 64 columns, summed in fixed order.
-template <typename T, int GATE>
+template <typename T>
 __global__ __launch_bounds__(256) void k_lra_w(const Geo* __restrict__ g, StateP<T> st, int n, int uslot, int wslot) {
-    if (gated_out(st.ctrl, GATE)) return;
+    if (st.ctrl->stop) return;
+    apply_rot(st);
+    wslot ^= st.ctrl->rot2;
     const int s = blockIdx.y, j = blockIdx.x;
     const int Jn = g->J[s][n];
     if (j >= Jn) return;
     const int I = g->I[s][n], Rq = g->Rq, R = g->R;
     const double* A = st.lra + g->aoff[n][s];
-    const T* U = st.U[uslot] + g->uoff[n][s];
+    const T* U = pick3(st.U, uslot) + g->uoff[n][s];
     __shared__ double part[4][64];
     const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
     double a = 0.0;
@@ -515,9 +517,10 @@ __global__ __launch_bounds__(256) void k_lra_w(const Geo* __restrict__ g, StateP
 // C_n^(s)[jn][c] = sum_{ja, jb} G_(n)[jn][(ja, jb)] W_a[ja][c] W_b[jb][c], where
 // (a, b) are the other two modes (W of modes before n from slot 0, after n
 // from slot 1).  One workgroup per (block, jn).
-template <typename T, int GATE>
+template <typename T>
 __global__ __launch_bounds__(256) void k_lra_c(const Geo* __restrict__ g, StateP<T> st, int n) {
-    if (gated_out(st.ctrl, GATE)) return;
+    if (st.ctrl->stop) return;
+    const int r2 = st.ctrl->rot2;
     const int s = blockIdx.y, jn = blockIdx.x;
     const int J0 = g->J[s][0], J1 = g->J[s][1], J2 = g->J[s][2];
     const int Jn = g->J[s][n];
@@ -526,8 +529,8 @@ __global__ __launch_bounds__(256) void k_lra_c(const Geo* __restrict__ g, StateP
     const int ma = (n == 0) ? 1 : 0, mb = (n == 2) ? 1 : 2;
     const int Ja = g->J[s][ma], Jb = g->J[s][mb];
     const long long wl = g->wslot_len;
-    const double* Wa = st.lra + g->woff[ma][s] + (ma < n ? 0 : wl);
-    const double* Wb = st.lra + g->woff[mb][s] + (mb < n ? 0 : wl);
+    const double* Wa = st.lra + g->woff[ma][s] + ((ma < n ? 0 : 1) ^ r2) * wl;
+    const double* Wb = st.lra + g->woff[mb][s] + ((mb < n ? 0 : 1) ^ r2) * wl;
     const double* G = st.lra + g->goff[s];
     __shared__ double part[4][64];
     const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
@@ -579,18 +582,16 @@ void launch_ttm_chain(const float* M, int I1, int I2, int I3, const double* A1, 
     hipLaunchKernelGGL(k_ttm1, dim3((unsigned)nb), dim3(256), 0, q, T2, I1, J2 * J3, A1, J1, G);
 }
 template <typename T>
-void launch_lra_w(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int uslot, int wslot, int gate, hipStream_t q) {
-    if (gate) hipLaunchKernelGGL((k_lra_w<T, 1>), dim3(Jmax, S), dim3(256), 0, q, g, st, n, uslot, wslot);
-    else hipLaunchKernelGGL((k_lra_w<T, 0>), dim3(Jmax, S), dim3(256), 0, q, g, st, n, uslot, wslot);
+void launch_lra_w(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int uslot, int wslot, hipStream_t q) {
+    hipLaunchKernelGGL(k_lra_w<T>, dim3(Jmax, S), dim3(256), 0, q, g, st, n, uslot, wslot);
 }
 template <typename T>
-void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int gate, hipStream_t q) {
-    if (gate) hipLaunchKernelGGL((k_lra_c<T, 1>), dim3(Jmax, S), dim3(256), 0, q, g, st, n);
-    else hipLaunchKernelGGL((k_lra_c<T, 0>), dim3(Jmax, S), dim3(256), 0, q, g, st, n);
+void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, hipStream_t q) {
+    hipLaunchKernelGGL(k_lra_c<T>, dim3(Jmax, S), dim3(256), 0, q, g, st, n);
 }
-template void launch_lra_w<float>(const Geo*, const StateP<float>&, int, int, int, int, int, int, hipStream_t);
-template void launch_lra_w<double>(const Geo*, const StateP<double>&, int, int, int, int, int, int, hipStream_t);
-template void launch_lra_c<float>(const Geo*, const StateP<float>&, int, int, int, int, hipStream_t);
-template void launch_lra_c<double>(const Geo*, const StateP<double>&, int, int, int, int, hipStream_t);
+template void launch_lra_w<float>(const Geo*, const StateP<float>&, int, int, int, int, int, hipStream_t);
+template void launch_lra_w<double>(const Geo*, const StateP<double>&, int, int, int, int, int, hipStream_t);
+template void launch_lra_c<float>(const Geo*, const StateP<float>&, int, int, int, hipStream_t);
+template void launch_lra_c<double>(const Geo*, const StateP<double>&, int, int, int, hipStream_t);
 
 }  // namespace cpd

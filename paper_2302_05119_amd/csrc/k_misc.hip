@@ -63,6 +63,7 @@ __global__ __launch_bounds__(256) void k_resid_slab(const Geo* __restrict__ g, S
                                                    double* __restrict__ part) {
     __shared__ double red[256];
     __shared__ double w[CPD_MAXR];
+    apply_rot(st);
     const int i1 = blockIdx.x;
     const int I2 = g->I[s][1], I3 = g->I[s][2], R = g->R, Rq = g->Rq;
     const T* U1 = st.U[1] + g->uoff[0][s] + (long long)i1 * Rq;

@@ -1,34 +1,90 @@
-// Launchers of the dense MTTKRP passes (kernels in mttkrp_kernels.h).  The
-// re-done sweep's instantiations (GATE = 1) live in k_mttkrp_redo.hip.
+// Launchers of the dense MTTKRP passes (kernels in mttkrp_kernels.h):
+// dispatch on the tensor operand type and on RT = Rq / 4.
 #include "mttkrp_kernels.h"
 
 namespace cpd {
 
-CPD_MTTKRP_IMPLS(extern template, 1)
-CPD_MTTKRP_IMPLS(template, 0)
+template <typename TM, typename T>
+static void pass1_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g, const StateP<T>& st, const ItemP1* items,
+                     int slot) {
+#define CPD_P1(RTV) \
+    case RTV: hipLaunchKernelGGL((k_pass1<TM, T, RTV>), grid, dim3(256), lds, q, g, st, items, slot); break;
+    switch (RT) {
+        CPD_P1(1) CPD_P1(2) CPD_P1(3) CPD_P1(4) CPD_P1(5) CPD_P1(6) CPD_P1(7) CPD_P1(8)
+        CPD_P1(9) CPD_P1(10) CPD_P1(11) CPD_P1(12) CPD_P1(13) CPD_P1(14) CPD_P1(15) CPD_P1(16)
+        default: break;
+    }
+#undef CPD_P1
+}
+template <typename TM, typename T, bool BLDS>
+static void pass2_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g, const StateP<T>& st, const ItemP2* items,
+                     int slot) {
+#define CPD_P2(RTV) \
+    case RTV: hipLaunchKernelGGL((k_pass2<TM, T, RTV, BLDS>), grid, dim3(256), lds, q, g, st, items, slot); break;
+    switch (RT) {
+        CPD_P2(1) CPD_P2(2) CPD_P2(3) CPD_P2(4) CPD_P2(5) CPD_P2(6) CPD_P2(7) CPD_P2(8)
+        CPD_P2(9) CPD_P2(10) CPD_P2(11) CPD_P2(12) CPD_P2(13) CPD_P2(14) CPD_P2(15) CPD_P2(16)
+        default: break;
+    }
+#undef CPD_P2
+}
+
+template <typename TA>
+static size_t pass1_lds(int Rq) {
+    size_t a = sizeof(TA) * 4 * 64 * (size_t)P1Shape<TA>::STRIDE, b = sizeof(TA) * 4 * 64 * (size_t)Rq;
+    return a > b ? a : b;
+}
+
+template <typename TM, typename T>
+static void pass2_dispatch(int Rq, dim3 grid, int maxI2, hipStream_t q, const Geo* g, const StateP<T>& st,
+                           const ItemP2* items, int slot) {
+    typedef typename AccType<TM>::type TA;
+    const size_t red = sizeof(TA) * 4 * 64 * (size_t)Rq;
+    const size_t bst = sizeof(TA) * (size_t)maxI2 * Rq;
+    if (bst <= 49152) pass2_rt<TM, T, true>(Rq / 4, grid, bst > red ? bst : red, q, g, st, items, slot);
+    else pass2_rt<TM, T, false>(Rq / 4, grid, red, q, g, st, items, slot);
+}
 
 template <typename T>
-void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int Rq, int slot, int gate, int mdtype,
+void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int Rq, int slot, int mdtype,
                   hipStream_t q) {
-    if (gate) pass1_impl<1, T>(g, st, items, nitems, Rq, slot, mdtype, q);
-    else pass1_impl<0, T>(g, st, items, nitems, Rq, slot, mdtype, q);
+    if (nitems <= 0) return;
+    const dim3 grid(nitems);
+    if constexpr (std::is_same<T, double>::value) {
+        pass1_rt<double, double>(Rq / 4, grid, pass1_lds<double>(Rq), q, g, st, items, slot);
+    } else {
+        const size_t lds = pass1_lds<float>(Rq);
+        if (mdtype == 1) pass1_rt<float, float>(Rq / 4, grid, lds, q, g, st, items, slot);
+        else if (mdtype == 2) pass1_rt<__hip_bfloat16, float>(Rq / 4, grid, lds, q, g, st, items, slot);
+        else pass1_rt<__half, float>(Rq / 4, grid, lds, q, g, st, items, slot);
+    }
 }
+
 template <typename T>
-void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int gate, int mdtype,
-                  int maxI2, hipStream_t q) {
-    if (gate) pass2_impl<1, T>(g, st, items, nitems, Rq, slot, mdtype, maxI2, q);
-    else pass2_impl<0, T>(g, st, items, nitems, Rq, slot, mdtype, maxI2, q);
+void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int mdtype, int maxI2,
+                  hipStream_t q) {
+    if (nitems <= 0) return;
+    const dim3 grid(nitems);
+    if constexpr (std::is_same<T, double>::value) {
+        pass2_dispatch<double, double>(Rq, grid, maxI2, q, g, st, items, slot);
+    } else {
+        if (mdtype == 1) pass2_dispatch<float, float>(Rq, grid, maxI2, q, g, st, items, slot);
+        else if (mdtype == 2) pass2_dispatch<__hip_bfloat16, float>(Rq, grid, maxI2, q, g, st, items, slot);
+        else pass2_dispatch<__half, float>(Rq, grid, maxI2, q, g, st, items, slot);
+    }
 }
+
 template <typename T>
-void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, int gate, hipStream_t q) {
-    if (gate) k2_impl<1, T>(g, st, items, nitems, slot, q);
-    else k2_impl<0, T>(g, st, items, nitems, slot, q);
+void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, hipStream_t q) {
+    if (nitems <= 0) return;
+    hipLaunchKernelGGL(k_k2<T>, dim3(nitems), dim3(256), 0, q, g, st, items, slot);
 }
-template void launch_pass1<float>(const Geo*, const StateP<float>&, const ItemP1*, int, int, int, int, int, hipStream_t);
-template void launch_pass1<double>(const Geo*, const StateP<double>&, const ItemP1*, int, int, int, int, int, hipStream_t);
-template void launch_pass2<float>(const Geo*, const StateP<float>&, const ItemP2*, int, int, int, int, int, int, hipStream_t);
-template void launch_pass2<double>(const Geo*, const StateP<double>&, const ItemP2*, int, int, int, int, int, int, hipStream_t);
-template void launch_k2<float>(const Geo*, const StateP<float>&, const ItemK2*, int, int, int, hipStream_t);
-template void launch_k2<double>(const Geo*, const StateP<double>&, const ItemK2*, int, int, int, hipStream_t);
+
+template void launch_pass1<float>(const Geo*, const StateP<float>&, const ItemP1*, int, int, int, int, hipStream_t);
+template void launch_pass1<double>(const Geo*, const StateP<double>&, const ItemP1*, int, int, int, int, hipStream_t);
+template void launch_pass2<float>(const Geo*, const StateP<float>&, const ItemP2*, int, int, int, int, int, hipStream_t);
+template void launch_pass2<double>(const Geo*, const StateP<double>&, const ItemP2*, int, int, int, int, int, hipStream_t);
+template void launch_k2<float>(const Geo*, const StateP<float>&, const ItemK2*, int, int, hipStream_t);
+template void launch_k2<double>(const Geo*, const StateP<double>&, const ItemK2*, int, int, hipStream_t);
 
 }  // namespace cpd

@@ -27,7 +27,10 @@ __device__ __forceinline__ double k_value(const Geo* __restrict__ g, const State
         const T* p = st.K1p + g->k1off[s] + (long long)i * nrg * Rq + col;
         for (int r = 0; r < nrg; ++r) acc += (double)p[r * Rq];
     } else if (KSRC == KSRC_K2) {
-        acc = (double)st.K2[g->k2off[s] + (long long)i * Rq + col];
+        const int nk = g->nk2[s];
+        const long long ps = (long long)g->I[s][1] * Rq;
+        const T* p = st.K2 + g->k2off[s] + (long long)i * Rq + col;
+        for (int ch = 0; ch < nk; ++ch) acc += (double)p[ch * ps];
     } else if (KSRC >= KSRC_LRA0) {
         // Tucker form: K_n[i][col] = sum_j A_n[i][j] C_n[j][col]
         const int n = KSRC - KSRC_LRA0, Jn = g->J[s][n];
@@ -44,11 +47,13 @@ __device__ __forceinline__ double k_value(const Geo* __restrict__ g, const State
     return acc;
 }
 
-template <typename T, int KSRC, int GATE>
+template <typename T, int KSRC>
 __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, StateP<T> st, const ItemU* __restrict__ items,
                                                 int n, int extrapolate) {
     const Ctrl* c = st.ctrl;
-    if (gated_out(c, GATE)) return;
+    if (c->stop) return;
+    apply_rot(st);
+    extrapolate = extrapolating(c, extrapolate);
     const ItemU it = items[blockIdx.x];
     const int s0 = it.s0, ns = it.ns, row0 = it.row0, nrows = it.nrows;
     const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R, Ln = g->L[n];
@@ -137,29 +142,22 @@ void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, in
 template void launch_extract_k<float>(const Geo*, const StateP<float>&, int, int, int, int, float*, int, int, hipStream_t);
 template void launch_extract_k<double>(const Geo*, const StateP<double>&, int, int, int, int, double*, int, int, hipStream_t);
 
-template <typename T, int GATE>
-static void update_k(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int extrap, size_t lds, int lra,
-                     hipStream_t q) {
+template <typename T>
+void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int lds_rows,
+                   int lra, hipStream_t q) {
+    if (nitems <= 0) return;
+    // lds_rows = max over items of ns * nrows; the shared-gradient buffer uses at most as much
+    const size_t lds = sizeof(double) * (size_t)lds_rows * (size_t)(2 * R);
     const int ks = lra ? KSRC_LRA0 + n : (n == 0 ? KSRC_K1P : (n == 1 ? KSRC_K2 : KSRC_PART));
 #define CPD_UPD(KS) \
-    case KS: hipLaunchKernelGGL((k_update<T, KS, GATE>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap); break;
+    case KS: hipLaunchKernelGGL((k_update<T, KS>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap); break;
     switch (ks) {
         CPD_UPD(KSRC_K1P) CPD_UPD(KSRC_K2) CPD_UPD(KSRC_PART) CPD_UPD(KSRC_LRA0) CPD_UPD(KSRC_LRA1) CPD_UPD(KSRC_LRA2)
         default: break;
     }
 #undef CPD_UPD
 }
-
-template <typename T>
-void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int gate,
-                   int lds_rows, int lra, hipStream_t q) {
-    if (nitems <= 0) return;
-    // lds_rows = max over items of ns * nrows; the shared-gradient buffer uses at most as much
-    const size_t lds = sizeof(double) * (size_t)lds_rows * (size_t)(2 * R);
-    if (gate) update_k<T, 1>(g, st, items, nitems, n, extrap, lds, lra, q);
-    else update_k<T, 0>(g, st, items, nitems, n, extrap, lds, lra, q);
-}
-template void launch_update<float>(const Geo*, const StateP<float>&, const ItemU*, int, int, int, int, int, int, int, hipStream_t);
-template void launch_update<double>(const Geo*, const StateP<double>&, const ItemU*, int, int, int, int, int, int, int, hipStream_t);
+template void launch_update<float>(const Geo*, const StateP<float>&, const ItemU*, int, int, int, int, int, int, hipStream_t);
+template void launch_update<double>(const Geo*, const StateP<double>&, const ItemU*, int, int, int, int, int, int, hipStream_t);
 
 }  // namespace cpd

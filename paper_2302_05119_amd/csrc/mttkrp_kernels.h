@@ -70,11 +70,12 @@ template <> struct P1Shape<double> { static constexpr int KC = 16, STRIDE = 17; 
 // wavefronts split the i3 range and are summed in LDS.  Tiles are staged with
 // every load of a tile in flight before the first LDS store.
 // ---------------------------------------------------------------------------
-template <typename TM, typename T, int RT, int GATE>
+template <typename TM, typename T, int RT>
 __global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP<T> st, const ItemP1* __restrict__ items,
                                                int slot) {
     typedef typename AccType<TM>::type TA;
-    if (gated_out(st.ctrl, GATE)) return;
+    if (st.ctrl->stop) return;
+    apply_rot(st);
     extern __shared__ char smraw[];
     const ItemP1 it = items[blockIdx.x];
     const int s = it.s, i1 = it.i1, rg = it.rg, row0 = rg * 64;
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP
     const int nrows = min(64, I2 - row0);
     typedef typename Raw<TM>::type TR;
     const CPD_GLOBAL TR* __restrict__ Ms = gptr((const TR*)g->M[s] + ((long long)i1 * I2 + row0) * I3);
-    const CPD_GLOBAL T* __restrict__ U3 = gptr(st.U[slot] + g->uoff[2][s]);
+    const CPD_GLOBAL T* __restrict__ U3 = gptr(pick3(st.U, slot) + g->uoff[2][s]);
     TA* sm = (TA*)smraw;
     constexpr int KC = P1Shape<TA>::KC, STRIDE = P1Shape<TA>::STRIDE, RPI = 64 / KC;
     TA* stage = sm + wave * 64 * STRIDE;
@@ -152,11 +153,12 @@ __global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP
 // index), so every tensor load is a coalesced 64-element row segment; NB rows
 // are loaded ahead of the matrix-core work.  U2 is staged in LDS when it fits.
 // ---------------------------------------------------------------------------
-template <typename TM, typename T, int RT, bool BLDS, int GATE>
+template <typename TM, typename T, int RT, bool BLDS>
 __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP<T> st, const ItemP2* __restrict__ items,
                                                int slot) {
     typedef typename AccType<TM>::type TA;
-    if (gated_out(st.ctrl, GATE)) return;
+    if (st.ctrl->stop) return;
+    apply_rot(st);
     extern __shared__ char smraw[];
     const ItemP2 it = items[blockIdx.x];
     const int s = it.s, chunk = it.chunk, q0 = it.q0;
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
     const int i3 = q0 + lane;
     const bool valid = i3 < I3;
     TA* sm = (TA*)smraw;
-    const CPD_GLOBAL T* __restrict__ U2g = gptr(st.U[slot] + g->uoff[1][s]);
+    const CPD_GLOBAL T* __restrict__ U2g = gptr(pick3(st.U, slot) + g->uoff[1][s]);
     if (BLDS) {
         for (int e = threadIdx.x; e < I2 * Rq; e += 256) sm[e] = (TA)U2g[e];
         __syncthreads();
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
 #pragma unroll
             for (int j = 0; j < NB; ++j) cur[j] = nxt[j];
         }
-        const CPD_GLOBAL T* __restrict__ U1 = gptr(st.U[slot] + g->uoff[0][s] + (long long)i1 * Rq + (lane & 3));
+        const CPD_GLOBAL T* __restrict__ U1 = gptr(pick3(st.U, slot) + g->uoff[0][s] + (long long)i1 * Rq + (lane & 3));
 #pragma unroll
         for (int t = 0; t < RT; ++t) z[t].scale((TA)U1[4 * t]);
     }
@@ -224,128 +226,35 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
 }
 
 // ---------------------------------------------------------------------------
-// mode-2 contraction K2[i2][c] = sum_i1 Y[i1][i2][c] U1[i1][c] (FP64 sums):
-// one workgroup per (block, 64 rows of i2).  Four thread groups take
-// interleaved quarters of i1 with all their loads in flight, then the
-// quarters are added in fixed order.
+// mode 2: K2[i2][r] = sum_i1 Y[i1][i2][r] U1[i1][r] with the new U^(1).  One
+// thread per element e = i2*Rq + r of a 256-wide column tile, one workgroup
+// per (block, tile, chunk of CPD_K2ROWS rows of i1); every Y load is a
+// coalesced row segment.  Chunk partials are summed in fixed order by the
+// factor update.
 // ---------------------------------------------------------------------------
-template <typename T, int GATE>
+template <typename T>
 __global__ __launch_bounds__(256) void k_k2(const Geo* __restrict__ g, StateP<T> st, const ItemK2* __restrict__ items, int slot) {
-    if (gated_out(st.ctrl, GATE)) return;
-    __shared__ double part[4][256];
+    if (st.ctrl->stop) return;
+    apply_rot(st);
     const ItemK2 it = items[blockIdx.x];
-    const int s = it.s, row0 = it.row0;
-    const int I1 = g->I[s][0], I2 = g->I[s][1], Rq = g->Rq;
-    const int nrows = min(64, I2 - row0);
-    const CPD_GLOBAL T* __restrict__ U1 = gptr(st.U[slot] + g->uoff[0][s]);
-    const CPD_GLOBAL T* __restrict__ Y = gptr(st.Y + g->yoff[s] + (long long)row0 * Rq);
+    const int s = it.s, Rq = g->Rq;
+    const int I1 = g->I[s][0], I2 = g->I[s][1];
     const long long ys = (long long)I2 * Rq;
-    const int grp = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    const int nout = nrows * Rq;
-    for (int e0 = 0; e0 < nout; e0 += 64) {
-        const int e = e0 + ln;
-        const int c = e % Rq;
-        double a = 0.0;
-        if (e < nout) {
-#pragma unroll 8
-            for (int i1 = grp; i1 < I1; i1 += 4) a += (double)Y[i1 * ys + e] * (double)U1[(long long)i1 * Rq + c];
-        }
-        part[grp][ln] = a;
-        __syncthreads();
-        if (grp == 0 && e < nout)
-            gptr_w(st.K2)[g->k2off[s] + (long long)row0 * Rq + e] = (T)(part[0][ln] + part[1][ln] + part[2][ln] + part[3][ln]);
-        __syncthreads();
+    const int e = it.col0 + (int)threadIdx.x;
+    if (e >= ys) return;
+    const int c = e % Rq;
+    const int i1a = it.chunk * CPD_K2ROWS, i1b = min(I1, i1a + CPD_K2ROWS);
+    const CPD_GLOBAL T* __restrict__ Y = gptr(st.Y + g->yoff[s] + e);
+    const CPD_GLOBAL T* __restrict__ U1 = gptr(pick3(st.U, slot) + g->uoff[0][s] + c);
+    T a0 = 0, a1 = 0;
+    int i1 = i1a;
+#pragma unroll 4
+    for (; i1 + 1 < i1b; i1 += 2) {
+        a0 += Y[i1 * ys] * U1[(long long)i1 * Rq];
+        a1 += Y[(i1 + 1) * ys] * U1[(long long)(i1 + 1) * Rq];
     }
+    if (i1 < i1b) a0 += Y[i1 * ys] * U1[(long long)i1 * Rq];
+    gptr_w(st.K2)[g->k2off[s] + (long long)it.chunk * ys + e] = a0 + a1;
 }
-
-// ---------------------------------------------------------------------------
-// launch templates: dispatch on the tensor operand type and on RT = Rq / 4.
-// GATE = 1 instantiates the kernels of the re-done sweep (distinct symbols,
-// built in their own translation unit).
-// ---------------------------------------------------------------------------
-template <int GATE, typename TM, typename T>
-static void pass1_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g, const StateP<T>& st, const ItemP1* items,
-                     int slot) {
-#define CPD_P1(RTV) \
-    case RTV: hipLaunchKernelGGL((k_pass1<TM, T, RTV, GATE>), grid, dim3(256), lds, q, g, st, items, slot); break;
-    switch (RT) {
-        CPD_P1(1) CPD_P1(2) CPD_P1(3) CPD_P1(4) CPD_P1(5) CPD_P1(6) CPD_P1(7) CPD_P1(8)
-        CPD_P1(9) CPD_P1(10) CPD_P1(11) CPD_P1(12) CPD_P1(13) CPD_P1(14) CPD_P1(15) CPD_P1(16)
-        default: break;
-    }
-#undef CPD_P1
-}
-template <int GATE, typename TM, typename T, bool BLDS>
-static void pass2_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g, const StateP<T>& st, const ItemP2* items,
-                     int slot) {
-#define CPD_P2(RTV) \
-    case RTV: hipLaunchKernelGGL((k_pass2<TM, T, RTV, BLDS, GATE>), grid, dim3(256), lds, q, g, st, items, slot); break;
-    switch (RT) {
-        CPD_P2(1) CPD_P2(2) CPD_P2(3) CPD_P2(4) CPD_P2(5) CPD_P2(6) CPD_P2(7) CPD_P2(8)
-        CPD_P2(9) CPD_P2(10) CPD_P2(11) CPD_P2(12) CPD_P2(13) CPD_P2(14) CPD_P2(15) CPD_P2(16)
-        default: break;
-    }
-#undef CPD_P2
-}
-
-template <typename TA>
-static size_t pass1_lds(int Rq) {
-    size_t a = sizeof(TA) * 4 * 64 * (size_t)P1Shape<TA>::STRIDE, b = sizeof(TA) * 4 * 64 * (size_t)Rq;
-    return a > b ? a : b;
-}
-
-template <int GATE, typename TM, typename T>
-static void pass2_dispatch(int Rq, dim3 grid, int maxI2, hipStream_t q, const Geo* g, const StateP<T>& st,
-                           const ItemP2* items, int slot) {
-    typedef typename AccType<TM>::type TA;
-    const size_t red = sizeof(TA) * 4 * 64 * (size_t)Rq;
-    const size_t bst = sizeof(TA) * (size_t)maxI2 * Rq;
-    if (bst <= 49152) pass2_rt<GATE, TM, T, true>(Rq / 4, grid, bst > red ? bst : red, q, g, st, items, slot);
-    else pass2_rt<GATE, TM, T, false>(Rq / 4, grid, red, q, g, st, items, slot);
-}
-
-template <int GATE, typename T>
-void pass1_impl(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int Rq, int slot, int mdtype,
-                hipStream_t q) {
-    if (nitems <= 0) return;
-    const dim3 grid(nitems);
-    if constexpr (std::is_same<T, double>::value) {
-        pass1_rt<GATE, double, double>(Rq / 4, grid, pass1_lds<double>(Rq), q, g, st, items, slot);
-    } else {
-        const size_t lds = pass1_lds<float>(Rq);
-        if (mdtype == 1) pass1_rt<GATE, float, float>(Rq / 4, grid, lds, q, g, st, items, slot);
-        else if (mdtype == 2) pass1_rt<GATE, __hip_bfloat16, float>(Rq / 4, grid, lds, q, g, st, items, slot);
-        else pass1_rt<GATE, __half, float>(Rq / 4, grid, lds, q, g, st, items, slot);
-    }
-}
-
-template <int GATE, typename T>
-void pass2_impl(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int mdtype, int maxI2,
-                hipStream_t q) {
-    if (nitems <= 0) return;
-    const dim3 grid(nitems);
-    if constexpr (std::is_same<T, double>::value) {
-        pass2_dispatch<GATE, double, double>(Rq, grid, maxI2, q, g, st, items, slot);
-    } else {
-        if (mdtype == 1) pass2_dispatch<GATE, float, float>(Rq, grid, maxI2, q, g, st, items, slot);
-        else if (mdtype == 2) pass2_dispatch<GATE, __hip_bfloat16, float>(Rq, grid, maxI2, q, g, st, items, slot);
-        else pass2_dispatch<GATE, __half, float>(Rq, grid, maxI2, q, g, st, items, slot);
-    }
-}
-
-template <int GATE, typename T>
-void k2_impl(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, hipStream_t q) {
-    if (nitems <= 0) return;
-    hipLaunchKernelGGL((k_k2<T, GATE>), dim3(nitems), dim3(256), 0, q, g, st, items, slot);
-}
-
-#define CPD_MTTKRP_IMPLS(SPEC, G)                                                                                        \
-    SPEC void pass1_impl<G, float>(const Geo*, const StateP<float>&, const ItemP1*, int, int, int, int, hipStream_t);      \
-    SPEC void pass1_impl<G, double>(const Geo*, const StateP<double>&, const ItemP1*, int, int, int, int, hipStream_t);    \
-    SPEC void pass2_impl<G, float>(const Geo*, const StateP<float>&, const ItemP2*, int, int, int, int, int, hipStream_t); \
-    SPEC void pass2_impl<G, double>(const Geo*, const StateP<double>&, const ItemP2*, int, int, int, int, int,           \
-                                    hipStream_t);                                                                      \
-    SPEC void k2_impl<G, float>(const Geo*, const StateP<float>&, const ItemK2*, int, int, hipStream_t);                  \
-    SPEC void k2_impl<G, double>(const Geo*, const StateP<double>&, const ItemK2*, int, int, hipStream_t);
 
 }  // namespace cpd

@@ -100,7 +100,7 @@ concpd_status validate(const concpd_config* c) {
 }
 
 void build_lists(const concpd_config* c, Lists* L) {
-    const int S = c->num_blocks, R = c->rank;
+    const int S = c->num_blocks, R = c->rank, Rq = (R + 3) / 4 * 4;
     L->p1.clear();
     L->p2.clear();
     L->k2.clear();
@@ -108,7 +108,8 @@ void build_lists(const concpd_config* c, Lists* L) {
     for (int s = 0; s < S; ++s) {
         const int I1 = (int)c->dims[3 * s], I2 = (int)c->dims[3 * s + 1], I3 = (int)c->dims[3 * s + 2];
         L->maxI2 = std::max(L->maxI2, I2);
-        for (int r0 = 0; r0 < I2; r0 += 64) L->k2.push_back({s, r0, 0, 0});
+        for (int ch = 0; ch * CPD_K2ROWS < I1; ++ch)
+            for (long long c0 = 0; c0 < (long long)I2 * Rq; c0 += 256) L->k2.push_back({s, (int)c0, ch, 0});
         for (int i1 = 0; i1 < I1; ++i1)
             for (int rg = 0; rg * 64 < I2; ++rg) L->p1.push_back({s, i1, rg, 0});
         for (int ch = 0; ch * 4 < I1; ++ch)
@@ -168,7 +169,8 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
         g->k1off[s] = k1;
         k1 += I1 * g->nrg[s] * Rq;
         g->k2off[s] = k2;
-        k2 += I2 * Rq;
+        g->nk2[s] = (int)((I1 + CPD_K2ROWS - 1) / CPD_K2ROWS);
+        k2 += g->nk2[s] * I2 * Rq;
     }
     P->uslot = u;
     P->ylen = y;
@@ -304,8 +306,21 @@ struct concpd_ctx_s {
     std::vector<double> normOrig;
     long long launched_iters;
     int profiling;
-    int fuse;  // run the small FP64 work inside the MTTKRP launches (CONCPD_NO_FUSE=1 turns it off)
+    // CONCPD_OVERLAP=1 runs the small FP64 kernels (core update, step
+    // matrices) on a second stream beside the MTTKRP passes they do not depend
+    // on.  Off by default: the cross-stream event waits cost more than the
+    // overlap gains at the benchmark sizes.
+    int overlap;
+    hipStream_t q2;
+    hipEvent_t fj[6];
     std::vector<hipEvent_t> ev1, ev2;  // begin/end pairs of timed pass launches
+    ~concpd_ctx_s() {
+        if (q2) {
+            (void)hipStreamSynchronize(q2);
+            for (int i = 0; i < 6; ++i) (void)hipEventDestroy(fj[i]);
+            (void)hipStreamDestroy(q2);
+        }
+    }
 };
 
 namespace {
@@ -335,8 +350,11 @@ StateP<T> make_state(char* ws, const Layout& P) {
     return st;
 }
 
+// One sweep of Algorithm 1 (extrapolated, or the redo of a rejected sweep:
+// the kernels read that from the control block).
 template <typename T>
-void run_sweep(concpd_ctx c, const StateP<T>& st, int extrap, int gate, int first) {
+void run_sweep(concpd_ctx c, const StateP<T>& st) {
+    const int extrap = 1;
     const Geo* g = c->dgeo;
     const int S = c->S, R = c->R, Rq = c->Rq;
     hipStream_t q = c->q;
@@ -345,24 +363,41 @@ void run_sweep(concpd_ctx c, const StateP<T>& st, int extrap, int gate, int firs
     const ItemK2* itk = (const ItemK2*)(c->ws + c->lay.itk2);
     const ItemU* itu[3];
     for (int n = 0; n < 3; ++n) itu[n] = (const ItemU*)(c->ws + c->lay.itu[n]);
-    const bool prof = c->profiling && gate == 0;
+    const bool prof = c->profiling;
     hipEvent_t e[4];
     if (prof)
         for (int i = 0; i < 4; ++i) (void)hipEventCreate(&e[i]);
+    // the second stream (if any) takes the small FP64 kernels
+    hipStream_t qa = c->overlap ? c->q2 : q;
+    auto fork = [&](int i) {
+        if (!c->overlap) return;
+        (void)hipEventRecord(c->fj[i], q);
+        (void)hipStreamWaitEvent(c->q2, c->fj[i], 0);
+    };
+    auto join = [&](int i) {
+        if (!c->overlap) return;
+        (void)hipEventRecord(c->fj[i], c->q2);
+        (void)hipStreamWaitEvent(q, c->fj[i], 0);
+    };
     // core update beside pass 1 (Y from the old U^(3), mode-1 partials)
-    cpd::launch_core<T>(g, st, S, R, extrap, gate, q);
+    fork(0);
+    cpd::launch_core<T>(g, st, S, R, extrap, qa);
     if (prof) (void)hipEventRecord(e[0], q);
-    cpd::launch_pass1<T>(g, st, it1, (int)c->lists.p1.size(), Rq, 1, gate, c->mdtype, q);
+    cpd::launch_pass1<T>(g, st, it1, (int)c->lists.p1.size(), Rq, 1, c->mdtype, q);
     if (prof) (void)hipEventRecord(e[1], q);
-    cpd::launch_update<T>(g, st, itu[0], (int)c->lists.u[0].size(), 0, R, extrap, gate, c->lists.lds_rows[0], 0, q);
+    join(1);
+    cpd::launch_update<T>(g, st, itu[0], (int)c->lists.u[0].size(), 0, R, extrap, c->lists.lds_rows[0], 0, q);
     // mode-2 step matrix beside the mode-2 contraction (new U^(1))
-    cpd::launch_prep<T>(g, st, S, R, 1, gate, q);
-    cpd::launch_k2<T>(g, st, itk, (int)c->lists.k2.size(), 0, gate, q);
-    cpd::launch_update<T>(g, st, itu[1], (int)c->lists.u[1].size(), 1, R, extrap, gate, c->lists.lds_rows[1], 0, q);
+    fork(2);
+    cpd::launch_prep<T>(g, st, S, R, 1, qa);
+    cpd::launch_k2<T>(g, st, itk, (int)c->lists.k2.size(), 0, q);
+    join(3);
+    cpd::launch_update<T>(g, st, itu[1], (int)c->lists.u[1].size(), 1, R, extrap, c->lists.lds_rows[1], 0, q);
     // mode-3 step matrix beside pass 2 (new U^(1), U^(2))
-    cpd::launch_prep<T>(g, st, S, R, 2, gate, q);
+    fork(4);
+    cpd::launch_prep<T>(g, st, S, R, 2, qa);
     if (prof) (void)hipEventRecord(e[2], q);
-    cpd::launch_pass2<T>(g, st, it2, (int)c->lists.p2.size(), Rq, 0, gate, c->mdtype, c->lists.maxI2, q);
+    cpd::launch_pass2<T>(g, st, it2, (int)c->lists.p2.size(), Rq, 0, c->mdtype, c->lists.maxI2, q);
     if (prof) {
         (void)hipEventRecord(e[3], q);
         c->ev1.push_back(e[0]);
@@ -370,38 +405,36 @@ void run_sweep(concpd_ctx c, const StateP<T>& st, int extrap, int gate, int firs
         c->ev2.push_back(e[2]);
         c->ev2.push_back(e[3]);
     }
-    cpd::launch_update<T>(g, st, itu[2], (int)c->lists.u[2].size(), 2, R, extrap, gate, c->lists.lds_rows[2], 0, q);
-    cpd::launch_finish<T>(g, st, S, R, first, gate, q);
+    join(5);
+    cpd::launch_update<T>(g, st, itu[2], (int)c->lists.u[2].size(), 2, R, extrap, c->lists.lds_rows[2], 0, q);
+    cpd::launch_finish<T>(g, st, S, R, q);
 }
 
 // The same sweep with the gradients taken from the Tucker form (Algorithm 2).
 template <typename T>
-void run_sweep_lra(concpd_ctx c, const StateP<T>& st, int extrap, int gate, int first) {
+void run_sweep_lra(concpd_ctx c, const StateP<T>& st) {
+    const int extrap = 1;
     const Geo* g = c->dgeo;
     const int S = c->S, R = c->R, J = c->lay.Jmax;
     hipStream_t q = c->q;
     const ItemU* itu[3];
     for (int n = 0; n < 3; ++n) itu[n] = (const ItemU*)(c->ws + c->lay.itu[n]);
-    cpd::launch_core<T>(g, st, S, R, extrap, gate, q);
+    cpd::launch_core<T>(g, st, S, R, extrap, q);
     for (int n = 0; n < 3; ++n) {
-        if (n > 0) cpd::launch_prep<T>(g, st, S, R, n, gate, q);
-        cpd::launch_lra_c<T>(g, st, S, J, n, gate, q);
-        cpd::launch_update<T>(g, st, itu[n], (int)c->lists.u[n].size(), n, R, extrap, gate, c->lists.lds_rows[n], 1, q);
-        cpd::launch_lra_w<T>(g, st, S, J, n, 0, 0, gate, q);
+        if (n > 0) cpd::launch_prep<T>(g, st, S, R, n, q);
+        cpd::launch_lra_c<T>(g, st, S, J, n, q);
+        cpd::launch_update<T>(g, st, itu[n], (int)c->lists.u[n].size(), n, R, extrap, c->lists.lds_rows[n], 1, q);
+        cpd::launch_lra_w<T>(g, st, S, J, n, 0, 0, q);
     }
-    cpd::launch_finish<T>(g, st, S, R, first, gate, q);
+    cpd::launch_finish<T>(g, st, S, R, q);
 }
 
+// One sweep: either an accepted iteration, or an extrapolated sweep that the
+// restart test rejects (then the next sweep redoes it and is accepted).
 template <typename T>
-void run_iteration(concpd_ctx c, const StateP<T>& st) {
-    if (c->lra) {
-        run_sweep_lra<T>(c, st, 1, 0, 1);
-        if (c->cfg.restart) run_sweep_lra<T>(c, st, 0, 1, 0);
-    } else {
-        run_sweep<T>(c, st, 1, 0, 1);
-        if (c->cfg.restart) run_sweep<T>(c, st, 0, 1, 0);
-    }
-    cpd::launch_commit<T>(c->dgeo, st, c->lay.uslot, c->S, c->Rq, c->R, c->lra ? c->geo.wslot_len : 0, c->q);
+void run_one_sweep(concpd_ctx c, const StateP<T>& st) {
+    if (c->lra) run_sweep_lra<T>(c, st);
+    else run_sweep<T>(c, st);
 }
 
 // Grams, b, F and RelErr of the iterate in slot 1.
@@ -410,18 +443,27 @@ void recompute_stats(concpd_ctx c, const StateP<T>& st) {
     if (c->lra) {
         // W of the iterate in both slots, then K3 = A_3 C_3 and the statistics
         for (int n = 0; n < 3; ++n)
-            for (int slot = 0; slot < 2; ++slot) cpd::launch_lra_w<T>(c->dgeo, st, c->S, c->lay.Jmax, n, 1, slot, 0, c->q);
-        cpd::launch_lra_c<T>(c->dgeo, st, c->S, c->lay.Jmax, 2, 0, c->q);
+            for (int slot = 0; slot < 2; ++slot) cpd::launch_lra_w<T>(c->dgeo, st, c->S, c->lay.Jmax, n, 1, slot, c->q);
+        cpd::launch_lra_c<T>(c->dgeo, st, c->S, c->lay.Jmax, 2, c->q);
         for (int s = 0; s < c->S; ++s)
             cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], c->R, st.K3 + c->geo.koff[s], c->Rq, 1, c->q);
         cpd::launch_init_stats<T>(c->dgeo, st, c->S, c->R, c->q);
         return;
     }
     const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
-    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->lists.maxI2, c->q);
+    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
     for (int s = 0; s < c->S; ++s)
         cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], c->R, st.K3 + c->geo.koff[s], c->Rq, 0, c->q);
     cpd::launch_init_stats<T>(c->dgeo, st, c->S, c->R, c->q);
+}
+
+// Physical slot of logical factor/lambda slot l (the device rotates slots;
+// synchronises the stream).
+int phys_slot3(concpd_ctx c, int l) {
+    int r3 = 0;
+    if (hipMemcpyAsync(&r3, &c->ctrl->rot3, sizeof r3, hipMemcpyDeviceToHost, c->q) != hipSuccess) return l;
+    if (hipStreamSynchronize(c->q) != hipSuccess) return l;
+    return (r3 + l) % 3;
 }
 
 concpd_status read_stats(concpd_ctx c, concpd_stats* out) {
@@ -527,9 +569,9 @@ void debug_passes(concpd_ctx c, const StateP<T>& st) {
     const ItemP1* it1 = (const ItemP1*)(c->ws + c->lay.it1);
     const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
     const ItemK2* itk = (const ItemK2*)(c->ws + c->lay.itk2);
-    cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->Rq, 1, 0, c->mdtype, c->q);
-    cpd::launch_k2<T>(c->dgeo, st, itk, (int)c->lists.k2.size(), 1, 0, c->q);
-    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, 0, c->mdtype, c->lists.maxI2, c->q);
+    cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->Rq, 1, c->mdtype, c->q);
+    cpd::launch_k2<T>(c->dgeo, st, itk, (int)c->lists.k2.size(), 1, c->q);
+    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
 }
 
 }  // namespace
@@ -586,8 +628,14 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
     c->launched_iters = 0;
     c->profiling = 0;
     {
-        const char* nf = getenv("CONCPD_NO_FUSE");
-        c->fuse = !(nf && nf[0] == '1');
+        const char* ov = getenv("CONCPD_OVERLAP");
+        c->overlap = ov && ov[0] == '1';
+        c->q2 = nullptr;
+        if (c->overlap) {
+            if (hipStreamCreateWithFlags(&c->q2, hipStreamNonBlocking) != hipSuccess) c->overlap = 0;
+            for (int i = 0; c->overlap && i < 6; ++i)
+                if (hipEventCreateWithFlags(&c->fj[i], hipEventDisableTiming) != hipSuccess) c->overlap = 0;
+        }
     }
     build_lists(&c->cfg, &c->lists);
     plan(&c->cfg, c->lists, &c->lay, &c->geo);
@@ -721,14 +769,35 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
 concpd_status concpd_step(concpd_ctx c, int32_t n_iter, concpd_stats* out) {
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
     if (n_iter < 0) return fail(CONCPD_EINVAL, "n_iter < 0");
-    for (int i = 0; i < n_iter; ++i) {
-        if (c->f64) run_iteration<double>(c, c->sd);
-        else run_iteration<float>(c, c->sf);
+    if (!out) {
+        // asynchronous: n_iter sweeps; a sweep rejected by the restart test
+        // is completed by the following one
+        for (int i = 0; i < n_iter; ++i) {
+            if (c->f64) run_one_sweep<double>(c, c->sd);
+            else run_one_sweep<float>(c, c->sf);
+        }
+        c->launched_iters += n_iter;
+        HIPCHECK(hipGetLastError());
+        return CONCPD_OK;
     }
-    c->launched_iters += n_iter;
-    HIPCHECK(hipGetLastError());
-    if (out) return read_stats(c, out);
-    return CONCPD_OK;
+    // synchronous: exactly n_iter accepted iterations (or until converged)
+    Ctrl h;
+    HIPCHECK(hipMemcpyAsync(&h, c->ctrl, sizeof h, hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    const long long target = h.k + n_iter;
+    long long todo = n_iter;
+    while (todo > 0 && !h.stop) {
+        for (long long i = 0; i < todo; ++i) {
+            if (c->f64) run_one_sweep<double>(c, c->sd);
+            else run_one_sweep<float>(c, c->sf);
+        }
+        c->launched_iters += todo;
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(&h, c->ctrl, sizeof h, hipMemcpyDeviceToHost, c->q));
+        HIPCHECK(hipStreamSynchronize(c->q));
+        todo = target - h.k;
+    }
+    return read_stats(c, out);
 }
 
 concpd_status concpd_fit(concpd_ctx c, concpd_stats* out) {
@@ -826,7 +895,7 @@ concpd_status concpd_get_factor(concpd_ctx c, int32_t n, int32_t s, double* dst)
     if (n < 0 || n > 2 || s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "n/s out of range");
     const int I = (int)c->dims[3 * s + n];
     const size_t cnt = (size_t)I * c->Rq;
-    const char* src = c->ws + c->lay.U[1] + (size_t)c->geo.uoff[n][s] * c->lay.esz;
+    const char* src = c->ws + c->lay.U[phys_slot3(c, 1)] + (size_t)c->geo.uoff[n][s] * c->lay.esz;
     if (c->f64) {
         std::vector<double> h(cnt);
         HIPCHECK(hipMemcpyAsync(h.data(), src, cnt * 8, hipMemcpyDeviceToHost, c->q));
@@ -846,7 +915,7 @@ concpd_status concpd_get_factor(concpd_ctx c, int32_t n, int32_t s, double* dst)
 concpd_status concpd_get_lambda(concpd_ctx c, int32_t s, double* dst) {
     if (!c || !dst) return fail(CONCPD_EINVAL, "NULL argument");
     if (s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "s out of range");
-    HIPCHECK(hipMemcpyAsync(dst, c->ws + c->lay.lam[1] + sizeof(double) * s * c->Rq, sizeof(double) * c->R,
+    HIPCHECK(hipMemcpyAsync(dst, c->ws + c->lay.lam[phys_slot3(c, 1)] + sizeof(double) * s * c->Rq, sizeof(double) * c->R,
                             hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipStreamSynchronize(c->q));
     return CONCPD_OK;

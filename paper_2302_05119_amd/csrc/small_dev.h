@@ -196,114 +196,160 @@ __device__ __forceinline__ double wave_sym_lmax_t(const double* __restrict__ A, 
     }
 }
 
-// Largest eigenvalue of an entrywise nonnegative symmetric n x n matrix A
-// (LDS, row stride ld), computed by the whole 256-thread workgroup.
-// Repeated squaring S <- S^2 (scaled by powers of two) turns
-// x = S 1 into the Perron vector of A; the Collatz-Wielandt bounds
-//     min_i (A x)_i / x_i  <=  lambda_max(A)  <=  max_i (A x)_i / x_i,
-// rigorous for any nonnegative A and positive x, then give lambda_max once
-// they agree to 1e-14.  Rows with a zero diagonal are zero rows of the PSD
-// matrix and are left out.  When the bounds do not close (tiny eigengap,
-// reducible pattern, a negative entry) the first wavefront falls back to
-// wave_sym_lmax_t.  Returns the same value to every thread.
-// work: 2 * n * ld + 576 doubles of LDS.
+// max_i S[i][i] for i < n (n <= NPM), every load in flight: indices past n
+// repeat the last diagonal entry.
+template <int NPM>
+__device__ __forceinline__ double diag_max(const double* __restrict__ S, int n, int ld) {
+    double m0 = 0.0, m1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NPM; i += 2) {
+        m0 = fmax(m0, S[min(i, n - 1) * (ld + 1)]);
+        m1 = fmax(m1, S[min(i + 1, n - 1) * (ld + 1)]);
+    }
+    return fmax(m0, m1);
+}
+
+// Squaring buffers of wg_lmax_nonneg: n padded to NP = 16 * ceil(n / 16),
+// row stride lp with 2 * lp = 32 (mod 64) dwords, so rows k and k+1 of a
+// matrix-core operand load fall in different LDS bank halves.
+__host__ __device__ inline int sq_np(int n) { return (n + 15) & ~15; }
+__host__ __device__ inline int sq_lp(int n) { return (sq_np(n) & 31) == 16 ? sq_np(n) : sq_np(n) + 16; }
+
+// Exact spectral norm of a nonnegative symmetric PSD matrix A (n x n, row
+// stride ld, in LDS), whole workgroup.  Repeated squaring S <- S^2 (with a
+// power-of-two rescaling from the largest diagonal entry, which bounds every
+// entry of a PSD matrix) drives S toward the leading eigenprojection; then
+// x = S 1 on the support (the rows with a positive diagonal) gives the
+// Collatz-Wielandt bounds min_i (Ax)_i / x_i <= lambda_max <= max_i (Ax)_i / x_i,
+// rigorous for a nonnegative matrix and a positive x, accepted once they agree
+// to 1e-14 relative.  The squarings run on the FP64 matrix cores: 16 x 16
+// output tiles (upper triangle, mirrored, so S stays exactly symmetric), one
+// tile per wavefront.  Negative or non-finite entries, n > 48, or bounds that
+// do not meet within 24 squarings go to the single-wave Lanczos + Sturm solver.
+// work: 2 * NP * lp + 576 doubles of LDS.
 template <int NMAX>
 __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, int n, int ld, double* __restrict__ work) {
+    constexpr int NPM = (NMAX + 15) & ~15;   // largest padded size of this instantiation
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int NP = sq_np(n), lp = sq_lp(n);
     double* __restrict__ S0 = work;
-    double* __restrict__ S1 = work + (NMAX <= 48 ? n * ld : 0);
-    double* __restrict__ xv = S1 + (NMAX <= 48 ? n * ld : 0);   // 64
-    double* __restrict__ red = xv + 64;       // 4 waves x 4
+    double* __restrict__ S1 = work + (NMAX <= 48 ? NP * lp : 0);
+    double* __restrict__ xv = S1 + (NMAX <= 48 ? NP * lp : 0);   // 64
+    double* __restrict__ red = xv + 64;       // 16
     double* __restrict__ res = red + 16;      // result broadcast
     double* __restrict__ wl = res + 16;       // fallback work (448)
-    // copy, check sign / finiteness, first scale
-    double mx = 0.0;
     int bad = 0;
-    for (int e = tid; e < n * n; e += 256) {
-        const double a = A[(e / n) * ld + e % n];
-        bad |= !(a >= 0.0) | !isfinite(a);
-        mx = fmax(mx, a);
-        if (NMAX <= 48) S0[(e / n) * ld + e % n] = a;
+    for (int e = tid; e < NP * NP; e += 256) {
+        const int i = e / NP, j = e % NP;
+        double v = 0.0;
+        if (i < n && j < n) {
+            v = A[i * ld + j];
+            bad |= !(v >= 0.0) | !isfinite(v);
+        }
+        if (NMAX <= 48) S0[i * lp + j] = v;
     }
-    mx = wave_max(mx);
     const int anybad = __syncthreads_or(bad);
-    if (lane == 0) red[wave] = mx;
-    __syncthreads();
-    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double dmax = diag_max<NPM>(A, n, ld);
     double result = 0.0;
     bool done = false;
-    if (!anybad && !(mx > 0.0)) {
+    if (!anybad && !(dmax > 0.0)) {
+        // a PSD matrix with a zero diagonal is zero
         result = 0.0;
         done = true;
     }
     if (NMAX <= 48 && !anybad && !done) {
-        int es = __builtin_amdgcn_frexp_exp(mx);  // S0 = A; entries scaled by 2^-es on read
+        int es = __builtin_amdgcn_frexp_exp(dmax);   // entries of Sa are read as Sa * 2^-es
+        const int nt = NP >> 4, ntile = nt * (nt + 1) / 2;
+        const int li = lane & 15, lk = lane >> 4;
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
         double* Sa = S0;
         double* Sb = S1;
         for (int it = 0; it < 24 && !done; ++it) {
-            // Sb = (Sa 2^-es)^2, the next scale exponent from its maximum
-            __syncthreads();
-            double m2 = 0.0;
-            for (int e = tid; e < n * n; e += 256) {
-                const int i = e / n, j = e % n;
-                if (j < i) continue;
-                const double* ri = Sa + i * ld;
-                const double* rj = Sa + j * ld;
-                double a0 = 0.0, a1 = 0.0;
-                int k = 0;
-                for (; k + 1 < n; k += 2) {
-                    a0 = fma(ri[k], rj[k], a0);
-                    a1 = fma(ri[k + 1], rj[k + 1], a1);
+            // Sb = (Sa 2^-es)^2, tile (ta, tb) on wavefront p % 4
+            for (int p = wv; p < ntile; p += 4) {
+                int ta = 0, rem = p;
+                while (rem >= nt - ta) {
+                    rem -= nt - ta;
+                    ++ta;
                 }
-                if (k < n) a0 = fma(ri[k], rj[k], a0);
-                const double v = ldexp(a0 + a1, -2 * es);
-                Sb[i * ld + j] = v;
-                Sb[j * ld + i] = v;
-                m2 = fmax(m2, v);
+                const int tb = ta + rem;
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
+                // all operand loads of the tile in flight; rows past NP read
+                // row NP-1 and are zeroed
+#pragma unroll
+                for (int k0 = 0; k0 < NPM; k0 += 4) {
+                    const double* rk = Sa + min(k0 + lk, NP - 1) * lp;
+                    const double a = rk[16 * ta + li], b = rk[16 * tb + li];
+                    const bool ok = k0 < NP;
+                    acc = mfma64(ok ? a : 0.0, ok ? b : 0.0, acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * ta + 4 * v + lk, c = 16 * tb + li;
+                    if (ta < tb || r <= c) {
+                        const double val = ldexp(acc[v], -2 * es);
+                        Sb[r * lp + c] = val;
+                        Sb[c * lp + r] = val;
+                    }
+                }
             }
-            m2 = wave_max(m2);
-            if (lane == 0) red[wave] = m2;
             __syncthreads();
-            m2 = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-            es = __builtin_amdgcn_frexp_exp(m2);
+            es = __builtin_amdgcn_frexp_exp(diag_max<NPM>(Sb, n, lp));
             double* t = Sa;
             Sa = Sb;
             Sb = t;
             if (it >= 5 && (it & 3) == 1) {
-                // x = S 1 over the support, then the two bounds
-                if (tid < n) {
-                    double x = 0.0;
-                    for (int j = 0; j < n; ++j) x += Sa[tid * ld + j];
-                    xv[tid] = x;
-                }
-                __syncthreads();
-                double lo = INFINITY, hi = -INFINITY;
-                int miss = 0;
-                if (tid < n && A[tid * ld + tid] > 0.0) {
-                    double y = 0.0;
-                    for (int j = 0; j < n; ++j) y = fma(A[tid * ld + j], xv[j], y);
-                    const double x = xv[tid];
-                    if (x > 0.0) {
-                        lo = y / x;
-                        hi = lo;
-                    } else {
-                        miss = 1;
+                // x = S 1 (column sums; S is exactly symmetric), y = A x, and
+                // the bounds over the support, on the first wavefront
+                if (wave == 0) {
+                    // column sums over the zero-padded NP rows, 16 loads in flight
+                    const int lc = min(lane, NP - 1);
+                    double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+#pragma unroll
+                    for (int j0 = 0; j0 < NPM; j0 += 4) {
+                        const bool ok = j0 < NP;
+                        const double* c0 = Sa + min(j0, NP - 4) * lp + lc;
+                        x0 += ok ? c0[0] : 0.0;
+                        x1 += ok ? c0[lp] : 0.0;
+                        x2 += ok ? c0[2 * lp] : 0.0;
+                        x3 += ok ? c0[3 * lp] : 0.0;
+                    }
+                    const double x = (lane < n) ? (x0 + x1) + (x2 + x3) : 0.0;
+                    xv[lane] = x;
+                    wave_sync();
+                    // y = A x (xv is zero past n, so clamped rows add nothing)
+                    const int la = min(lane, n - 1);
+                    double y0 = 0.0, y1 = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NPM; j += 2) {
+                        y0 = fma(A[min(j, n - 1) * ld + la], xv[j], y0);
+                        y1 = fma(A[min(j + 1, n - 1) * ld + la], xv[j + 1], y1);
+                    }
+                    const double y = y0 + y1;
+                    double lo = INFINITY, hi = -INFINITY;
+                    int miss = 0;
+                    if (lane < n && A[lane * ld + lane] > 0.0) {
+                        if (x > 0.0) {
+                            lo = y / x;
+                            hi = lo;
+                        } else {
+                            miss = 1;
+                        }
+                    }
+                    wave_minmax(lo, hi);
+                    miss = __any(miss);
+                    if (lane == 0) {
+                        red[8] = lo;
+                        red[9] = hi;
+                        red[10] = (!miss && hi >= lo && hi - lo <= 1e-14 * hi) ? 1.0 : 0.0;
                     }
                 }
-                lo = wave_min(lo);
-                hi = wave_max(hi);
-                const int anymiss = __syncthreads_or(miss);
-                if (tid == 0) {
-                    red[8] = lo;
-                    red[9] = hi;
-                }
                 __syncthreads();
-                lo = red[8];
-                hi = red[9];
-                if (!anymiss && hi >= lo && hi - lo <= 1e-14 * hi) {
-                    result = 0.5 * (lo + hi);
+                if (red[10] != 0.0) {
+                    result = 0.5 * (red[8] + red[9]);
                     done = true;
                 }
+                __syncthreads();
             }
         }
     }
@@ -320,61 +366,111 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
     return result;
 }
 
-// Gram V = U^T U (FP64) of an I x R factor with row stride Rq.  Rows are
-// staged through LDS in tiles of `tile` rows; the R(R+1)/2 pair sums
-// accumulate in LDS (accl), one owner thread per pair.  All threads of the
-// workgroup take part.
+// V = U^T U (R x R, FP64, exactly symmetric) of an I x R factor with row
+// stride Rq, and, when K != nullptr, bout[a] = sum_i K[i][a] U[i][a] (the core
+// term b = colsum(K ⊛ U)).  The Gram runs on the FP64 matrix cores: 16-column
+// tiles of U, one 16 x 16 output tile per tile pair (ta <= tb), four rows per
+// step; wave w takes the row steps w, w+4, ... and the four partial tiles are
+// added in fixed order through LDS (lds: 256 + 256 doubles).  Only the upper
+// triangle is formed and mirrored.
 template <typename T>
-__device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R, int Rq, double* __restrict__ out, T* __restrict__ tileb,
-                           int tile, double* __restrict__ accl) {
-    const int npair = R * (R + 1) / 2;
-    const int nt = blockDim.x;
-    for (int p = threadIdx.x; p < npair; p += nt) accl[p] = 0.0;
-    for (int r0 = 0; r0 < I; r0 += tile) {
-        const int nr = min(tile, I - r0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < nr * Rq; e += nt) tileb[e] = U[(long long)r0 * Rq + e];
-        __syncthreads();
-        for (int p = threadIdx.x; p < npair; p += nt) {
-            int a = 0, rem = p;
-            while (rem >= R - a) { rem -= R - a; ++a; }
-            const T* ca = tileb + a;
-            const T* cb = tileb + a + rem;
-            double s0 = 0.0, s1 = 0.0;
-            int i = 0;
-            for (; i + 1 < nr; i += 2) {
-                s0 = fma((double)ca[i * Rq], (double)cb[i * Rq], s0);
-                s1 = fma((double)ca[(i + 1) * Rq], (double)cb[(i + 1) * Rq], s1);
+__device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R, int Rq, double* __restrict__ out,
+                                           const T* __restrict__ K, double* __restrict__ bout, char* lds) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nt = (R + 15) >> 4;                       // column tiles (<= 4)
+    const int li = lane & 15, lk = lane >> 4;
+    double* part = (double*)lds;                        // [4 waves][64 lanes][4]
+    double* bpart = part + 4 * 256;                     // [4][64]
+    v4d acc[10];
+#pragma unroll
+    for (int p = 0; p < 10; ++p) acc[p] = (v4d){0.0, 0.0, 0.0, 0.0};
+    // row steps of 4 rows, wave w takes steps w, w+4, ...; batches of GB steps
+    // with every global load of the batch in flight (clamped addresses,
+    // zeros outside the factor)
+    constexpr int GB = 8;
+    const int nsteps = (I + 3) >> 2;
+    for (int sb = wv; sb < nsteps; sb += 4 * GB) {
+        double u[GB][4];
+#pragma unroll
+        for (int q = 0; q < GB; ++q) {
+            const int row = 4 * (sb + 4 * q) + lk;
+            const int rc = min(row, I - 1);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int col = 16 * t + li;
+                const double v = (double)U[(long long)rc * Rq + min(col, R - 1)];
+                u[q][t] = (t < nt && row < I && col < R) ? v : 0.0;
             }
-            if (i < nr) s0 = fma((double)ca[i * Rq], (double)cb[i * Rq], s0);
-            accl[p] += s0 + s1;
+        }
+#pragma unroll
+        for (int q = 0; q < GB; ++q) {
+            int p = 0;
+#pragma unroll
+            for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+                for (int tb = ta; tb < 4; ++tb, ++p)
+                    if (tb < nt) acc[p] = mfma64(u[q][ta], u[q][tb], acc[p]);
         }
     }
-    __syncthreads();
-    for (int p = threadIdx.x; p < npair; p += nt) {
-        int a = 0, rem = p;
-        while (rem >= R - a) { rem -= R - a; ++a; }
-        const int b = a + rem;
-        out[a * R + b] = accl[p];
-        out[b * R + a] = accl[p];
+    // b = colsum(K ⊛ U): column c = lane, rows of phase wave, 8 rows in flight
+    double bacc = 0.0;
+    if (K != nullptr) {
+        const int lc = min(lane, R - 1);
+        for (int i0 = wv; i0 < I; i0 += 32) {
+            double kv[8], uv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const long long o = (long long)min(i0 + 4 * q, I - 1) * Rq + lc;
+                kv[q] = (double)K[o];
+                uv[q] = (double)U[o];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (i0 + 4 * q < I) bacc = fma(kv[q], uv[q], bacc);
+        }
+        bpart[wv * 64 + lane] = bacc;
     }
+    int p = 0;
+#pragma unroll
+    for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+        for (int tb = ta; tb < 4; ++tb, ++p) {
+            if (tb >= nt) continue;
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) part[(wv * 64 + lane) * 4 + v] = acc[p][v];
+            __syncthreads();
+            // thread e: lane e % 64, register e / 64 of the tile
+            const int l2 = tid & 63, v2 = tid >> 6;
+            const double d = ((part[(0 * 64 + l2) * 4 + v2] + part[(1 * 64 + l2) * 4 + v2]) + part[(2 * 64 + l2) * 4 + v2]) +
+                             part[(3 * 64 + l2) * 4 + v2];
+            const int r = 16 * ta + 4 * v2 + (l2 >> 4), c = 16 * tb + (l2 & 15);
+            if (r < R && c < R && (ta < tb || r <= c)) {
+                out[r * R + c] = d;
+                out[c * R + r] = d;
+            }
+        }
+    __syncthreads();
+    if (K != nullptr && tid < R) bout[tid] = ((bpart[tid] + bpart[64 + tid]) + bpart[128 + tid]) + bpart[192 + tid];
     __syncthreads();
 }
 
 // LDS (bytes) of the eigenvalue work (matrix, three R-vectors, squaring
-// buffers and fallback work) and of the Gram (pair accumulators, row tile).
+// buffers and fallback work) and of the Gram (cross-wave partial tiles).
 __host__ __device__ inline size_t eig_lds_bytes(int R) {
     const size_t ld = (size_t)(R | 1);
-    return sizeof(double) * ((size_t)R * ld + 192 + (R <= 48 ? 2 * (size_t)R * ld : 0) + 576);
+    return sizeof(double) * ((size_t)R * ld + 192 + (R <= 48 ? 2 * (size_t)sq_np(R) * sq_lp(R) : 0) + 576);
 }
-__host__ __device__ inline size_t gram_acc_bytes(int R) { return sizeof(double) * (size_t)(R * (R + 1) / 2 + 1); }
 template <typename T>
-__host__ __device__ inline size_t gram_lds_bytes(int R, int Rq, int tile) {
-    return ((gram_acc_bytes(R) + 255) & ~(size_t)255) + sizeof(T) * (size_t)tile * Rq;
+__host__ __device__ inline size_t gram_lds_bytes(int Rq, int with_k) {
+    (void)Rq;
+    (void)with_k;
+    return sizeof(double) * (4 * 256 + 4 * 64);
 }
 template <typename T>
 __host__ __device__ inline size_t prep_lds_bytes(int R, int Rq) {
-    const size_t a = eig_lds_bytes(R), b = gram_lds_bytes<T>(R, Rq, 128);
+    const size_t a = eig_lds_bytes(R), b = gram_lds_bytes<T>(Rq, 0);
     return a > b ? a : b;
 }
 
@@ -443,8 +539,7 @@ __device__ __forceinline__ void prep_block(const Geo* __restrict__ g, const Stat
     const int S = g->S, R = g->R, Rq = g->Rq, ld = R | 1, RR = R * R;
     const int m = n - 1;
     double* Vm = st.V[0] + (m * S + s) * RR;
-    block_gram<T>(st.U[0] + g->uoff[m][s], g->I[s][m], R, Rq, Vm,
-                  (T*)(smraw + ((gram_acc_bytes(R) + 255) & ~(size_t)255)), 128, (double*)smraw);
+    block_gram<T>(st.U[0] + g->uoff[m][s], g->I[s][m], R, Rq, Vm, nullptr, nullptr, smraw);
     __threadfence_block();
     __syncthreads();
     const int tid = threadIdx.x;
