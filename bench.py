@@ -52,6 +52,27 @@ def cpu_baseline(P, U0, lam0, budget_s=12.0):
 
 
 LRA_WORKLOAD = "c3_lra_10x256cube_r20"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mttkrp_hbm_traffic_c2_10x100cube_r20.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2302_05119_amd", "csrc", "mttkrp_kernels.h")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE / WRITE_SIZE runs scaled by a plain-copy calibration), or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+
+    try:
+        text = open(TRAFFIC_FILE).read()
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"kernel_source_sha256 = ([0-9a-f]{64})", text)
+    t = re.search(r"traffic_bytes_per_launch\[" + re.escape(kernel) + r"\] = (\d+)", text)
+    if not m or not t or m.group(1) != sha:
+        return None
+    return int(t.group(1))
 
 
 def lra_leg(steps: int, warmup: int):
@@ -183,7 +204,7 @@ def main():
         "config": {"workload": WORKLOAD, "blocks": S, "dims": list(I), "rank": R, "coupled": list(w["L"]),
                    "snr_db": w["snr"], "path": "CoNCPD-APG dense, FP32 MFMA"},
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom[0]),
                      "avg_launch_us": dom[2] * 1e6, "algorithmic_bytes_per_launch": dom[1]},
         "mttkrp_tflops": mttkrp_tflops,
         "pass_us": {"pass1": avg1 * 1e6, "pass2": avg2 * 1e6},
