@@ -99,6 +99,20 @@ concpd_status validate(const concpd_config* c) {
     return CONCPD_OK;
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin (blockIdx % 8), and each XCD
+// has its own L2.  Reordering a list built in memory order so that XCD x runs
+// the contiguous range x * n / 8 .. of it keeps items that share cache lines
+// (neighbouring row segments of the tensor, of Y) in one L2.
+template <typename Item>
+void xcd_order(std::vector<Item>& v) {
+    const size_t n8 = v.size() - v.size() % 8, per = n8 / 8;
+    if (per < 2) return;
+    std::vector<Item> out(v.size());
+    for (size_t b = 0; b < n8; ++b) out[b] = v[(b % 8) * per + b / 8];
+    for (size_t b = n8; b < v.size(); ++b) out[b] = v[b];
+    v.swap(out);
+}
+
 void build_lists(const concpd_config* c, Lists* L) {
     const int S = c->num_blocks, R = c->rank, Rq = (R + 3) / 4 * 4;
     L->p1.clear();
@@ -115,6 +129,9 @@ void build_lists(const concpd_config* c, Lists* L) {
         for (int ch = 0; ch * 4 < I1; ++ch)
             for (int q0 = 0; q0 < I3; q0 += 64) L->p2.push_back({s, ch, q0, 0});
     }
+    xcd_order(L->p1);
+    xcd_order(L->p2);
+    xcd_order(L->k2);
     for (int n = 0; n < 3; ++n) {
         L->u[n].clear();
         int lds_rows = 1;
