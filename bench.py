@@ -75,7 +75,7 @@ def measured_traffic(kernel: str):
     return int(t.group(1))
 
 
-def lra_leg(steps: int, warmup: int):
+def lra_leg(steps: int, warmup: int, dense_steps: int = 30):
     """lraCoNCPD-APG on 10 blocks of 256^3 (Tucker 30^3): compression time and
     iterations/s of the compressed iterations (step 2)."""
     import torch
@@ -90,6 +90,18 @@ def lra_leg(steps: int, warmup: int):
     tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
     del P
     m = CoupledCP(tens, w["R"], w["L"], compute="f32", init_U=U0, init_lambda=lam0, tucker_ranks=w["tucker"])
+    # the plain path on the same blocks, for comparison (then the lra path
+    # continues from the same starting point)
+    dense = CoupledCP(tens, w["R"], w["L"], compute="f32", init_U=U0, init_lambda=lam0)
+    dense.step(3)
+    kd0 = dense.stats()["k"]
+    torch.cuda.synchronize()
+    td0 = time.perf_counter()
+    dense.step(dense_steps, sync=False)
+    torch.cuda.synchronize()
+    td1 = time.perf_counter()
+    dense_rate = (dense.stats()["k"] - kd0) / (td1 - td0)
+    del dense
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     m.lra_compress()
@@ -102,7 +114,8 @@ def lra_leg(steps: int, warmup: int):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     st = m.stats()
-    return {"workload": LRA_WORKLOAD, "compress_s": t1 - t0, "iter_per_s": (st["k"] - k0) / (t3 - t2), "sweeps": steps,
+    return {"workload": LRA_WORKLOAD, "compress_s": t1 - t0, "iter_per_s": (st["k"] - k0) / (t3 - t2),
+            "dense_iter_per_s_same_blocks": dense_rate, "sweeps": steps,
             "warmup": warmup, "fit_compressed": st["fit"], "global_fit": m.global_fit(), "iterations": st["k"],
             "restarts": st["restarts"]}
 

@@ -107,7 +107,9 @@ void launch_sum_split(const double* part, int nsplit, long long n, double* out, 
 void launch_eig_top(const Geo* g, double* lra, double* sig, long long sig_stride, double* work, long long work_stride, int nmat, hipStream_t q);
 void launch_ttm_chain(const float* M, int I1, int I2, int I3, const double* A1, const double* A2, const double* A3, int J1, int J2, int J3, double* T1, double* T2, double* G, hipStream_t q);
 template <typename T> void launch_lra_w(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int uslot, int wslot, hipStream_t q);
-template <typename T> void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, hipStream_t q);
+// LDS of the core-contraction kernel: G slice, two W factors, phase partials.
+inline size_t lra_c_lds_bytes(int Jmax, int Rq) { return sizeof(double) * ((size_t)Jmax * Jmax + 2 * (size_t)Jmax * Rq + 256); }
+template <typename T> void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int Rq, int n, hipStream_t q);
 void launch_sum_parts(const double* part, int np, double* out, hipStream_t q);
 void launch_convert(const void* src, int dst_dtype, void* dst, long long n, hipStream_t q);
 void launch_finite_check(const void* src, int dtype, long long n, int* flag, hipStream_t q);

@@ -36,7 +36,16 @@ __device__ __forceinline__ double k_value(const Geo* __restrict__ g, const State
         const int n = KSRC - KSRC_LRA0, Jn = g->J[s][n];
         const double* A = st.lra + g->aoff[n][s] + (long long)i * Jn;
         const double* C = st.lra + g->coff[s] + col;
-        for (int j = 0; j < Jn; ++j) acc = fma(A[j], C[(long long)j * Rq], acc);
+        double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int j = 0;
+        for (; j + 3 < Jn; j += 4) {
+            acc = fma(A[j], C[(long long)j * Rq], acc);
+            a1 = fma(A[j + 1], C[(long long)(j + 1) * Rq], a1);
+            a2 = fma(A[j + 2], C[(long long)(j + 2) * Rq], a2);
+            a3 = fma(A[j + 3], C[(long long)(j + 3) * Rq], a3);
+        }
+        for (; j < Jn; ++j) acc = fma(A[j], C[(long long)j * Rq], acc);
+        acc = (acc + a1) + (a2 + a3);
     } else {
         const int I3 = g->I[s][2], nch = g->nchunk[s];
         const T* p = st.part + g->poff[s] + (long long)i * Rq + col;
@@ -84,8 +93,16 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
         const int s = s0 + sl, i = row0 + rr;
         const double* P = st.P + (long long)s * RR;
         const double* u = uh + (sl * nrows + rr) * R;
-        double gr = 0.0;
-        for (int r = 0; r < R; ++r) gr += u[r] * P[r * R + col];
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        int r = 0;
+        for (; r + 3 < R; r += 4) {
+            g0 = fma(u[r], P[r * R + col], g0);
+            g1 = fma(u[r + 1], P[(r + 1) * R + col], g1);
+            g2 = fma(u[r + 2], P[(r + 2) * R + col], g2);
+            g3 = fma(u[r + 3], P[(r + 3) * R + col], g3);
+        }
+        for (; r < R; ++r) g0 = fma(u[r], P[r * R + col], g0);
+        double gr = (g0 + g1) + (g2 + g3);
         const double kv = k_value<T, KSRC>(g, st, s, i, col);
         gr -= kv * st.lam[0][s * Rq + col];
         if (KSRC == KSRC_PART || KSRC == KSRC_LRA2) st.K3[g->koff[s] + (long long)i * Rq + col] = (T)kv;

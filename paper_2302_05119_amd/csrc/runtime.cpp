@@ -96,6 +96,12 @@ concpd_status validate(const concpd_config* c) {
             }
     if (c->tucker_ranks && c->tensor_dtype != CONCPD_F32)
         return fail(CONCPD_ENOTSUP, "lra compression needs F32 tensors");
+    if (c->tucker_ranks) {
+        int jm = 1;
+        for (int i = 0; i < 3 * c->num_blocks; ++i) jm = std::max(jm, (int)c->tucker_ranks[i]);
+        if (cpd::lra_c_lds_bytes(jm, (c->rank + 3) / 4 * 4) > 65536)
+            return fail(CONCPD_ENOTSUP, "Tucker rank %d with rank %d exceeds the core-contraction LDS budget", jm, c->rank);
+    }
     return CONCPD_OK;
 }
 
@@ -439,7 +445,7 @@ void run_sweep_lra(concpd_ctx c, const StateP<T>& st) {
     cpd::launch_core<T>(g, st, S, R, extrap, q);
     for (int n = 0; n < 3; ++n) {
         if (n > 0) cpd::launch_prep<T>(g, st, S, R, n, q);
-        cpd::launch_lra_c<T>(g, st, S, J, n, q);
+        cpd::launch_lra_c<T>(g, st, S, J, c->Rq, n, q);
         cpd::launch_update<T>(g, st, itu[n], (int)c->lists.u[n].size(), n, R, extrap, c->lists.lds_rows[n], 1, q);
         cpd::launch_lra_w<T>(g, st, S, J, n, 0, 0, q);
     }
@@ -461,7 +467,7 @@ void recompute_stats(concpd_ctx c, const StateP<T>& st) {
         // W of the iterate in both slots, then K3 = A_3 C_3 and the statistics
         for (int n = 0; n < 3; ++n)
             for (int slot = 0; slot < 2; ++slot) cpd::launch_lra_w<T>(c->dgeo, st, c->S, c->lay.Jmax, n, 1, slot, c->q);
-        cpd::launch_lra_c<T>(c->dgeo, st, c->S, c->lay.Jmax, 2, c->q);
+        cpd::launch_lra_c<T>(c->dgeo, st, c->S, c->lay.Jmax, c->Rq, 2, c->q);
         for (int s = 0; s < c->S; ++s)
             cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], c->R, st.K3 + c->geo.koff[s], c->Rq, 1, c->q);
         cpd::launch_init_stats<T>(c->dgeo, st, c->S, c->R, c->q);
