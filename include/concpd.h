@@ -186,18 +186,21 @@ concpd_status concpd_set_state(concpd_ctx ctx, const double* const* U, const dou
 
 /* Loss F and its partial gradients at an arbitrary point, without touching the
  * iterate (autograd form): dF/dlambda^(s) = H lambda - b (eq. solbpgG) and
- * dF/dU^(n,s) = U D H_{-n} D - M_(n) U^{⊙-n} D (eq. solbpgU), all blocks at the
- * same point.
- *   U_dev      [S*3] device I_n x R row-major arrays in the context's factor type
- *              (double for compute_dtype F64, else float); shared columns are
- *              read from block 0.
+ * dF/dU^(n,s) = U D H_{-n} D - M_(n) U^{⊙-n} D (eq. solbpgU), every block at
+ * the same point, F = sum_s 1/2 ||M^(s) - [[lambda^(s); U^(.,s)]]||^2.
+ *   U_dev      [S*3] device I_n x R row-major arrays (index 3*s + n) in the
+ *              context's factor type (double for compute_dtype F64, else float).
  *   lambda_dev [S] device double R-vectors.
- *   gU_dev     [S*3] device outputs like U_dev; for a mode with L_n > 0 the
- *              first L_n columns of every block receive the sum over s
- *              (eq. solbpgUCI summed over the blocks sharing U_C).
+ *   coupled    1: the first L_n columns of every mode-n factor are the shared
+ *              U_C, read from block 0, and every block's gU receives the
+ *              gradient with respect to U_C (the sum over s, eq. solbpgUCI);
+ *              0: every block's factors are taken as given and gU holds each
+ *              block's own gradient (a caller that ties parameters sums them).
+ *   gU_dev     [S*3] device outputs shaped like U_dev.
  *   glam_dev   [S] device double outputs.  *loss receives F (host).
- * Synchronises.  Errors: EINVAL, ESTATE (not supported in lra mode), EHIP. */
-concpd_status concpd_loss_grad(concpd_ctx ctx, const void* const* U_dev, const void* const* lambda_dev,
+ * Inputs and outputs may not overlap.  Synchronises.
+ * Errors: EINVAL (NULL pointer), ESTATE (lra mode), EHIP. */
+concpd_status concpd_loss_grad(concpd_ctx ctx, const void* const* U_dev, const void* const* lambda_dev, int32_t coupled,
                                double* loss, void* const* gU_dev, void* const* glam_dev);
 
 /* Test hook: K = M^(s)_(n) U^{⊙-n} at the current iterate, I_n x R row-major
@@ -212,6 +215,39 @@ concpd_status concpd_debug_mttkrp(concpd_ctx ctx, int32_t n, int32_t s, void* de
  * record.  Errors: EHIP. */
 concpd_status concpd_profile(concpd_ctx ctx, int32_t enable);
 concpd_status concpd_profile_read(concpd_ctx ctx, double* ms_pass1, double* ms_pass2, int64_t* launches);
+
+/* Launch options of a context (batching form).
+ *   CONCPD_OPT_GRAPH_SWEEPS  n > 0: concpd_step queues sweeps as replays of one
+ *                            captured HIP graph of n sweeps (all decisions are
+ *                            taken on the device, so a sweep is a fixed kernel
+ *                            sequence); 0 (default): direct kernel launches.
+ *   CONCPD_OPT_OVERLAP       1: the small FP64 kernels run on a second stream
+ *                            beside the MTTKRP passes (default 0).
+ *   CONCPD_OPT_K2_ROWS       i1 rows per workgroup of the mode-2 contraction
+ *                            (8..64, default 16).
+ * Synchronises.  Errors: EINVAL (unknown option or value), EHIP. */
+typedef enum concpd_option {
+    CONCPD_OPT_GRAPH_SWEEPS = 1,
+    CONCPD_OPT_OVERLAP = 2,
+    CONCPD_OPT_K2_ROWS = 3
+} concpd_option;
+concpd_status concpd_set_option(concpd_ctx ctx, int32_t option, int64_t value);
+concpd_status concpd_get_option(concpd_ctx ctx, int32_t option, int64_t* value);
+
+typedef struct concpd_tuning {
+    int32_t k2_rows;              /* chosen CONCPD_OPT_K2_ROWS */
+    int32_t graph_sweeps;         /* chosen CONCPD_OPT_GRAPH_SWEEPS */
+    double us_per_sweep;          /* measured time per sweep of the choice */
+    double us_per_sweep_default;  /* of the default configuration */
+    int32_t candidates;           /* configurations timed */
+} concpd_tuning;
+
+/* Autotuner: times `sweeps` sweeps (HIP events on the context stream) of every
+ * candidate launch configuration (mode-2 chunk rows 8/16/32 x graph sweeps
+ * 0/1/4) from the same iterate, restoring the iterate after each, and keeps
+ * the fastest.  The iterate is unchanged on return.  Synchronises.
+ * Errors: EINVAL (sweeps not in [1, 10000]), ESTATE (converged iterate), EHIP. */
+concpd_status concpd_autotune(concpd_ctx ctx, int32_t sweeps, concpd_tuning* out);
 
 /* Release the host context.  Queued work is synchronised first; the workspace
  * and the tensors stay owned by the caller. */

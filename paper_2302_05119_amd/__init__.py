@@ -5,3 +5,4 @@ include/concpd.h); this package only marshals arguments to it.
 """
 from ._lib import ConcpdError, load  # noqa: F401
 from .model import CoupledCP  # noqa: F401
+from .autograd import CoupledCPLoss, coupled_cp_loss  # noqa: F401

@@ -51,6 +51,21 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("k2_rows", ctypes.c_int32),
+        ("graph_sweeps", ctypes.c_int32),
+        ("us_per_sweep", ctypes.c_double),
+        ("us_per_sweep_default", ctypes.c_double),
+        ("candidates", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+OPT_GRAPH_SWEEPS, OPT_OVERLAP, OPT_K2_ROWS = 1, 2, 3
+
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)
 _DPP = ctypes.POINTER(ctypes.POINTER(ctypes.c_double))
@@ -67,12 +82,15 @@ SIGNATURES = {
     "lra_compress": (ctypes.c_int, [_P, _I32P, ctypes.POINTER(Stats)]),
     "lra_step": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Stats)]),
     "lra_get_tucker": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _DP]),
+    "concpd_set_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64]),
+    "concpd_get_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "concpd_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Tuning)]),
     "concpd_global_fit": (ctypes.c_int, [_P, _DP]),
     "concpd_get_factor": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _DP]),
     "concpd_get_lambda": (ctypes.c_int, [_P, ctypes.c_int32, _DP]),
     "concpd_get_lipschitz": (ctypes.c_int, [_P, _DP, _DP, _DP]),
     "concpd_set_state": (ctypes.c_int, [_P, _DPP, _DPP, _DPP, _DPP, _DP, _DP, _DP, ctypes.c_double, ctypes.c_int64]),
-    "concpd_loss_grad": (ctypes.c_int, [_P, _PP, _PP, _DP, _PP, _PP]),
+    "concpd_loss_grad": (ctypes.c_int, [_P, _PP, _PP, ctypes.c_int32, _DP, _PP, _PP]),
     "concpd_debug_mttkrp": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
     "concpd_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "concpd_profile_read": (ctypes.c_int, [_P, _DP, _DP, ctypes.POINTER(ctypes.c_int64)]),

@@ -7,7 +7,8 @@
 #define CPD_MAXR 64   // components per block
 
 // Device-side control block: scalars of the outer iteration (Algorithm 1).
-#define CPD_K2ROWS 16   // i1 rows per mode-2 contraction chunk
+#define CPD_K2ROWS_DEFAULT 16   // i1 rows per mode-2 contraction chunk
+#define CPD_K2ROWS_MIN 8         // smallest chunk the workspace is sized for
 
 struct Ctrl {
     double t;          // t_{k-1} (Appendix A, parameter settings)
@@ -51,8 +52,9 @@ struct Geo {
     long long coff[CPD_MAXS];     // C_n^(s) = G_(n) (⊙ W): Jmax x Rq (double)
     long long wslot_len;          // doubles per W slot (slot 1 follows slot 0)
     long long k1off[CPD_MAXS];    // mode-1 MTTKRP partials per 64-row group: I1 x nrg x Rq
-    long long k2off[CPD_MAXS];    // mode-2 MTTKRP partials per chunk of CPD_K2ROWS i1 rows: nk2 x I2 x Rq
-    int nk2[CPD_MAXS];            // ceil(I1 / CPD_K2ROWS)
+    long long k2off[CPD_MAXS];    // mode-2 MTTKRP partials per chunk of k2rows i1 rows: nk2 x I2 x Rq
+    int nk2[CPD_MAXS];            // ceil(I1 / k2rows)
+    int k2rows;                   // i1 rows per mode-2 contraction chunk
     int nrg[CPD_MAXS];            // ceil(I2 / 64)
     const void* M[CPD_MAXS];      // block tensors in the MTTKRP operand type
     int mdtype;                   // operand type of M (concpd_dtype)
@@ -107,6 +109,9 @@ void launch_sum_split(const double* part, int nsplit, long long n, double* out, 
 void launch_eig_top(const Geo* g, double* lra, double* sig, long long sig_stride, double* work, long long work_stride, int nmat, hipStream_t q);
 void launch_ttm_chain(const float* M, int I1, int I2, int I3, const double* A1, const double* A2, const double* A3, int J1, int J2, int J3, double* T1, double* T2, double* G, hipStream_t q);
 template <typename T> void launch_lra_w(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int uslot, int wslot, hipStream_t q);
+template <typename T>
+void launch_grad(const Geo* g, const StateP<T>& st, int S, int R, int Rq, const int* In, int L0, int L1, int L2,
+                 double* const* glam, double* Fblk, T* const* gU0, T* const* gU1, T* const* gU2, int coupled, hipStream_t q);
 // LDS of the core-contraction kernel: G slice, two W factors, phase partials.
 inline size_t lra_c_lds_bytes(int Jmax, int Rq) { return sizeof(double) * ((size_t)Jmax * Jmax + 2 * (size_t)Jmax * Rq + 256); }
 template <typename T> void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int Rq, int n, hipStream_t q);

@@ -22,23 +22,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     prep_block<T, NMAX>(g, st, blockIdx.x, n, smraw);
 }
 
-// F^(s) = 1/2 (||M||^2 - 2 lam^T b + lam^T H lam), H = V0 ⊛ V1 ⊛ V2 (eq. costfunc
-// expanded with the Hadamard-of-Grams identity of Appendix A).
-__device__ __forceinline__ double block_objective(const double* lam, const double* V0, const double* V1, const double* V2,
-                                  const double* b, double normM2, int R) {
-    __shared__ double red[256];
-    const int tid = threadIdx.x, RR = R * R;
-    double part = 0.0;
-    for (int i = tid; i < RR; i += 256) part += lam[i / R] * lam[i % R] * V0[i] * V1[i] * V2[i];
-    if (tid < R) part -= 2.0 * lam[tid] * b[tid];
-    red[tid] = part;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) red[tid] += red[tid + o];
-        __syncthreads();
-    }
-    return 0.5 * (normM2 + red[0]);
-}
 
 // After the mode-3 update: Gram of U^(3), b (the data term (U^⊙)^T vec(M) of
 // eq. solapgG, reused by the next core update) and F^(s).  The last workgroup

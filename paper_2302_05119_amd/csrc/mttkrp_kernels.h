@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
 // ---------------------------------------------------------------------------
 // mode 2: K2[i2][r] = sum_i1 Y[i1][i2][r] U1[i1][r] with the new U^(1).  One
 // thread per element e = i2*Rq + r of a 256-wide column tile, one workgroup
-// per (block, tile, chunk of CPD_K2ROWS rows of i1); every Y load is a
+// per (block, tile, chunk of k2rows rows of i1); every Y load is a
 // coalesced row segment.  Chunk partials are summed in fixed order by the
 // factor update.
 // ---------------------------------------------------------------------------
@@ -243,7 +243,8 @@ __global__ __launch_bounds__(256) void k_k2(const Geo* __restrict__ g, StateP<T>
     const int e = it.col0 + (int)threadIdx.x;
     if (e >= ys) return;
     const int c = e % Rq;
-    const int i1a = it.chunk * CPD_K2ROWS, i1b = min(I1, i1a + CPD_K2ROWS);
+    const int kr = g->k2rows;
+    const int i1a = it.chunk * kr, i1b = min(I1, i1a + kr);
     const CPD_GLOBAL T* __restrict__ Y = gptr(st.Y + g->yoff[s] + e);
     const CPD_GLOBAL T* __restrict__ U1 = gptr(pick3(st.U, slot) + g->uoff[0][s] + c);
     T a0 = 0, a1 = 0;

@@ -40,6 +40,12 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t geo, ctrl, U[3], lam[3], V[2], b[2], P, Ld_cur, Ld_prev, Lu_cur, Lu_prev, LC_prev, Fblk, normM2, normOrig, Y,
         K3, part, K1p, K2, it1, it2, itk2, itu[3], scratch, shadow, lra, flag, total;
+    // loss/gradient evaluation point (autograd form): factors, lambda, Grams,
+    // b, step matrices, per-block F, control block, output pointer tables
+    size_t gU, glam, gV, gb, gP, gF, gctrl, gptr;
+    // autotuner snapshot of the persistent iterate state (ctrl .. normOrig,
+    // and the Tucker-form W slots)
+    size_t snap, snap_len, snap_w;
     long long uslot, ylen, klen, plen, shadow_elems[CPD_MAXS], lra_len;
     // lra region (doubles from its base): compression scratch
     long long l_sig, l_part, l_work, l_t1, l_t2, sig_stride, work_stride;
@@ -119,7 +125,7 @@ void xcd_order(std::vector<Item>& v) {
     v.swap(out);
 }
 
-void build_lists(const concpd_config* c, Lists* L) {
+void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAULT) {
     const int S = c->num_blocks, R = c->rank, Rq = (R + 3) / 4 * 4;
     L->p1.clear();
     L->p2.clear();
@@ -128,7 +134,7 @@ void build_lists(const concpd_config* c, Lists* L) {
     for (int s = 0; s < S; ++s) {
         const int I1 = (int)c->dims[3 * s], I2 = (int)c->dims[3 * s + 1], I3 = (int)c->dims[3 * s + 2];
         L->maxI2 = std::max(L->maxI2, I2);
-        for (int ch = 0; ch * CPD_K2ROWS < I1; ++ch)
+        for (int ch = 0; ch * k2rows < I1; ++ch)
             for (long long c0 = 0; c0 < (long long)I2 * Rq; c0 += 256) L->k2.push_back({s, (int)c0, ch, 0});
         for (int i1 = 0; i1 < I1; ++i1)
             for (int rg = 0; rg * 64 < I2; ++rg) L->p1.push_back({s, i1, rg, 0});
@@ -172,6 +178,7 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     for (int n = 0; n < 3; ++n) g->L[n] = c->coupled[n];
     g->upd_core = c->update_core;
     g->mdtype = c->compute_dtype;
+    g->k2rows = CPD_K2ROWS_DEFAULT;
     long long u = 0, y = 0, k = 0, p = 0, k1 = 0, k2 = 0;
     for (int n = 0; n < 3; ++n)
         for (int s = 0; s < S; ++s) {
@@ -192,8 +199,8 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
         g->k1off[s] = k1;
         k1 += I1 * g->nrg[s] * Rq;
         g->k2off[s] = k2;
-        g->nk2[s] = (int)((I1 + CPD_K2ROWS - 1) / CPD_K2ROWS);
-        k2 += g->nk2[s] * I2 * Rq;
+        g->nk2[s] = (int)((I1 + CPD_K2ROWS_DEFAULT - 1) / CPD_K2ROWS_DEFAULT);
+        k2 += ((I1 + CPD_K2ROWS_MIN - 1) / CPD_K2ROWS_MIN) * I2 * Rq;   // room for the smallest chunk
     }
     P->uslot = u;
     P->ylen = y;
@@ -227,13 +234,28 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     P->K2 = take((size_t)k2 * P->esz);
     P->it1 = take(sizeof(ItemP1) * std::max<size_t>(1, L.p1.size()));
     P->it2 = take(sizeof(ItemP2) * std::max<size_t>(1, L.p2.size()));
-    P->itk2 = take(sizeof(ItemK2) * std::max<size_t>(1, L.k2.size()));
+    {
+        Lists Lmin;
+        build_lists(c, &Lmin, CPD_K2ROWS_MIN);
+        P->itk2 = take(sizeof(ItemK2) * std::max<size_t>(1, std::max(L.k2.size(), Lmin.k2.size())));
+    }
     for (int n = 0; n < 3; ++n) P->itu[n] = take(sizeof(ItemU) * std::max<size_t>(1, L.u[n].size()));
     size_t scr = 4096;
     for (int s = 0; s < S; ++s) scr = std::max<size_t>(scr, (size_t)c->dims[3 * s]);
     P->scratch_len = scr;
     P->scratch = take(sizeof(double) * scr);
     P->flag = take(sizeof(int) * 4);
+    P->gU = take((size_t)u * P->esz);
+    P->glam = take(sizeof(double) * S * Rq);
+    P->gV = take(sizeof(double) * 3 * S * R * R);
+    P->gb = take(sizeof(double) * S * Rq);
+    P->gP = take(sizeof(double) * 3 * S * R * R);
+    P->gF = take(sizeof(double) * S);
+    P->gctrl = take(sizeof(Ctrl));
+    P->gptr = take(sizeof(void*) * 4 * S);
+    P->snap_len = P->normOrig + sizeof(double) * S - P->ctrl;
+    P->snap = take(P->snap_len);
+    P->snap_w = 0;
     if (c->compute_dtype == CONCPD_BF16 || c->compute_dtype == CONCPD_F16) {
         long long tot = 0;
         for (int s = 0; s < S; ++s) {
@@ -290,6 +312,7 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
         a += t2;
         P->lra_len = a;
         P->lra = take(sizeof(double) * (size_t)a);
+        P->snap_w = take(sizeof(double) * 2 * (size_t)g->wslot_len);
     }
     P->total = off;
 }
@@ -336,8 +359,20 @@ struct concpd_ctx_s {
     int overlap;
     hipStream_t q2;
     hipEvent_t fj[6];
+    // CONCPD_OPT_GRAPH_SWEEPS > 0: sweeps are replayed from a captured graph
+    // of that many sweeps (captured on a private stream, launched on q)
+    int graph_sweeps;
+    hipStream_t qcap;
+    hipGraphExec_t gexec;
+    int k2rows;
     std::vector<hipEvent_t> ev1, ev2;  // begin/end pairs of timed pass launches
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+    }
     ~concpd_ctx_s() {
+        drop_graph();
+        if (qcap) (void)hipStreamDestroy(qcap);
         if (q2) {
             (void)hipStreamSynchronize(q2);
             for (int i = 0; i < 6; ++i) (void)hipEventDestroy(fj[i]);
@@ -458,6 +493,44 @@ template <typename T>
 void run_one_sweep(concpd_ctx c, const StateP<T>& st) {
     if (c->lra) run_sweep_lra<T>(c, st);
     else run_sweep<T>(c, st);
+}
+
+// Queue `count` sweeps: replays of the captured graph when graph mode is on
+// (the remainder, and profiled or two-stream sweeps, launch directly).
+concpd_status launch_sweeps(concpd_ctx c, long long count) {
+    const int gs = c->graph_sweeps;
+    long long direct = count;
+    if (gs > 0 && !c->profiling && !c->overlap && count >= gs) {
+        if (!c->gexec) {
+            if (!c->qcap) HIPCHECK(hipStreamCreateWithFlags(&c->qcap, hipStreamNonBlocking));
+            hipStream_t q = c->q;
+            c->q = c->qcap;
+            HIPCHECK(hipStreamBeginCapture(c->qcap, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < gs; ++i) {
+                if (c->f64) run_one_sweep<double>(c, c->sd);
+                else run_one_sweep<float>(c, c->sf);
+            }
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->qcap, &graph);
+            c->q = q;
+            if (e != hipSuccess) return fail(CONCPD_EHIP, "sweep capture: %s", hipGetErrorString(e));
+            const hipError_t e2 = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e2 != hipSuccess) {
+                c->gexec = nullptr;
+                return fail(CONCPD_EHIP, "graph instantiate: %s", hipGetErrorString(e2));
+            }
+        }
+        for (long long i = 0; i + gs <= count; i += gs) HIPCHECK(hipGraphLaunch(c->gexec, c->q));
+        direct = count % gs;
+    }
+    for (long long i = 0; i < direct; ++i) {
+        if (c->f64) run_one_sweep<double>(c, c->sd);
+        else run_one_sweep<float>(c, c->sf);
+    }
+    c->launched_iters += count;
+    HIPCHECK(hipGetLastError());
+    return CONCPD_OK;
 }
 
 // Grams, b, F and RelErr of the iterate in slot 1.
@@ -597,6 +670,68 @@ void debug_passes(concpd_ctx c, const StateP<T>& st) {
     cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
 }
 
+// Loss and gradients at a caller-given point (autograd form): the point is
+// packed into its own slot set (every logical slot addresses it), the dense
+// MTTKRP passes run on it, then the per-block and per-factor gradient kernels.
+template <typename T>
+concpd_status loss_grad_t(concpd_ctx c, const StateP<T>& st, const void* const* U_dev, const void* const* lam_dev, int coupled,
+                          double* loss, void* const* gU_dev, void* const* glam_dev) {
+    const Layout& P = c->lay;
+    const size_t esz = sizeof(T);
+    StateP<T> sg = st;
+    T* Ug = (T*)(c->ws + P.gU);
+    for (int i = 0; i < 3; ++i) sg.U[i] = Ug;
+    for (int i = 0; i < 3; ++i) sg.lam[i] = (double*)(c->ws + P.glam);
+    for (int i = 0; i < 2; ++i) sg.V[i] = (double*)(c->ws + P.gV);
+    for (int i = 0; i < 2; ++i) sg.b[i] = (double*)(c->ws + P.gb);
+    sg.P = (double*)(c->ws + P.gP);
+    sg.ctrl = (Ctrl*)(c->ws + P.gctrl);
+    HIPCHECK(hipMemsetAsync(c->ws + P.gctrl, 0, sizeof(Ctrl), c->q));
+    HIPCHECK(hipMemsetAsync(Ug, 0, (size_t)P.uslot * esz, c->q));
+    HIPCHECK(hipMemsetAsync(sg.lam[0], 0, sizeof(double) * c->S * c->Rq, c->q));
+    // pack: I_n x R (row stride R) -> I_n x Rq; shared columns from block 0 when coupled
+    for (int s = 0; s < c->S; ++s) {
+        for (int n = 0; n < 3; ++n) {
+            const int I = (int)c->dims[3 * s + n];
+            T* dst = Ug + c->geo.uoff[n][s];
+            HIPCHECK(hipMemcpy2DAsync(dst, c->Rq * esz, U_dev[3 * s + n], c->R * esz, c->R * esz, I, hipMemcpyDeviceToDevice, c->q));
+            if (coupled && c->L[n] > 0 && s > 0)
+                HIPCHECK(hipMemcpy2DAsync(dst, c->Rq * esz, U_dev[n], c->R * esz, c->L[n] * esz, I, hipMemcpyDeviceToDevice, c->q));
+        }
+        HIPCHECK(hipMemcpyAsync(sg.lam[0] + (size_t)s * c->Rq, lam_dev[s], sizeof(double) * c->R, hipMemcpyDeviceToDevice, c->q));
+    }
+    // output pointer tables: gU for mode n at [n * S + s], glam at [3 S + s]
+    std::vector<void*> tab(4 * c->S);
+    for (int s = 0; s < c->S; ++s) {
+        for (int n = 0; n < 3; ++n) tab[n * c->S + s] = gU_dev[3 * s + n];
+        tab[3 * c->S + s] = glam_dev[s];
+    }
+    void** dtab = (void**)(c->ws + P.gptr);
+    HIPCHECK(hipMemcpyAsync(dtab, tab.data(), sizeof(void*) * tab.size(), hipMemcpyHostToDevice, c->q));
+    const ItemP1* it1 = (const ItemP1*)(c->ws + P.it1);
+    const ItemP2* it2 = (const ItemP2*)(c->ws + P.it2);
+    const ItemK2* itk = (const ItemK2*)(c->ws + P.itk2);
+    cpd::launch_pass1<T>(c->dgeo, sg, it1, (int)c->lists.p1.size(), c->Rq, 1, c->mdtype, c->q);
+    cpd::launch_k2<T>(c->dgeo, sg, itk, (int)c->lists.k2.size(), 0, c->q);
+    cpd::launch_pass2<T>(c->dgeo, sg, it2, (int)c->lists.p2.size(), c->Rq, 0, c->mdtype, c->lists.maxI2, c->q);
+    for (int s = 0; s < c->S; ++s)
+        cpd::launch_extract_k<T>(c->dgeo, sg, s, 2, (int)c->dims[3 * s + 2], c->R, sg.K3 + c->geo.koff[s], c->Rq, 0, c->q);
+    int In[3] = {1, 1, 1};
+    for (int s = 0; s < c->S; ++s)
+        for (int n = 0; n < 3; ++n) In[n] = std::max(In[n], (int)c->dims[3 * s + n]);
+    double* Fg = (double*)(c->ws + P.gF);
+    cpd::launch_grad<T>(c->dgeo, sg, c->S, c->R, c->Rq, In, c->L[0], c->L[1], c->L[2], (double* const*)(dtab + 3 * c->S), Fg,
+                        (T* const*)dtab, (T* const*)(dtab + c->S), (T* const*)(dtab + 2 * c->S), coupled, c->q);
+    HIPCHECK(hipGetLastError());
+    std::vector<double> F(c->S);
+    HIPCHECK(hipMemcpyAsync(F.data(), Fg, sizeof(double) * c->S, hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    double tot = 0.0;
+    for (int s = 0; s < c->S; ++s) tot += F[s];
+    *loss = tot;
+    return CONCPD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -653,6 +788,10 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
     {
         const char* ov = getenv("CONCPD_OVERLAP");
         c->overlap = ov && ov[0] == '1';
+        c->graph_sweeps = 0;
+        c->qcap = nullptr;
+        c->gexec = nullptr;
+        c->k2rows = CPD_K2ROWS_DEFAULT;
         c->q2 = nullptr;
         if (c->overlap) {
             if (hipStreamCreateWithFlags(&c->q2, hipStreamNonBlocking) != hipSuccess) c->overlap = 0;
@@ -795,13 +934,7 @@ concpd_status concpd_step(concpd_ctx c, int32_t n_iter, concpd_stats* out) {
     if (!out) {
         // asynchronous: n_iter sweeps; a sweep rejected by the restart test
         // is completed by the following one
-        for (int i = 0; i < n_iter; ++i) {
-            if (c->f64) run_one_sweep<double>(c, c->sd);
-            else run_one_sweep<float>(c, c->sf);
-        }
-        c->launched_iters += n_iter;
-        HIPCHECK(hipGetLastError());
-        return CONCPD_OK;
+        return launch_sweeps(c, n_iter);
     }
     // synchronous: exactly n_iter accepted iterations (or until converged)
     Ctrl h;
@@ -810,12 +943,8 @@ concpd_status concpd_step(concpd_ctx c, int32_t n_iter, concpd_stats* out) {
     const long long target = h.k + n_iter;
     long long todo = n_iter;
     while (todo > 0 && !h.stop) {
-        for (long long i = 0; i < todo; ++i) {
-            if (c->f64) run_one_sweep<double>(c, c->sd);
-            else run_one_sweep<float>(c, c->sf);
-        }
-        c->launched_iters += todo;
-        HIPCHECK(hipGetLastError());
+        const concpd_status r = launch_sweeps(c, todo);
+        if (r != CONCPD_OK) return r;
         HIPCHECK(hipMemcpyAsync(&h, c->ctrl, sizeof h, hipMemcpyDeviceToHost, c->q));
         HIPCHECK(hipStreamSynchronize(c->q));
         todo = target - h.k;
@@ -874,6 +1003,7 @@ concpd_status lra_compress(concpd_ctx c, const int32_t* ranks, concpd_stats* out
     }
     c->geo.lra = 1;
     c->lra = 1;
+    c->drop_graph();
     HIPCHECK(hipMemcpyAsync(c->dgeo, &c->geo, sizeof(Geo), hipMemcpyHostToDevice, c->q));
     HIPCHECK(hipStreamSynchronize(c->q));
     // statistics of the current iterate against the compressed blocks
@@ -1003,15 +1133,16 @@ concpd_status concpd_set_state(concpd_ctx c, const double* const* U, const doubl
     return CONCPD_OK;
 }
 
-concpd_status concpd_loss_grad(concpd_ctx c, const void* const* U_dev, const void* const* lambda_dev, double* loss,
-                               void* const* gU_dev, void* const* glam_dev) {
-    (void)U_dev;
-    (void)lambda_dev;
-    (void)loss;
-    (void)gU_dev;
-    (void)glam_dev;
-    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
-    return fail(CONCPD_ENOTSUP, "concpd_loss_grad not available yet");
+concpd_status concpd_loss_grad(concpd_ctx c, const void* const* U_dev, const void* const* lambda_dev, int32_t coupled,
+                               double* loss, void* const* gU_dev, void* const* glam_dev) {
+    if (!c || !U_dev || !lambda_dev || !loss || !gU_dev || !glam_dev) return fail(CONCPD_EINVAL, "NULL argument");
+    if (c->lra) return fail(CONCPD_ESTATE, "concpd_loss_grad is not available in lra mode");
+    for (int i = 0; i < 3 * c->S; ++i)
+        if (!U_dev[i] || !gU_dev[i]) return fail(CONCPD_EINVAL, "NULL factor pointer %d", i);
+    for (int s = 0; s < c->S; ++s)
+        if (!lambda_dev[s] || !glam_dev[s]) return fail(CONCPD_EINVAL, "NULL lambda pointer %d", s);
+    if (c->f64) return loss_grad_t<double>(c, c->sd, U_dev, lambda_dev, coupled, loss, gU_dev, glam_dev);
+    return loss_grad_t<float>(c, c->sf, U_dev, lambda_dev, coupled, loss, gU_dev, glam_dev);
 }
 
 concpd_status concpd_debug_mttkrp(concpd_ctx c, int32_t n, int32_t s, void* dev_out) {
@@ -1055,6 +1186,134 @@ concpd_status concpd_profile_read(concpd_ctx c, double* ms1, double* ms2, int64_
     for (hipEvent_t e : c->ev2) (void)hipEventDestroy(e);
     c->ev1.clear();
     c->ev2.clear();
+    return CONCPD_OK;
+}
+
+concpd_status concpd_set_option(concpd_ctx c, int32_t option, int64_t value) {
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    HIPCHECK(hipStreamSynchronize(c->q));
+    switch (option) {
+    case CONCPD_OPT_GRAPH_SWEEPS:
+        if (value < 0 || value > 64) return fail(CONCPD_EINVAL, "graph sweeps %lld not in [0, 64]", (long long)value);
+        if (value != c->graph_sweeps) c->drop_graph();
+        c->graph_sweeps = (int)value;
+        return CONCPD_OK;
+    case CONCPD_OPT_OVERLAP:
+        if (value != 0 && !c->q2) {
+            HIPCHECK(hipStreamCreateWithFlags(&c->q2, hipStreamNonBlocking));
+            for (int i = 0; i < 6; ++i) HIPCHECK(hipEventCreateWithFlags(&c->fj[i], hipEventDisableTiming));
+        }
+        c->overlap = value != 0;
+        return CONCPD_OK;
+    case CONCPD_OPT_K2_ROWS: {
+        if (value < CPD_K2ROWS_MIN || value > 64)
+            return fail(CONCPD_EINVAL, "mode-2 chunk rows %lld not in [%d, 64]", (long long)value, CPD_K2ROWS_MIN);
+        Lists L;
+        build_lists(&c->cfg, &L, (int)value);
+        c->lists.k2 = L.k2;
+        HIPCHECK(hipMemcpy(c->ws + c->lay.itk2, c->lists.k2.data(), c->lists.k2.size() * sizeof(ItemK2), hipMemcpyHostToDevice));
+        c->k2rows = (int)value;
+        c->geo.k2rows = (int)value;
+        for (int s = 0; s < c->S; ++s) c->geo.nk2[s] = (int)((c->dims[3 * s] + value - 1) / value);
+        HIPCHECK(hipMemcpy(c->dgeo, &c->geo, sizeof(Geo), hipMemcpyHostToDevice));
+        c->drop_graph();
+        return CONCPD_OK;
+    }
+    default:
+        return fail(CONCPD_EINVAL, "unknown option %d", option);
+    }
+}
+
+concpd_status concpd_get_option(concpd_ctx c, int32_t option, int64_t* value) {
+    if (!c || !value) return fail(CONCPD_EINVAL, "NULL argument");
+    switch (option) {
+    case CONCPD_OPT_GRAPH_SWEEPS: *value = c->graph_sweeps; return CONCPD_OK;
+    case CONCPD_OPT_OVERLAP: *value = c->overlap; return CONCPD_OK;
+    case CONCPD_OPT_K2_ROWS: *value = c->k2rows; return CONCPD_OK;
+    default: return fail(CONCPD_EINVAL, "unknown option %d", option);
+    }
+}
+
+concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) {
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    if (sweeps < 1 || sweeps > 10000) return fail(CONCPD_EINVAL, "sweeps %d not in [1, 10000]", sweeps);
+    Ctrl h;
+    HIPCHECK(hipMemcpyAsync(&h, c->ctrl, sizeof h, hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    if (h.stop) return fail(CONCPD_ESTATE, "autotune needs an iterate that has not converged");
+    const Layout& P = c->lay;
+    const size_t wbytes = c->lra ? sizeof(double) * 2 * (size_t)c->geo.wslot_len : 0;
+    char* wlive = c->lra ? c->ws + P.lra + sizeof(double) * (size_t)c->geo.woff[0][0] : nullptr;
+    auto snapshot = [&]() -> concpd_status {
+        HIPCHECK(hipMemcpyAsync(c->ws + P.snap, c->ws + P.ctrl, P.snap_len, hipMemcpyDeviceToDevice, c->q));
+        if (wbytes) HIPCHECK(hipMemcpyAsync(c->ws + P.snap_w, wlive, wbytes, hipMemcpyDeviceToDevice, c->q));
+        return CONCPD_OK;
+    };
+    auto restore = [&]() -> concpd_status {
+        HIPCHECK(hipMemcpyAsync(c->ws + P.ctrl, c->ws + P.snap, P.snap_len, hipMemcpyDeviceToDevice, c->q));
+        if (wbytes) HIPCHECK(hipMemcpyAsync(wlive, c->ws + P.snap_w, wbytes, hipMemcpyDeviceToDevice, c->q));
+        return CONCPD_OK;
+    };
+    concpd_status r = snapshot();
+    if (r != CONCPD_OK) return r;
+    const int prof = c->profiling, ov = c->overlap;
+    c->profiling = 0;
+    c->overlap = 0;
+    const int k2c[3] = {8, 16, 32};
+    const int gsc[3] = {0, 1, 4};
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    double best = INFINITY, dflt = INFINITY;
+    int bk = c->k2rows, bg = c->graph_sweeps, ncand = 0;
+    for (int ki = 0; ki < 3; ++ki) {
+        if (c->lra && ki > 0) break;   // the mode-2 contraction is not on the lra path
+        r = concpd_set_option(c, CONCPD_OPT_K2_ROWS, k2c[ki]);
+        if (r != CONCPD_OK) break;
+        for (int gi = 0; gi < 3; ++gi) {
+            r = concpd_set_option(c, CONCPD_OPT_GRAPH_SWEEPS, gsc[gi]);
+            if (r != CONCPD_OK) break;
+            if ((r = restore()) != CONCPD_OK) break;
+            if ((r = launch_sweeps(c, 4)) != CONCPD_OK) break;   // warm-up (and graph capture)
+            if ((r = restore()) != CONCPD_OK) break;
+            HIPCHECK(hipEventRecord(e0, c->q));
+            if ((r = launch_sweeps(c, sweeps)) != CONCPD_OK) break;
+            HIPCHECK(hipEventRecord(e1, c->q));
+            HIPCHECK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1e3 * ms / sweeps;
+            ++ncand;
+            if (k2c[ki] == CPD_K2ROWS_DEFAULT && gsc[gi] == 0) dflt = us;
+            if (us < best) {
+                best = us;
+                bk = k2c[ki];
+                bg = gsc[gi];
+            }
+        }
+        if (r != CONCPD_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->profiling = prof;
+    c->overlap = ov;
+    if (r != CONCPD_OK) return r;
+    if (!c->lra) {
+        r = concpd_set_option(c, CONCPD_OPT_K2_ROWS, bk);
+        if (r != CONCPD_OK) return r;
+    }
+    r = concpd_set_option(c, CONCPD_OPT_GRAPH_SWEEPS, bg);
+    if (r != CONCPD_OK) return r;
+    r = restore();
+    if (r != CONCPD_OK) return r;
+    HIPCHECK(hipStreamSynchronize(c->q));
+    if (out) {
+        out->k2_rows = c->k2rows;
+        out->graph_sweeps = bg;
+        out->us_per_sweep = best;
+        out->us_per_sweep_default = dflt;
+        out->candidates = ncand;
+    }
     return CONCPD_OK;
 }
 

@@ -152,6 +152,56 @@ class CoupledCP:
         src = getattr(self, "_ranks_c", None) or self._tucker_c
         return [int(src[3 * s + n]) for n in range(3)]
 
+    def loss_grad(self, U, lam, coupled: bool = False):
+        """F and its gradients at the point (U [n][s] device tensors I_n x R in the
+        factor type, lam [s] device float64 R-vectors).  Returns (F, gU [n][s],
+        glam [s]); with coupled=True the shared columns come from block 0 and
+        every block receives the gradient with respect to them (summed over s)."""
+        import torch
+
+        ftype = torch.float64 if self.compute == "f64" else torch.float32
+        dev = self.tensors[0].device
+        Uc = [[None] * self.S for _ in range(3)]
+        for n in range(3):
+            for s in range(self.S):
+                t = U[n][s]
+                if t.dtype != ftype or t.device != dev or tuple(t.shape) != (self.dims[s][n], self.R):
+                    raise ValueError(f"U[{n}][{s}] must be a {ftype} tensor of shape {(self.dims[s][n], self.R)} on {dev}")
+                Uc[n][s] = t.contiguous()
+        lc = []
+        for s in range(self.S):
+            t = lam[s]
+            if t.dtype != torch.float64 or t.device != dev or t.numel() != self.R:
+                raise ValueError(f"lam[{s}] must be a float64 tensor of {self.R} entries on {dev}")
+            lc.append(t.contiguous())
+        gU = [[torch.empty_like(Uc[n][s]) for s in range(self.S)] for n in range(3)]
+        gl = [torch.empty_like(lc[s]) for s in range(self.S)]
+        order = [(n, s) for s in range(self.S) for n in range(3)]
+        pU = _void_ptr_array([Uc[n][s].data_ptr() for n, s in order])
+        pL = _void_ptr_array([t.data_ptr() for t in lc])
+        pgU = _void_ptr_array([gU[n][s].data_ptr() for n, s in order])
+        pgL = _void_ptr_array([t.data_ptr() for t in gl])
+        F = ctypes.c_double()
+        torch.cuda.current_stream(dev).synchronize()
+        check(self._lib.concpd_loss_grad(self.ctx, pU, pL, int(bool(coupled)), ctypes.byref(F), pgU, pgL))
+        return F.value, gU, gl
+
+    # -- launch options (batching form) -------------------------------------
+    _OPTS = {"graph_sweeps": _lib.OPT_GRAPH_SWEEPS, "overlap": _lib.OPT_OVERLAP, "k2_rows": _lib.OPT_K2_ROWS}
+
+    def set_option(self, name: str, value: int) -> None:
+        check(self._lib.concpd_set_option(self.ctx, self._OPTS[name], int(value)))
+
+    def get_option(self, name: str) -> int:
+        v = ctypes.c_int64()
+        check(self._lib.concpd_get_option(self.ctx, self._OPTS[name], ctypes.byref(v)))
+        return v.value
+
+    def autotune(self, sweeps: int = 20) -> dict:
+        t = _lib.Tuning()
+        check(self._lib.concpd_autotune(self.ctx, int(sweeps), ctypes.byref(t)))
+        return t.as_dict()
+
     def stats(self) -> dict:
         return self.step(0)
 

@@ -1,0 +1,176 @@
+"""Batching form: graph replay of sweeps, launch options, the autotuner, and
+grouped launches over many blocks of uneven size (EEG-shaped workloads), in
+FP32 and in the BF16-operand precision form.
+
+Graph replays are checked bitwise against eager launches of an identical
+context after every replay, with eager work and synchronisations between
+them.  Precision-form tolerances: FP32 1e-5 per teacher-forced step; BF16
+operands 2e-2 per step and final fit within 1e-3 of the FP64 oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import apg
+from oracle.apg import DenseData, Options
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / n if n > 0 else np.linalg.norm(a - b)
+
+
+def model(P, U0, lam0, compute="f32", **kw):
+    import torch
+    from paper_2302_05119_amd import CoupledCP
+    dev = torch.device("cuda:0")
+    tens = [torch.from_numpy(np.ascontiguousarray(X)).to(dev) for X in P.tensors]
+    return CoupledCP(tens, P.R, P.L, compute=compute, init_U=U0, init_lambda=lam0, **kw)
+
+
+def factors(m):
+    return [m.factor(n, s) for n in range(3) for s in range(m.S)]
+
+
+@pytest.mark.parametrize("gs", [1, 4])
+def test_graph_replay_matches_eager(gs):
+    import torch
+    say(f"[graph] sweeps per graph = {gs}")
+    L = (2, 0, 0)
+    P = synth.coupled_problem([(24, 40, 33), (24, 17, 50), (24, 29, 8)], 6, L, 10.0, 801)
+    U0, lam0 = synth.uniform_init(P.dims, 6, L, 802)
+    me = model(P, U0, lam0)
+    mg = model(P, U0, lam0)
+    mg.set_option("graph_sweeps", gs)
+    assert mg.get_option("graph_sweeps") == gs
+    scratch = torch.zeros(1 << 20, device="cuda:0")
+    for rep in range(5):
+        se = me.step(gs)
+        sg = mg.step(gs)
+        # eager work of the program between replays
+        scratch.add_(1.0)
+        torch.cuda.synchronize()
+        assert se["k"] == sg["k"] and se["F"] == sg["F"] and se["restarts"] == sg["restarts"], (rep, se, sg)
+        for a, b in zip(factors(me), factors(mg)):
+            np.testing.assert_array_equal(a, b)
+    # asynchronous replays, then a synchronised check
+    me.step(3 * gs, sync=False)
+    mg.step(3 * gs, sync=False)
+    for a, b in zip(factors(me), factors(mg)):
+        np.testing.assert_array_equal(a, b)
+    assert float(scratch[0]) == 5.0
+
+
+def test_k2_rows_option_within_tolerance():
+    say("[options] mode-2 chunk rows")
+    L = (3, 0, 0)
+    P = synth.coupled_problem([(70, 45, 40)] * 3, 8, L, 10.0, 811)
+    U0, lam0 = synth.uniform_init(P.dims, 8, L, 812)
+    ref = apg.run(DenseData(P.tensors), U0, lam0, Options(L=L), iters=3)
+    for k2 in (8, 16, 32, 64):
+        m = model(P, U0, lam0)
+        m.set_option("k2_rows", k2)
+        s = m.step(3)
+        e = max(rel(m.factor(n, b), ref.U[n][b]) for n in range(3) for b in range(3))
+        say(f"   k2_rows={k2} F={s['F']:.10e} oracle={ref.F:.10e} max factor err={e:.2e}")
+        assert abs(s["F"] - ref.F) / ref.F <= 1e-5 and e <= 1e-4
+
+
+def test_autotune_keeps_the_iterate():
+    say("[autotune]")
+    L = (5, 0, 0)
+    P = synth.coupled_problem([(60, 60, 60)] * 4, 10, L, 10.0, 821)
+    U0, lam0 = synth.uniform_init(P.dims, 10, L, 822)
+    m = model(P, U0, lam0)
+    m.step(2)
+    before, st0 = factors(m), m.stats()
+    t = m.autotune(8)
+    say(f"   {t}")
+    assert t["candidates"] == 9 and t["k2_rows"] in (8, 16, 32) and t["graph_sweeps"] in (0, 1, 4)
+    assert t["us_per_sweep"] <= t["us_per_sweep_default"]
+    st1 = m.stats()
+    assert st1["k"] == st0["k"] and st1["F"] == st0["F"]
+    for a, b in zip(before, factors(m)):
+        np.testing.assert_array_equal(a, b)
+    s = m.step(3)
+    assert s["k"] == st0["k"] + 3
+
+
+def eeg_small(seed, S=6, T=(20, 90), R=6):
+    return synth.eeg_problem(S, T, R, 5.0, seed, channels=16, freqs=12)
+
+
+@pytest.mark.parametrize("compute,tol", [("f32", 1e-5), ("bf16", 2e-2), ("f16", 2e-2)])
+def test_uneven_eeg_blocks_teacher_forced(compute, tol):
+    say(f"[eeg] uneven blocks, compute={compute}")
+    P = eeg_small(831)
+    R, L = P.R, P.L
+    U0, lam0 = synth.uniform_init(P.dims, R, L, 832)
+    data = DenseData(P.tensors)
+    opt = Options(L=L)
+    st = apg.run(data, U0, lam0, opt, iters=2)
+    st.U = [[u.astype(np.float32).astype(np.float64) for u in per] for per in st.U]
+    st.U_prev = [[u.astype(np.float32).astype(np.float64) for u in per] for per in st.U_prev]
+    st.F = apg.objective(data, st.lam, st.U)
+    st.relerr = apg.relerr(data, st.lam, st.U)
+    m = model(P, st.U, st.lam, compute=compute)
+    Lu_prev = [[st.Lu_prev[n][s] for n in range(3)] for s in range(P.S)]
+    m.set_state(st.U, st.lam, st.U_prev, st.lam_prev, st.Ld_prev, Lu_prev, st.LC_prev, t=st.t, k=st.k)
+    new = apg.iterate(data, st, opt)
+    s1 = m.step(1)
+    errs = [rel(m.factor(n, b), new.U[n][b]) for n in range(3) for b in range(P.S)]
+    errs += [rel(m.lam(b), new.lam[b]) for b in range(P.S)]
+    say(f"   F gpu={s1['F']:.10e} oracle={new.F:.10e}; worst factor/lambda error {max(errs):.2e}")
+    assert abs(s1["F"] - new.F) / new.F <= tol
+    assert max(errs) <= tol
+
+
+def test_eeg_bf16_final_fit_matches_oracle():
+    say("[eeg] BF16 operands, final fit")
+    P = synth.eeg_problem(8, (40, 160), 10, 5.0, 841, channels=16, freqs=15)
+    U0, lam0 = synth.uniform_init(P.dims, P.R, P.L, 842)
+    ref = apg.run(DenseData(P.tensors), U0, lam0, Options(L=P.L), iters=100)
+    rf = apg.fit(P.tensors, ref.lam, ref.U)
+    for compute in ("bf16", "f16"):
+        m = model(P, U0, lam0, compute=compute)
+        m.step(100)
+        gf = m.global_fit()
+        say(f"   {compute}: global fit gpu={gf:.6f} oracle={rf:.6f}")
+        assert abs(gf - rf) <= 1e-3
+
+
+def test_full_size_c4_eeg_teacher_forced_fp32_and_bf16_fit():
+    # 16 EEG-shaped blocks 64 x 60 x T_s, T_s in [200, 2000], R = 30, channel
+    # and frequency factors fully shared, 5 dB
+    name = "c4_eeg_bf16_16blocks_r30"
+    say("[c4 full] teacher-forced FP32 iteration; BF16 vs FP32 fit")
+    P = synth.make_workload(name)
+    U0, lam0 = synth.workload_init(name, P)
+    U0 = [[u.astype(np.float32).astype(np.float64) for u in per] for per in U0]
+    data = DenseData(P.tensors)
+    opt = Options(L=P.L)
+    new = apg.iterate(data, apg.initial_state(data, U0, lam0), opt)
+    m = model(P, U0, lam0, compute="f32")
+    s1 = m.step(1)
+    say(f"   F gpu={s1['F']:.10e} oracle={new.F:.10e}")
+    assert abs(s1["F"] - new.F) / new.F <= 1e-5
+    for b in (0, P.S - 1):
+        for n in range(3):
+            assert rel(m.factor(n, b), new.U[n][b]) <= 1e-5
+    m.step(59)
+    mb = model(P, U0, lam0, compute="bf16")
+    mb.step(60)
+    f32, fb = m.global_fit(), mb.global_fit()
+    say(f"   60 iterations: global fit FP32 {f32:.6f}  BF16 {fb:.6f}")
+    assert abs(f32 - fb) <= 1e-3
