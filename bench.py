@@ -120,6 +120,70 @@ def lra_leg(steps: int, warmup: int, dense_steps: int = 30):
             "restarts": st["restarts"]}
 
 
+def precision_leg(P, U0, lam0, w, steps, fit_fp32, k_fp32):
+    """Precision form on the same workload: BF16 tensor operands (FP32
+    accumulation, FP64 small work), iterations/s and the fit after as many
+    iterations as the FP32 run, against the FP32 fit."""
+    import torch
+
+    from paper_2302_05119_amd import CoupledCP
+
+    dev = torch.device("cuda:0")
+    tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
+    m = CoupledCP(tens, w["R"], w["L"], compute="bf16", init_U=U0, init_lambda=lam0)
+    m.autotune(20)
+    m.step(10)
+    k0 = m.stats()["k"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(steps, sync=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = m.stats()
+    rate = (st["k"] - k0) / (t1 - t0)
+    if st["k"] < k_fp32:
+        m.step(int(k_fp32 - st["k"]))
+    st = m.stats()
+    return {"workload": WORKLOAD, "dtype": "bf16 operands, fp32 accumulation", "iter_per_s": rate,
+            "fit_after_same_iterations": st["fit"], "fit_fp32": fit_fp32, "fit_delta": st["fit"] - fit_fp32,
+            "iterations": st["k"]}
+
+
+def batched_leg(steps):
+    """Batching form on the EEG-shaped workload (16 blocks 64 x 60 x T_s, T_s
+    in [200, 2000], R = 30, channel and frequency factors shared): every mode
+    is one grouped launch over the uneven blocks, sweeps replay from a captured
+    graph when the autotuner picks it; BF16 operands, against FP32."""
+    import torch
+
+    import synth
+    from paper_2302_05119_amd import CoupledCP
+
+    name = "c4_eeg_bf16_16blocks_r30"
+    w = synth.WORKLOADS[name]
+    P = synth.make_workload(name)
+    U0, lam0 = synth.workload_init(name, P)
+    dev = torch.device("cuda:0")
+    tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
+    res = {"workload": name, "blocks": P.S, "T_s": P.meta["T"], "rank": P.R}
+    for compute in ("fp32", "bf16"):
+        m = CoupledCP(tens, P.R, P.L, compute="f32" if compute == "fp32" else "bf16", init_U=U0, init_lambda=lam0)
+        tune = m.autotune(10)
+        m.step(5)
+        k0 = m.stats()["k"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.step(steps, sync=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = m.stats()
+        res[compute] = {"iter_per_s": (st["k"] - k0) / (t1 - t0), "fit": st["fit"], "global_fit": m.global_fit(),
+                        "iterations": st["k"], "tuning": tune}
+        del m
+    res["fit_delta_bf16"] = res["bf16"]["global_fit"] - res["fp32"]["global_fit"]
+    return res
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
     """Plain device copies of known size: the HBM byte counters read on these
     calibrate the counters read on the path's kernels."""
@@ -142,6 +206,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lra-steps", type=int, default=300, help="iterations of the lra leg (0: skip it)")
+    ap.add_argument("--forms-steps", type=int, default=200, help="iterations of the BF16 and batched legs (0: skip)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="time the default launch configuration instead of the autotuned one")
     ap.add_argument("--copy-calibration", action="store_true", help="only run the copy kernels used to "
                     "calibrate HBM byte counters")
     args = ap.parse_args()
@@ -166,6 +233,7 @@ def main():
     tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
     m = CoupledCP(tens, w["R"], w["L"], compute="f32", init_U=U0, init_lambda=lam0)
     s_init = m.stats()
+    tuning = m.autotune(20) if args.autotune else None
 
     m.step(args.warmup, sync=False)
     k0 = m.stats()["k"]
@@ -224,6 +292,10 @@ def main():
         "fit": {"after_steps": st["fit"], "global": gfit, "initial": s_init["fit"], "restarts": st["restarts"],
                 "iterations": st["k"], "sweeps_timed": args.steps, "iterations_timed": accepted},
     }
+    out["tuning"] = tuning
+    if args.forms_steps > 0:
+        out["bf16_c2"] = precision_leg(P, U0, lam0, w, args.forms_steps, st["fit"], st["k"])
+        out["batched_c4"] = batched_leg(args.forms_steps)
     if args.lra_steps > 0:
         out["lra"] = lra_leg(args.lra_steps, max(1, args.warmup // 2))
     if not args.no_cpu_baseline:

@@ -55,6 +55,8 @@ struct Geo {
     long long k2off[CPD_MAXS];    // mode-2 MTTKRP partials per chunk of k2rows i1 rows: nk2 x I2 x Rq
     int nk2[CPD_MAXS];            // ceil(I1 / k2rows)
     int k2rows;                   // i1 rows per mode-2 contraction chunk
+    int mvec[CPD_MAXS];           // 1: every operand row starts 16-byte aligned (vector loads)
+    long long mld[CPD_MAXS];      // row stride (elements) of the operand tensor M[s]
     int nrg[CPD_MAXS];            // ceil(I2 / 64)
     const void* M[CPD_MAXS];      // block tensors in the MTTKRP operand type
     int mdtype;                   // operand type of M (concpd_dtype)
@@ -116,6 +118,6 @@ void launch_grad(const Geo* g, const StateP<T>& st, int S, int R, int Rq, const 
 inline size_t lra_c_lds_bytes(int Jmax, int Rq) { return sizeof(double) * ((size_t)Jmax * Jmax + 2 * (size_t)Jmax * Rq + 256); }
 template <typename T> void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int Rq, int n, hipStream_t q);
 void launch_sum_parts(const double* part, int np, double* out, hipStream_t q);
-void launch_convert(const void* src, int dst_dtype, void* dst, long long n, hipStream_t q);
+void launch_pad_copy(const void* src, int src_dtype, void* dst, int dst_dtype, long long rows, int I3, int ld, hipStream_t q);
 void launch_finite_check(const void* src, int dtype, long long n, int* flag, hipStream_t q);
 }  // namespace cpd

@@ -35,18 +35,16 @@ __global__ void k_sum_parts(const double* __restrict__ part, int np, double* __r
     *out = acc;
 }
 
-template <typename TD>
-__global__ __launch_bounds__(256) void k_convert_f32(const float* __restrict__ x, TD* __restrict__ y, long long n) {
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) y[i] = (TD)x[i];
-}
-template <>
-__global__ __launch_bounds__(256) void k_convert_f32<__hip_bfloat16>(const float* __restrict__ x, __hip_bfloat16* __restrict__ y,
-                                                                      long long n) {
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) y[i] = __float2bfloat16(x[i]);
-}
-template <>
-__global__ __launch_bounds__(256) void k_convert_f32<__half>(const float* __restrict__ x, __half* __restrict__ y, long long n) {
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) y[i] = __float2half(x[i]);
+// Operand copy of a tensor with every row padded to ld elements (zeros), so
+// each row starts 16-byte aligned: y[r][c] = x[r][c] for c < I3, else 0.
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_pad_copy(const TS* __restrict__ x, TD* __restrict__ y, long long rows, int I3, int ld) {
+    const long long n = rows * ld;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const long long r = i / ld;
+        const int c = (int)(i % ld);
+        y[i] = c < I3 ? (TD)x[r * I3 + c] : (TD)0.0f;
+    }
 }
 
 template <typename TS>
@@ -101,11 +99,16 @@ void launch_sqnorm(const void* src, int dtype, long long n, double* out, double*
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, q, part, npart, out);
 }
 
-void launch_convert(const void* src, int dst_dtype, void* dst, long long n, hipStream_t q) {
-    long long nb = (n + 255) / 256;
+void launch_pad_copy(const void* src, int src_dtype, void* dst, int dst_dtype, long long rows, int I3, int ld, hipStream_t q) {
+    long long nb = (rows * ld + 255) / 256;
     if (nb > 8192) nb = 8192;
-    if (dst_dtype == 2) hipLaunchKernelGGL(k_convert_f32<__hip_bfloat16>, dim3((unsigned)nb), dim3(256), 0, q, (const float*)src, (__hip_bfloat16*)dst, n);
-    else hipLaunchKernelGGL(k_convert_f32<__half>, dim3((unsigned)nb), dim3(256), 0, q, (const float*)src, (__half*)dst, n);
+    if (nb < 1) nb = 1;
+    const dim3 gr((unsigned)nb), bl(256);
+    if (src_dtype == 0) hipLaunchKernelGGL((k_pad_copy<double, double>), gr, bl, 0, q, (const double*)src, (double*)dst, rows, I3, ld);
+    else if (dst_dtype == 1) hipLaunchKernelGGL((k_pad_copy<float, float>), gr, bl, 0, q, (const float*)src, (float*)dst, rows, I3, ld);
+    else if (dst_dtype == 2)
+        hipLaunchKernelGGL((k_pad_copy<float, __hip_bfloat16>), gr, bl, 0, q, (const float*)src, (__hip_bfloat16*)dst, rows, I3, ld);
+    else hipLaunchKernelGGL((k_pad_copy<float, __half>), gr, bl, 0, q, (const float*)src, (__half*)dst, rows, I3, ld);
 }
 
 void launch_finite_check(const void* src, int dtype, long long n, int* flag, hipStream_t q) {

@@ -31,7 +31,11 @@ static void pass2_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g,
 
 template <typename TA>
 static size_t pass1_lds(int Rq) {
-    size_t a = sizeof(TA) * 4 * 64 * (size_t)P1Shape<TA>::STRIDE, b = sizeof(TA) * 4 * 64 * (size_t)Rq;
+    // per wave: the transposed U3 chunk (KC x 4 x RTP, RTP <= Rq / 4 + 3);
+    // then the cross-wave reduction (4 x 64 x Rq)
+    const size_t va = 16 / sizeof(TA), rtp = ((size_t)Rq / 4 + va - 1) / va * va;
+    size_t a = sizeof(TA) * 4 * (size_t)P1Shape<TA>::KC * 4 * rtp;
+    size_t b = sizeof(TA) * 4 * 64 * (size_t)Rq;
     return a > b ? a : b;
 }
 
@@ -39,8 +43,9 @@ template <typename TM, typename T>
 static void pass2_dispatch(int Rq, dim3 grid, int maxI2, hipStream_t q, const Geo* g, const StateP<T>& st,
                            const ItemP2* items, int slot) {
     typedef typename AccType<TM>::type TA;
+    const size_t va = 16 / sizeof(TA), rtp = ((size_t)Rq / 4 + va - 1) / va * va;
     const size_t red = sizeof(TA) * 4 * 64 * (size_t)Rq;
-    const size_t bst = sizeof(TA) * (size_t)maxI2 * Rq;
+    const size_t bst = sizeof(TA) * (size_t)maxI2 * 4 * rtp;   // transposed U2
     if (bst <= 49152) pass2_rt<TM, T, true>(Rq / 4, grid, bst > red ? bst : red, q, g, st, items, slot);
     else pass2_rt<TM, T, false>(Rq / 4, grid, red, q, g, st, items, slot);
 }

@@ -82,42 +82,99 @@ __global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP
     const int I2 = g->I[s][1], I3 = g->I[s][2], Rq = g->Rq;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nrows = min(64, I2 - row0);
+    // epilogue mapping (phase, column) and its U2 values, loaded now so their
+    // latency overlaps the main loop
+    // (Rq = 4 RT, so there are 64 / RT phases and at most EPQ rows per thread)
+    constexpr int EPR = 64 / RT, EPQ = (64 + EPR - 1) / EPR;
+    const int ep_rp = EPR, ep_j = threadIdx.x / Rq, ep_c = threadIdx.x % Rq;
+    const bool ep_on = ep_j < ep_rp;
+    T u2v[EPQ];
+    double ep_part = 0.0;
+    {
+        const CPD_GLOBAL T* __restrict__ U2 = gptr(st.U[1] + g->uoff[1][s] + (long long)row0 * Rq);
+#pragma unroll
+        for (int q = 0; q < EPQ; ++q) {
+            const int r = ep_j + q * ep_rp;
+            u2v[q] = (ep_on && r < nrows) ? U2[(long long)r * Rq + ep_c] : (T)0;
+        }
+    }
     typedef typename Raw<TM>::type TR;
-    const CPD_GLOBAL TR* __restrict__ Ms = gptr((const TR*)g->M[s] + ((long long)i1 * I2 + row0) * I3);
+    const long long ldm = g->mld[s];   // operand row stride (>= I3)
+    const CPD_GLOBAL TR* __restrict__ Ms = gptr((const TR*)g->M[s] + ((long long)i1 * I2 + row0) * ldm);
     const CPD_GLOBAL T* __restrict__ U3 = gptr(pick3(st.U, slot) + g->uoff[2][s]);
     TA* sm = (TA*)smraw;
-    constexpr int KC = P1Shape<TA>::KC, STRIDE = P1Shape<TA>::STRIDE, RPI = 64 / KC;
-    TA* stage = sm + wave * 64 * STRIDE;
+    constexpr int KC = P1Shape<TA>::KC;
+    constexpr int VE = 16 / (int)sizeof(TR);          // tensor elements per 16-byte load
+    constexpr int VA = 16 / (int)sizeof(TA);          // operand elements per 16-byte LDS read
+    constexpr int RTP = (RT + VA - 1) / VA * VA;      // padded operand run per lane
+    constexpr int UPL = (KC * 4 * RT + 63) / 64;      // U3 chunk elements loaded per lane
+    // U3 rows of the chunk, transposed so that lane l's operands
+    // U3[k][4t + l%4], t < RT, are one contiguous run: [KC][4][RTP]
+    TA* ustage = sm + wave * (KC * 4 * RTP);
 
-    const int kq = (I3 + 3) / 4;
+    // the four wavefronts split i3 at multiples of KC (so chunks stay aligned)
+    const int kq = ((I3 + 3) / 4 + KC - 1) / KC * KC;
     const int kb = min(I3, wave * kq), ke = min(I3, kb + kq);
     Acc4<TA> acc[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) acc[t].zero();
 
-    const int cc = lane % KC, rsub = lane / KC;
-    for (int k0 = kb; k0 < ke; k0 += KC) {
+    // Lane l owns tensor row l of the row group (rows past the group repeat
+    // its last row; their outputs are never stored) and keeps its KC
+    // consecutive elements of the chunk in registers as the A operand: 16-byte
+    // loads when every row of the block starts 16-byte aligned.  The next
+    // chunk is loaded while the current one is consumed.
+    const bool vec = g->mvec[s] != 0;
+    const CPD_GLOBAL TR* __restrict__ Mrow = Ms + (long long)min(lane, nrows - 1) * ldm;
+    TA buf[KC], nbuf[KC], ubuf[UPL], nubuf[UPL];
+    auto load_chunk = [&](int k0, TA (&ab)[KC], TA (&ub)[UPL]) {
         const int kc = min(KC, ke - k0);
-        TA buf[KC];
+        if (vec && kc == KC) {
+            const CPD_GLOBAL u32x4* vp = (const CPD_GLOBAL u32x4*)(Mrow + k0);
 #pragma unroll
-        for (int j = 0; j < KC; ++j) {
-            const int r = j * RPI + rsub;
-            buf[j] = (r < nrows && cc < kc) ? cvt<TA, TM>(Ms[(long long)r * I3 + k0 + cc]) : (TA)0;
+            for (int v = 0; v < KC / VE; ++v) {
+                const u32x4 w = vp[v];
+                const TR* e = (const TR*)&w;
+#pragma unroll
+                for (int j = 0; j < VE; ++j) ab[v * VE + j] = cvt<TA, TM>(e[j]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < KC; ++j) {
+                const TA v = cvt<TA, TM>(Mrow[k0 + min(j, kc - 1)]);
+                ab[j] = (j < kc) ? v : (TA)0;
+            }
         }
 #pragma unroll
-        for (int j = 0; j < KC; ++j) stage[(j * RPI + rsub) * STRIDE + cc] = buf[j];
-        wave_sync();
-        const CPD_GLOBAL T* __restrict__ urow = U3 + (long long)k0 * Rq + (lane & 3);
-#pragma unroll 4
-        for (int kk = 0; kk < kc; ++kk) {
-            const TA a = stage[lane * STRIDE + kk];
-            TA bb[RT];
+        for (int q = 0; q < UPL; ++q) {
+            const int e = q * 64 + lane, kk = e / (4 * RT), c = e % (4 * RT);
+            const TA v = (TA)U3[(long long)(k0 + min(kk, kc - 1)) * Rq + c];
+            ub[q] = (kk < kc) ? v : (TA)0;
+        }
+    };
+    if (kb < ke) load_chunk(kb, buf, ubuf);
+    for (int k0 = kb; k0 < ke; k0 += KC) {
 #pragma unroll
-            for (int t = 0; t < RT; ++t) bb[t] = (TA)urow[(long long)kk * Rq + 4 * t];
-#pragma unroll
-            for (int t = 0; t < RT; ++t) acc[t].mma(a, bb[t]);
+        for (int q = 0; q < UPL; ++q) {
+            const int e = q * 64 + lane, kk = e / (4 * RT), c = e % (4 * RT);
+            if (e < KC * 4 * RT) ustage[(kk * 4 + (c & 3)) * RTP + (c >> 2)] = ubuf[q];
         }
         wave_sync();
+        if (k0 + KC < ke) load_chunk(k0 + KC, nbuf, nubuf);
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            TA bb[RTP];
+            const TA* ur = ustage + (kk * 4 + (lane & 3)) * RTP;
+#pragma unroll
+            for (int v = 0; v < RTP / VA; ++v) *(u32x4*)&bb[v * VA] = *(const u32x4*)(ur + v * VA);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) acc[t].mma(buf[kk], bb[t]);
+        }
+        wave_sync();
+#pragma unroll
+        for (int j = 0; j < KC; ++j) buf[j] = nbuf[j];
+#pragma unroll
+        for (int q = 0; q < UPL; ++q) ubuf[q] = nubuf[q];
     }
     __syncthreads();
     TA* red = sm;  // [4 waves][64 rows][Rq]
@@ -127,23 +184,34 @@ __global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP
         for (int v = 0; v < 4; ++v)
             red[(wave * 64 + 4 * (lane >> 2) + v) * Rq + 4 * t + (lane & 3)] = acc[t].get(v);
     __syncthreads();
+    // Epilogue: thread (phase j, column c) with Rq * RP <= 256 sums the four
+    // wave partials of rows j, j + RP, ..., writes Y, and accumulates the
+    // mode-1 partial sum_r Y[r][c] U2_old[row0 + r][c] over its rows (U2
+    // prefetched at kernel start); the RP phase sums are added in fixed order.
     CPD_GLOBAL T* __restrict__ Y = gptr_w(st.Y + g->yoff[s] + ((long long)i1 * I2 + row0) * Rq);
-    for (int e = threadIdx.x; e < nrows * Rq; e += 256) {
-        const int r = e / Rq, c = e % Rq;
-        const TA v = red[(0 * 64 + r) * Rq + c] + red[(1 * 64 + r) * Rq + c] + red[(2 * 64 + r) * Rq + c] +
-                     red[(3 * 64 + r) * Rq + c];
-        Y[(long long)r * Rq + c] = (T)v;
-        red[r * Rq + c] = (TA)(T)v;
+    if (ep_on) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < EPQ; ++q) {
+            const int r = ep_j + q * ep_rp;
+            if (r < nrows) {
+                const TA v = red[(0 * 64 + r) * Rq + ep_c] + red[(1 * 64 + r) * Rq + ep_c] + red[(2 * 64 + r) * Rq + ep_c] +
+                             red[(3 * 64 + r) * Rq + ep_c];
+                const T yv = (T)v;
+                Y[(long long)r * Rq + ep_c] = yv;
+                a += (double)yv * (double)u2v[q];
+            }
+        }
+        ep_part = a;
     }
     __syncthreads();
-    // mode-1 partial over this row group: sum_r Y[r][c] U2_old[row0 + r][c]
+    double* kp = (double*)smraw;   // [RP][Rq]
+    if (ep_on) kp[ep_j * Rq + ep_c] = ep_part;
+    __syncthreads();
     if (threadIdx.x < Rq) {
-        const int c = threadIdx.x;
-        const CPD_GLOBAL T* __restrict__ U2 = gptr(st.U[1] + g->uoff[1][s] + (long long)row0 * Rq + c);
         double a = 0.0;
-#pragma unroll 8
-        for (int r = 0; r < nrows; ++r) a += (double)red[r * Rq + c] * (double)U2[(long long)r * Rq];
-        gptr_w(st.K1p)[g->k1off[s] + ((long long)i1 * g->nrg[s] + rg) * Rq + c] = (T)a;
+        for (int j = 0; j < ep_rp; ++j) a += kp[j * Rq + threadIdx.x];
+        gptr_w(st.K1p)[g->k1off[s] + ((long long)i1 * g->nrg[s] + rg) * Rq + threadIdx.x] = (T)a;
     }
 }
 
@@ -168,9 +236,24 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
     const int i3 = q0 + lane;
     const bool valid = i3 < I3;
     TA* sm = (TA*)smraw;
+    constexpr int VA = 16 / (int)sizeof(TA);          // operand elements per 16-byte LDS read
+    constexpr int RTP = (RT + VA - 1) / VA * VA;      // padded operand run per lane
     const CPD_GLOBAL T* __restrict__ U2g = gptr(pick3(st.U, slot) + g->uoff[1][s]);
+    // U1 row of this slab (the scale of the mode-3 partial), loaded now
+    TA u1v[RT];
+    {
+        const CPD_GLOBAL T* __restrict__ U1 =
+            gptr(pick3(st.U, slot) + g->uoff[0][s] + (long long)min(i1, I1 - 1) * Rq + (lane & 3));
+#pragma unroll
+        for (int t = 0; t < RT; ++t) u1v[t] = (TA)U1[4 * t];
+    }
     if (BLDS) {
-        for (int e = threadIdx.x; e < I2 * Rq; e += 256) sm[e] = (TA)U2g[e];
+        // U2 transposed so that lane l's operands U2[i2][4t + l%4], t < RT,
+        // are one contiguous run: [I2][4][RTP]
+        for (int e = threadIdx.x; e < I2 * Rq; e += 256) {
+            const int i2 = e / Rq, c = e % Rq;
+            sm[(i2 * 4 + (c & 3)) * RTP + (c >> 2)] = (TA)U2g[e];
+        }
         __syncthreads();
     }
     Acc4<TA> z[RT];
@@ -179,23 +262,36 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
     constexpr int NB = 16;
     if (i1 < I1) {
         typedef typename Raw<TM>::type TR;
-        const CPD_GLOBAL TR* __restrict__ Mp = gptr((const TR*)g->M[s] + (long long)i1 * I2 * I3 + (valid ? i3 : 0));
+        const long long ldm = g->mld[s];   // operand row stride (>= I3)
+        const CPD_GLOBAL TR* __restrict__ Mp = gptr((const TR*)g->M[s] + (long long)i1 * I2 * ldm + (valid ? i3 : 0));
         TA cur[NB], nxt[NB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) cur[j] = (valid && j < I2) ? cvt<TA, TM>(Mp[(long long)j * I3]) : (TA)0;
+        for (int j = 0; j < NB; ++j) {
+            // clamped (always valid) address, zero outside: no branch per load
+            const TA v = cvt<TA, TM>(Mp[(long long)min(j, I2 - 1) * ldm]);
+            cur[j] = (valid && j < I2) ? v : (TA)0;
+        }
         for (int i2b = 0; i2b < I2; i2b += NB) {
             const int nb2 = i2b + NB;
 #pragma unroll
-            for (int j = 0; j < NB; ++j) nxt[j] = (valid && nb2 + j < I2) ? cvt<TA, TM>(Mp[(long long)(nb2 + j) * I3]) : (TA)0;
+            for (int j = 0; j < NB; ++j) {
+                const TA v = cvt<TA, TM>(Mp[(long long)min(nb2 + j, I2 - 1) * ldm]);
+                nxt[j] = (valid && nb2 + j < I2) ? v : (TA)0;
+            }
             const int jm = min(NB, I2 - i2b);
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 if (j < jm) {
                     const int i2 = i2b + j;
-                    TA bb[RT];
+                    TA bb[RTP];
+                    if (BLDS) {
+                        const TA* ur = sm + (i2 * 4 + (lane & 3)) * RTP;
 #pragma unroll
-                    for (int t = 0; t < RT; ++t)
-                        bb[t] = BLDS ? sm[i2 * Rq + 4 * t + (lane & 3)] : (TA)U2g[(long long)i2 * Rq + 4 * t + (lane & 3)];
+                        for (int v = 0; v < RTP / VA; ++v) *(u32x4*)&bb[v * VA] = *(const u32x4*)(ur + v * VA);
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) bb[t] = (TA)U2g[(long long)i2 * Rq + 4 * t + (lane & 3)];
+                    }
 #pragma unroll
                     for (int t = 0; t < RT; ++t) z[t].mma(cur[j], bb[t]);
                 }
@@ -203,9 +299,8 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
 #pragma unroll
             for (int j = 0; j < NB; ++j) cur[j] = nxt[j];
         }
-        const CPD_GLOBAL T* __restrict__ U1 = gptr(pick3(st.U, slot) + g->uoff[0][s] + (long long)i1 * Rq + (lane & 3));
 #pragma unroll
-        for (int t = 0; t < RT; ++t) z[t].scale((TA)U1[4 * t]);
+        for (int t = 0; t < RT; ++t) z[t].scale(u1v[t]);
     }
     if (BLDS) __syncthreads();
     TA* red = sm;  // [4 waves][64][Rq]

@@ -36,6 +36,7 @@ concpd_status fail(concpd_status st, const char* fmt, ...) {
     } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+int operand_bytes(int dtype) { return dtype == CONCPD_F64 ? 8 : (dtype == CONCPD_F32 ? 4 : 2); }
 
 struct Layout {
     size_t geo, ctrl, U[3], lam[3], V[2], b[2], P, Ld_cur, Ld_prev, Lu_cur, Lu_prev, LC_prev, Fblk, normM2, normOrig, Y,
@@ -46,7 +47,7 @@ struct Layout {
     // autotuner snapshot of the persistent iterate state (ctrl .. normOrig,
     // and the Tucker-form W slots)
     size_t snap, snap_len, snap_w;
-    long long uslot, ylen, klen, plen, shadow_elems[CPD_MAXS], lra_len;
+    long long uslot, ylen, klen, plen, shadow_elems[CPD_MAXS], shadow_off[CPD_MAXS], shadow_ld[CPD_MAXS], lra_len;
     // lra region (doubles from its base): compression scratch
     long long l_sig, l_part, l_work, l_t1, l_t2, sig_stride, work_stride;
     int nsplit, Imax, Jmax;
@@ -256,13 +257,23 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     P->snap_len = P->normOrig + sizeof(double) * S - P->ctrl;
     P->snap = take(P->snap_len);
     P->snap_w = 0;
-    if (c->compute_dtype == CONCPD_BF16 || c->compute_dtype == CONCPD_F16) {
-        long long tot = 0;
+    {
+        // Operand copies: every block of a 16-bit compute type, and every
+        // block whose rows would not start 16-byte aligned, gets a copy with
+        // rows padded to ld = I3 rounded up to 16 bytes, 256-byte aligned.
+        const int me = operand_bytes(c->compute_dtype), ve = 16 / me;
+        const bool half = c->compute_dtype == CONCPD_BF16 || c->compute_dtype == CONCPD_F16;
+        size_t tot = 0;
         for (int s = 0; s < S; ++s) {
-            P->shadow_elems[s] = c->dims[3 * s] * c->dims[3 * s + 1] * c->dims[3 * s + 2];
-            tot += P->shadow_elems[s];
+            const long long I3 = c->dims[3 * s + 2];
+            const bool copy = half || I3 % ve != 0;
+            const long long ld = (I3 + ve - 1) / ve * ve;
+            P->shadow_ld[s] = copy ? ld : 0;
+            P->shadow_elems[s] = copy ? c->dims[3 * s] * c->dims[3 * s + 1] * ld : 0;
+            P->shadow_off[s] = (long long)tot;
+            if (copy) tot = align256(tot + (size_t)P->shadow_elems[s] * me);
         }
-        P->shadow = take((size_t)tot * 2);
+        P->shadow = tot ? take(tot) : 0;
     }
     if (c->tucker_ranks) {
         long long a = 0;
@@ -865,14 +876,22 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
 
     INIT_HIP(hipMemsetAsync(c->ws, 0, c->lay.total, c->q));
     // operand copies of the tensors
-    for (int s = 0; s < c->S; ++s) c->geo.M[s] = c->tensors[s];
-    if (c->mdtype == CONCPD_BF16 || c->mdtype == CONCPD_F16) {
-        size_t off = c->lay.shadow;
-        for (int s = 0; s < c->S; ++s) {
-            cpd::launch_convert(c->tensors[s], c->mdtype, c->ws + off, c->lay.shadow_elems[s], c->q);
-            c->geo.M[s] = c->ws + off;
-            off += (size_t)c->lay.shadow_elems[s] * 2;
+    for (int s = 0; s < c->S; ++s) {
+        c->geo.M[s] = c->tensors[s];
+        c->geo.mld[s] = c->dims[3 * s + 2];
+        if (c->lay.shadow_ld[s] > 0) {
+            char* dst = c->ws + c->lay.shadow + c->lay.shadow_off[s];
+            cpd::launch_pad_copy(c->tensors[s], cfg->tensor_dtype, dst, c->mdtype, c->dims[3 * s] * c->dims[3 * s + 1],
+                                 (int)c->dims[3 * s + 2], (int)c->lay.shadow_ld[s], c->q);
+            c->geo.M[s] = dst;
+            c->geo.mld[s] = c->lay.shadow_ld[s];
         }
+    }
+    // blocks whose operand rows all start 16-byte aligned take 16-byte loads
+    {
+        const int me = operand_bytes(c->mdtype);
+        for (int s = 0; s < c->S; ++s)
+            c->geo.mvec[s] = (c->geo.mld[s] % (16 / me) == 0) && ((uintptr_t)c->geo.M[s] % 16 == 0);
     }
     c->dgeo = (Geo*)(c->ws + c->lay.geo);
     INIT_HIP(hipMemcpyAsync(c->dgeo, &c->geo, sizeof(Geo), hipMemcpyHostToDevice, c->q));
@@ -897,7 +916,9 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
         const long long n = c->dims[3 * s] * c->dims[3 * s + 1] * c->dims[3 * s + 2];
         cpd::launch_finite_check(c->tensors[s], cfg->tensor_dtype, n, dflag, c->q);
         cpd::launch_sqnorm(c->tensors[s], cfg->tensor_dtype, n, (double*)(c->ws + c->lay.normOrig) + s, scratch, 1024, c->q);
-        cpd::launch_sqnorm(c->geo.M[s], c->mdtype, n, (double*)(c->ws + c->lay.normM2) + s, scratch, 1024, c->q);
+        // the operand copy's padding is zero, so its norm runs over I1 I2 ld
+        cpd::launch_sqnorm(c->geo.M[s], c->mdtype, c->dims[3 * s] * c->dims[3 * s + 1] * c->geo.mld[s],
+                           (double*)(c->ws + c->lay.normM2) + s, scratch, 1024, c->q);
     }
     int hflag = 0;
     INIT_HIP(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, c->q));
