@@ -207,6 +207,15 @@ concpd_status concpd_loss_grad(concpd_ctx ctx, const void* const* U_dev, const v
  * float (double in F64 mode) written to dev_out.  Synchronises. */
 concpd_status concpd_debug_mttkrp(concpd_ctx ctx, int32_t n, int32_t s, void* dev_out);
 
+/* Test hook: the largest eigenvalue of each of `count` symmetric n x n FP64
+ * matrices (host, row-major, packed one after another), computed on the
+ * device by the same code that gives the spectral norms of eq. eqLipsLd /
+ * eqLipsLu in a sweep: repeated squaring with Collatz-Wielandt bounds for
+ * nonnegative matrices, Lanczos with Sturm multisection otherwise.  Results
+ * to host_out [count].  1 <= n <= 64, 1 <= count <= 65535.  Needs no context;
+ * allocates and synchronises.  Errors: EINVAL, EHIP. */
+concpd_status concpd_debug_spectral_norm(const double* host_A, int32_t n, int32_t count, double* host_out);
+
 /* Per-kernel timing of the dense MTTKRP passes (pass 1: M x_3 U^(3); pass 2:
  * the mode-3 MTTKRP) of later concpd_step calls: with enable != 0, HIP events
  * are recorded on the context stream around each pass launch of every

@@ -92,6 +92,7 @@ SIGNATURES = {
     "concpd_set_state": (ctypes.c_int, [_P, _DPP, _DPP, _DPP, _DPP, _DP, _DP, _DP, ctypes.c_double, ctypes.c_int64]),
     "concpd_loss_grad": (ctypes.c_int, [_P, _PP, _PP, ctypes.c_int32, _DP, _PP, _PP]),
     "concpd_debug_mttkrp": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
+    "concpd_debug_spectral_norm": (ctypes.c_int, [_DP, ctypes.c_int32, ctypes.c_int32, _DP]),
     "concpd_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "concpd_profile_read": (ctypes.c_int, [_P, _DP, _DP, ctypes.POINTER(ctypes.c_int64)]),
     "concpd_destroy": (ctypes.c_int, [_P]),

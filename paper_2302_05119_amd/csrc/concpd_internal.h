@@ -95,6 +95,7 @@ struct ItemK2 { int s, col0, chunk, pad; };         // mode-2 contraction: block
 
 // Kernel launchers (defined in the .hip files).
 namespace cpd {
+void launch_spectral_norm(const double* mats, int n, int count, double* out, hipStream_t q);
 template <typename T> void launch_core(const Geo* g, const StateP<T>& st, int S, int R, int extrap, hipStream_t q);
 template <typename T> void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, hipStream_t q);
 template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);

@@ -4,6 +4,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <float.h>
+#include <limits.h>
 #include <math.h>
 #include "concpd_internal.h"
 

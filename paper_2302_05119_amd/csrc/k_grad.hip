@@ -16,7 +16,7 @@ __global__ __launch_bounds__(256) void k_grad_block(const Geo* __restrict__ g, S
                                                     double* __restrict__ Fblk) {
     const int s = blockIdx.x, tid = threadIdx.x;
     const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R;
-    extern __shared__ char smraw[];
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
     double* V0 = st.V[0] + (0 * S + s) * RR;
     double* V1 = st.V[0] + (1 * S + s) * RR;
     double* V2 = st.V[0] + (2 * S + s) * RR;

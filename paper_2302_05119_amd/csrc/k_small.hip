@@ -10,7 +10,7 @@ template <typename T, int NMAX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_core(const Geo* __restrict__ g, StateP<T> st, int extrapolate) {
     if (st.ctrl->stop) return;
     apply_rot(st);
-    extern __shared__ char smraw[];
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
     core_block<T, NMAX>(g, st, blockIdx.x, extrapolating(st.ctrl, extrapolate), smraw);
 }
 
@@ -18,7 +18,7 @@ template <typename T, int NMAX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_prep(const Geo* __restrict__ g, StateP<T> st, int n) {
     if (st.ctrl->stop) return;
     apply_rot(st);
-    extern __shared__ char smraw[];
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
     prep_block<T, NMAX>(g, st, blockIdx.x, n, smraw);
 }
 
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     apply_rot(st);
     const int s = blockIdx.x, tid = threadIdx.x;
     const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R;
-    extern __shared__ char smraw[];
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
     __shared__ int last;
     __shared__ double fb[CPD_MAXS], nb[CPD_MAXS];
     double* V2 = st.V[0] + (2 * S + s) * RR;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_init_stats(const Geo* __restrict__ g, S
     apply_rot(st);
     const int s = blockIdx.x, tid = threadIdx.x;
     const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R;
-    extern __shared__ char smraw[];
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
     __shared__ int last;
     __shared__ double fb[CPD_MAXS], nb[CPD_MAXS];
     for (int m = 0; m < 2; ++m)
@@ -161,18 +161,33 @@ __global__ __launch_bounds__(256) void k_init_stats(const Geo* __restrict__ g, S
     c->counter_aux = 0u;
 }
 
+// Spectral norms of `count` symmetric n x n matrices (row-major, packed one
+// after another), one workgroup each, by the same device code as the sweep.
+template <int NMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_spectral_norm(const double* __restrict__ mats, int n,
+                                                                                                  double* __restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
+    double* A = (double*)smraw;
+    const int ld = n | 1;
+    const double* src = mats + (long long)blockIdx.x * n * n;
+    for (int i = threadIdx.x; i < n * n; i += 256) A[(i / n) * ld + i % n] = src[i];
+    __syncthreads();
+    const double v = wg_lmax_nonneg<NMAX>(A, n, ld, eig_work(A, n));
+    if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
-// launchers
-// ---------------------------------------------------------------------------
-#define CPD_NMAX_DISPATCH(R, CALL) \
-    do {                              \
-        if ((R) <= 16) { CALL(16); }  \
-        else if ((R) <= 32) { CALL(32); } \
-        else if ((R) <= 48) { CALL(48); } \
-        else { CALL(64); }            \
+#define CPD_NMAX_DISPATCH(R, CALL)        \
+    do {                                  \
+        switch (nmax_class(R)) {          \
+        case 16: CALL(16); break;         \
+        case 24: CALL(24); break;         \
+        case 32: CALL(32); break;         \
+        case 48: CALL(48); break;         \
+        default: CALL(64); break;         \
+        }                                 \
     } while (0)
 
 template <typename T>
@@ -197,6 +212,12 @@ template <typename T>
 void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q) {
     const int Rq = (R + 3) / 4 * 4;
     hipLaunchKernelGGL(k_init_stats<T>, dim3(S), dim3(256), gram_lds_bytes<T>(Rq, 1), q, g, st);
+}
+
+void launch_spectral_norm(const double* mats, int n, int count, double* out, hipStream_t q) {
+#define CPD_SN(N) hipLaunchKernelGGL((k_spectral_norm<N>), dim3(count), dim3(256), eig_lds_bytes(n), q, mats, n, out)
+    CPD_NMAX_DISPATCH(n, CPD_SN);
+#undef CPD_SN
 }
 
 #define CPD_INST_SMALL(T)                                                                                  \

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP
     typedef typename AccType<TM>::type TA;
     if (st.ctrl->stop) return;
     apply_rot(st);
-    extern __shared__ char smraw[];
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
     const ItemP1 it = items[blockIdx.x];
     const int s = it.s, i1 = it.i1, rg = it.rg, row0 = rg * 64;
     const int I2 = g->I[s][1], I3 = g->I[s][2], Rq = g->Rq;
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
     typedef typename AccType<TM>::type TA;
     if (st.ctrl->stop) return;
     apply_rot(st);
-    extern __shared__ char smraw[];
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
     const ItemP2 it = items[blockIdx.x];
     const int s = it.s, chunk = it.chunk, q0 = it.q0;
     const int I1 = g->I[s][0], I2 = g->I[s][1], I3 = g->I[s][2], Rq = g->Rq;

@@ -1182,6 +1182,25 @@ concpd_status concpd_debug_mttkrp(concpd_ctx c, int32_t n, int32_t s, void* dev_
     return CONCPD_OK;
 }
 
+concpd_status concpd_debug_spectral_norm(const double* host_A, int32_t n, int32_t count, double* host_out) {
+    if (!host_A || !host_out) return fail(CONCPD_EINVAL, "NULL argument");
+    if (n < 1 || n > CPD_MAXR) return fail(CONCPD_EINVAL, "n = %d not in [1, %d]", n, CPD_MAXR);
+    if (count < 1 || count > 65535) return fail(CONCPD_EINVAL, "count = %d not in [1, 65535]", count);
+    const size_t nm = (size_t)n * n * count;
+    double* d = nullptr;
+    HIPCHECK(hipMalloc(&d, sizeof(double) * (nm + count)));
+    hipError_t e = hipMemcpy(d, host_A, sizeof(double) * nm, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        cpd::launch_spectral_norm(d, n, count, d + nm, 0);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(host_out, d + nm, sizeof(double) * count, hipMemcpyDeviceToHost);
+    const hipError_t ef = hipFree(d);
+    if (e == hipSuccess) e = ef;
+    if (e != hipSuccess) return fail(CONCPD_EHIP, "spectral norm: %s", hipGetErrorString(e));
+    return CONCPD_OK;
+}
+
 concpd_status concpd_profile(concpd_ctx c, int32_t enable) {
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
     c->profiling = enable != 0;

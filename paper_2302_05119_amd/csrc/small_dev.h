@@ -116,7 +116,7 @@ __device__ __forceinline__ double wave_sym_lmax_t(const double* __restrict__ A, 
     double* __restrict__ dl = w + 128;   // alpha_k
     double* __restrict__ el = w + 256;   // beta_k^2
     const int mmax = min(n + 8, MM);
-    int m = 0;
+    int m = 0, ka = 0;
     double anorm;
     {
         double row[NMAX];
@@ -130,8 +130,14 @@ __device__ __forceinline__ double wave_sym_lmax_t(const double* __restrict__ A, 
             amax = fmax(amax, fabs(row[j]));
         }
         if (__ballot(bad)) return __longlong_as_double(0x7ff8000000000000LL);
-        anorm = wave_max(amax) * n;  // >= ||A||_2
-        if (!(anorm > 0.0)) return 0.0;
+        const double am = wave_max(amax);
+        if (!(am > 0.0)) return 0.0;
+        // work on A 2^-ka (largest entry in [1/2, 1)) so that no norm of a
+        // Lanczos vector overflows or underflows; the result is scaled back
+        ka = __builtin_amdgcn_frexp_exp(am);
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j) row[j] = ldexp(row[j], -ka);
+        anorm = ldexp(am, -ka) * n;  // >= ||A 2^-ka||_2
         double q = (lane < n) ? 1.0 / sqrt((double)n) : 0.0, qprev = 0.0, beta = 0.0;
         for (int k = 0; k < mmax; ++k) {
             if (k > 0 && !(beta > 1e-14 * anorm)) break;
@@ -175,6 +181,7 @@ __device__ __forceinline__ double wave_sym_lmax_t(const double* __restrict__ A, 
     const int ke = ilogb(sc);
     lo = ldexp(lo, -ke);
     hi = ldexp(hi, -ke);
+    const int kr = ke + ka;   // undoes both scalings
     if (NMAX <= 48) {
         double d[MM], e2[MM];
 #pragma unroll
@@ -182,7 +189,7 @@ __device__ __forceinline__ double wave_sym_lmax_t(const double* __restrict__ A, 
             d[i] = (i < m) ? ldexp(dl[i], -ke) : 4.0;
             e2[i] = (i + 1 < m) ? ldexp(el[i], -2 * ke) : 0.0;
         }
-        return ldexp(multisect_top<MM, double[MM]>(d, e2, m, lo, hi), ke);
+        return ldexp(multisect_top<MM, double[MM]>(d, e2, m, lo, hi), kr);
     } else {
         wave_sync();
         for (int i = lane; i < MM; i += 64) {
@@ -192,7 +199,7 @@ __device__ __forceinline__ double wave_sym_lmax_t(const double* __restrict__ A, 
         wave_sync();
         const double* dp = dl;
         const double* ep = el;
-        return ldexp(multisect_top<MM, const double*>(dp, ep, m, lo, hi), ke);
+        return ldexp(multisect_top<MM, const double*>(dp, ep, m, lo, hi), kr);
     }
 }
 
@@ -215,6 +222,244 @@ __device__ __forceinline__ double diag_max(const double* __restrict__ S, int n, 
 __host__ __device__ inline int sq_np(int n) { return (n + 15) & ~15; }
 __host__ __device__ inline int sq_lp(int n) { return (sq_np(n) & 31) == 16 ? sq_np(n) : sq_np(n) + 16; }
 
+// Size class of the R x R spectral-norm work (the NMAX template argument of
+// the small kernels): 16, 24, 32, 48 or 64.
+__host__ __device__ inline int nmax_class(int R) { return R <= 16 ? 16 : R <= 24 ? 24 : R <= 32 ? 32 : R <= 48 ? 48 : 64; }
+
+// Squaring buffers of the vector-ALU path (n <= NPM <= 32): NPM rows of
+// NPM + 2 doubles.  The stride is an odd multiple of four dwords, so the
+// 16-byte reads of sixteen consecutive rows fall in distinct bank quads.
+__host__ __device__ inline int vsq_doubles(int NPM) { return 2 * NPM * (NPM + 2) + 80; }
+
+// Largest int over the wavefront (uniform result): maxima inside rows of 16
+// lanes by row shifts, then across rows by the row broadcasts, so that lane 63
+// ends with the maximum of all lanes.
+__device__ __forceinline__ int wave_max_i32(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// One DPP move of a double (two 32-bit halves); lanes without a source keep `old`.
+template <int CTRL, int RMASK>
+__device__ __forceinline__ double dpp_f64(double v, double old) {
+    const long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+    const int l = __builtin_amdgcn_update_dpp((int)o, (int)b, CTRL, RMASK, 0xf, false);
+    const int h = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, RMASK, 0xf, false);
+    return __longlong_as_double(((long long)h << 32) | (unsigned int)l);
+}
+
+// Wavefront min of lo and max of hi (uniform results), by the same DPP
+// pattern as wave_max_i32.
+__device__ __forceinline__ void wave_minmax_dpp(double& lo, double& hi) {
+#define CPD_MM_STEP(C, M)                               \
+    lo = fmin(lo, dpp_f64<C, M>(lo, INFINITY));          \
+    hi = fmax(hi, dpp_f64<C, M>(hi, -INFINITY));
+    CPD_MM_STEP(0x111, 0xf)
+    CPD_MM_STEP(0x112, 0xf)
+    CPD_MM_STEP(0x114, 0xf)
+    CPD_MM_STEP(0x118, 0xf)
+    CPD_MM_STEP(0x142, 0xa)
+    CPD_MM_STEP(0x143, 0xc)
+#undef CPD_MM_STEP
+    const long long bl = __double_as_longlong(lo), bh = __double_as_longlong(hi);
+    lo = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(bl >> 32), 63) << 32) |
+                              (unsigned int)__builtin_amdgcn_readlane((int)bl, 63));
+    hi = __longlong_as_double(((long long)__builtin_amdgcn_readlane((int)(bh >> 32), 63) << 32) |
+                              (unsigned int)__builtin_amdgcn_readlane((int)bh, 63));
+}
+
+// Repeated squaring on the vector ALU for n <= NPM (16, 24 or 32).  At these
+// sizes an FP64 matrix-core tile is mostly padding and FP64 FMA runs at the
+// matrix-core rate, so the squarings are dot products of rows (S is
+// symmetric, so a column is a row).  They run on the first wavefront alone,
+// with no workgroup barrier between squarings: lane l forms 2 x 2 blocks
+// (rows 2a, 2a+1; columns 2b, 2b+1; a <= b) of the upper triangle of S^2 from
+// 16-byte row reads (two FMAs per read, eight independent chains), writes
+// each block and its mirror (S stays exactly symmetric: the two halves of a
+// diagonal block are the same products summed in the same order), and the
+// power-of-two rescaling of the next squaring comes from the largest
+// diagonal exponent, a DPP maximum over the wavefront.  The stopping test is
+// that of wg_lmax_nonneg.  All threads enter; the result is broadcast.
+// Returns false (nothing decided) on a negative or non-finite entry, on a
+// nonzero matrix with a zero diagonal (not PSD), or when the bounds do not
+// meet within 24 squarings.
+template <int NPM>
+__device__ __forceinline__ bool wg_lmax_vsq(const double* __restrict__ A, int n, int ld, double* __restrict__ work,
+                                            double& result) {
+    static_assert(NPM == 16 || NPM == 24 || NPM == 32, "vector squaring path");
+    constexpr int LP = NPM + 2;
+    constexpr int HM = NPM / 2;                              // row pairs
+    constexpr int BPL = (HM * (HM + 1) / 2 + 63) / 64;       // blocks per lane
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* __restrict__ S0 = work;
+    double* __restrict__ S1 = work + NPM * LP;
+    double* __restrict__ dg = S1 + NPM * LP;   // 64: x of the test
+    double* __restrict__ red = dg + 64;        // result broadcast
+    const int ne = (n + 1) & ~1, h = ne >> 1;
+    if (wave == 0) {
+        // A (zero-padded to NPM x NPM) into registers: the entry check, the
+        // largest diagonal exponent e0, then S0 = A 2^-e0 (largest diagonal
+        // entry in [1/2, 1); every entry of a PSD matrix is at most its
+        // largest diagonal entry) and S1 = 0 (its padding is never written)
+        constexpr int EPT = (NPM * NPM + 63) / 64;
+        double av[EPT];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {   // every load in flight (clamped addresses)
+            const int e = lane + 64 * q, i = e / NPM, j = e % NPM;
+            av[q] = A[min(i, n - 1) * ld + min(j, n - 1)];
+        }
+        // branch-free tests (bitwise, not short-circuit, so no load waits
+        // behind a branch)
+        int bad = 0, nz = 0, ex0 = INT_MIN;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = lane + 64 * q, i = e / NPM, j = e % NPM;
+            const double a = av[q];
+            const int in = (e < NPM * NPM) & (i < n) & (j < n);
+            bad |= in & ((a >= 0.0) ? 0 : 1) | in & (isfinite(a) ? 0 : 1);
+            nz |= in & ((a != 0.0) ? 1 : 0);
+            const int ea = __builtin_amdgcn_frexp_exp(a);
+            ex0 = (in & (i == j) & (a > 0.0)) ? max(ex0, ea) : ex0;
+            av[q] = in ? a : 0.0;
+        }
+        double res = 0.0, ok = 0.0;
+        const int e0 = wave_max_i32(ex0);
+        if (__any(bad)) {
+            ok = 0.0;   // the Lanczos path decides
+        } else if (e0 == INT_MIN) {
+            ok = __any(nz) ? 0.0 : 1.0;   // zero diagonal: zero if PSD, else not PSD
+        } else {
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int e = lane + 64 * q, i = e / NPM, j = e % NPM;
+                if (e < NPM * NPM) {
+                    S0[i * LP + j] = ldexp(av[q], -e0);
+                    S1[i * LP + j] = 0.0;
+                }
+            }
+            // the lane's blocks (a, b), a <= b < h
+            const int nblk = h * (h + 1) / 2;
+            int ba[BPL], bb[BPL];
+            bool bv[BPL];
+#pragma unroll
+            for (int m = 0; m < BPL; ++m) {
+                // block row a: the number of row starts t*h - t(t-1)/2 (t >= 1)
+                // not above the block index
+                const int bi = lane + 64 * m;
+                bv[m] = bi < nblk;
+                const int bc = bv[m] ? bi : 0;
+                int a = 0;
+#pragma unroll
+                for (int t = 1; t < HM; ++t) a += (bc >= t * h - t * (t - 1) / 2) & (t < h);
+                ba[m] = a;
+                bb[m] = a + bc - (a * h - a * (a - 1) / 2);
+            }
+            wave_sync();
+            int es = 0;   // entries of S are read as S * 2^-es
+            for (int it = 0; it < 24; ++it) {
+                const double* __restrict__ Sa = (it & 1) ? S1 : S0;
+                double* __restrict__ Sb = (it & 1) ? S0 : S1;
+                int ex = INT_MIN;
+#pragma unroll
+                for (int m = 0; m < BPL; ++m) {
+                    if (64 * m >= nblk) break;   // uniform
+                    const int r0 = 2 * ba[m], c0 = 2 * bb[m];
+                    const double* x0 = Sa + r0 * LP;
+                    const double* x1 = x0 + LP;
+                    const double* y0 = Sa + c0 * LP;
+                    const double* y1 = y0 + LP;
+                    double s00a = 0.0, s00b = 0.0, s01a = 0.0, s01b = 0.0;
+                    double s10a = 0.0, s10b = 0.0, s11a = 0.0, s11b = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NPM; k += 2) {
+                        const d2 p0 = *(const d2*)(x0 + k), p1 = *(const d2*)(x1 + k);
+                        const d2 q0 = *(const d2*)(y0 + k), q1 = *(const d2*)(y1 + k);
+                        s00a = fma(p0.x, q0.x, s00a);
+                        s00b = fma(p0.y, q0.y, s00b);
+                        s01a = fma(p0.x, q1.x, s01a);
+                        s01b = fma(p0.y, q1.y, s01b);
+                        s10a = fma(p1.x, q0.x, s10a);
+                        s10b = fma(p1.y, q0.y, s10b);
+                        s11a = fma(p1.x, q1.x, s11a);
+                        s11b = fma(p1.y, q1.y, s11b);
+                    }
+                    const double v00 = ldexp(s00a + s00b, -2 * es), v01 = ldexp(s01a + s01b, -2 * es);
+                    const double v10 = ldexp(s10a + s10b, -2 * es), v11 = ldexp(s11a + s11b, -2 * es);
+                    if (bv[m]) {
+                        *(d2*)(Sb + r0 * LP + c0) = (d2){v00, v01};
+                        *(d2*)(Sb + (r0 + 1) * LP + c0) = (d2){v10, v11};
+                        *(d2*)(Sb + c0 * LP + r0) = (d2){v00, v10};
+                        *(d2*)(Sb + (c0 + 1) * LP + r0) = (d2){v01, v11};
+                        if (ba[m] == bb[m]) {
+                            if (v00 > 0.0) ex = max(ex, __builtin_amdgcn_frexp_exp(v00));
+                            if (v11 > 0.0) ex = max(ex, __builtin_amdgcn_frexp_exp(v11));
+                        }
+                    }
+                }
+                es = wave_max_i32(ex);
+                if (es == INT_MIN) es = 0;
+                wave_sync();
+                if (it >= 4 && (it < 8 || (it & 1))) {
+                    // x = S 1 (row sums; S is exactly symmetric), y = A x, and
+                    // the Collatz-Wielandt bounds over the support
+                    const double* rs = Sb + min(lane, NPM - 1) * LP;
+                    double xa = 0.0, xb = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NPM; k += 2) {
+                        const d2 v = *(const d2*)(rs + k);
+                        xa += v.x;
+                        xb += v.y;
+                    }
+                    const double x = (lane < n) ? xa + xb : 0.0;
+                    dg[lane] = x;
+                    wave_sync();
+                    // dg is zero past n, so the clamped columns add nothing
+                    const double* ar = A + min(lane, n - 1) * ld;
+                    double ya = 0.0, yb = 0.0;
+#pragma unroll
+                    for (int j = 0; j < NPM; j += 2) {
+                        const d2 xv = *(const d2*)(dg + j);
+                        ya = fma(ar[min(j, n - 1)], xv.x, ya);
+                        yb = fma(ar[min(j + 1, n - 1)], xv.y, yb);
+                    }
+                    const double y = ya + yb;
+                    double lo = INFINITY, hi = -INFINITY;
+                    int miss = 0;
+                    if (lane < n && A[lane * ld + lane] > 0.0) {
+                        if (x > 0.0) {
+                            lo = y / x;
+                            hi = lo;
+                        } else {
+                            miss = 1;
+                        }
+                    }
+                    wave_minmax_dpp(lo, hi);
+                    miss = __any(miss);
+                    wave_sync();
+                    if (!miss && hi >= lo && hi - lo <= 1e-14 * hi) {   // uniform
+                        res = 0.5 * (lo + hi);
+                        ok = 1.0;
+                        break;
+                    }
+                }
+            }
+        }
+        if (lane == 0) {
+            red[0] = res;
+            red[1] = ok;
+        }
+    }
+    __syncthreads();
+    result = red[0];
+    return red[1] != 0.0;
+}
+
 // Exact spectral norm of a nonnegative symmetric PSD matrix A (n x n, row
 // stride ld, in LDS), whole workgroup.  Repeated squaring S <- S^2 (with a
 // power-of-two rescaling from the largest diagonal entry, which bounds every
@@ -222,15 +467,33 @@ __host__ __device__ inline int sq_lp(int n) { return (sq_np(n) & 31) == 16 ? sq_
 // x = S 1 on the support (the rows with a positive diagonal) gives the
 // Collatz-Wielandt bounds min_i (Ax)_i / x_i <= lambda_max <= max_i (Ax)_i / x_i,
 // rigorous for a nonnegative matrix and a positive x, accepted once they agree
-// to 1e-14 relative.  The squarings run on the FP64 matrix cores: 16 x 16
+// to 1e-14 relative.  Up to n = 32 the squarings run on the vector ALU
+// (wg_lmax_vsq); above, on the FP64 matrix cores: 16 x 16
 // output tiles (upper triangle, mirrored, so S stays exactly symmetric), one
 // tile per wavefront.  Negative or non-finite entries, n > 48, or bounds that
 // do not meet within 24 squarings go to the single-wave Lanczos + Sturm solver.
 // work: 2 * NP * lp + 576 doubles of LDS.
 template <int NMAX>
 __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, int n, int ld, double* __restrict__ work) {
-    constexpr int NPM = (NMAX + 15) & ~15;   // largest padded size of this instantiation
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if constexpr (NMAX <= 32) {
+        double r = 0.0;
+        const bool ok = wg_lmax_vsq<NMAX>(A, n, ld, work, r);
+        double* __restrict__ wl = work + vsq_doubles(NMAX);   // fallback work (448)
+        double* __restrict__ res = wl + 448;
+        if (!ok) {
+            __syncthreads();
+            if (wave == 0) {
+                const double v = wave_sym_lmax_t<NMAX>(A, n, ld, wl);
+                if (lane == 0) res[0] = v;
+            }
+            __syncthreads();
+            r = res[0];
+        }
+        __syncthreads();
+        return r;
+    }
+    constexpr int NPM = (NMAX + 15) & ~15;   // largest padded size of this instantiation
     const int NP = sq_np(n), lp = sq_lp(n);
     double* __restrict__ S0 = work;
     double* __restrict__ S1 = work + (NMAX <= 48 ? NP * lp : 0);
@@ -238,6 +501,11 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
     double* __restrict__ red = xv + 64;       // 16
     double* __restrict__ res = red + 16;      // result broadcast
     double* __restrict__ wl = res + 16;       // fallback work (448)
+    // S0 = A 2^-e0 with the largest diagonal entry in [1/2, 1): every entry
+    // of a PSD matrix is at most its largest diagonal entry, so no product of
+    // the first squaring overflows or underflows
+    const double dmax = diag_max<NPM>(A, n, ld);
+    const int e0 = (dmax > 0.0 && isfinite(dmax)) ? __builtin_amdgcn_frexp_exp(dmax) : 0;
     int bad = 0;
     for (int e = tid; e < NP * NP; e += 256) {
         const int i = e / NP, j = e % NP;
@@ -246,10 +514,9 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
             v = A[i * ld + j];
             bad |= !(v >= 0.0) | !isfinite(v);
         }
-        if (NMAX <= 48) S0[i * lp + j] = v;
+        if (NMAX <= 48) S0[i * lp + j] = ldexp(v, -e0);
     }
     const int anybad = __syncthreads_or(bad);
-    const double dmax = diag_max<NPM>(A, n, ld);
     double result = 0.0;
     bool done = false;
     if (!anybad && !(dmax > 0.0)) {
@@ -258,7 +525,7 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
         done = true;
     }
     if (NMAX <= 48 && !anybad && !done) {
-        int es = __builtin_amdgcn_frexp_exp(dmax);   // entries of Sa are read as Sa * 2^-es
+        int es = 0;   // entries of Sa are read as Sa * 2^-es
         const int nt = NP >> 4, ntile = nt * (nt + 1) / 2;
         const int li = lane & 15, lk = lane >> 4;
         const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -478,8 +745,15 @@ __device__ __forceinline__ double block_objective(const double* lam, const doubl
 // buffers and fallback work) and of the Gram (cross-wave partial tiles).
 __host__ __device__ inline size_t eig_lds_bytes(int R) {
     const size_t ld = (size_t)(R | 1);
-    return sizeof(double) * ((size_t)R * ld + 192 + (R <= 48 ? 2 * (size_t)sq_np(R) * sq_lp(R) : 0) + 576);
+    const int c = nmax_class(R);
+    const size_t sq = c <= 32 ? (size_t)vsq_doubles(c) + 456 : (c <= 48 ? 2 * (size_t)sq_np(R) * sq_lp(R) : 0) + 576;
+    return sizeof(double) * ((size_t)R * ld + 192 + 2 + sq);
 }
+
+// The eigenvalue work area after the matrix and three R-vectors: an even
+// offset in doubles, so 16-byte aligned when A is (pointer arithmetic only,
+// which keeps the LDS address space visible to the compiler).
+__device__ __forceinline__ double* eig_work(double* A, int R) { return A + ((R * (R | 1) + 192 + 1) & ~1); }
 template <typename T>
 __host__ __device__ inline size_t gram_lds_bytes(int Rq, int with_k) {
     (void)Rq;
@@ -502,7 +776,7 @@ __device__ __forceinline__ void core_block(const Geo* __restrict__ g, const Stat
     const int S = g->S, R = g->R, Rq = g->Rq, ld = R | 1, RR = R * R;
     double* A = (double*)smraw;
     double* lv = A + R * ld;   // lambda_{k-1} | lambda_{k-1} - lambda_{k-2} | new lambda
-    double* work = lv + 192;
+    double* work = eig_work(A, R);
     const double* V0 = st.V[1] + (0 * S + s) * RR;
     const double* V1 = st.V[1] + (1 * S + s) * RR;
     const double* V2 = st.V[1] + (2 * S + s) * RR;
@@ -562,7 +836,7 @@ __device__ __forceinline__ void prep_block(const Geo* __restrict__ g, const Stat
     __syncthreads();
     const int tid = threadIdx.x;
     double* A = (double*)smraw;
-    double* work = A + R * ld + 192;
+    double* work = eig_work(A, R);
     const double* lam = st.lam[0] + s * Rq;
     const double* Va = st.V[0] + (0 * S + s) * RR;
     const double* Vb = (n == 1) ? st.V[1] + (2 * S + s) * RR : st.V[0] + (1 * S + s) * RR;

@@ -286,3 +286,20 @@ class CoupledCP:
             self.close()
         except Exception:
             pass
+
+
+def spectral_norm(mats) -> np.ndarray:
+    """Largest eigenvalues of symmetric n x n FP64 matrices ([count, n, n] or
+    [n, n]) computed on the device by the sweep's spectral-norm code (the
+    Lipschitz constants of eqs. eqLipsLd / eqLipsLu)."""
+    a = np.ascontiguousarray(np.asarray(mats, dtype=np.float64))
+    single = a.ndim == 2
+    if single:
+        a = a[None]
+    if a.ndim != 3 or a.shape[1] != a.shape[2]:
+        raise ValueError("expected [count, n, n] or [n, n]")
+    out = np.zeros(a.shape[0], dtype=np.float64)
+    lib = load()
+    check(lib.concpd_debug_spectral_norm(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.shape[1], a.shape[0],
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out[0] if single else out
