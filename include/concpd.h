@@ -234,11 +234,17 @@ concpd_status concpd_profile_read(concpd_ctx ctx, double* ms_pass1, double* ms_p
  *                            beside the MTTKRP passes (default 0).
  *   CONCPD_OPT_K2_ROWS       i1 rows per workgroup of the mode-2 contraction
  *                            (8..64, default 16).
+ *   CONCPD_OPT_P1_SPLIT      wavefronts that share one 64-row item of pass 1
+ *                            (M x_3 U^(3)), splitting its i3 range: 1, 2 or 4;
+ *                            0 (default): chosen from the item count (about
+ *                            two wavefronts per SIMD).  Get returns the split
+ *                            in use.
  * Synchronises.  Errors: EINVAL (unknown option or value), EHIP. */
 typedef enum concpd_option {
     CONCPD_OPT_GRAPH_SWEEPS = 1,
     CONCPD_OPT_OVERLAP = 2,
-    CONCPD_OPT_K2_ROWS = 3
+    CONCPD_OPT_K2_ROWS = 3,
+    CONCPD_OPT_P1_SPLIT = 4
 } concpd_option;
 concpd_status concpd_set_option(concpd_ctx ctx, int32_t option, int64_t value);
 concpd_status concpd_get_option(concpd_ctx ctx, int32_t option, int64_t* value);
@@ -249,12 +255,13 @@ typedef struct concpd_tuning {
     double us_per_sweep;          /* measured time per sweep of the choice */
     double us_per_sweep_default;  /* of the default configuration */
     int32_t candidates;           /* configurations timed */
+    int32_t p1_split;             /* chosen CONCPD_OPT_P1_SPLIT (the split in use) */
 } concpd_tuning;
 
-/* Autotuner: times `sweeps` sweeps (HIP events on the context stream) of every
- * candidate launch configuration (mode-2 chunk rows 8/16/32 x graph sweeps
- * 0/1/4) from the same iterate, restoring the iterate after each, and keeps
- * the fastest.  The iterate is unchanged on return.  Synchronises.
+/* Autotuner: times `sweeps` sweeps (HIP events on the context stream) of
+ * candidate launch configurations from the same iterate, restoring the
+ * iterate after each, and keeps the fastest: first the pass-1 split 1/2/4
+ * (dense path), then mode-2 chunk rows 8/16/32 x graph sweeps 0/1/4.  The iterate is unchanged on return.  Synchronises.
  * Errors: EINVAL (sweeps not in [1, 10000]), ESTATE (converged iterate), EHIP. */
 concpd_status concpd_autotune(concpd_ctx ctx, int32_t sweeps, concpd_tuning* out);
 

@@ -88,7 +88,7 @@ struct StateP {
 };
 
 // Work items of the grouped kernels (host-built lists, one entry per workgroup).
-struct ItemP1 { int s, i1, rg, pad; };              // pass 1: block, slab, 64-row group
+struct ItemP1 { int s, i1, rg, pad; };              // pass 1: block (< 0: empty), slab, 64-row group
 struct ItemP2 { int s, chunk, q0, pad; };           // pass 2: block, 4-slab chunk, i3 start
 struct ItemU  { int s0, ns, row0, nrows; };         // update: blocks [s0, s0+ns), rows
 struct ItemK2 { int s, col0, chunk, pad; };         // mode-2 contraction: block, column tile start, i1 chunk
@@ -100,7 +100,7 @@ template <typename T> void launch_core(const Geo* g, const StateP<T>& st, int S,
 template <typename T> void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, hipStream_t q);
 template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
 template <typename T> void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
-template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int Rq, int slot, int mdtype, hipStream_t q);
+template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int P, int Rq, int slot, int mdtype, hipStream_t q);
 template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int mdtype, int maxI2, hipStream_t q);
 template <typename T> void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, hipStream_t q);
 template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int lds_rows, int lra, hipStream_t q);

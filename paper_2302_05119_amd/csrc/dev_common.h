@@ -64,10 +64,21 @@ __device__ __forceinline__ void wave_minmax(double& lo, double& hi) {
 // max(0, x) that keeps NaN (the projection must not hide a non-finite value).
 __device__ __forceinline__ double relu_keep_nan(double x) { return (x > 0.0 || x != x) ? x : 0.0; }
 
-// Acquire-load of a value written by another workgroup of the same launch.
+// A double handed from one workgroup to another of the same launch: the
+// writer stores it with an agent-scope atomic store (written through to the
+// coherence point shared by all XCDs), waits for the store to complete
+// (wait_stores) and only then takes its arrival count; the reader loads it
+// with an agent-scope atomic load after seeing the final count.  This orders
+// the one value without the device-scope fences, which on this multi-L2 part
+// write back and invalidate the whole L2 of the XCD.
+__device__ __forceinline__ void store_agent(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ double load_agent(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// s_waitcnt vmcnt(0): every global load and store of the wavefront has completed.
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // An accepted sweep rotates the slots instead of copying them: logical slot l
 // of the factors and lambda (0: x_k being built, 1: x_{k-1}, 2: x_{k-2}) is

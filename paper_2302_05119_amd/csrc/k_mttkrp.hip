@@ -6,9 +6,9 @@ namespace cpd {
 
 template <typename TM, typename T>
 static void pass1_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g, const StateP<T>& st, const ItemP1* items,
-                     int slot) {
+                     int nitems, int P, int slot) {
 #define CPD_P1(RTV) \
-    case RTV: hipLaunchKernelGGL((k_pass1<TM, T, RTV>), grid, dim3(256), lds, q, g, st, items, slot); break;
+    case RTV: hipLaunchKernelGGL((k_pass1<TM, T, RTV>), grid, dim3(256), lds, q, g, st, items, nitems, P, slot); break;
     switch (RT) {
         CPD_P1(1) CPD_P1(2) CPD_P1(3) CPD_P1(4) CPD_P1(5) CPD_P1(6) CPD_P1(7) CPD_P1(8)
         CPD_P1(9) CPD_P1(10) CPD_P1(11) CPD_P1(12) CPD_P1(13) CPD_P1(14) CPD_P1(15) CPD_P1(16)
@@ -29,14 +29,13 @@ static void pass2_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g,
 #undef CPD_P2
 }
 
-template <typename TA>
-static size_t pass1_lds(int Rq) {
-    // per wave: the transposed U3 chunk (KC x 4 x RTP, RTP <= Rq / 4 + 3);
-    // then the cross-wave reduction (4 x 64 x Rq)
-    const size_t va = 16 / sizeof(TA), rtp = ((size_t)Rq / 4 + va - 1) / va * va;
-    size_t a = sizeof(TA) * 4 * (size_t)P1Shape<TA>::KC * 4 * rtp;
-    size_t b = sizeof(TA) * 4 * 64 * (size_t)Rq;
-    return a > b ? a : b;
+// pass 1 LDS: four staging areas (64-byte chunk x 4 x RTP operands), then,
+// when P > 1, the partial accumulators of the four wavefronts (RT x 4 x 64)
+template <typename TM>
+static size_t pass1_lds(int RT, int P) {
+    typedef typename AccType<TM>::type TA;
+    const size_t kc = 64 / sizeof(typename Raw<TM>::type), va = 16 / sizeof(TA), rtp = ((size_t)RT + va - 1) / va * va;
+    return sizeof(TA) * (4 * kc * 4 * rtp + (P > 1 ? 4 * (size_t)RT * 4 * 64 : 0));
 }
 
 template <typename TM, typename T>
@@ -51,17 +50,18 @@ static void pass2_dispatch(int Rq, dim3 grid, int maxI2, hipStream_t q, const Ge
 }
 
 template <typename T>
-void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int Rq, int slot, int mdtype,
+void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int P, int Rq, int slot, int mdtype,
                   hipStream_t q) {
     if (nitems <= 0) return;
-    const dim3 grid(nitems);
+    const dim3 grid((nitems * P + 3) / 4);
+    const int RT = Rq / 4;
     if constexpr (std::is_same<T, double>::value) {
-        pass1_rt<double, double>(Rq / 4, grid, pass1_lds<double>(Rq), q, g, st, items, slot);
+        pass1_rt<double, double>(RT, grid, pass1_lds<double>(RT, P), q, g, st, items, nitems, P, slot);
     } else {
-        const size_t lds = pass1_lds<float>(Rq);
-        if (mdtype == 1) pass1_rt<float, float>(Rq / 4, grid, lds, q, g, st, items, slot);
-        else if (mdtype == 2) pass1_rt<__hip_bfloat16, float>(Rq / 4, grid, lds, q, g, st, items, slot);
-        else pass1_rt<__half, float>(Rq / 4, grid, lds, q, g, st, items, slot);
+        if (mdtype == 1) pass1_rt<float, float>(RT, grid, pass1_lds<float>(RT, P), q, g, st, items, nitems, P, slot);
+        else if (mdtype == 2)
+            pass1_rt<__hip_bfloat16, float>(RT, grid, pass1_lds<__hip_bfloat16>(RT, P), q, g, st, items, nitems, P, slot);
+        else pass1_rt<__half, float>(RT, grid, pass1_lds<__half>(RT, P), q, g, st, items, nitems, P, slot);
     }
 }
 
@@ -85,8 +85,8 @@ void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitem
     hipLaunchKernelGGL(k_k2<T>, dim3(nitems), dim3(256), 0, q, g, st, items, slot);
 }
 
-template void launch_pass1<float>(const Geo*, const StateP<float>&, const ItemP1*, int, int, int, int, hipStream_t);
-template void launch_pass1<double>(const Geo*, const StateP<double>&, const ItemP1*, int, int, int, int, hipStream_t);
+template void launch_pass1<float>(const Geo*, const StateP<float>&, const ItemP1*, int, int, int, int, int, hipStream_t);
+template void launch_pass1<double>(const Geo*, const StateP<double>&, const ItemP1*, int, int, int, int, int, hipStream_t);
 template void launch_pass2<float>(const Geo*, const StateP<float>&, const ItemP2*, int, int, int, int, int, hipStream_t);
 template void launch_pass2<double>(const Geo*, const StateP<double>&, const ItemP2*, int, int, int, int, int, hipStream_t);
 template void launch_k2<float>(const Geo*, const StateP<float>&, const ItemK2*, int, int, hipStream_t);

@@ -46,13 +46,12 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     const double F = block_objective(st.lam[0] + s * Rq, st.V[0] + (0 * S + s) * RR, st.V[0] + (1 * S + s) * RR, V2, b,
                                      st.normM2[s], R);
     if (tid == 0) {
-        st.Fblk[s] = F;
-        __threadfence();
+        store_agent(&st.Fblk[s], F);
+        wait_stores();
         last = (atomicAdd(&c->counter_finish, 1u) == (unsigned)(gridDim.x - 1));
     }
     __syncthreads();
     if (!last) return;
-    __threadfence();
     if (tid < S) {
         fb[tid] = load_agent(&st.Fblk[tid]);
         nb[tid] = st.normM2[tid];
@@ -135,13 +134,12 @@ __global__ __launch_bounds__(256) void k_init_stats(const Geo* __restrict__ g, S
     const double F = block_objective(st.lam[1] + s * Rq, st.V[1] + (0 * S + s) * RR, st.V[1] + (1 * S + s) * RR, V2, b,
                                      st.normM2[s], R);
     if (tid == 0) {
-        st.Fblk[s] = F;
-        __threadfence();
+        store_agent(&st.Fblk[s], F);
+        wait_stores();
         last = (atomicAdd(&c->counter_aux, 1u) == (unsigned)(gridDim.x - 1));
     }
     __syncthreads();
     if (!last) return;
-    __threadfence();
     if (tid < S) {
         fb[tid] = load_agent(&st.Fblk[tid]);
         nb[tid] = st.normM2[tid];

@@ -30,6 +30,7 @@ template <> struct Acc4<float> {
     __device__ void mma(float a, float b) { v = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, v, 0, 0, 0); }
     __device__ float get(int i) const { return v[i]; }
     __device__ void scale(float u) { v *= u; }
+    __device__ void set(const float (&x)[4]) { v = (v4f){x[0], x[1], x[2], x[3]}; }
 };
 template <> struct Acc4<double> {
     double v[4];
@@ -43,6 +44,10 @@ template <> struct Acc4<double> {
     __device__ void scale(double u) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) v[i] *= u;
+    }
+    __device__ void set(const double (&x)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = x[i];
     }
 };
 
@@ -60,158 +65,183 @@ template <> __device__ __forceinline__ double cvt<double, double>(double x) { re
 template <> __device__ __forceinline__ float cvt<float, __hip_bfloat16>(unsigned short x) { return __uint_as_float((unsigned)x << 16); }
 template <> __device__ __forceinline__ float cvt<float, __half>(unsigned short x) { return __half2float(__ushort_as_half(x)); }
 
-// i3 columns staged per step; the odd LDS row stride keeps column reads
-// conflict-free.
-template <typename TA> struct P1Shape { static constexpr int KC = 32, STRIDE = 33; };
-template <> struct P1Shape<double> { static constexpr int KC = 16, STRIDE = 17; };
+// ---------------------------------------------------------------------------
+// pass 1: one wavefront per (block, i1 slab, 64-row group of i2) item, or P
+// wavefronts per item (P = 1, 2 or 4, one value per launch) that split the
+// i3 range and add their partial accumulators in LDS in a fixed order.  A
+// workgroup holds 4 / P items.  Lane l owns tensor row l of the row group
+// (rows past the group repeat its last row; their outputs are never stored)
+// and streams it in chunks of 64 bytes (raw storage bits, 16-byte loads when
+// every row starts 16-byte aligned), the next chunk in flight while the
+// current one is consumed.  The U3 rows of a chunk are staged in the
+// wavefront's own LDS area, transposed so that lane l's B operands
+// U3[k][4t + l%4], t < RT, are one contiguous run.  No workgroup barrier
+// unless P > 1.
+// ---------------------------------------------------------------------------
+template <typename TA, int RT>
+__device__ __forceinline__ void load_run(const TA* __restrict__ p, TA (&bb)[RT]) {
+    // RT consecutive operands from LDS with the widest reads
+    constexpr int VA = 16 / (int)sizeof(TA);
+#pragma unroll
+    for (int v = 0; v < RT / VA; ++v) {
+        const u32x4 w = *(const u32x4*)(p + v * VA);
+#pragma unroll
+        for (int j = 0; j < VA; ++j) bb[v * VA + j] = ((const TA*)&w)[j];
+    }
+    constexpr int R0 = RT / VA * VA;
+    if constexpr (RT - R0 >= 2 && sizeof(TA) == 4) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 w = *(const u32x2*)(p + R0);
+        bb[R0] = ((const TA*)&w)[0];
+        bb[R0 + 1] = ((const TA*)&w)[1];
+        if constexpr (RT - R0 == 3) bb[R0 + 2] = p[R0 + 2];
+    } else if constexpr (RT - R0 == 1) {
+        bb[R0] = p[R0];
+    }
+}
 
-// ---------------------------------------------------------------------------
-// pass 1: one workgroup per (block, i1 slab, 64-row group of i2); the four
-// wavefronts split the i3 range and are summed in LDS.  Tiles are staged with
-// every load of a tile in flight before the first LDS store.
-// ---------------------------------------------------------------------------
 template <typename TM, typename T, int RT>
 __global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP<T> st, const ItemP1* __restrict__ items,
-                                               int slot) {
+                                               int nitems, int P, int slot) {
     typedef typename AccType<TM>::type TA;
+    typedef typename Raw<TM>::type TR;
     if (st.ctrl->stop) return;
     apply_rot(st);
     extern __shared__ __attribute__((aligned(16))) char smraw[];
-    const ItemP1 it = items[blockIdx.x];
-    const int s = it.s, i1 = it.i1, rg = it.rg, row0 = rg * 64;
-    const int I2 = g->I[s][1], I3 = g->I[s][2], Rq = g->Rq;
+    constexpr int KC = 64 / (int)sizeof(TR);          // chunk: 64 bytes of a row
+    constexpr int NV = 4;                             // 16-byte words per chunk
+    constexpr int VA = 16 / (int)sizeof(TA);
+    constexpr int RTP = (RT + VA - 1) / VA * VA;      // padded operand run
+    constexpr int UPL = (KC * 4 * RT + 63) / 64;      // U3 chunk elements per lane
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ii = blockIdx.x * (4 / P) + wave / P, part = wave % P;
+    const ItemP1 it = items[min(ii, nitems - 1)];
+    const bool live = ii < nitems && it.s >= 0;
+    const int s = live ? it.s : 0, i1 = it.i1, rg = it.rg, row0 = rg * 64;
+    const int I2 = g->I[s][1], I3 = g->I[s][2], Rq = g->Rq;
     const int nrows = min(64, I2 - row0);
-    // epilogue mapping (phase, column) and its U2 values, loaded now so their
-    // latency overlaps the main loop
-    // (Rq = 4 RT, so there are 64 / RT phases and at most EPQ rows per thread)
-    constexpr int EPR = 64 / RT, EPQ = (64 + EPR - 1) / EPR;
-    const int ep_rp = EPR, ep_j = threadIdx.x / Rq, ep_c = threadIdx.x % Rq;
-    const bool ep_on = ep_j < ep_rp;
-    T u2v[EPQ];
-    double ep_part = 0.0;
+    const int myrow = min(lane, nrows - 1);
+    // the U2 values of the lane's accumulator rows (mode-1 partial), early
+    T u2v[RT][4];
     {
         const CPD_GLOBAL T* __restrict__ U2 = gptr(st.U[1] + g->uoff[1][s] + (long long)row0 * Rq);
 #pragma unroll
-        for (int q = 0; q < EPQ; ++q) {
-            const int r = ep_j + q * ep_rp;
-            u2v[q] = (ep_on && r < nrows) ? U2[(long long)r * Rq + ep_c] : (T)0;
-        }
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 4 * (lane >> 2) + v;
+                const T u = U2[(long long)min(r, nrows - 1) * Rq + 4 * t + (lane & 3)];
+                u2v[t][v] = (r < nrows) ? u : (T)0;
+            }
     }
-    typedef typename Raw<TM>::type TR;
     const long long ldm = g->mld[s];   // operand row stride (>= I3)
-    const CPD_GLOBAL TR* __restrict__ Ms = gptr((const TR*)g->M[s] + ((long long)i1 * I2 + row0) * ldm);
+    const CPD_GLOBAL TR* __restrict__ Mrow = gptr((const TR*)g->M[s] + ((long long)i1 * I2 + row0 + myrow) * ldm);
     const CPD_GLOBAL T* __restrict__ U3 = gptr(pick3(st.U, slot) + g->uoff[2][s]);
-    TA* sm = (TA*)smraw;
-    constexpr int KC = P1Shape<TA>::KC;
-    constexpr int VE = 16 / (int)sizeof(TR);          // tensor elements per 16-byte load
-    constexpr int VA = 16 / (int)sizeof(TA);          // operand elements per 16-byte LDS read
-    constexpr int RTP = (RT + VA - 1) / VA * VA;      // padded operand run per lane
-    constexpr int UPL = (KC * 4 * RT + 63) / 64;      // U3 chunk elements loaded per lane
-    // U3 rows of the chunk, transposed so that lane l's operands
-    // U3[k][4t + l%4], t < RT, are one contiguous run: [KC][4][RTP]
-    TA* ustage = sm + wave * (KC * 4 * RTP);
-
-    // the four wavefronts split i3 at multiples of KC (so chunks stay aligned)
-    const int kq = ((I3 + 3) / 4 + KC - 1) / KC * KC;
-    const int kb = min(I3, wave * kq), ke = min(I3, kb + kq);
+    TA* ustage = (TA*)smraw + wave * (KC * 4 * RTP);
+    // this wavefront's share of i3, in whole chunks
+    const int nck = (I3 + KC - 1) / KC, cpp = (nck + P - 1) / P;
+    const int kb = live ? min(I3, part * cpp * KC) : 0, ke = live ? min(I3, kb + cpp * KC) : 0;
+    const bool vec = g->mvec[s] != 0;
     Acc4<TA> acc[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) acc[t].zero();
-
-    // Lane l owns tensor row l of the row group (rows past the group repeat
-    // its last row; their outputs are never stored) and keeps its KC
-    // consecutive elements of the chunk in registers as the A operand: 16-byte
-    // loads when every row of the block starts 16-byte aligned.  The next
-    // chunk is loaded while the current one is consumed.
-    const bool vec = g->mvec[s] != 0;
-    const CPD_GLOBAL TR* __restrict__ Mrow = Ms + (long long)min(lane, nrows - 1) * ldm;
-    TA buf[KC], nbuf[KC], ubuf[UPL], nubuf[UPL];
-    auto load_chunk = [&](int k0, TA (&ab)[KC], TA (&ub)[UPL]) {
+    u32x4 cur[NV], nxt[NV];
+    TA ub[UPL], nub[UPL];
+    auto load_chunk = [&](int k0, u32x4 (&w)[NV], TA (&u)[UPL]) {
         const int kc = min(KC, ke - k0);
         if (vec && kc == KC) {
             const CPD_GLOBAL u32x4* vp = (const CPD_GLOBAL u32x4*)(Mrow + k0);
 #pragma unroll
-            for (int v = 0; v < KC / VE; ++v) {
-                const u32x4 w = vp[v];
-                const TR* e = (const TR*)&w;
-#pragma unroll
-                for (int j = 0; j < VE; ++j) ab[v * VE + j] = cvt<TA, TM>(e[j]);
-            }
+            for (int v = 0; v < NV; ++v) w[v] = vp[v];
         } else {
+            TR e[KC];
 #pragma unroll
             for (int j = 0; j < KC; ++j) {
-                const TA v = cvt<TA, TM>(Mrow[k0 + min(j, kc - 1)]);
-                ab[j] = (j < kc) ? v : (TA)0;
+                const TR x = Mrow[k0 + min(j, kc - 1)];
+                e[j] = (j < kc) ? x : (TR)0;
             }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) w[v] = *(const u32x4*)&e[v * (KC / NV)];
         }
 #pragma unroll
         for (int q = 0; q < UPL; ++q) {
             const int e = q * 64 + lane, kk = e / (4 * RT), c = e % (4 * RT);
-            const TA v = (TA)U3[(long long)(k0 + min(kk, kc - 1)) * Rq + c];
-            ub[q] = (kk < kc) ? v : (TA)0;
+            const TA x = (TA)U3[(long long)(k0 + min(kk, kc - 1)) * Rq + c];
+            u[q] = (kk < kc) ? x : (TA)0;
         }
     };
-    if (kb < ke) load_chunk(kb, buf, ubuf);
+    if (kb < ke) load_chunk(kb, cur, ub);
     for (int k0 = kb; k0 < ke; k0 += KC) {
 #pragma unroll
         for (int q = 0; q < UPL; ++q) {
             const int e = q * 64 + lane, kk = e / (4 * RT), c = e % (4 * RT);
-            if (e < KC * 4 * RT) ustage[(kk * 4 + (c & 3)) * RTP + (c >> 2)] = ubuf[q];
+            if (e < KC * 4 * RT) ustage[(kk * 4 + (c & 3)) * RTP + (c >> 2)] = ub[q];
         }
         wave_sync();
-        if (k0 + KC < ke) load_chunk(k0 + KC, nbuf, nubuf);
+        if (k0 + KC < ke) load_chunk(k0 + KC, nxt, nub);
+        const TR* el = (const TR*)cur;
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
-            TA bb[RTP];
-            const TA* ur = ustage + (kk * 4 + (lane & 3)) * RTP;
+            TA bb[RT];
+            load_run<TA, RT>(ustage + (kk * 4 + (lane & 3)) * RTP, bb);
+            const TA a = cvt<TA, TM>(el[kk]);
 #pragma unroll
-            for (int v = 0; v < RTP / VA; ++v) *(u32x4*)&bb[v * VA] = *(const u32x4*)(ur + v * VA);
-#pragma unroll
-            for (int t = 0; t < RT; ++t) acc[t].mma(buf[kk], bb[t]);
+            for (int t = 0; t < RT; ++t) acc[t].mma(a, bb[t]);
         }
         wave_sync();
 #pragma unroll
-        for (int j = 0; j < KC; ++j) buf[j] = nbuf[j];
+        for (int v = 0; v < NV; ++v) cur[v] = nxt[v];
 #pragma unroll
-        for (int q = 0; q < UPL; ++q) ubuf[q] = nubuf[q];
+        for (int q = 0; q < UPL; ++q) ub[q] = nub[q];
     }
-    __syncthreads();
-    TA* red = sm;  // [4 waves][64 rows][Rq]
+    if (P > 1) {
+        // partial accumulators of the P wavefronts of an item, added in part order
+        TA* red = (TA*)smraw + 4 * (KC * 4 * RTP);   // [4 waves][RT][4][64]
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+        for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            red[(wave * 64 + 4 * (lane >> 2) + v) * Rq + 4 * t + (lane & 3)] = acc[t].get(v);
-    __syncthreads();
-    // Epilogue: thread (phase j, column c) with Rq * RP <= 256 sums the four
-    // wave partials of rows j, j + RP, ..., writes Y, and accumulates the
-    // mode-1 partial sum_r Y[r][c] U2_old[row0 + r][c] over its rows (U2
-    // prefetched at kernel start); the RP phase sums are added in fixed order.
-    CPD_GLOBAL T* __restrict__ Y = gptr_w(st.Y + g->yoff[s] + ((long long)i1 * I2 + row0) * Rq);
-    if (ep_on) {
-        double a = 0.0;
+            for (int v = 0; v < 4; ++v) red[((wave * RT + t) * 4 + v) * 64 + lane] = acc[t].get(v);
+        __syncthreads();
+        if (part == 0) {
 #pragma unroll
-        for (int q = 0; q < EPQ; ++q) {
-            const int r = ep_j + q * ep_rp;
-            if (r < nrows) {
-                const TA v = red[(0 * 64 + r) * Rq + ep_c] + red[(1 * 64 + r) * Rq + ep_c] + red[(2 * 64 + r) * Rq + ep_c] +
-                             red[(3 * 64 + r) * Rq + ep_c];
-                const T yv = (T)v;
-                Y[(long long)r * Rq + ep_c] = yv;
-                a += (double)yv * (double)u2v[q];
+            for (int t = 0; t < RT; ++t) {
+                TA x[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    x[v] = red[((wave * RT + t) * 4 + v) * 64 + lane];
+                    for (int p = 1; p < P; ++p) x[v] += red[(((wave + p) * RT + t) * 4 + v) * 64 + lane];
+                }
+                acc[t].set(x);
             }
         }
-        ep_part = a;
     }
-    __syncthreads();
-    double* kp = (double*)smraw;   // [RP][Rq]
-    if (ep_on) kp[ep_j * Rq + ep_c] = ep_part;
-    __syncthreads();
-    if (threadIdx.x < Rq) {
+    if (!live || part != 0) return;
+    // Y rows straight from the accumulators (lane: rows 4(l/4)+v, column
+    // 4t + l%4), and the mode-1 partial sum_r Y[r][c] U2_old[row0 + r][c]:
+    // the lane's four rows, then the sixteen lanes of the column in a fixed
+    // butterfly order
+    CPD_GLOBAL T* __restrict__ Y = gptr_w(st.Y + g->yoff[s] + ((long long)i1 * I2 + row0) * Rq);
+    double kp[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
         double a = 0.0;
-        for (int j = 0; j < ep_rp; ++j) a += kp[j * Rq + threadIdx.x];
-        gptr_w(st.K1p)[g->k1off[s] + ((long long)i1 * g->nrg[s] + rg) * Rq + threadIdx.x] = (T)a;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 4 * (lane >> 2) + v;
+            const T yv = (T)acc[t].get(v);
+            if (r < nrows) Y[(long long)r * Rq + 4 * t + (lane & 3)] = yv;
+            a += (double)yv * (double)u2v[t][v];
+        }
+        kp[t] = a;
+    }
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) kp[t] += __shfl_xor(kp[t], o, 64);
+    if (lane < 4) {
+        CPD_GLOBAL T* __restrict__ K1p = gptr_w(st.K1p) + g->k1off[s] + ((long long)i1 * g->nrg[s] + rg) * Rq;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) K1p[4 * t + lane] = (T)kp[t];
     }
 }
 

@@ -62,6 +62,7 @@ struct Lists {
     std::vector<ItemU> u[3];
     int maxI2;
     int lds_rows[3];
+    int p1_split;   // wavefronts per pass-1 item (1, 2 or 4)
 };
 
 concpd_status validate(const concpd_config* c) {
@@ -117,16 +118,18 @@ concpd_status validate(const concpd_config* c) {
 // the contiguous range x * n / 8 .. of it keeps items that share cache lines
 // (neighbouring row segments of the tensor, of Y) in one L2.
 template <typename Item>
-void xcd_order(std::vector<Item>& v) {
-    const size_t n8 = v.size() - v.size() % 8, per = n8 / 8;
+void xcd_order(std::vector<Item>& v, size_t grp = 1) {
+    // v holds whole workgroups of grp consecutive items
+    const size_t ng = v.size() / grp, n8 = ng - ng % 8, per = n8 / 8;
     if (per < 2) return;
     std::vector<Item> out(v.size());
-    for (size_t b = 0; b < n8; ++b) out[b] = v[(b % 8) * per + b / 8];
-    for (size_t b = n8; b < v.size(); ++b) out[b] = v[b];
+    for (size_t b = 0; b < n8; ++b)
+        for (size_t j = 0; j < grp; ++j) out[b * grp + j] = v[((b % 8) * per + b / 8) * grp + j];
+    for (size_t b = n8 * grp; b < v.size(); ++b) out[b] = v[b];
     v.swap(out);
 }
 
-void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAULT) {
+void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAULT, int p1split = 0) {
     const int S = c->num_blocks, R = c->rank, Rq = (R + 3) / 4 * 4;
     L->p1.clear();
     L->p2.clear();
@@ -142,7 +145,20 @@ void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAU
         for (int ch = 0; ch * 4 < I1; ++ch)
             for (int q0 = 0; q0 < I3; q0 += 64) L->p2.push_back({s, ch, q0, 0});
     }
-    xcd_order(L->p1);
+    // pass 1: the smallest split P of i3 over wavefronts that gives about two
+    // wavefronts per SIMD, no more than the 64-byte chunks of the shortest row;
+    // the list is padded to whole workgroups (4 / P items) with empty items
+    {
+        int minck = 1 << 30;
+        for (int s = 0; s < S; ++s) minck = std::min(minck, (int)((c->dims[3 * s + 2] + 15) / 16));
+        int P = 1;
+        if (p1split > 0) P = p1split;
+        else
+            while (P < 4 && L->p1.size() * P < 2048 && 2 * P <= minck) P *= 2;
+        L->p1_split = P;
+        while (L->p1.size() % (4 / P)) L->p1.push_back({-1, 0, 0, 0});
+        xcd_order(L->p1, 4 / P);
+    }
     xcd_order(L->p2);
     xcd_order(L->k2);
     for (int n = 0; n < 3; ++n) {
@@ -233,7 +249,7 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     P->part = take((size_t)p * P->esz);
     P->K1p = take((size_t)k1 * P->esz);
     P->K2 = take((size_t)k2 * P->esz);
-    P->it1 = take(sizeof(ItemP1) * std::max<size_t>(1, L.p1.size()));
+    P->it1 = take(sizeof(ItemP1) * (L.p1.size() + 4));   // room for the padding of any split
     P->it2 = take(sizeof(ItemP2) * std::max<size_t>(1, L.p2.size()));
     {
         Lists Lmin;
@@ -376,6 +392,7 @@ struct concpd_ctx_s {
     hipStream_t qcap;
     hipGraphExec_t gexec;
     int k2rows;
+    int p1split = 0;   // requested pass-1 split (0: automatic)
     std::vector<hipEvent_t> ev1, ev2;  // begin/end pairs of timed pass launches
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -452,7 +469,7 @@ void run_sweep(concpd_ctx c, const StateP<T>& st) {
     fork(0);
     cpd::launch_core<T>(g, st, S, R, extrap, qa);
     if (prof) (void)hipEventRecord(e[0], q);
-    cpd::launch_pass1<T>(g, st, it1, (int)c->lists.p1.size(), Rq, 1, c->mdtype, q);
+    cpd::launch_pass1<T>(g, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, Rq, 1, c->mdtype, q);
     if (prof) (void)hipEventRecord(e[1], q);
     join(1);
     cpd::launch_update<T>(g, st, itu[0], (int)c->lists.u[0].size(), 0, R, extrap, c->lists.lds_rows[0], 0, q);
@@ -676,7 +693,7 @@ void debug_passes(concpd_ctx c, const StateP<T>& st) {
     const ItemP1* it1 = (const ItemP1*)(c->ws + c->lay.it1);
     const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
     const ItemK2* itk = (const ItemK2*)(c->ws + c->lay.itk2);
-    cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->Rq, 1, c->mdtype, c->q);
+    cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->q);
     cpd::launch_k2<T>(c->dgeo, st, itk, (int)c->lists.k2.size(), 1, c->q);
     cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
 }
@@ -722,7 +739,7 @@ concpd_status loss_grad_t(concpd_ctx c, const StateP<T>& st, const void* const* 
     const ItemP1* it1 = (const ItemP1*)(c->ws + P.it1);
     const ItemP2* it2 = (const ItemP2*)(c->ws + P.it2);
     const ItemK2* itk = (const ItemK2*)(c->ws + P.itk2);
-    cpd::launch_pass1<T>(c->dgeo, sg, it1, (int)c->lists.p1.size(), c->Rq, 1, c->mdtype, c->q);
+    cpd::launch_pass1<T>(c->dgeo, sg, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->q);
     cpd::launch_k2<T>(c->dgeo, sg, itk, (int)c->lists.k2.size(), 0, c->q);
     cpd::launch_pass2<T>(c->dgeo, sg, it2, (int)c->lists.p2.size(), c->Rq, 0, c->mdtype, c->lists.maxI2, c->q);
     for (int s = 0; s < c->S; ++s)
@@ -1245,11 +1262,23 @@ concpd_status concpd_set_option(concpd_ctx c, int32_t option, int64_t value) {
         }
         c->overlap = value != 0;
         return CONCPD_OK;
+    case CONCPD_OPT_P1_SPLIT: {
+        if (value != 0 && value != 1 && value != 2 && value != 4)
+            return fail(CONCPD_EINVAL, "pass-1 split %lld not 0, 1, 2 or 4", (long long)value);
+        Lists L;
+        build_lists(&c->cfg, &L, c->k2rows, (int)value);
+        c->lists.p1 = L.p1;
+        c->lists.p1_split = L.p1_split;
+        c->p1split = (int)value;
+        HIPCHECK(hipMemcpy(c->ws + c->lay.it1, c->lists.p1.data(), c->lists.p1.size() * sizeof(ItemP1), hipMemcpyHostToDevice));
+        c->drop_graph();
+        return CONCPD_OK;
+    }
     case CONCPD_OPT_K2_ROWS: {
         if (value < CPD_K2ROWS_MIN || value > 64)
             return fail(CONCPD_EINVAL, "mode-2 chunk rows %lld not in [%d, 64]", (long long)value, CPD_K2ROWS_MIN);
         Lists L;
-        build_lists(&c->cfg, &L, (int)value);
+        build_lists(&c->cfg, &L, (int)value, c->p1split);
         c->lists.k2 = L.k2;
         HIPCHECK(hipMemcpy(c->ws + c->lay.itk2, c->lists.k2.data(), c->lists.k2.size() * sizeof(ItemK2), hipMemcpyHostToDevice));
         c->k2rows = (int)value;
@@ -1270,6 +1299,7 @@ concpd_status concpd_get_option(concpd_ctx c, int32_t option, int64_t* value) {
     case CONCPD_OPT_GRAPH_SWEEPS: *value = c->graph_sweeps; return CONCPD_OK;
     case CONCPD_OPT_OVERLAP: *value = c->overlap; return CONCPD_OK;
     case CONCPD_OPT_K2_ROWS: *value = c->k2rows; return CONCPD_OK;
+    case CONCPD_OPT_P1_SPLIT: *value = c->lists.p1_split; return CONCPD_OK;
     default: return fail(CONCPD_EINVAL, "unknown option %d", option);
     }
 }
@@ -1305,26 +1335,53 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
     double best = INFINITY, dflt = INFINITY;
-    int bk = c->k2rows, bg = c->graph_sweeps, ncand = 0;
-    for (int ki = 0; ki < 3; ++ki) {
+    int bk = c->k2rows, bg = c->graph_sweeps, ncand = 0, bp = c->p1split;
+    auto time_sweeps = [&](double& us) -> concpd_status {
+        concpd_status q;
+        if ((q = restore()) != CONCPD_OK) return q;
+        if ((q = launch_sweeps(c, 4)) != CONCPD_OK) return q;   // warm-up (and graph capture)
+        if ((q = restore()) != CONCPD_OK) return q;
+        HIPCHECK(hipEventRecord(e0, c->q));
+        if ((q = launch_sweeps(c, sweeps)) != CONCPD_OK) return q;
+        HIPCHECK(hipEventRecord(e1, c->q));
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        us = 1e3 * ms / sweeps;
+        ++ncand;
+        return CONCPD_OK;
+    };
+    if (!c->lra) {
+        // the pass-1 split of i3 over wavefronts (direct launches, default chunk rows)
+        Lists La;
+        build_lists(&c->cfg, &La, CPD_K2ROWS_DEFAULT, 0);
+        const int p_auto = La.p1_split;
+        double bpu = INFINITY;
+        const int psc[3] = {1, 2, 4};
+        if ((r = concpd_set_option(c, CONCPD_OPT_GRAPH_SWEEPS, 0)) == CONCPD_OK)
+            r = concpd_set_option(c, CONCPD_OPT_K2_ROWS, CPD_K2ROWS_DEFAULT);
+        for (int pi = 0; pi < 3 && r == CONCPD_OK; ++pi) {
+            if ((r = concpd_set_option(c, CONCPD_OPT_P1_SPLIT, psc[pi])) != CONCPD_OK) break;
+            double us = 0.0;
+            if ((r = time_sweeps(us)) != CONCPD_OK) break;
+            if (psc[pi] == p_auto) dflt = us;
+            if (us < bpu) {
+                bpu = us;
+                bp = psc[pi];
+            }
+        }
+        if (r == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_P1_SPLIT, bp);
+    }
+    for (int ki = 0; ki < 3 && r == CONCPD_OK; ++ki) {
         if (c->lra && ki > 0) break;   // the mode-2 contraction is not on the lra path
         r = concpd_set_option(c, CONCPD_OPT_K2_ROWS, k2c[ki]);
         if (r != CONCPD_OK) break;
         for (int gi = 0; gi < 3; ++gi) {
             r = concpd_set_option(c, CONCPD_OPT_GRAPH_SWEEPS, gsc[gi]);
             if (r != CONCPD_OK) break;
-            if ((r = restore()) != CONCPD_OK) break;
-            if ((r = launch_sweeps(c, 4)) != CONCPD_OK) break;   // warm-up (and graph capture)
-            if ((r = restore()) != CONCPD_OK) break;
-            HIPCHECK(hipEventRecord(e0, c->q));
-            if ((r = launch_sweeps(c, sweeps)) != CONCPD_OK) break;
-            HIPCHECK(hipEventRecord(e1, c->q));
-            HIPCHECK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-            const double us = 1e3 * ms / sweeps;
-            ++ncand;
-            if (k2c[ki] == CPD_K2ROWS_DEFAULT && gsc[gi] == 0) dflt = us;
+            double us = 0.0;
+            if ((r = time_sweeps(us)) != CONCPD_OK) break;
+            if (c->lra && k2c[ki] == CPD_K2ROWS_DEFAULT && gsc[gi] == 0) dflt = us;
             if (us < best) {
                 best = us;
                 bk = k2c[ki];
@@ -1349,6 +1406,7 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
     HIPCHECK(hipStreamSynchronize(c->q));
     if (out) {
         out->k2_rows = c->k2rows;
+        out->p1_split = c->lists.p1_split;
         out->graph_sweeps = bg;
         out->us_per_sweep = best;
         out->us_per_sweep_default = dflt;

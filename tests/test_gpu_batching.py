@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import synth
+from paper_2302_05119_amd import ConcpdError
 from oracle import apg
 from oracle.apg import DenseData, Options
 
@@ -87,6 +88,27 @@ def test_k2_rows_option_within_tolerance():
         assert abs(s["F"] - ref.F) / ref.F <= 1e-5 and e <= 1e-4
 
 
+def test_p1_split_option_within_tolerance():
+    # 3 x 33 row-group items (a count that needs empty padding items for
+    # splits 1 and 2); I3 = 100 spans several 64-byte chunks and a ragged tail
+    say("[options] pass-1 split")
+    L = (3, 0, 0)
+    P = synth.coupled_problem([(33, 45, 100)] * 3, 8, L, 10.0, 815)
+    U0, lam0 = synth.uniform_init(P.dims, 8, L, 816)
+    ref = apg.run(DenseData(P.tensors), U0, lam0, Options(L=L), iters=3)
+    for split in (1, 2, 4, 0):
+        m = model(P, U0, lam0)
+        m.set_option("p1_split", split)
+        assert m.get_option("p1_split") in ((1, 2, 4) if split == 0 else (split,))
+        s = m.step(3)
+        e = max(rel(m.factor(n, b), ref.U[n][b]) for n in range(3) for b in range(3))
+        say(f"   p1_split={split} F={s['F']:.10e} oracle={ref.F:.10e} max factor err={e:.2e}")
+        assert abs(s["F"] - ref.F) / ref.F <= 1e-5 and e <= 1e-4
+    m = model(P, U0, lam0)
+    with pytest.raises(ConcpdError):
+        m.set_option("p1_split", 3)
+
+
 def test_autotune_keeps_the_iterate():
     say("[autotune]")
     L = (5, 0, 0)
@@ -97,7 +119,8 @@ def test_autotune_keeps_the_iterate():
     before, st0 = factors(m), m.stats()
     t = m.autotune(8)
     say(f"   {t}")
-    assert t["candidates"] == 9 and t["k2_rows"] in (8, 16, 32) and t["graph_sweeps"] in (0, 1, 4)
+    assert t["candidates"] == 12 and t["k2_rows"] in (8, 16, 32) and t["graph_sweeps"] in (0, 1, 4)
+    assert t["p1_split"] in (1, 2, 4) and m.get_option("p1_split") == t["p1_split"]
     assert t["us_per_sweep"] <= t["us_per_sweep_default"]
     st1 = m.stats()
     assert st1["k"] == st0["k"] and st1["F"] == st0["F"]
