@@ -236,9 +236,9 @@ concpd_status concpd_profile_read(concpd_ctx ctx, double* ms_pass1, double* ms_p
  *                            (8..64, default 16).
  *   CONCPD_OPT_P1_SPLIT      wavefronts that share one 64-row item of pass 1
  *                            (M x_3 U^(3)), splitting its i3 range: 1, 2 or 4;
- *                            0 (default): chosen from the item count (about
- *                            two wavefronts per SIMD).  Get returns the split
- *                            in use.
+ *                            0 (default): chosen from the item count (at
+ *                            least 1.5 wavefronts per SIMD).  Get returns the
+ *                            split in use.
  * Synchronises.  Errors: EINVAL (unknown option or value), EHIP. */
 typedef enum concpd_option {
     CONCPD_OPT_GRAPH_SWEEPS = 1,

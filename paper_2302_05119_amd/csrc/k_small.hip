@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 // sums F over the blocks in block order, applies the restart test of
 // Algorithm 1 and, for an accepted sweep, commits it: Lipschitz constants,
 // k, t, w_hat, the stopping rule and the slot rotation.
-template <typename T>
+template <typename T, int NMAX>
 __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, StateP<T> st) {
     Ctrl* c = st.ctrl;
     if (c->stop) return;
@@ -38,13 +38,38 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     __shared__ int last;
     __shared__ double fb[CPD_MAXS], nb[CPD_MAXS];
+    // what the last workgroup needs, read now so that its latency overlaps the
+    // Gram (no workgroup of this launch writes any of it before the last one)
+    const double nrm = (tid < S) ? st.normM2[tid] : 1.0;
+    const double ldc = (tid < S) ? st.Ld_cur[tid] : 0.0;
+    const double luc = (tid < 3 * S) ? st.Lu_cur[tid] : 0.0;
+    const int redo0 = c->redo, restart_on = c->restart_on, reset_t = c->reset_t;
+    const double F_prev = c->F_prev, rel_old = c->rel_prev, t_old = c->t, tol = c->tol;
+    const long long k_old = c->k;
+    const long long restarts = c->restarts;
+    const int rot3 = c->rot3, rot2 = c->rot2;
+    // the objective's other inputs (Grams of the new modes 1 and 2, lambda)
+    constexpr int EP = (NMAX * NMAX + 255) / 256;
+    double v0[EP], v1[EP];
+    {
+        const double* V0 = st.V[0] + (0 * S + s) * RR;
+        const double* V1 = st.V[0] + (1 * S + s) * RR;
+#pragma unroll
+        for (int q = 0; q < EP; ++q) {
+            const int i = min(tid + 256 * q, RR - 1);
+            v0[q] = V0[i];
+            v1[q] = V1[i];
+        }
+    }
+    __shared__ double lam[64];
+    if (tid < 64) lam[tid] = st.lam[0][s * Rq + min(tid, R - 1)];
+    const double nrm_s = st.normM2[s];
     double* V2 = st.V[0] + (2 * S + s) * RR;
     double* b = st.b[0] + s * Rq;
-    block_gram<T>(st.U[0] + g->uoff[2][s], g->I[s][2], R, Rq, V2, st.K3 + g->koff[s], b, smraw);
-    __threadfence_block();
-    __syncthreads();
-    const double F = block_objective(st.lam[0] + s * Rq, st.V[0] + (0 * S + s) * RR, st.V[0] + (1 * S + s) * RR, V2, b,
-                                     st.normM2[s], R);
+    double* V2l = (double*)(smraw + gram_lds_bytes<T>(Rq, 1));
+    double* bl = V2l + RR;
+    block_gram<T>(st.U[0] + g->uoff[2][s], g->I[s][2], R, Rq, V2, st.K3 + g->koff[s], b, smraw, V2l, bl);
+    const double F = block_objective_pf<EP>(lam, v0, v1, V2l, bl, nrm_s, R);
     if (tid == 0) {
         store_agent(&st.Fblk[s], F);
         wait_stores();
@@ -54,7 +79,7 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     if (!last) return;
     if (tid < S) {
         fb[tid] = load_agent(&st.Fblk[tid]);
-        nb[tid] = st.normM2[tid];
+        nb[tid] = nrm;
     }
     __syncthreads();
     __shared__ int accept;
@@ -71,7 +96,7 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
         c->nonfinite = !isfinite(Fs);
         // restart test of Algorithm 1: a rejected extrapolated sweep leaves
         // x_{k-1} in place and the next sweep redoes it without extrapolation
-        const int reject = !c->redo && c->restart_on && Fs >= c->F_prev;
+        const int reject = !redo0 && restart_on && Fs >= F_prev;
         if (reject) c->redo = 1;
         accept = !reject;
         fsum = Fs;
@@ -82,11 +107,10 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     if (!accept) return;
     // accept: the Lipschitz constants of this sweep become the previous ones
     __shared__ double lu[3 * CPD_MAXS];
-    if (tid < S) st.Ld_prev[tid] = st.Ld_cur[tid];
+    if (tid < S) st.Ld_prev[tid] = ldc;
     if (tid < 3 * S) {
-        const double v = st.Lu_cur[tid];
-        st.Lu_prev[tid] = v;
-        lu[tid] = v;
+        st.Lu_prev[tid] = luc;
+        lu[tid] = luc;
     }
     __syncthreads();
     if (tid < 3) {
@@ -95,22 +119,20 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
         st.LC_prev[tid] = LC;
     }
     if (tid != 0) return;
-    const int redo = c->redo;
-    c->restarts += redo;
-    c->last_restarted = redo;
-    const double rel_old = c->rel_prev;
+    c->restarts = restarts + redo0;
+    c->last_restarted = redo0;
     c->F_prev = fsum;
     c->rel_prev = rsum;
-    c->k += 1;
-    double t_k = 0.5 * (1.0 + sqrt(1.0 + 4.0 * c->t * c->t));
-    if (redo && c->reset_t) t_k = 1.0;
+    c->k = k_old + 1;
+    double t_k = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t_old * t_old));
+    if (redo0 && reset_t) t_k = 1.0;
     c->t = t_k;
     c->w_hat = (t_k - 1.0) / (0.5 * (1.0 + sqrt(1.0 + 4.0 * t_k * t_k)));
-    if (c->tol > 0.0 && fabs(rsum - rel_old) < c->tol) c->stop = 1;
+    if (tol > 0.0 && fabs(rsum - rel_old) < tol) c->stop = 1;
     c->redo = 0;
     // x_{k-2} <- x_{k-1} <- x_k by slot rotation
-    c->rot3 = (c->rot3 + 2) % 3;
-    c->rot2 ^= 1;
+    c->rot3 = (rot3 + 2) % 3;
+    c->rot2 = rot2 ^ 1;
 }
 
 // Iterate in slot 1 (initial or restored): Grams of every factor, b from the
@@ -204,7 +226,9 @@ void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, hipStre
 template <typename T>
 void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q) {
     const int Rq = (R + 3) / 4 * 4;
-    hipLaunchKernelGGL(k_finish<T>, dim3(S), dim3(256), gram_lds_bytes<T>(Rq, 1), q, g, st);
+#define CPD_FIN(N) hipLaunchKernelGGL((k_finish<T, N>), dim3(S), dim3(256), finish_lds_bytes<T>(R, Rq), q, g, st)
+    CPD_NMAX_DISPATCH(R, CPD_FIN);
+#undef CPD_FIN
 }
 template <typename T>
 void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q) {

@@ -31,9 +31,7 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
     double* gc = uh + ns * nrows * R;      // [ns][nrows][Ln]
     const int tot = ns * nrows * R;
     const double what = c->w_hat, dw = c->delta_w;
-    double LC = 0.0;
-    if (Ln > 0)
-        for (int b = 0; b < S; ++b) LC += st.Lu_cur[n * S + b];
+    const double LC = (Ln > 0) ? strided_sum(st.Lu_cur + n * S, 1, S) : 0.0;
     const double wC = (Ln > 0) ? extrap_weight(extrapolate, what, st.LC_prev[n], LC, dw) : 0.0;
 
     // extrapolated point
@@ -52,16 +50,22 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
         const int s = s0 + sl, i = row0 + rr;
         const double* P = st.P + (long long)s * RR;
         const double* u = uh + (sl * nrows + rr) * R;
-        double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-        int r = 0;
-        for (; r + 3 < R; r += 4) {
-            g0 = fma(u[r], P[r * R + col], g0);
-            g1 = fma(u[r + 1], P[(r + 1) * R + col], g1);
-            g2 = fma(u[r + 2], P[(r + 2) * R + col], g2);
-            g3 = fma(u[r + 3], P[(r + 3) * R + col], g3);
+        // four chains by r mod 4, then the remainder into the first; eight
+        // entries of the P column in flight per step
+        double ga[4] = {0.0, 0.0, 0.0, 0.0};
+        const int R4 = R & ~3;
+        for (int r0 = 0; r0 < R; r0 += 8) {
+            double pv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) pv[q] = P[min(r0 + q, R - 1) * R + col];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (r0 + q < R4) ga[q & 3] = fma(u[r0 + q], pv[q], ga[q & 3]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (r0 + q >= R4 && r0 + q < R) ga[0] = fma(u[r0 + q], pv[q], ga[0]);
         }
-        for (; r < R; ++r) g0 = fma(u[r], P[r * R + col], g0);
-        double gr = (g0 + g1) + (g2 + g3);
+        double gr = (ga[0] + ga[1]) + (ga[2] + ga[3]);
         const double kv = k_value<T, KSRC>(g, st, s, i, col);
         gr -= kv * st.lam[0][s * Rq + col];
         if (KSRC == KSRC_PART || KSRC == KSRC_LRA2) st.K3[g->koff[s] + (long long)i * Rq + col] = (T)kv;

@@ -277,30 +277,45 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
 #pragma unroll
         for (int t = 0; t < RT; ++t) u1v[t] = (TA)U1[4 * t];
     }
-    if (BLDS) {
-        // U2 transposed so that lane l's operands U2[i2][4t + l%4], t < RT,
-        // are one contiguous run: [I2][4][RTP]
-        for (int e = threadIdx.x; e < I2 * Rq; e += 256) {
-            const int i2 = e / Rq, c = e % Rq;
-            sm[(i2 * 4 + (c & 3)) * RTP + (c >> 2)] = (TA)U2g[e];
-        }
-        __syncthreads();
-    }
     Acc4<TA> z[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) z[t].zero();
     constexpr int NB = 16;
-    if (i1 < I1) {
-        typedef typename Raw<TM>::type TR;
-        const long long ldm = g->mld[s];   // operand row stride (>= I3)
-        const CPD_GLOBAL TR* __restrict__ Mp = gptr((const TR*)g->M[s] + (long long)i1 * I2 * ldm + (valid ? i3 : 0));
-        TA cur[NB], nxt[NB];
+    // the first NB rows of the slab are requested before the U2 staging, so
+    // their latency overlaps it (clamped, always valid addresses; zeros
+    // outside the slab)
+    typedef typename Raw<TM>::type TR;
+    const bool live = i1 < I1;
+    const long long ldm = g->mld[s];   // operand row stride (>= I3)
+    const CPD_GLOBAL TR* __restrict__ Mp =
+        gptr((const TR*)g->M[s] + (long long)min(i1, I1 - 1) * I2 * ldm + (valid ? i3 : 0));
+    TA cur[NB], nxt[NB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            // clamped (always valid) address, zero outside: no branch per load
-            const TA v = cvt<TA, TM>(Mp[(long long)min(j, I2 - 1) * ldm]);
-            cur[j] = (valid && j < I2) ? v : (TA)0;
+    for (int j = 0; j < NB; ++j) {
+        const TA v = cvt<TA, TM>(Mp[(long long)min(j, I2 - 1) * ldm]);
+        cur[j] = (live && valid && j < I2) ? v : (TA)0;
+    }
+    if (BLDS) {
+        // U2 transposed so that lane l's operands U2[i2][4t + l%4], t < RT,
+        // are one contiguous run: [I2][4][RTP]
+        // (eight loads per thread in flight per step, clamped addresses)
+        const int nu = I2 * Rq;
+        for (int e0 = threadIdx.x; e0 < nu; e0 += 256 * 8) {
+            T v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = U2g[min(e0 + 256 * j, nu - 1)];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int e = e0 + 256 * j;
+                if (e < nu) {
+                    const int i2 = e / Rq, c = e % Rq;
+                    sm[(i2 * 4 + (c & 3)) * RTP + (c >> 2)] = (TA)v[j];
+                }
+            }
         }
+        __syncthreads();
+    }
+    if (live) {
         for (int i2b = 0; i2b < I2; i2b += NB) {
             const int nb2 = i2b + NB;
 #pragma unroll

@@ -376,7 +376,9 @@ __device__ __forceinline__ bool wg_lmax_vsq(const double* __restrict__ A, int n,
                     const double* y1 = y0 + LP;
                     double s00a = 0.0, s00b = 0.0, s01a = 0.0, s01b = 0.0;
                     double s10a = 0.0, s10b = 0.0, s11a = 0.0, s11b = 0.0;
-#pragma unroll
+                    // four steps (sixteen row reads) in flight: enough overlap
+                    // without hoisting every read into registers
+#pragma unroll 4
                     for (int k = 0; k < NPM; k += 2) {
                         const d2 p0 = *(const d2*)(x0 + k), p1 = *(const d2*)(x1 + k);
                         const d2 q0 = *(const d2*)(y0 + k), q1 = *(const d2*)(y1 + k);
@@ -639,10 +641,12 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
 // tiles of U, one 16 x 16 output tile per tile pair (ta <= tb), four rows per
 // step; wave w takes the row steps w, w+4, ... and the four partial tiles are
 // added in fixed order through LDS (lds: 256 + 256 doubles).  Only the upper
-// triangle is formed and mirrored.
+// triangle is formed and mirrored.  lout / lbout (optional, LDS): copies of V
+// (row stride R) and b for the caller.
 template <typename T>
 __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R, int Rq, double* __restrict__ out,
-                                           const T* __restrict__ K, double* __restrict__ bout, char* lds) {
+                                           const T* __restrict__ K, double* __restrict__ bout, char* lds,
+                                           double* __restrict__ lout = nullptr, double* __restrict__ lbout = nullptr) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nt = (R + 15) >> 4;                       // column tiles (<= 4)
@@ -716,10 +720,18 @@ __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R
             if (r < R && c < R && (ta < tb || r <= c)) {
                 out[r * R + c] = d;
                 out[c * R + r] = d;
+                if (lout) {
+                    lout[r * R + c] = d;
+                    lout[c * R + r] = d;
+                }
             }
         }
     __syncthreads();
-    if (K != nullptr && tid < R) bout[tid] = ((bpart[tid] + bpart[64 + tid]) + bpart[128 + tid]) + bpart[192 + tid];
+    if (K != nullptr && tid < R) {
+        const double bb = ((bpart[tid] + bpart[64 + tid]) + bpart[128 + tid]) + bpart[192 + tid];
+        bout[tid] = bb;
+        if (lbout) lbout[tid] = bb;
+    }
     __syncthreads();
 }
 
@@ -731,6 +743,30 @@ __device__ __forceinline__ double block_objective(const double* lam, const doubl
     const int tid = threadIdx.x, RR = R * R;
     double part = 0.0;
     for (int i = tid; i < RR; i += 256) part += lam[i / R] * lam[i % R] * V0[i] * V1[i] * V2[i];
+    if (tid < R) part -= 2.0 * lam[tid] * b[tid];
+    red[tid] = part;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    return 0.5 * (normM2 + red[0]);
+}
+
+// The same objective from values already at hand: V0, V1 entries tid + 256 q
+// in registers, lambda, V2 (row stride R) and b in LDS.  Same products and
+// the same summation order as block_objective.
+template <int EP>
+__device__ __forceinline__ double block_objective_pf(const double* lam, const double (&v0)[EP], const double (&v1)[EP],
+                                                     const double* V2, const double* b, double normM2, int R) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x, RR = R * R;
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < EP; ++q) {
+        const int i = tid + 256 * q;
+        if (i < RR) part += lam[i / R] * lam[i % R] * v0[q] * v1[q] * V2[i];
+    }
     if (tid < R) part -= 2.0 * lam[tid] * b[tid];
     red[tid] = part;
     __syncthreads();
@@ -760,10 +796,16 @@ __host__ __device__ inline size_t gram_lds_bytes(int Rq, int with_k) {
     (void)with_k;
     return sizeof(double) * (4 * 256 + 4 * 64);
 }
+// finish: the Gram's partial tiles, then copies of the new Gram and b
+template <typename T>
+__host__ __device__ inline size_t finish_lds_bytes(int R, int Rq) {
+    return gram_lds_bytes<T>(Rq, 1) + sizeof(double) * ((size_t)R * R + 64);
+}
 template <typename T>
 __host__ __device__ inline size_t prep_lds_bytes(int R, int Rq) {
+    // the eigenvalue work (or the Gram's partial tiles), then the new Gram
     const size_t a = eig_lds_bytes(R), b = gram_lds_bytes<T>(Rq, 0);
-    return a > b ? a : b;
+    return (a > b ? a : b) + sizeof(double) * (size_t)R * R;
 }
 
 // Core tensor update (eq. solD with the gradient of eq. solapgG at the
@@ -780,43 +822,68 @@ __device__ __forceinline__ void core_block(const Geo* __restrict__ g, const Stat
     const double* V0 = st.V[1] + (0 * S + s) * RR;
     const double* V1 = st.V[1] + (1 * S + s) * RR;
     const double* V2 = st.V[1] + (2 * S + s) * RR;
-    for (int i = tid; i < RR; i += 256) A[(i / R) * ld + i % R] = V0[i] * V1[i] * V2[i];
+    // every global read of the update issued first; V1 * V2 stays in
+    // registers for the step matrix of mode 1
+    constexpr int EP = (NMAX * NMAX + 255) / 256;
+    double v0[EP], v12[EP];
+#pragma unroll
+    for (int m = 0; m < EP; ++m) {
+        const int i = min(tid + 256 * m, RR - 1);
+        v0[m] = V0[i];
+        v12[m] = V1[i] * V2[i];
+    }
     const double* l1 = st.lam[1] + s * Rq;
     const double* l2 = st.lam[2] + s * Rq;
-    double lam1 = 0.0, dlam = 0.0;
+    const int tl = min(tid, R - 1);
+    const double l1v = l1[tl], l2v = l2[tl], bv = st.b[1][s * Rq + tl];
+    const double w_hat = c->w_hat, dw = c->delta_w, Ldp = st.Ld_prev[s];
+    const int upd = g->upd_core;
+#pragma unroll
+    for (int m = 0; m < EP; ++m) {
+        const int i = tid + 256 * m;
+        if (i < RR) A[(i / R) * ld + i % R] = v0[m] * v12[m];
+    }
+    const double lam1 = (tid < R) ? l1v : 0.0;
+    const double dlam = (tid < R) ? lam1 - l2v : 0.0;
     if (tid < 64) {
-        lam1 = (tid < R) ? l1[tid] : 0.0;
-        dlam = (tid < R) ? lam1 - l2[tid] : 0.0;
         lv[tid] = lam1;
         lv[64 + tid] = dlam;
     }
     __syncthreads();
     // H lam_{k-1} and H (lam_{k-1} - lam_{k-2}); the gradient at the
-    // extrapolated point combines them once the weight is known
+    // extrapolated point combines them once the weight is known (lv is zero
+    // past R, so the clamped columns add nothing)
     double h1 = 0.0, h2 = 0.0;
-    if (tid < R)
-        for (int r = 0; r < R; ++r) {
-            const double h = A[tid * ld + r];
+    {
+        const double* ar = A + tl * ld;
+#pragma unroll 8
+        for (int r = 0; r < NMAX; ++r) {
+            const double h = ar[min(r, R - 1)];
             h1 = fma(h, lv[r], h1);
             h2 = fma(h, lv[64 + r], h2);
         }
+    }
     const double Ld = wg_lmax_nonneg<NMAX>(A, R, ld, work);
-    const double wd = extrap_weight(extrapolate, c->w_hat, st.Ld_prev[s], Ld, c->delta_w);
+    const double wd = extrap_weight(extrapolate, w_hat, Ldp, Ld, dw);
     double nl = lam1;
-    if (g->upd_core && Ld > 0.0 && tid < R) {
+    if (upd && Ld > 0.0 && tid < R) {
         const double lhat = lam1 + wd * dlam;
-        const double gr = (h1 + wd * h2) - st.b[1][s * Rq + tid];
+        const double gr = (h1 + wd * h2) - bv;
         nl = relu_keep_nan(lhat - gr / Ld);
     }
     if (tid < Rq) st.lam[0][s * Rq + tid] = (tid < R) ? nl : 0.0;
     if (tid < 64) lv[128 + tid] = (tid < R) ? nl : 0.0;
     if (tid == 0) st.Ld_cur[s] = Ld;
     __syncthreads();
-    for (int i = tid; i < RR; i += 256) {
-        const int r = i / R, cc = i % R;
-        const double p = lv[128 + r] * lv[128 + cc] * V1[i] * V2[i];
-        st.P[s * RR + i] = p;
-        A[r * ld + cc] = p;
+#pragma unroll
+    for (int m = 0; m < EP; ++m) {
+        const int i = tid + 256 * m;
+        if (i < RR) {
+            const int r = i / R, cc = i % R;
+            const double p = lv[128 + r] * lv[128 + cc] * v12[m];
+            st.P[s * RR + i] = p;
+            A[r * ld + cc] = p;
+        }
     }
     __syncthreads();
     const double Lu = wg_lmax_nonneg<NMAX>(A, R, ld, work);
@@ -829,22 +896,33 @@ __device__ __forceinline__ void core_block(const Geo* __restrict__ g, const Stat
 template <typename T, int NMAX>
 __device__ __forceinline__ void prep_block(const Geo* __restrict__ g, const StateP<T>& st, int s, int n, char* smraw) {
     const int S = g->S, R = g->R, Rq = g->Rq, ld = R | 1, RR = R * R;
-    const int m = n - 1;
+    const int m = n - 1, tid = threadIdx.x;
     double* Vm = st.V[0] + (m * S + s) * RR;
-    block_gram<T>(st.U[0] + g->uoff[m][s], g->I[s][m], R, Rq, Vm, nullptr, nullptr, smraw);
-    __threadfence_block();
-    __syncthreads();
-    const int tid = threadIdx.x;
+    // the other Gram of the step matrix (mode 3 of x_{k-1} for n = 1, the new
+    // mode 1 for n = 2) and lambda, read before the Gram so their latency
+    // overlaps it; the new Gram comes back through LDS
+    const double* Vo = (n == 1) ? st.V[1] + (2 * S + s) * RR : st.V[0] + (0 * S + s) * RR;
+    constexpr int EP = (NMAX * NMAX + 255) / 256;
+    double vo[EP];
+#pragma unroll
+    for (int q = 0; q < EP; ++q) vo[q] = Vo[min(tid + 256 * q, RR - 1)];
+    __shared__ double lam[64];
+    if (tid < 64) lam[tid] = st.lam[0][s * Rq + min(tid, R - 1)];
     double* A = (double*)smraw;
+    double* Vl = (double*)(smraw + prep_lds_bytes<T>(R, Rq) - sizeof(double) * (size_t)RR);   // new Gram (LDS)
+    block_gram<T>(st.U[0] + g->uoff[m][s], g->I[s][m], R, Rq, Vm, nullptr, nullptr, smraw, Vl);
     double* work = eig_work(A, R);
-    const double* lam = st.lam[0] + s * Rq;
-    const double* Va = st.V[0] + (0 * S + s) * RR;
-    const double* Vb = (n == 1) ? st.V[1] + (2 * S + s) * RR : st.V[0] + (1 * S + s) * RR;
-    for (int i = tid; i < RR; i += 256) {
-        const int r = i / R, cc = i % R;
-        const double p = lam[r] * lam[cc] * Va[i] * Vb[i];
-        st.P[s * RR + i] = p;
-        A[r * ld + cc] = p;
+    // P = D (Va * Vb) D with Va = Gram of mode 1, Vb = Gram of mode 3 (n = 1)
+    // or of mode 2 (n = 2)
+#pragma unroll
+    for (int q = 0; q < EP; ++q) {
+        const int i = tid + 256 * q;
+        if (i < RR) {
+            const int r = i / R, cc = i % R;
+            const double p = (n == 1) ? lam[r] * lam[cc] * Vl[i] * vo[q] : lam[r] * lam[cc] * vo[q] * Vl[i];
+            st.P[s * RR + i] = p;
+            A[r * ld + cc] = p;
+        }
     }
     __syncthreads();
     const double Lu = wg_lmax_nonneg<NMAX>(A, R, ld, work);
