@@ -217,11 +217,13 @@ concpd_status concpd_debug_mttkrp(concpd_ctx ctx, int32_t n, int32_t s, void* de
 concpd_status concpd_debug_spectral_norm(const double* host_A, int32_t n, int32_t count, double* host_out);
 
 /* Per-kernel timing of the dense MTTKRP passes (pass 1: M x_3 U^(3); pass 2:
- * the mode-3 MTTKRP) of later concpd_step calls: with enable != 0, HIP events
- * are recorded on the context stream around each pass launch of every
- * extrapolated sweep.  concpd_profile_read synchronises and returns the summed
- * milliseconds and the number of timed launches of each pass, then clears the
- * record.  Errors: EHIP. */
+ * the mode-3 MTTKRP) of later concpd_step calls: with enable != 0, every sweep
+ * launches each pass 4 times back to back between two HIP events on the
+ * context stream (a pass is a pure function of the iterate within a sweep, so
+ * the repeats rewrite the same outputs and leave the iterate unchanged).
+ * concpd_profile_read synchronises and returns the summed milliseconds and
+ * the number of timed launches of each pass, then clears the record.
+ * Errors: EHIP. */
 concpd_status concpd_profile(concpd_ctx ctx, int32_t enable);
 concpd_status concpd_profile_read(concpd_ctx ctx, double* ms_pass1, double* ms_pass2, int64_t* launches);
 

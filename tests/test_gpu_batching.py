@@ -109,6 +109,28 @@ def test_p1_split_option_within_tolerance():
         m.set_option("p1_split", 3)
 
 
+def test_profiled_sweeps_leave_the_iterate_unchanged():
+    # profiling repeats each MTTKRP pass back to back; the iterate must match
+    # an unprofiled twin bit for bit
+    say("[profile] repeated pass launches")
+    L = (3, 0, 0)
+    P = synth.coupled_problem([(40, 45, 60)] * 2, 6, L, 10.0, 841)
+    U0, lam0 = synth.uniform_init(P.dims, 6, L, 842)
+    a, b = model(P, U0, lam0), model(P, U0, lam0)
+    a.step(2)
+    b.step(2)
+    a.profile(True)
+    sa = a.step(3)
+    a.profile(False)
+    ms1, ms2, n = a.profile_read()
+    sb = b.step(3)
+    say(f"   pass1 {ms1:.3f} ms pass2 {ms2:.3f} ms over {n} launches")
+    assert n >= 12 and n % 4 == 0 and ms1 > 0 and ms2 > 0
+    assert sa["k"] == sb["k"] and sa["F"] == sb["F"]
+    for x, y in zip(factors(a), factors(b)):
+        np.testing.assert_array_equal(x, y)
+
+
 def test_autotune_keeps_the_iterate():
     say("[autotune]")
     L = (5, 0, 0)
