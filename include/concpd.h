@@ -241,12 +241,19 @@ concpd_status concpd_profile_read(concpd_ctx ctx, double* ms_pass1, double* ms_p
  *                            0 (default): chosen from the item count (at
  *                            least 1.5 wavefronts per SIMD).  Get returns the
  *                            split in use.
+ *   CONCPD_OPT_P1_DMA        1: pass 1 streams the tensor into LDS by DMA,
+ *                            two 32-byte chunks of every row in flight per
+ *                            wavefront; 0: through registers.  Possible when
+ *                            every operand row is 16-byte aligned and the
+ *                            compute type is FP32 or 16-bit (EINVAL
+ *                            otherwise); default 1 for 16-bit storage.
  * Synchronises.  Errors: EINVAL (unknown option or value), EHIP. */
 typedef enum concpd_option {
     CONCPD_OPT_GRAPH_SWEEPS = 1,
     CONCPD_OPT_OVERLAP = 2,
     CONCPD_OPT_K2_ROWS = 3,
-    CONCPD_OPT_P1_SPLIT = 4
+    CONCPD_OPT_P1_SPLIT = 4,
+    CONCPD_OPT_P1_DMA = 5
 } concpd_option;
 concpd_status concpd_set_option(concpd_ctx ctx, int32_t option, int64_t value);
 concpd_status concpd_get_option(concpd_ctx ctx, int32_t option, int64_t* value);
@@ -258,12 +265,14 @@ typedef struct concpd_tuning {
     double us_per_sweep_default;  /* of the default configuration */
     int32_t candidates;           /* configurations timed */
     int32_t p1_split;             /* chosen CONCPD_OPT_P1_SPLIT (the split in use) */
+    int32_t p1_dma;               /* chosen CONCPD_OPT_P1_DMA */
 } concpd_tuning;
 
 /* Autotuner: times `sweeps` sweeps (HIP events on the context stream) of
  * candidate launch configurations from the same iterate, restoring the
  * iterate after each, and keeps the fastest: first the pass-1 split 1/2/4
- * (dense path), then mode-2 chunk rows 8/16/32 x graph sweeps 0/1/4.  The iterate is unchanged on return.  Synchronises.
+ * (x DMA off/on where possible; dense path), then mode-2 chunk rows 8/16/32 x
+ * graph sweeps 0/1/4.  The iterate is unchanged on return.  Synchronises.
  * Errors: EINVAL (sweeps not in [1, 10000]), ESTATE (converged iterate), EHIP. */
 concpd_status concpd_autotune(concpd_ctx ctx, int32_t sweeps, concpd_tuning* out);
 

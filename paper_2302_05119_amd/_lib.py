@@ -59,13 +59,14 @@ class Tuning(ctypes.Structure):
         ("us_per_sweep_default", ctypes.c_double),
         ("candidates", ctypes.c_int32),
         ("p1_split", ctypes.c_int32),
+        ("p1_dma", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
-OPT_GRAPH_SWEEPS, OPT_OVERLAP, OPT_K2_ROWS, OPT_P1_SPLIT = 1, 2, 3, 4
+OPT_GRAPH_SWEEPS, OPT_OVERLAP, OPT_K2_ROWS, OPT_P1_SPLIT, OPT_P1_DMA = 1, 2, 3, 4, 5
 
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)

@@ -100,7 +100,7 @@ template <typename T> void launch_core(const Geo* g, const StateP<T>& st, int S,
 template <typename T> void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, hipStream_t q);
 template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
 template <typename T> void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
-template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int P, int Rq, int slot, int mdtype, hipStream_t q);
+template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int P, int Rq, int slot, int mdtype, int dma, hipStream_t q);
 template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int mdtype, int maxI2, hipStream_t q);
 template <typename T> void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, hipStream_t q);
 template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int lds_rows, int lra, hipStream_t q);

@@ -16,6 +16,22 @@ static void pass1_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g,
     }
 #undef CPD_P1
 }
+template <typename TM>
+static void pass1d_rt(int RT, dim3 grid, hipStream_t q, const Geo* g, const StateP<float>& st, const ItemP1* items, int nitems,
+                      int P, int slot) {
+#define CPD_P1D(RTV)                                                                                        \
+    case RTV: {                                                                                             \
+        const size_t lds = 4 * (size_t)P1D<TM, RTV>::WAVE;                                                  \
+        hipLaunchKernelGGL((k_pass1d<TM, RTV>), grid, dim3(256), lds, q, g, st, items, nitems, P, slot);    \
+        break;                                                                                              \
+    }
+    switch (RT) {
+        CPD_P1D(1) CPD_P1D(2) CPD_P1D(3) CPD_P1D(4) CPD_P1D(5) CPD_P1D(6) CPD_P1D(7) CPD_P1D(8)
+        CPD_P1D(9) CPD_P1D(10) CPD_P1D(11) CPD_P1D(12) CPD_P1D(13) CPD_P1D(14) CPD_P1D(15) CPD_P1D(16)
+        default: break;
+    }
+#undef CPD_P1D
+}
 template <typename TM, typename T, bool BLDS>
 static void pass2_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g, const StateP<T>& st, const ItemP2* items,
                      int slot) {
@@ -51,12 +67,18 @@ static void pass2_dispatch(int Rq, dim3 grid, int maxI2, hipStream_t q, const Ge
 
 template <typename T>
 void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int P, int Rq, int slot, int mdtype,
-                  hipStream_t q) {
+                  int dma, hipStream_t q) {
     if (nitems <= 0) return;
     const dim3 grid((nitems * P + 3) / 4);
     const int RT = Rq / 4;
     if constexpr (std::is_same<T, double>::value) {
+        (void)dma;
         pass1_rt<double, double>(RT, grid, pass1_lds<double>(RT, P), q, g, st, items, nitems, P, slot);
+    } else if (dma) {
+        // every block's operand rows 16-byte aligned: the LDS-DMA stream
+        if (mdtype == 1) pass1d_rt<float>(RT, grid, q, g, st, items, nitems, P, slot);
+        else if (mdtype == 2) pass1d_rt<__hip_bfloat16>(RT, grid, q, g, st, items, nitems, P, slot);
+        else pass1d_rt<__half>(RT, grid, q, g, st, items, nitems, P, slot);
     } else {
         if (mdtype == 1) pass1_rt<float, float>(RT, grid, pass1_lds<float>(RT, P), q, g, st, items, nitems, P, slot);
         else if (mdtype == 2)
@@ -85,8 +107,8 @@ void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitem
     hipLaunchKernelGGL(k_k2<T>, dim3(nitems), dim3(256), 0, q, g, st, items, slot);
 }
 
-template void launch_pass1<float>(const Geo*, const StateP<float>&, const ItemP1*, int, int, int, int, int, hipStream_t);
-template void launch_pass1<double>(const Geo*, const StateP<double>&, const ItemP1*, int, int, int, int, int, hipStream_t);
+template void launch_pass1<float>(const Geo*, const StateP<float>&, const ItemP1*, int, int, int, int, int, int, hipStream_t);
+template void launch_pass1<double>(const Geo*, const StateP<double>&, const ItemP1*, int, int, int, int, int, int, hipStream_t);
 template void launch_pass2<float>(const Geo*, const StateP<float>&, const ItemP2*, int, int, int, int, int, hipStream_t);
 template void launch_pass2<double>(const Geo*, const StateP<double>&, const ItemP2*, int, int, int, int, int, hipStream_t);
 template void launch_k2<float>(const Geo*, const StateP<float>&, const ItemK2*, int, int, hipStream_t);

@@ -246,6 +246,243 @@ __global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP
 }
 
 // ---------------------------------------------------------------------------
+// pass 1 with the tensor streamed straight into LDS (same items, splits and
+// outputs as k_pass1; every block's operand rows 16-byte aligned; FP32 or
+// 16-bit storage).  A chunk is 16 values of i3 of every row of the item and
+// the 16 matching rows of U3.  Both arrive by LDS DMA (global_load_lds: no
+// registers), so each wavefront keeps two chunks in flight in a ring of
+// three LDS stages: before consuming chunk c it waits for all but the group
+// of chunk c+1, then requests chunk c+2 into the stage chunk c-1 used.
+// Requests past the end repeat the last chunk (cache hits), which keeps the
+// number of groups in flight, and so the wait count, fixed.
+//
+// Lane l streams tensor row l (16-byte pieces land in lane order); the lane
+// class q = l % 4 owns output columns RT q .. RT q + RT - 1, so its B operands
+// are one contiguous run of a raw U3 row.
+// ---------------------------------------------------------------------------
+// One 16-byte LDS DMA: lane l's 16 bytes at g land at LDS byte offset
+// lds + 16 l.  The address register is an input only (no register is
+// written), M0 holds the LDS offset.
+__device__ __forceinline__ void lds_dma16(const void* g, unsigned lds) {
+    // lds is the same in every lane of the wavefront
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(__builtin_amdgcn_readfirstlane(lds)), "v"(g)
+                 : "memory", "m0");
+}
+// s_waitcnt vmcnt(N) (N < 64), other counters untouched.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x70 | 0xF00);
+}
+
+// RT consecutive FP32 words at p, where p is 4 RT q words past a 16-byte
+// boundary: 16-byte reads when RT is a multiple of 4, 8-byte reads when even.
+template <int RT>
+__device__ __forceinline__ void load_cols(const float* __restrict__ p, float (&bb)[RT]) {
+    if constexpr (RT % 4 == 0) {
+#pragma unroll
+        for (int v = 0; v < RT / 4; ++v) {
+            const v4f w = *(const v4f*)(p + 4 * v);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bb[4 * v + j] = w[j];
+        }
+    } else if constexpr (RT % 2 == 0) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int v = 0; v < RT / 2; ++v) {
+            const f2 w = *(const f2*)(p + 2 * v);
+            bb[2 * v] = w[0];
+            bb[2 * v + 1] = w[1];
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) bb[t] = p[t];
+    }
+}
+
+#ifndef CPD_P1D_CBY
+#define CPD_P1D_CBY 32   // bytes of each tensor row per chunk
+#endif
+#ifndef CPD_P1D_NSTG
+#define CPD_P1D_NSTG 3   // LDS stages per wavefront (NSTG - 1 chunks in flight)
+#endif
+template <typename TM, int RT>
+struct P1D {
+    typedef typename Raw<TM>::type TR;
+    static constexpr int NSTG = CPD_P1D_NSTG;
+    static constexpr int KC = CPD_P1D_CBY / (int)sizeof(TR);       // i3 values per chunk
+    static constexpr int NA = CPD_P1D_CBY / 16;                     // tensor DMAs per chunk
+    static constexpr int UBY = KC * 4 * RT * 4;                     // U3 bytes per chunk (FP32 factors)
+    static constexpr int NUF = UBY / 1024;                          // full U3 DMAs
+    static constexpr int NUL = (UBY % 1024) / 16;                   // lanes of the last, partial one
+    static constexpr int NU = NUF + (NUL > 0 ? 1 : 0);              // U3 DMAs per chunk
+    static constexpr int ABY = 64 * CPD_P1D_CBY;                    // tensor bytes per chunk
+    static constexpr int CBYTES = CPD_P1D_CBY;                      // bytes of a row per chunk
+    static constexpr int STG = ABY + UBY;                           // one stage (16-byte multiple)
+    static constexpr int RING = NSTG * STG;                         // one wavefront's ring
+    static constexpr int WAVE = RING > RT * 1024 ? RING : RT * 1024; // its LDS (ring, or P > 1 partials)
+    static constexpr int G = NA + NU;                               // DMAs per chunk
+    static_assert(UBY % 16 == 0, "U3 chunk in 16-byte pieces");
+};
+
+template <typename TM, int RT>
+__global__ __launch_bounds__(256) void k_pass1d(const Geo* __restrict__ g, StateP<float> st, const ItemP1* __restrict__ items,
+                                                int nitems, int P, int slot) {
+    typedef P1D<TM, RT> D;
+    typedef typename D::TR TR;
+    constexpr int KC = D::KC, EPP = 16 / (int)sizeof(TR);   // values per 16-byte piece
+    if (st.ctrl->stop) return;
+    apply_rot(st);
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, q = lane & 3;
+    const int ii = blockIdx.x * (4 / P) + wave / P, part = wave % P;
+    const ItemP1 it = items[min(ii, nitems - 1)];
+    const bool live = ii < nitems && it.s >= 0;
+    const int s = live ? it.s : 0, i1 = it.i1, rg = it.rg, row0 = rg * 64;
+    const int I2 = g->I[s][1], I3 = g->I[s][2], Rq = g->Rq;
+    const int nrows = min(64, I2 - row0);
+    const int myrow = min(lane, nrows - 1);
+    // U2 values of the lane's accumulator rows (mode-1 partial), early
+    float u2v[RT][4];
+    {
+        const CPD_GLOBAL float* __restrict__ U2 = gptr(st.U[1] + g->uoff[1][s] + (long long)row0 * Rq);
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 4 * (lane >> 2) + v;
+                const float u = U2[(long long)min(r, nrows - 1) * Rq + RT * q + t];
+                u2v[t][v] = (r < nrows) ? u : 0.f;
+            }
+    }
+    const long long ldm = g->mld[s];
+    const TR* Mrow = (const TR*)g->M[s] + ((long long)i1 * I2 + row0 + myrow) * ldm;
+    const float* U3 = pick3(st.U, slot) + g->uoff[2][s];
+    const long long u3bytes = (long long)I3 * Rq * 4;
+    const unsigned ring = (unsigned)(unsigned long long)(__attribute__((address_space(3))) char*)smraw + wave * D::WAVE;
+    const char* ringp = smraw + wave * D::WAVE;
+    // this wavefront's share of i3, in whole chunks
+    const int nck = (I3 + KC - 1) / KC, cpp = (nck + P - 1) / P;
+    const int cb = live ? min(nck, part * cpp) : 0, ce = live ? min(nck, cb + cpp) : 0;
+    const int cl = max(ce - 1, cb);   // last chunk (requests past the end repeat it)
+    // chunks before the last lie wholly inside the row and the factor: plain
+    // offsets; the last one clamps every piece into its buffer
+    const char* Mlane = (const char*)Mrow;
+    const char* Ulane = (const char*)U3 + lane * 16;
+    auto request = [&](int c, int stage) {
+        const int cc = min(c, cl);
+        const unsigned sb = ring + stage * D::STG;
+        if (cc < cl) {
+            const char* mp = Mlane + (long long)cc * D::CBYTES;
+            const char* up = Ulane + (long long)cc * D::UBY;
+#pragma unroll
+            for (int j = 0; j < D::NA; ++j) lds_dma16(mp + 16 * j, sb + j * 1024);
+#pragma unroll
+            for (int u = 0; u < D::NU; ++u)
+                if (u < D::NUF || lane < D::NUL) lds_dma16(up + 1024 * u, sb + D::ABY + u * 1024);
+        } else {
+            // a tensor piece past the row end is moved back inside it (its
+            // values meet zero rows of U3); U3 bytes past the factor repeat
+            // its last 16 bytes (those rows are zeroed before use)
+#pragma unroll
+            for (int j = 0; j < D::NA; ++j) {
+                const long long e = min((long long)cc * KC + j * EPP, ldm - EPP);
+                lds_dma16(Mrow + e, sb + j * 1024);
+            }
+#pragma unroll
+            for (int u = 0; u < D::NU; ++u) {
+                const long long b = min((long long)cc * D::UBY + u * 1024 + lane * 16, u3bytes - 16);
+                if (u < D::NUF || lane < D::NUL) lds_dma16((const char*)U3 + b, sb + D::ABY + u * 1024);
+            }
+        }
+    };
+    Acc4<float> acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[t].zero();
+    if (cb < ce) {
+#pragma unroll
+        for (int j = 0; j < D::NSTG - 1; ++j) request(cb + j, j);
+        int stage = 0;
+        for (int c = cb; c < ce; ++c) {
+            wait_vm<(D::NSTG - 2) * D::G>();   // chunk c has landed; the next NSTG-2 may be in flight
+            const char* sp = ringp + stage * D::STG;
+            const float* ur = (const float*)(sp + D::ABY);
+            const int kc = min(KC, I3 - c * KC);
+            if (kc < KC) {
+                // U3 rows past the factor's end read clamped data: zero them
+                for (int e = lane; e < (KC - kc) * Rq; e += 64) ((float*)ur)[kc * Rq + e] = 0.f;
+            }
+            wave_sync();
+            request(c + D::NSTG - 1, stage == 0 ? D::NSTG - 1 : stage - 1);
+#pragma unroll
+            for (int pc = 0; pc < KC / EPP; ++pc) {
+                const u32x4 w = *(const u32x4*)(sp + pc * 1024 + lane * 16);
+                const TR* ev = (const TR*)&w;
+#pragma unroll
+                for (int x = 0; x < EPP; ++x) {
+                    const int kk = pc * EPP + x;
+                    const float a = cvt<float, TM>(ev[x]);
+                    float bb[RT];
+                    load_cols<RT>(ur + kk * Rq + RT * q, bb);
+#pragma unroll
+                    for (int t = 0; t < RT; ++t) acc[t].mma(a, bb[t]);
+                }
+            }
+            // (the wait before the next request also retires this chunk's
+            // LDS reads before its stage is overwritten)
+            stage = (stage == D::NSTG - 1) ? 0 : stage + 1;
+        }
+    }
+    wait_vm<0>();   // no DMA may still be writing this wavefront's LDS when it leaves
+    if (P > 1) {
+        // partial accumulators of the P wavefronts of an item, each in its own
+        // (drained) ring as [RT][4][64], added in part order
+        static_assert(RT * 4 * 64 * 4 <= D::WAVE, "partials fit the wavefront's area");
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ((float*)ringp)[(t * 4 + v) * 64 + lane] = acc[t].get(v);
+        __syncthreads();
+        if (part == 0) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                float x[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    x[v] = ((const float*)ringp)[(t * 4 + v) * 64 + lane];
+                    for (int p = 1; p < P; ++p) x[v] += ((const float*)(ringp + p * D::WAVE))[(t * 4 + v) * 64 + lane];
+                }
+                acc[t].set(x);
+            }
+        }
+    }
+    if (!live || part != 0) return;
+    CPD_GLOBAL float* __restrict__ Y = gptr_w(st.Y + g->yoff[s] + ((long long)i1 * I2 + row0) * Rq);
+    double kp[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        double a = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 4 * (lane >> 2) + v;
+            const float yv = acc[t].get(v);
+            if (r < nrows) Y[(long long)r * Rq + RT * q + t] = yv;
+            a += (double)yv * (double)u2v[t][v];
+        }
+        kp[t] = a;
+    }
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1)
+#pragma unroll
+        for (int t = 0; t < RT; ++t) kp[t] += __shfl_xor(kp[t], o, 64);
+    if (lane < 4) {
+        CPD_GLOBAL float* __restrict__ K1p = gptr_w(st.K1p) + g->k1off[s] + ((long long)i1 * g->nrg[s] + rg) * Rq;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) K1p[RT * lane + t] = (float)kp[t];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // pass 2: one workgroup per (block, chunk of 4 i1 slabs, 64 consecutive i3);
 // wavefront w takes slab 4*chunk + w.  Lanes run along i3 (the contiguous
 // index), so every tensor load is a coalesced 64-element row segment; NB rows

@@ -397,6 +397,7 @@ struct concpd_ctx_s {
     hipGraphExec_t gexec;
     int k2rows;
     int p1split = 0;   // requested pass-1 split (0: automatic)
+    int p1dma = 0, p1dma_ok = 0;   // pass 1 by LDS DMA (in use / possible)
     std::vector<hipEvent_t> ev1, ev2;  // begin/end pairs of timed pass launches
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -478,7 +479,7 @@ void run_sweep(concpd_ctx c, const StateP<T>& st) {
     // launches and not the dispatch gap before the first one
     if (prof) (void)hipEventRecord(e[0], q);
     for (int rep = 0; rep < (prof ? CPD_PROF_REPS : 1); ++rep)
-        cpd::launch_pass1<T>(g, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, Rq, 1, c->mdtype, q);
+        cpd::launch_pass1<T>(g, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, Rq, 1, c->mdtype, c->p1dma, q);
     if (prof) (void)hipEventRecord(e[1], q);
     join(1);
     cpd::launch_update<T>(g, st, itu[0], (int)c->lists.u[0].size(), 0, R, extrap, c->lists.lds_rows[0], 0, q);
@@ -703,7 +704,7 @@ void debug_passes(concpd_ctx c, const StateP<T>& st) {
     const ItemP1* it1 = (const ItemP1*)(c->ws + c->lay.it1);
     const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
     const ItemK2* itk = (const ItemK2*)(c->ws + c->lay.itk2);
-    cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->q);
+    cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->p1dma, c->q);
     cpd::launch_k2<T>(c->dgeo, st, itk, (int)c->lists.k2.size(), 1, c->q);
     cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
 }
@@ -749,7 +750,7 @@ concpd_status loss_grad_t(concpd_ctx c, const StateP<T>& st, const void* const* 
     const ItemP1* it1 = (const ItemP1*)(c->ws + P.it1);
     const ItemP2* it2 = (const ItemP2*)(c->ws + P.it2);
     const ItemK2* itk = (const ItemK2*)(c->ws + P.itk2);
-    cpd::launch_pass1<T>(c->dgeo, sg, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->q);
+    cpd::launch_pass1<T>(c->dgeo, sg, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->p1dma, c->q);
     cpd::launch_k2<T>(c->dgeo, sg, itk, (int)c->lists.k2.size(), 0, c->q);
     cpd::launch_pass2<T>(c->dgeo, sg, it2, (int)c->lists.p2.size(), c->Rq, 0, c->mdtype, c->lists.maxI2, c->q);
     for (int s = 0; s < c->S; ++s)
@@ -917,8 +918,17 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
     // blocks whose operand rows all start 16-byte aligned take 16-byte loads
     {
         const int me = operand_bytes(c->mdtype);
-        for (int s = 0; s < c->S; ++s)
+        bool all = true;
+        for (int s = 0; s < c->S; ++s) {
             c->geo.mvec[s] = (c->geo.mld[s] % (16 / me) == 0) && ((uintptr_t)c->geo.M[s] % 16 == 0);
+            all = all && c->geo.mvec[s];
+        }
+        // pass 1 can stream the tensor by LDS DMA when every row is 16-byte
+        // aligned; by default it does so for 16-bit storage, whose 32-byte
+        // chunks carry twice the values (measured: faster for BF16 at every
+        // shape, slower for FP32 rows of a few thousand values)
+        c->p1dma_ok = all && !c->f64;
+        c->p1dma = c->p1dma_ok && c->mdtype != 1;
     }
     c->dgeo = (Geo*)(c->ws + c->lay.geo);
     INIT_HIP(hipMemcpyAsync(c->dgeo, &c->geo, sizeof(Geo), hipMemcpyHostToDevice, c->q));
@@ -1272,6 +1282,12 @@ concpd_status concpd_set_option(concpd_ctx c, int32_t option, int64_t value) {
         }
         c->overlap = value != 0;
         return CONCPD_OK;
+    case CONCPD_OPT_P1_DMA:
+        if (value != 0 && value != 1) return fail(CONCPD_EINVAL, "pass-1 DMA %lld not 0 or 1", (long long)value);
+        if (value && !c->p1dma_ok) return fail(CONCPD_EINVAL, "pass-1 DMA needs 16-byte aligned rows and a 32/16-bit compute type");
+        if (value != c->p1dma) c->drop_graph();
+        c->p1dma = (int)value;
+        return CONCPD_OK;
     case CONCPD_OPT_P1_SPLIT: {
         if (value != 0 && value != 1 && value != 2 && value != 4)
             return fail(CONCPD_EINVAL, "pass-1 split %lld not 0, 1, 2 or 4", (long long)value);
@@ -1310,6 +1326,7 @@ concpd_status concpd_get_option(concpd_ctx c, int32_t option, int64_t* value) {
     case CONCPD_OPT_OVERLAP: *value = c->overlap; return CONCPD_OK;
     case CONCPD_OPT_K2_ROWS: *value = c->k2rows; return CONCPD_OK;
     case CONCPD_OPT_P1_SPLIT: *value = c->lists.p1_split; return CONCPD_OK;
+    case CONCPD_OPT_P1_DMA: *value = c->p1dma; return CONCPD_OK;
     default: return fail(CONCPD_EINVAL, "unknown option %d", option);
     }
 }
@@ -1368,19 +1385,27 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
         const int p_auto = La.p1_split;
         double bpu = INFINITY;
         const int psc[3] = {1, 2, 4};
+        const int dma_dflt = c->p1dma_ok && c->mdtype != 1;
+        int bd = c->p1dma;
         if ((r = concpd_set_option(c, CONCPD_OPT_GRAPH_SWEEPS, 0)) == CONCPD_OK)
             r = concpd_set_option(c, CONCPD_OPT_K2_ROWS, CPD_K2ROWS_DEFAULT);
-        for (int pi = 0; pi < 3 && r == CONCPD_OK; ++pi) {
-            if ((r = concpd_set_option(c, CONCPD_OPT_P1_SPLIT, psc[pi])) != CONCPD_OK) break;
-            double us = 0.0;
-            if ((r = time_sweeps(us)) != CONCPD_OK) break;
-            if (psc[pi] == p_auto) dflt = us;
-            if (us < bpu) {
-                bpu = us;
-                bp = psc[pi];
+        for (int di = 0; di < (c->p1dma_ok ? 2 : 1) && r == CONCPD_OK; ++di) {
+            const int dma = c->p1dma_ok ? di : 0;
+            if ((r = concpd_set_option(c, CONCPD_OPT_P1_DMA, dma)) != CONCPD_OK) break;
+            for (int pi = 0; pi < 3 && r == CONCPD_OK; ++pi) {
+                if ((r = concpd_set_option(c, CONCPD_OPT_P1_SPLIT, psc[pi])) != CONCPD_OK) break;
+                double us = 0.0;
+                if ((r = time_sweeps(us)) != CONCPD_OK) break;
+                if (psc[pi] == p_auto && dma == dma_dflt) dflt = us;
+                if (us < bpu) {
+                    bpu = us;
+                    bp = psc[pi];
+                    bd = dma;
+                }
             }
         }
         if (r == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_P1_SPLIT, bp);
+        if (r == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_P1_DMA, bd);
     }
     for (int ki = 0; ki < 3 && r == CONCPD_OK; ++ki) {
         if (c->lra && ki > 0) break;   // the mode-2 contraction is not on the lra path
@@ -1417,6 +1442,7 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
     if (out) {
         out->k2_rows = c->k2rows;
         out->p1_split = c->lists.p1_split;
+        out->p1_dma = c->p1dma;
         out->graph_sweeps = bg;
         out->us_per_sweep = best;
         out->us_per_sweep_default = dflt;

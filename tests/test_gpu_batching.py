@@ -109,6 +109,28 @@ def test_p1_split_option_within_tolerance():
         m.set_option("p1_split", 3)
 
 
+@pytest.mark.parametrize("compute,tol", [("f32", 1e-5), ("bf16", 2e-2)])
+def test_p1_dma_and_register_paths_match_oracle(compute, tol):
+    # pass 1 by LDS DMA and through registers, every split, on rows whose
+    # last 16-value chunk is ragged (I3 = 100 and 57) and item counts that need
+    # empty padding items
+    say(f"[options] pass-1 DMA / register paths, compute={compute}")
+    L = (3, 0, 0)
+    P = synth.coupled_problem([(33, 45, 100), (33, 70, 57), (33, 45, 100)], 8, L, 10.0, 851)
+    U0, lam0 = synth.uniform_init(P.dims, 8, L, 852)
+    ref = apg.run(DenseData(P.tensors), U0, lam0, Options(L=L), iters=2)
+    for dma in (1, 0):
+        for split in (1, 2, 4):
+            m = model(P, U0, lam0, compute=compute)
+            m.set_option("p1_dma", dma)
+            m.set_option("p1_split", split)
+            assert m.get_option("p1_dma") == dma
+            s = m.step(2)
+            e = max(rel(m.factor(n, b), ref.U[n][b]) for n in range(3) for b in range(3))
+            say(f"   dma={dma} split={split} F={s['F']:.10e} oracle={ref.F:.10e} max factor err={e:.2e}")
+            assert abs(s["F"] - ref.F) / ref.F <= tol and e <= 10 * tol
+
+
 def test_profiled_sweeps_leave_the_iterate_unchanged():
     # profiling repeats each MTTKRP pass back to back; the iterate must match
     # an unprofiled twin bit for bit
@@ -141,8 +163,10 @@ def test_autotune_keeps_the_iterate():
     before, st0 = factors(m), m.stats()
     t = m.autotune(8)
     say(f"   {t}")
-    assert t["candidates"] == 12 and t["k2_rows"] in (8, 16, 32) and t["graph_sweeps"] in (0, 1, 4)
+    # 60-value FP32 rows are 16-byte aligned: the pass-1 DMA path is a candidate
+    assert t["candidates"] == 15 and t["k2_rows"] in (8, 16, 32) and t["graph_sweeps"] in (0, 1, 4)
     assert t["p1_split"] in (1, 2, 4) and m.get_option("p1_split") == t["p1_split"]
+    assert t["p1_dma"] in (0, 1) and m.get_option("p1_dma") == t["p1_dma"]
     assert t["us_per_sweep"] <= t["us_per_sweep_default"]
     st1 = m.stats()
     assert st1["k"] == st0["k"] and st1["F"] == st0["F"]
