@@ -56,10 +56,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mttkrp_hbm_traffic_c2_10x100cube_
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2302_05119_amd", "csrc", "mttkrp_kernels.h")
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, tuning=None):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE / WRITE_SIZE runs scaled by a plain-copy calibration), or None
-    when the kernel source has changed since the counters were taken."""
+    when the kernel source has changed since the counters were taken, or when
+    this run's pass-1 configuration is not the one they were taken on."""
     import hashlib
     import re
 
@@ -69,7 +70,10 @@ def measured_traffic(kernel: str):
     except OSError:
         return None
     m = re.search(r"kernel_source_sha256 = ([0-9a-f]{64})", text)
-    t = re.search(r"traffic_bytes_per_launch\[" + re.escape(kernel) + r"\] = (\d+)", text)
+    key = kernel
+    if kernel.startswith("pass1") and tuning is not None:
+        key = f"{kernel} p1_dma={tuning['p1_dma']} p1_split={tuning['p1_split']}"
+    t = re.search(r"traffic_bytes_per_launch\[" + re.escape(key) + r"\] = (\d+)", text)
     if not m or not t or m.group(1) != sha:
         return None
     return int(t.group(1))
@@ -234,6 +238,7 @@ def main():
     m = CoupledCP(tens, w["R"], w["L"], compute="f32", init_U=U0, init_lambda=lam0)
     s_init = m.stats()
     tuning = m.autotune(20) if args.autotune else None
+    p1cfg = {"p1_dma": m.get_option("p1_dma"), "p1_split": m.get_option("p1_split")}
 
     m.step(args.warmup, sync=False)
     k0 = m.stats()["k"]
@@ -285,7 +290,7 @@ def main():
         "config": {"workload": WORKLOAD, "blocks": S, "dims": list(I), "rank": R, "coupled": list(w["L"]),
                    "snr_db": w["snr"], "path": "CoNCPD-APG dense, FP32 MFMA"},
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom[0]),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom[0], p1cfg),
                      "avg_launch_us": dom[2] * 1e6, "algorithmic_bytes_per_launch": dom[1]},
         "mttkrp_tflops": mttkrp_tflops,
         "pass_us": {"pass1": avg1 * 1e6, "pass2": avg2 * 1e6},
