@@ -248,3 +248,61 @@ def test_full_size_c3_compression_and_iteration(dev):
         assert rel(m.lam(s), new.lam[s]) <= 1e-5
         for n in range(3):
             assert rel(m.factor(n, s), new.U[n][s]) <= 1e-5
+
+
+def test_c5_configuration_downsampled_teacher_forced(dev):
+    # the 4 x 512^3 workload's configuration on a 64^3 downsample: R = 40
+    # (the matrix-core spectral-norm class), mode 1 fully shared, Tucker 40^3
+    say("[c5 64^3] teacher-forced lra iterations, R = 40")
+    L = (40, 0, 0)
+    P = synth.coupled_problem([(64, 64, 64)] * 4, 40, L, 15.0, 661, dtype=np.float32)
+    ranks = (40, 40, 40)
+    m, data, st, new, s0, s1 = lra_teacher_forced(dev, P, 40, L, ranks, 2, 662)
+    say(f"   F_prev gpu={s0['F']:.12e} oracle={st.F:.12e}; F gpu={s1['F']:.12e} oracle={new.F:.12e}")
+    assert abs(s0["F"] - st.F) / st.F <= 1e-5
+    assert abs(s1["F"] - new.F) / new.F <= 1e-5
+    Ld, Lu, LC = m.lipschitz()
+    np.testing.assert_allclose(Ld, new.Ld_prev, rtol=1e-6)
+    np.testing.assert_allclose(LC, new.LC_prev, rtol=1e-6)
+    for s in range(P.S):
+        np.testing.assert_allclose(Lu[s], [new.Lu_prev[n][s] for n in range(3)], rtol=1e-6)
+        assert rel(m.lam(s), new.lam[s]) <= 1e-5
+        for n in range(3):
+            e = rel(m.factor(n, s), new.U[n][s])
+            assert e <= 1e-5, (n, s, e)
+
+
+def test_full_size_c5_compression_and_fit(dev):
+    # 4 blocks of 512^3, R = 40, Tucker 40^3, 15 dB: properties that hold at
+    # any size (orthonormal bases, the leading subspace of one mode against
+    # the oracle's eigh, and the fit reaching the noise level)
+    say("[c5 full] 4 x 512^3 compression and 200 lra iterations")
+    name = "c5_lra_4x512cube_r40"
+    w = synth.WORKLOADS[name]
+    P = synth.make_workload(name)
+    ranks = tuple(w["tucker"])
+    U0, lam0 = synth.workload_init(name, P)
+    m = make_model(P, U0, lam0, dev, ranks)
+    m.lra_compress()
+    A0, _ = m.tucker(0)
+    for n in range(3):
+        orth = np.linalg.norm(A0[n].T @ A0[n] - np.eye(ranks[n]))
+        say(f"   block 0 mode {n}: ||A^T A - I|| = {orth:.1e}")
+        assert orth <= 1e-12
+    X0 = P.tensors[0]
+    Xu = X0.reshape(X0.shape[0], -1).astype(np.float64)
+    ev, V = np.linalg.eigh(Xu @ Xu.T)
+    Vr = V[:, ::-1][:, : ranks[0]]
+    gap = (ev[-ranks[0]] - ev[-ranks[0] - 1]) / ev[-1]
+    dist = np.linalg.norm(A0[0] @ A0[0].T - Vr @ Vr.T, 2)
+    say(f"   block 0 mode 0 subspace distance {dist:.1e} (relative gap {gap:.1e})")
+    assert dist <= 1e-12 / max(gap, 1e-12) + 1e-11
+    del Xu
+    st = m.lra_step(200)
+    gf = m.global_fit()
+    rho = 10 ** (-w["snr"] / 20)
+    say(f"   k={st['k']} restarts={st['restarts']} fit(X~)={st['fit']:.5f} global fit={gf:.5f} "
+        f"(noise level 1 - rho/sqrt(1+rho^2) = {1 - rho / np.sqrt(1 + rho * rho):.5f})")
+    assert st["k"] == 200 and not st["nonfinite"]
+    assert st["fit"] > 0.95
+    assert 0.80 <= gf <= 0.85
