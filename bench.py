@@ -52,6 +52,7 @@ def cpu_baseline(P, U0, lam0, budget_s=12.0):
 
 
 LRA_WORKLOAD = "c3_lra_10x256cube_r20"
+LRA_WORKLOAD_C5 = "c5_lra_4x512cube_r40"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mttkrp_hbm_traffic_c2_10x100cube_r20.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2302_05119_amd", "csrc", "mttkrp_kernels.h")
 
@@ -79,18 +80,19 @@ def measured_traffic(kernel: str, tuning=None):
     return int(t.group(1))
 
 
-def lra_leg(steps: int, warmup: int, dense_steps: int = 30):
-    """lraCoNCPD-APG on 10 blocks of 256^3 (Tucker 30^3): compression time and
-    iterations/s of the compressed iterations (step 2)."""
+def lra_leg(steps: int, warmup: int, dense_steps: int = 30, name: str = LRA_WORKLOAD):
+    """lraCoNCPD-APG (10 blocks of 256^3 with Tucker 30^3, or 4 blocks of 512^3
+    with Tucker 40^3): compression time and iterations/s of the compressed
+    iterations (step 2), beside the plain path on the same blocks."""
     import torch
 
     import synth
     from paper_2302_05119_amd import CoupledCP
 
     dev = torch.device("cuda:0")
-    w = synth.WORKLOADS[LRA_WORKLOAD]
-    P = synth.make_workload(LRA_WORKLOAD)
-    U0, lam0 = synth.workload_init(LRA_WORKLOAD, P)
+    w = synth.WORKLOADS[name]
+    P = synth.make_workload(name)
+    U0, lam0 = synth.workload_init(name, P)
     tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
     del P
     m = CoupledCP(tens, w["R"], w["L"], compute="f32", init_U=U0, init_lambda=lam0, tucker_ranks=w["tucker"])
@@ -118,7 +120,7 @@ def lra_leg(steps: int, warmup: int, dense_steps: int = 30):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     st = m.stats()
-    return {"workload": LRA_WORKLOAD, "compress_s": t1 - t0, "iter_per_s": (st["k"] - k0) / (t3 - t2),
+    return {"workload": name, "compress_s": t1 - t0, "iter_per_s": (st["k"] - k0) / (t3 - t2),
             "dense_iter_per_s_same_blocks": dense_rate, "sweeps": steps,
             "warmup": warmup, "fit_compressed": st["fit"], "global_fit": m.global_fit(), "iterations": st["k"],
             "restarts": st["restarts"]}
@@ -303,6 +305,7 @@ def main():
         out["batched_c4"] = batched_leg(args.forms_steps)
     if args.lra_steps > 0:
         out["lra"] = lra_leg(args.lra_steps, max(1, args.warmup // 2))
+        out["lra_c5"] = lra_leg(args.lra_steps, max(1, args.warmup // 2), name=LRA_WORKLOAD_C5)
     if not args.no_cpu_baseline:
         U0r = [[m_u.astype(np.float32).astype(np.float64) for m_u in per] for per in U0]
         out["cpu_baseline"] = cpu_baseline(P, U0r, lam0)
