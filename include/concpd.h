@@ -6,7 +6,7 @@
  * Decomposition Using Optimal Gradient and Low-rank Approximation",
  * arXiv 2302.05119).
  *
- * Problem (Section II-B, eq. tensormodel and eq. costfunc): given blocks
+ * Problem (Section II-C, eq. tensormodel and eq. costfunc): given blocks
  * M^(s) (s = 1..S) of size I1 x I2 x I3, find lambda^(s) >= 0 (the
  * super-diagonal of the core D^(s)) and factors U^(n,s) >= 0 of size
  * I_n x R whose first L_n columns are shared by every block, minimising
@@ -56,7 +56,7 @@ typedef struct concpd_config {
     int32_t num_blocks;     /* S >= 1, at most 64 */
     int32_t rank;           /* R, components per block, 1..64 */
     int32_t coupled[3];     /* L_n, 0 <= L_n <= R: the first L_n columns of every
-                               mode-n factor are shared by all blocks (Section II-B);
+                               mode-n factor are shared by all blocks (Section II-C);
                                a mode with L_n > 0 needs equal I_n in every block */
     const int64_t* dims;    /* [S*3]: I_n of block s at dims[3*s + n], each >= 1 */
     int32_t tensor_dtype;   /* element type of the caller's tensors: CONCPD_F64 or CONCPD_F32 */
@@ -66,13 +66,25 @@ typedef struct concpd_config {
                                in the workspace and run 16-bit MFMA with FP32 accumulation.
                                Grams, Lipschitz constants, the core update, the objective
                                and the restart test are FP64 in every mode. */
-    int32_t update_core;    /* 1: update D^(s) (CoNCPD-APG); 0: keep lambda fixed (-NC) */
+    int32_t update_core;    /* 1: update D^(s) (CoNCPD-APG); 0: keep lambda fixed, the -NC
+                               variant of Section III-C (core tensors removed, i.e. merged
+                               into the factors: the seeded initialisation then sets
+                               lambda = 1; a caller's init_lambda is kept as given) */
     int32_t restart;        /* 1: restart rule of Algorithm 1 */
     double delta_w;         /* delta_w < 1 of eq. eqextrawd / eqextrawu (paper: 0.9999) */
     double tol;             /* concpd_fit stops when |RelErr_k - RelErr_{k-1}| < tol */
     int32_t max_it;         /* concpd_fit iteration limit (paper: 1000) */
     const int32_t* tucker_ranks; /* [S*3] Tucker ranks J_n <= I_n for lra_compress, or NULL
                                when the context will not be compressed */
+    const int32_t* block_ranks;  /* [S] per-block rank R^(s), max(1, L_1, L_2, L_3) <= R^(s) <= R,
+                               or NULL for R^(s) = R.  Uneven ranks (the model of Section II-C
+                               allows a rank per block) are run as rank R with the columns
+                               R^(s)..R-1 of block s held at zero and lambda_r = 0 there, an
+                               exact embedding: such columns have zero gradient, zero rows
+                               and columns in every Hadamard Gram and leave every
+                               Lipschitz constant unchanged.  Host factor and lambda arrays
+                               keep the stride R; columns >= R^(s) are ignored on input and
+                               read back as zero. */
 } concpd_config;
 
 typedef struct concpd_stats {
@@ -104,7 +116,8 @@ concpd_status concpd_query_workspace(const concpd_config* cfg, size_t* bytes);
  *                seeded U[0,1] draw (SplitMix64, order: n, then s, then row,
  *                then column; shared columns drawn once).  Shared columns are
  *                taken from block 0.
- *   init_lambda  [S] host R-vectors, or NULL for a seeded U[0,1] draw.
+ *   init_lambda  [S] host R-vectors, or NULL for a seeded U[0,1] draw
+ *                (all ones when update_core = 0).
  *   workspace    device buffer of ws_bytes >= concpd_query_workspace(cfg).
  *   stream       hipStream_t (NULL = default stream).
  * Errors: EINVAL, ENOTSUP, ENONFINITE (NaN/Inf in init arrays or tensors), EHIP.

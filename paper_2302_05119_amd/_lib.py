@@ -31,6 +31,7 @@ class Config(ctypes.Structure):
         ("tol", ctypes.c_double),
         ("max_it", ctypes.c_int32),
         ("tucker_ranks", ctypes.POINTER(ctypes.c_int32)),
+        ("block_ranks", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 

@@ -104,6 +104,12 @@ concpd_status validate(const concpd_config* c) {
                 if (c->dims[3 * s + n] > 512)
                     return fail(CONCPD_ENOTSUP, "lra compression supports I_n <= 512 (block %d mode %d)", s, n);
             }
+    if (c->block_ranks) {
+        const int lmax = std::max(std::max(c->coupled[0], c->coupled[1]), std::max(c->coupled[2], 1));
+        for (int s = 0; s < c->num_blocks; ++s)
+            if (c->block_ranks[s] < lmax || c->block_ranks[s] > c->rank)
+                return fail(CONCPD_EINVAL, "block_ranks[%d] = %d not in [max(1, L_n), rank]", s, c->block_ranks[s]);
+    }
     if (c->tucker_ranks && c->tensor_dtype != CONCPD_F32)
         return fail(CONCPD_ENOTSUP, "lra compression needs F32 tensors");
     if (c->tucker_ranks) {
@@ -367,6 +373,7 @@ struct concpd_ctx_s {
     std::vector<int64_t> dims;
     std::vector<int32_t> tucker;
     int S, R, Rq, L[3];
+    std::vector<int> rk;   // R^(s): block s uses columns 0..rk[s]-1, the rest stay zero
     bool f64;
     int mdtype;
     std::vector<const void*> tensors;
@@ -630,7 +637,7 @@ void pack_factors(concpd_ctx c, const double* const* U, std::vector<T>& out) {
             const double* shared = U[3 * 0 + n];
             T* dst = out.data() + c->geo.uoff[n][s];
             for (int i = 0; i < I; ++i)
-                for (int r = 0; r < c->R; ++r)
+                for (int r = 0; r < c->rk[s]; ++r)
                     dst[(size_t)i * c->Rq + r] = (T)(r < c->L[n] ? shared[(size_t)i * c->R + r] : src[(size_t)i * c->R + r]);
         }
 }
@@ -638,6 +645,13 @@ void pack_factors(concpd_ctx c, const double* const* U, std::vector<T>& out) {
 bool all_finite(const double* p, size_t n) {
     for (size_t i = 0; i < n; ++i)
         if (!isfinite(p[i])) return false;
+    return true;
+}
+
+// the first `used` columns of a rows x ld row-major array are finite
+bool cols_finite(const double* p, int64_t rows, int ld, int used) {
+    for (int64_t i = 0; i < rows; ++i)
+        if (!all_finite(p + i * ld, used)) return false;
     return true;
 }
 
@@ -653,7 +667,7 @@ concpd_status upload_iterate(concpd_ctx c, const double* const* U, const double*
     HIPCHECK(hipMemcpyAsync(c->ws + c->lay.U[0], h1.data(), bytes, hipMemcpyHostToDevice, c->q));
     std::vector<double> l1((size_t)c->S * c->Rq, 0.0), l2((size_t)c->S * c->Rq, 0.0);
     for (int s = 0; s < c->S; ++s)
-        for (int r = 0; r < c->R; ++r) {
+        for (int r = 0; r < c->rk[s]; ++r) {
             l1[(size_t)s * c->Rq + r] = lam[s][r];
             l2[(size_t)s * c->Rq + r] = (lamp ? lamp : lam)[s][r];
         }
@@ -810,6 +824,9 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
     c->R = cfg->rank;
     c->Rq = (c->R + 3) / 4 * 4;
     for (int n = 0; n < 3; ++n) c->L[n] = cfg->coupled[n];
+    c->rk.assign(c->S, c->R);
+    if (cfg->block_ranks) c->rk.assign(cfg->block_ranks, cfg->block_ranks + c->S);
+    c->cfg.block_ranks = c->rk.data();
     c->dims.assign(cfg->dims, cfg->dims + 3 * c->S);
     c->cfg.dims = c->dims.data();
     if (cfg->tucker_ranks) {
@@ -864,20 +881,22 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
                         else v[(size_t)i * c->R + r] = rng.uniform();
                     }
             }
+        // without a core update (the -NC variant of Section III-C, core
+        // tensors removal) D^(s) is merged into the factors: lambda = 1
         for (int s = 0; s < c->S; ++s) {
             hl[s].resize(c->R);
-            for (int r = 0; r < c->R; ++r) hl[s][r] = rng.uniform();
+            for (int r = 0; r < c->R; ++r) hl[s][r] = cfg->update_core ? rng.uniform() : 1.0;
         }
     }
     for (int i = 0; i < 3 * c->S; ++i) pU[i] = init_U ? init_U[i] : hU[i].data();
     for (int s = 0; s < c->S; ++s) pl[s] = init_lambda ? init_lambda[s] : hl[s].data();
     for (int s = 0; s < c->S; ++s) {
         for (int n = 0; n < 3; ++n)
-            if (!pU[3 * s + n] || !all_finite(pU[3 * s + n], (size_t)c->dims[3 * s + n] * c->R)) {
+            if (!pU[3 * s + n] || !cols_finite(pU[3 * s + n], c->dims[3 * s + n], c->R, c->rk[s])) {
                 delete c;
                 return fail(pU[3 * s + n] ? CONCPD_ENONFINITE : CONCPD_EINVAL, "init_U[%d] missing or not finite", 3 * s + n);
             }
-        if (!pl[s] || !all_finite(pl[s], c->R)) {
+        if (!pl[s] || !all_finite(pl[s], c->rk[s])) {
             delete c;
             return fail(pl[s] ? CONCPD_ENONFINITE : CONCPD_EINVAL, "init_lambda[%d] missing or not finite", s);
         }
@@ -1169,12 +1188,14 @@ concpd_status concpd_set_state(concpd_ctx c, const double* const* U, const doubl
     if (!(t >= 1.0) || k < 0) return fail(CONCPD_EINVAL, "t must be >= 1 and k >= 0");
     for (int s = 0; s < c->S; ++s) {
         for (int n = 0; n < 3; ++n) {
-            const size_t cnt = (size_t)c->dims[3 * s + n] * c->R;
+            const int64_t I = c->dims[3 * s + n];
+            const int rk = c->rk[s];
             if (!U[3 * s + n]) return fail(CONCPD_EINVAL, "U[%d] is NULL", 3 * s + n);
-            if (!all_finite(U[3 * s + n], cnt) || (U_prev && (!U_prev[3 * s + n] || !all_finite(U_prev[3 * s + n], cnt))))
+            if (!cols_finite(U[3 * s + n], I, c->R, rk) ||
+                (U_prev && (!U_prev[3 * s + n] || !cols_finite(U_prev[3 * s + n], I, c->R, rk))))
                 return fail(CONCPD_ENONFINITE, "U / U_prev[%d] missing or not finite", 3 * s + n);
         }
-        if (!lam[s] || !all_finite(lam[s], c->R) || (lam_prev && (!lam_prev[s] || !all_finite(lam_prev[s], c->R))))
+        if (!lam[s] || !all_finite(lam[s], c->rk[s]) || (lam_prev && (!lam_prev[s] || !all_finite(lam_prev[s], c->rk[s]))))
             return fail(CONCPD_ENONFINITE, "lambda / lambda_prev[%d] missing or not finite", s);
     }
     concpd_status r = c->f64 ? upload_iterate<double>(c, U, U_prev, lam, lam_prev)

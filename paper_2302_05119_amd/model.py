@@ -33,6 +33,17 @@ def _void_ptr_array(ptrs):
     return (ctypes.c_void_p * len(ptrs))(*ptrs)
 
 
+def _stride_r(a, R):
+    """Copy of a (rows x R^(s) or rows x R, or an R^(s)-vector) in the ABI's
+    stride-R layout; the columns past R^(s) are ignored by the library."""
+    a = np.asarray(a, dtype=np.float64)
+    if a.shape[-1] == R:
+        return a
+    out = np.zeros(a.shape[:-1] + (R,), dtype=np.float64)
+    out[..., :a.shape[-1]] = a
+    return out
+
+
 class CoupledCP:
     """Coupled nonnegative CP decomposition of S third-order blocks on one GPU.
 
@@ -42,11 +53,13 @@ class CoupledCP:
     compute      "f64" | "f32" | "bf16" | "f16": MTTKRP operand type.
     init_U       optional [n][s] arrays (I_n x R); init_lambda optional [s] arrays.
     tucker_ranks optional (J1, J2, J3) or [S][3] for lra_compress.
+    block_ranks  optional [S] per-block ranks R^(s) <= rank (Section II-C);
+                 factors and lambdas of block s then have R^(s) columns.
     """
 
     def __init__(self, tensors, rank: int, coupled=(0, 0, 0), compute: str = "f32", init_U=None, init_lambda=None,
                  seed: int = 0, update_core: bool = True, restart: bool = True, delta_w: float = 0.9999,
-                 tol: float = 1e-8, max_it: int = 1000, tucker_ranks=None, stream=None):
+                 tol: float = 1e-8, max_it: int = 1000, tucker_ranks=None, block_ranks=None, stream=None):
         import torch
 
         self._lib = load()
@@ -84,6 +97,11 @@ class CoupledCP:
         cfg.tol = float(tol)
         cfg.max_it = int(max_it)
         cfg.tucker_ranks = self._tucker_c
+        self.block_ranks = [self.R] * S if block_ranks is None else [int(r) for r in block_ranks]
+        if len(self.block_ranks) != S:
+            raise ValueError("block_ranks needs one rank per block")
+        self._branks_c = (ctypes.c_int32 * S)(*self.block_ranks) if block_ranks is not None else None
+        cfg.block_ranks = self._branks_c
         self.cfg = cfg
         self.compute = compute
         nbytes = ctypes.c_size_t()
@@ -96,10 +114,10 @@ class CoupledCP:
         keepU = keepL = None
         pU = pL = None
         if init_U is not None:
-            flat = [init_U[n][s] for s in range(S) for n in range(3)]
+            flat = [_stride_r(init_U[n][s], self.R) for s in range(S) for n in range(3)]
             keepU, pU = _dbl_ptr_array(flat)
         if init_lambda is not None:
-            keepL, pL = _dbl_ptr_array(init_lambda)
+            keepL, pL = _dbl_ptr_array([_stride_r(x, self.R) for x in init_lambda])
         ctx = ctypes.c_void_p()
         check(self._lib.concpd_init(ctypes.byref(cfg), tptrs, pU, pL, ctypes.c_uint64(seed), ctypes.c_void_p(self._ws_ptr),
                                     ctypes.c_size_t(int(nbytes.value)), ctypes.c_void_p(self.stream.cuda_stream),
@@ -207,18 +225,19 @@ class CoupledCP:
         return self.step(0)
 
     # -- read-back --------------------------------------------------------
-    def factor(self, n: int, s: int) -> np.ndarray:
+    def factor(self, n: int, s: int, padded: bool = False) -> np.ndarray:
+        """U^(n,s), I_n x R^(s) (I_n x R with the zero columns if padded)."""
         out = np.empty((self.dims[s][n], self.R), dtype=np.float64)
         check(self._lib.concpd_get_factor(self.ctx, n, s, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-        return out
+        return out if padded else out[:, :self.block_ranks[s]].copy()
 
     def factors(self):
         return [[self.factor(n, s) for s in range(self.S)] for n in range(3)]
 
-    def lam(self, s: int) -> np.ndarray:
+    def lam(self, s: int, padded: bool = False) -> np.ndarray:
         out = np.empty(self.R, dtype=np.float64)
         check(self._lib.concpd_get_lambda(self.ctx, s, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-        return out
+        return out if padded else out[:self.block_ranks[s]].copy()
 
     def lams(self):
         return [self.lam(s) for s in range(self.S)]
@@ -246,14 +265,14 @@ class CoupledCP:
 
     def set_state(self, U, lam, U_prev=None, lam_prev=None, Ld_prev=None, Lu_prev=None, LC_prev=None, t=1.0, k=0):
         """U, U_prev: [n][s] arrays; Lu_prev [s][n] (or [n][s] transposed by caller); None entries mean 'none'."""
-        flat = lambda UU: [UU[n][s] for s in range(self.S) for n in range(3)]  # noqa: E731
+        flat = lambda UU: [_stride_r(UU[n][s], self.R) for s in range(self.S) for n in range(3)]  # noqa: E731
         kU, pU = _dbl_ptr_array(flat(U))
-        kL, pL = _dbl_ptr_array(lam)
+        kL, pL = _dbl_ptr_array([_stride_r(x, self.R) for x in lam])
         kUp = pUp = kLp = pLp = None
         if U_prev is not None:
             kUp, pUp = _dbl_ptr_array(flat(U_prev))
         if lam_prev is not None:
-            kLp, pLp = _dbl_ptr_array(lam_prev)
+            kLp, pLp = _dbl_ptr_array([_stride_r(x, self.R) for x in lam_prev])
 
         def _arr(x, shape):
             if x is None:

@@ -1,7 +1,7 @@
 """Seeded synthetic inputs for coupled nonnegative CP decomposition.
 
 This module only draws random numbers and assembles test problems from the
-generative model of Section II-B (eq. tensormodel: a sum of R rank-1 terms per
+generative model of Section II-C (eq. tensormodel: a sum of R rank-1 terms per
 block, the first L_n columns of every mode-n factor shared by all blocks).  It
 holds none of the fitting method's arithmetic, so the CPU oracle and the HIP
 path can both be fed from it without sharing code.

@@ -84,6 +84,16 @@ def test_invalid_configs_rejected_with_message(lib, kw, expect):
     assert len(lib.concpd_last_error()) > 0
 
 
+@pytest.mark.parametrize("ranks,expect", [((6, 3), 0), ((6, 6), 0), ((6, 2), 1), ((7, 6), 1), ((0, 6), 1)])
+def test_block_ranks_validated(lib, ranks, expect):
+    # R = 6 with L = (3, 0, 0): every R^(s) must lie in [3, 6]
+    c = _cfg(S=2, R=6, L=(3, 0, 0))
+    arr = (ctypes.c_int32 * 2)(*ranks)
+    c.block_ranks = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+    st, _ = query(lib, c)
+    assert st == expect, lib.concpd_last_error()
+
+
 def test_order_other_than_three_not_supported(lib):
     c = _cfg()
     c.order = 4

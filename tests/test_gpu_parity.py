@@ -84,10 +84,10 @@ def oracle_state_rounded(st, to32):
     return st
 
 
-def teacher_forced(dev, P, R, L, compute, k_before, seed, overshoot=False):
+def teacher_forced(dev, P, R, L, compute, k_before, seed, overshoot=False, update_core=True):
     U0, lam0 = synth.uniform_init(P.dims, R, L, seed)
     data = DenseData(P.tensors)
-    opt = Options(L=L)
+    opt = Options(L=L, update_core=update_core)
     st = apg.run(data, U0, lam0, opt, iters=k_before)
     if overshoot:
         st.U_prev = [[u * 0.2 for u in per] for per in st.U]
@@ -96,7 +96,7 @@ def teacher_forced(dev, P, R, L, compute, k_before, seed, overshoot=False):
     st = oracle_state_rounded(st, compute != "f64")
     st.F = apg.objective(data, st.lam, st.U)
     st.relerr = apg.relerr(data, st.lam, st.U)
-    m = make_model(P, st.U, st.lam, dev, compute)
+    m = make_model(P, st.U, st.lam, dev, compute, update_core=update_core)
     Lu_prev = [[st.Lu_prev[n][s] for n in range(3)] for s in range(P.S)]
     m.set_state(st.U, st.lam, st.U_prev, st.lam_prev, st.Ld_prev, Lu_prev, st.LC_prev, t=st.t, k=st.k)
     s0 = m.stats()

@@ -27,7 +27,7 @@ MUTATIONS = {
     "hadamard_skip": (("hadamard_of_grams", _skip_ignored), pins.test_gradients_match_finite_differences, ()),
     # step twice too long
     "half_lipschitz": (("spectral_norm", lambda A: 0.5 * _orig_sn(A)),
-                       pins.test_unextrapolated_sweep_is_exact_block_minimisation_rank1, ((1, 0, 1),)),
+                       pins.test_unextrapolated_sweep_is_exact_block_minimisation_rank1, ((1, 0, 1), True)),
     # wrong t recursion
     "t_recursion": (("t_next", lambda t: 0.5 * (1.0 + np.sqrt(1.0 + 2.0 * t * t))),
                     pins.test_t_sequence_closed_forms, ()),

@@ -255,19 +255,22 @@ def _coord_min(Ffun, x0):
     return max(0.0, x0 - b / (2 * a))
 
 
+@pytest.mark.parametrize("update_core", [True, False])
 @pytest.mark.parametrize("L", [(0, 0, 0), (1, 0, 1), (1, 1, 1)])
-def test_unextrapolated_sweep_is_exact_block_minimisation_rank1(L):
+def test_unextrapolated_sweep_is_exact_block_minimisation_rank1(L, update_core):
+    # update_core=False is the -NC variant (Section III-C, no core update): the lambda
+    # coordinates are skipped and only the factor blocks are minimised.
     P = synth.coupled_problem([(3, 4, 2), (3, 4, 2), (3, 4, 2)], 1, L, 10.0, 11, dtype=np.float64)
     U0, lam0 = synth.uniform_init(P.dims, 1, L, 12)
     data = DenseData(P.tensors)
     st = apg.initial_state(data, U0, lam0)
-    lam_new, U_new, _ = apg.sweep(data, st, 0.0, False, Options(L=L))
+    lam_new, U_new, _ = apg.sweep(data, st, 0.0, False, Options(L=L, update_core=update_core))
 
     S = 3
     lam = [l.copy() for l in lam0]
     U = [[u.copy() for u in per] for per in U0]
     F = lambda lm, Uu: apg.objective(data, lm, Uu)  # noqa: E731
-    for s in range(S):
+    for s in range(S if update_core else 0):
         def fl(x, s=s):
             lm = [l.copy() for l in lam]
             lm[s][0] = x
@@ -321,6 +324,24 @@ def test_restart_keeps_objective_monotone_and_factors_nonnegative():
                 if P.L[n]:
                     np.testing.assert_array_equal(st.U[n][s][:, :P.L[n]], st.U[n][0][:, :P.L[n]])
         assert all(np.all(l >= 0) for l in st.lam)
+
+
+def test_nc_variant_keeps_core_and_stays_monotone():
+    # -NC (Section III-C): D^(s) never changes, bit for bit, and the accepted
+    # objective still never increases, with restarts on.
+    P, U0, lam0 = small_problem(dims=((5, 6, 4), (5, 7, 4)), R=3, L=(2, 0, 1), snr=10.0, seed=23)
+    data = DenseData(P.tensors)
+    opt = Options(L=P.L, update_core=False)
+    st = apg.initial_state(data, U0, lam0)
+    F_prev = st.F
+    for _ in range(40):
+        st = apg.iterate(data, st, opt)
+        assert st.F <= F_prev * (1 + 1e-14)
+        F_prev = st.F
+        for s in range(2):
+            np.testing.assert_array_equal(st.lam[s], lam0[s])
+    full = apg.run(data, U0, lam0, Options(L=P.L), iters=40)
+    assert not np.allclose(full.lam[0], lam0[0])
 
 
 def test_unextrapolated_sweep_never_increases_objective():
@@ -392,6 +413,35 @@ def test_core_term_reuse_and_objective_expansion():
         F_exp = 0.5 * (np.sum(data.X[s] ** 2) - 2 * lam0[s] @ b + lam0[s] @ H @ lam0[s])
         r = data.X[s] - apg.reconstruct(lam0[s], Us)
         assert F_exp == pytest.approx(0.5 * np.sum(r * r), rel=1e-11)
+
+
+def _uneven(U0, lam0, ranks):
+    U = [[u[:, :ranks[s]].copy() for s, u in enumerate(per)] for per in U0]
+    return U, [l[:ranks[s]].copy() for s, l in enumerate(lam0)]
+
+
+def test_uneven_ranks_native_equal_zero_padded():
+    # Section II-C lets each block have its own R^(s) (>= every L_n).  The
+    # oracle runs the blocks at their own ranks; the padded run embeds them at
+    # R = max R^(s) with zero columns and lambda_r = 0, and must agree.
+    ranks = (4, 2, 3)
+    P, U0, lam0 = small_problem(dims=((5, 6, 4), (5, 7, 4), (5, 8, 4)), R=4, L=(2, 0, 1), snr=10.0, seed=41)
+    Un, ln = _uneven(U0, lam0, ranks)
+    Up = [[np.concatenate([u, np.zeros((u.shape[0], 4 - u.shape[1]))], axis=1) for u in per] for per in Un]
+    lp = [np.concatenate([l, np.zeros(4 - l.size)]) for l in ln]
+    data = DenseData(P.tensors)
+    a = apg.run(data, Un, ln, Options(L=P.L), iters=8)
+    b = apg.run(data, Up, lp, Options(L=P.L), iters=8)
+    assert a.restarts == b.restarts
+    assert b.F == pytest.approx(a.F, rel=1e-12)
+    for s, r in enumerate(ranks):
+        np.testing.assert_allclose(b.lam[s][:r], a.lam[s], rtol=1e-11)
+        assert np.all(b.lam[s][r:] == 0.0)
+        for n in range(3):
+            np.testing.assert_allclose(b.U[n][s][:, :r], a.U[n][s], rtol=1e-11, atol=1e-14)
+            assert np.all(b.U[n][s][:, r:] == 0.0)
+            if P.L[n]:
+                np.testing.assert_array_equal(a.U[n][s][:, :P.L[n]], a.U[n][0][:, :P.L[n]])
 
 
 def test_zero_padding_of_components_is_exact():
