@@ -84,6 +84,8 @@ SIGNATURES = {
     "concpd_fit": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "lra_compress": (ctypes.c_int, [_P, _I32P, ctypes.POINTER(Stats)]),
     "lra_step": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Stats)]),
+    "lra_compress_cp": (ctypes.c_int, [_P, _DPP, ctypes.c_uint64, ctypes.c_double, ctypes.c_int32,
+                                       _I32P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Stats)]),
     "lra_get_tucker": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _DP]),
     "concpd_set_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64]),
     "concpd_get_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),

@@ -787,6 +787,75 @@ concpd_status loss_grad_t(concpd_ctx c, const StateP<T>& st, const void* const* 
 
 }  // namespace
 
+// Compression by an unconstrained CPD fitted with ALS (the paper's own first
+// step of Algorithm 2).  The ALS factors live in the iterate's current slot
+// while the fit runs, so the sweep's MTTKRP passes serve it unchanged; the
+// APG iterate is saved to the host before and put back after.
+template <typename T>
+concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, double eps, int max_it, int32_t* iters, double* relerr_out) {
+    const int S = c->S, R = c->R;
+    double* L = (double*)(c->ws + c->lay.lra);
+    double* Lfac = L + c->lay.l_sig;
+    double* rel = L + c->lay.l_work;
+    double* xx = rel + S;
+    int* act = (int*)(xx + S);
+    int* bad = act + S;
+    int Imax[3] = {1, 1, 1};
+    for (int s = 0; s < S; ++s)
+        for (int n = 0; n < 3; ++n) Imax[n] = std::max(Imax[n], (int)c->dims[3 * s + n]);
+    std::vector<int> hact(S, 1), hbad(S, 0);
+    std::vector<double> prev(S), cur(S);
+    HIPCHECK(hipMemcpyAsync(act, hact.data(), sizeof(int) * S, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipMemcpyAsync(bad, hbad.data(), sizeof(int) * S, hipMemcpyHostToDevice, c->q));
+    // RelErr_0 at the starting point
+    debug_passes<T>(c, st);
+    cpd::launch_als_fit<T>(c->dgeo, st, S, R, act, rel, xx, c->q);
+    HIPCHECK(hipMemcpyAsync(prev.data(), rel, sizeof(double) * S, hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    for (int s = 0; s < S; ++s) {
+        if (iters) iters[s] = 0;
+        if (relerr_out) relerr_out[s] = prev[s];
+        if (!isfinite(prev[s])) return fail(CONCPD_ENONFINITE, "ALS: RelErr of block %d at the start is not finite", s);
+    }
+    const ItemP1* it1 = (const ItemP1*)(c->ws + c->lay.it1);
+    const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
+    const ItemK2* itk = (const ItemK2*)(c->ws + c->lay.itk2);
+    int active = S;
+    for (int it = 1; it <= max_it && active > 0; ++it) {
+        cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->p1dma, c->q);
+        cpd::launch_als_chol<T>(c->dgeo, st, S, R, 0, act, Lfac, bad, c->q);
+        cpd::launch_als_solve<T>(c->dgeo, st, S, R, 0, Imax[0], act, Lfac, c->q);
+        cpd::launch_k2<T>(c->dgeo, st, itk, (int)c->lists.k2.size(), 1, c->q);
+        cpd::launch_als_chol<T>(c->dgeo, st, S, R, 1, act, Lfac, bad, c->q);
+        cpd::launch_als_solve<T>(c->dgeo, st, S, R, 1, Imax[1], act, Lfac, c->q);
+        cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
+        cpd::launch_als_chol<T>(c->dgeo, st, S, R, 2, act, Lfac, bad, c->q);
+        cpd::launch_als_solve<T>(c->dgeo, st, S, R, 2, Imax[2], act, Lfac, c->q);
+        cpd::launch_als_fit<T>(c->dgeo, st, S, R, act, rel, xx, c->q);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(cur.data(), rel, sizeof(double) * S, hipMemcpyDeviceToHost, c->q));
+        HIPCHECK(hipMemcpyAsync(hbad.data(), bad, sizeof(int) * S, hipMemcpyDeviceToHost, c->q));
+        HIPCHECK(hipStreamSynchronize(c->q));
+        for (int s = 0; s < S; ++s) {
+            if (!hact[s]) continue;
+            if (hbad[s] || !isfinite(cur[s]))
+                return fail(CONCPD_ENONFINITE, "ALS: block %d has a singular Gram or a non-finite fit at iteration %d", s, it);
+            if (iters) iters[s] = it;
+            if (relerr_out) relerr_out[s] = cur[s];
+            if (fabs(cur[s] - prev[s]) < eps) {
+                hact[s] = 0;
+                --active;
+            }
+            prev[s] = cur[s];
+        }
+        HIPCHECK(hipMemcpyAsync(act, hact.data(), sizeof(int) * S, hipMemcpyHostToDevice, c->q));
+    }
+    cpd::launch_als_export<T>(c->dgeo, st, S, xx, c->q);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(c->q));
+    return CONCPD_OK;
+}
+
 extern "C" {
 
 const char* concpd_last_error(void) { return g_err.c_str(); }
@@ -1089,6 +1158,86 @@ concpd_status lra_compress(concpd_ctx c, const int32_t* ranks, concpd_stats* out
     h.stop = 0;
     h.redo = 0;
     HIPCHECK(hipMemcpy(c->ctrl, &h, sizeof h, hipMemcpyHostToDevice));
+    if (c->f64) recompute_stats<double>(c, c->sd);
+    else recompute_stats<float>(c, c->sf);
+    HIPCHECK(hipGetLastError());
+    return read_stats(c, out);
+}
+
+concpd_status lra_compress_cp(concpd_ctx c, const double* const* init, uint64_t seed, double eps, int32_t max_it,
+                              int32_t* iters, double* relerr, concpd_stats* out) {
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    if (c->lra) return fail(CONCPD_ESTATE, "lra_compress_cp: the context is already compressed");
+    if (c->tucker.empty()) return fail(CONCPD_ESTATE, "lra_compress_cp: needs tucker_ranks (J_n >= R reserves the storage)");
+    for (int i = 0; i < 3 * c->S; ++i)
+        if (c->tucker[i] < c->R)
+            return fail(CONCPD_EINVAL, "lra_compress_cp: tucker_ranks[%d] = %d < rank %d", i, c->tucker[i], c->R);
+    for (int s = 0; s < c->S; ++s)
+        if (c->rk[s] != c->R) return fail(CONCPD_ENOTSUP, "lra_compress_cp: block ranks below R are not supported");
+    if (!(eps >= 0.0) || !isfinite(eps)) return fail(CONCPD_EINVAL, "eps must be finite and >= 0");
+    if (max_it < 0) return fail(CONCPD_EINVAL, "max_it must be >= 0");
+    const int S = c->S, R = c->R;
+    // starting factors (host, FP64): the caller's, or a seeded U[0,1] draw
+    std::vector<std::vector<double>> h(3 * S);
+    if (!init) {
+        SplitMix64 rng{seed};
+        for (int n = 0; n < 3; ++n)
+            for (int s = 0; s < S; ++s) {
+                h[3 * s + n].resize((size_t)c->dims[3 * s + n] * R);
+                for (double& v : h[3 * s + n]) v = rng.uniform();
+            }
+    }
+    for (int i = 0; i < 3 * S; ++i) {
+        const double* p = init ? init[i] : h[i].data();
+        if (!p) return fail(CONCPD_EINVAL, "init[%d] is NULL", i);
+        if (!all_finite(p, (size_t)c->dims[i] * R)) return fail(CONCPD_ENONFINITE, "init[%d] is not finite", i);
+    }
+    // save the APG iterate's current slot and the control block
+    const int phys = phys_slot3(c, 1);
+    const size_t slot_bytes = (size_t)c->lay.uslot * c->lay.esz;
+    char* slot = c->ws + c->lay.U[phys];
+    std::vector<char> saved(slot_bytes);
+    Ctrl hc;
+    HIPCHECK(hipMemcpyAsync(saved.data(), slot, slot_bytes, hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipMemcpyAsync(&hc, c->ctrl, sizeof hc, hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    // the starting factors into that slot (every block its own; no sharing)
+    {
+        std::vector<char> packed(slot_bytes, 0);
+        for (int s = 0; s < S; ++s)
+            for (int n = 0; n < 3; ++n) {
+                const double* src = init ? init[3 * s + n] : h[3 * s + n].data();
+                const int I = (int)c->dims[3 * s + n];
+                for (int i = 0; i < I; ++i)
+                    for (int r = 0; r < R; ++r) {
+                        const size_t e = (size_t)c->geo.uoff[n][s] + (size_t)i * c->Rq + r;
+                        if (c->f64) ((double*)packed.data())[e] = src[(size_t)i * R + r];
+                        else ((float*)packed.data())[e] = (float)src[(size_t)i * R + r];
+                    }
+            }
+        HIPCHECK(hipMemcpyAsync(slot, packed.data(), slot_bytes, hipMemcpyHostToDevice, c->q));
+        Ctrl run = hc;
+        run.stop = 0;
+        run.redo = 0;
+        HIPCHECK(hipMemcpyAsync(c->ctrl, &run, sizeof run, hipMemcpyHostToDevice, c->q));
+        HIPCHECK(hipStreamSynchronize(c->q));
+    }
+    c->drop_graph();
+    concpd_status st = c->f64 ? als_fit_all<double>(c, c->sd, eps, max_it, iters, relerr)
+                              : als_fit_all<float>(c, c->sf, eps, max_it, iters, relerr);
+    // the APG iterate and the control block back in place
+    hipStreamSynchronize(c->q);
+    hc.stop = 0;
+    hc.redo = 0;
+    HIPCHECK(hipMemcpyAsync(slot, saved.data(), slot_bytes, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipMemcpyAsync(c->ctrl, &hc, sizeof hc, hipMemcpyHostToDevice, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    if (st != CONCPD_OK) return st;
+    for (int s = 0; s < S; ++s)
+        for (int n = 0; n < 3; ++n) c->geo.J[s][n] = R;
+    c->geo.lra = 1;
+    c->lra = 1;
+    HIPCHECK(hipMemcpyAsync(c->dgeo, &c->geo, sizeof(Geo), hipMemcpyHostToDevice, c->q));
     if (c->f64) recompute_stats<double>(c, c->sd);
     else recompute_stats<float>(c, c->sf);
     HIPCHECK(hipGetLastError());

@@ -1,0 +1,194 @@
+"""The paper's own compression step of Algorithm 2 on the GPU: a rank-R
+unconstrained CPD of every block fitted by ALS (Section III-B; the ALS
+settings of Section IV), through the C ABI, against the FP64 oracle
+``oracle.cpals``, and the lra iterations on the resulting Kruskal form
+(eq. eqlrau / eqlrag).
+
+Tolerances: the ALS factors live in FP32 and K_n comes from FP32 matrix-core
+MTTKRPs, and each solve multiplies the relative error of K_n by up to
+cond(H_n) (at most 1.6e3 for these draws; measured errors are about
+1e-8 cond(H_n)), so factors after one ALS iteration are compared at 1e-4
+normwise; RelErr is compared at 1e-6 absolute and the
+iteration counts exactly (the CPU model of FP32 factor rounding moves RelErr
+by < 1e-9 on these problems, far inside eps = 1e-4).  The lra iterations are
+compared teacher-forced (both sides from the same point, the oracle on its own
+compression) at 1e-4, a bound set by the two compressions' difference.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import apg, cpals
+from oracle.apg import Options, TuckerData
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / n if n > 0 else np.linalg.norm(a - b)
+
+
+def make_model(P, dev, R, L=(0, 0, 0), U0=None, lam0=None, tucker=None, **kw):
+    import torch
+    from paper_2302_05119_amd import CoupledCP
+    tens = [torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev) for X in P.tensors]
+    return CoupledCP(tens, R, L, compute="f32", init_U=U0, init_lambda=lam0, seed=5,
+                     tucker_ranks=tucker or (R, R, R), **kw)
+
+
+def als_inits(P, R, seed):
+    rng = np.random.default_rng(seed)
+    # [n][s], rounded to FP32 (the device holds the factors in FP32)
+    per = [[rng.random((d[n], R)).astype(np.float32).astype(np.float64) for n in range(3)] for d in P.dims]
+    return [[per[s][n] for s in range(P.S)] for n in range(3)]
+
+
+@pytest.mark.parametrize("dims,R", [([(20, 24, 18), (16, 30, 22)], 5), ([(40, 36, 50)] * 2, 8), ([(21, 70, 100)], 20)])
+def test_one_als_iteration_matches_oracle(dev, dims, R):
+    say(f"[cp-als] one iteration dims={dims} R={R}")
+    P = synth.coupled_problem(dims, R, (0, 0, 0), 15.0, 301 + R, dtype=np.float32)
+    init = als_inits(P, R, 302 + R)
+    m = make_model(P, dev, R)
+    out = m.lra_compress_cp(init=init, eps=0.0, max_it=1)
+    assert out["als_iters"] == [1] * P.S and out["lra"] == 1
+    for s in range(P.S):
+        X = P.tensors[s].astype(np.float64)
+        want = cpals.als_iteration(X, [init[n][s] for n in range(3)])
+        A, G = m.tucker(s)
+        for n in range(3):
+            e = rel(A[n], want[n])
+            say(f"   s={s} n={n} rel={e:.2e} cond={np.linalg.cond(apg.hadamard_of_grams(want, skip=n)):.1e}")
+            assert e <= 1e-4
+        sup = np.zeros((R, R, R))
+        sup[np.arange(R), np.arange(R), np.arange(R)] = 1.0
+        np.testing.assert_array_equal(G, sup)
+        assert out["als_relerr"][s] == pytest.approx(cpals.relerr(X, want), abs=1e-6)
+
+
+@pytest.mark.parametrize("dims,R,snr", [([(20, 24, 18), (16, 30, 22)], 5, 15.0), ([(40, 36, 50)] * 2, 8, 10.0)])
+def test_full_als_run_matches_oracle(dev, dims, R, snr):
+    say(f"[cp-als] full run dims={dims} R={R}")
+    P = synth.coupled_problem(dims, R, (0, 0, 0), snr, 311 + R, dtype=np.float32)
+    init = als_inits(P, R, 312 + R)
+    m = make_model(P, dev, R)
+    before = [[m.factor(n, s) for s in range(P.S)] for n in range(3)]
+    out = m.lra_compress_cp(init=init)
+    for s in range(P.S):
+        X = P.tensors[s].astype(np.float64)
+        U, it, hist = cpals.cp_als(X, [init[n][s] for n in range(3)], 1e-4, 200)
+        A, G = m.tucker(s)
+        say(f"   s={s} iters gpu={out['als_iters'][s]} oracle={it} relerr gpu={out['als_relerr'][s]:.9f} "
+            f"oracle={hist[-1]:.9f}")
+        assert out["als_iters"][s] == it
+        assert out["als_relerr"][s] == pytest.approx(hist[-1], abs=1e-6)
+        # the reported RelErr is that of the returned factors
+        assert out["als_relerr"][s] == pytest.approx(cpals.relerr(X, A), abs=1e-6)
+        for n in range(3):
+            assert rel(A[n], U[n]) <= 1e-3
+    # the APG iterate is untouched by the compression
+    for n in range(3):
+        for s in range(P.S):
+            np.testing.assert_array_equal(m.factor(n, s), before[n][s])
+
+
+def test_lra_iterations_on_cp_compression(dev):
+    say("[cp-als] lra iterations on the Kruskal form")
+    L, R = (3, 0, 0), 6
+    P = synth.coupled_problem([(17, 30, 25), (17, 28, 21), (17, 30, 25)], R, L, 15.0, 321, dtype=np.float32)
+    U0, lam0 = synth.uniform_init(P.dims, R, L, 322)
+    init = als_inits(P, R, 323)
+    m = make_model(P, dev, R, L, U0=U0, lam0=lam0)
+    out = m.lra_compress_cp(init=init, eps=0.0, max_it=4)
+    facs, its, rels = cpals.compress_all_cp([X.astype(np.float64) for X in P.tensors],
+                                            [[init[n][s] for n in range(3)] for s in range(P.S)], 0.0, 4)
+    assert out["als_iters"] == its
+    cores, bases = zip(*[cpals.kruskal_as_tucker(U) for U in facs])
+    data = TuckerData(list(cores), list(bases))
+    U32 = [[u.astype(np.float32).astype(np.float64) for u in per] for per in U0]
+    st0 = apg.initial_state(data, U32, lam0)
+    s0 = m.stats()
+    say(f"   F0 gpu={s0['F']:.10e} oracle={st0.F:.10e}")
+    assert abs(s0["F"] - st0.F) / st0.F <= 1e-4
+    st1 = apg.iterate(data, st0, Options(L=L))
+    s1 = m.lra_step(1)
+    say(f"   F1 gpu={s1['F']:.10e} oracle={st1.F:.10e}")
+    assert abs(s1["F"] - st1.F) / st1.F <= 1e-4
+    for s in range(P.S):
+        assert rel(m.lam(s), st1.lam[s]) <= 1e-4
+        for n in range(3):
+            assert rel(m.factor(n, s), st1.U[n][s]) <= 1e-4
+    ref = apg.run(data, None, None, Options(L=L), iters=59, state=st1)
+    s60 = m.lra_step(59)
+    gf = m.global_fit()
+    rf = apg.fit(P.tensors, ref.lam, ref.U)
+    say(f"   after 60: global fit gpu={gf:.8f} oracle={rf:.8f}")
+    assert abs(gf - rf) <= 1e-3
+    assert s60["k"] == 60
+
+
+def test_noiseless_exact_rank_reaches_fp32_floor(dev):
+    say("[cp-als] noiseless exact rank")
+    R = 4
+    P = synth.coupled_problem([(30, 32, 34)] * 2, R, (0, 0, 0), None, 331, dtype=np.float32)
+    m = make_model(P, dev, R)
+    out = m.lra_compress_cp(eps=0.0, max_it=200, seed=3)
+    say(f"   relerr={out['als_relerr']} iters={out['als_iters']}")
+    assert max(out["als_relerr"]) < 1e-4
+
+
+def test_seeded_start_is_deterministic(dev):
+    say("[cp-als] seeded start")
+    P = synth.coupled_problem([(20, 21, 22)] * 2, 4, (0, 0, 0), 10.0, 341, dtype=np.float32)
+    a, b = make_model(P, dev, 4), make_model(P, dev, 4)
+    oa, ob = a.lra_compress_cp(seed=11), b.lra_compress_cp(seed=11)
+    assert oa["als_iters"] == ob["als_iters"] and oa["als_relerr"] == ob["als_relerr"]
+    for s in range(2):
+        for x, y in zip(a.tucker(s)[0], b.tucker(s)[0]):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_rejections(dev):
+    import torch
+    from paper_2302_05119_amd import ConcpdError, CoupledCP
+    say("[cp-als] rejections")
+    P = synth.coupled_problem([(12, 13, 14)] * 2, 4, (0, 0, 0), 10.0, 351, dtype=np.float32)
+    tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
+    with pytest.raises(ConcpdError):
+        CoupledCP(tens, 4, (0, 0, 0)).lra_compress_cp()                        # no compressed-form storage
+    with pytest.raises(ConcpdError):
+        CoupledCP(tens, 4, (0, 0, 0), tucker_ranks=(3, 4, 4)).lra_compress_cp()  # J_1 < R
+    with pytest.raises(ConcpdError):
+        CoupledCP(tens, 4, (0, 0, 0), tucker_ranks=(4, 4, 4), block_ranks=(4, 3)).lra_compress_cp()
+    m = CoupledCP(tens, 4, (0, 0, 0), tucker_ranks=(4, 4, 4))
+    with pytest.raises(ConcpdError):
+        m.lra_compress_cp(eps=-1.0)
+    # a rank-deficient start (two equal columns) has a singular Gram
+    rng = np.random.default_rng(1)
+    bad = [[rng.random((d[n], 4)) for d in P.dims] for n in range(3)]
+    for n in range(3):
+        for s in range(2):
+            bad[n][s][:, 1] = bad[n][s][:, 0]
+    before = m.factor(0, 0)
+    with pytest.raises(ConcpdError):
+        m.lra_compress_cp(init=bad)
+    np.testing.assert_array_equal(m.factor(0, 0), before)
+    assert m.stats()["lra"] == 0
+    m.lra_compress_cp()
+    with pytest.raises(ConcpdError):
+        m.lra_compress_cp()                                                  # already compressed
