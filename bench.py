@@ -80,10 +80,12 @@ def measured_traffic(kernel: str, tuning=None):
     return int(t.group(1))
 
 
-def lra_leg(steps: int, warmup: int, dense_steps: int = 30, name: str = LRA_WORKLOAD):
+def lra_leg(steps: int, warmup: int, dense_steps: int = 30, name: str = LRA_WORKLOAD, compress: str = "thosvd"):
     """lraCoNCPD-APG (10 blocks of 256^3 with Tucker 30^3, or 4 blocks of 512^3
     with Tucker 40^3): compression time and iterations/s of the compressed
-    iterations (step 2), beside the plain path on the same blocks."""
+    iterations (step 2), beside the plain path on the same blocks.  compress:
+    "thosvd" (truncated HOSVD) or "cp_als" (the paper's rank-R CPD by ALS,
+    eps = 1e-4, at most 200 iterations, seeded U[0,1] start)."""
     import torch
 
     import synth
@@ -110,7 +112,12 @@ def lra_leg(steps: int, warmup: int, dense_steps: int = 30, name: str = LRA_WORK
     del dense
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    m.lra_compress()
+    extra = {}
+    if compress == "cp_als":
+        c = m.lra_compress_cp(eps=1e-4, max_it=200, seed=w["seed"] + 3000)
+        extra = {"als_iters": c["als_iters"], "als_relerr": c["als_relerr"]}
+    else:
+        m.lra_compress()
     t1 = time.perf_counter()
     m.lra_step(warmup, sync=False)
     k0 = m.stats()["k"]
@@ -120,7 +127,8 @@ def lra_leg(steps: int, warmup: int, dense_steps: int = 30, name: str = LRA_WORK
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     st = m.stats()
-    return {"workload": name, "compress_s": t1 - t0, "iter_per_s": (st["k"] - k0) / (t3 - t2),
+    return {"workload": name, "compression": compress, **extra, "compress_s": t1 - t0,
+            "iter_per_s": (st["k"] - k0) / (t3 - t2),
             "dense_iter_per_s_same_blocks": dense_rate, "sweeps": steps,
             "warmup": warmup, "fit_compressed": st["fit"], "global_fit": m.global_fit(), "iterations": st["k"],
             "restarts": st["restarts"]}
@@ -306,6 +314,9 @@ def main():
     if args.lra_steps > 0:
         out["lra"] = lra_leg(args.lra_steps, max(1, args.warmup // 2))
         out["lra_c5"] = lra_leg(args.lra_steps, max(1, args.warmup // 2), name=LRA_WORKLOAD_C5)
+        out["lra_cp_als"] = lra_leg(args.lra_steps, max(1, args.warmup // 2), compress="cp_als")
+        out["lra_c5_cp_als"] = lra_leg(args.lra_steps, max(1, args.warmup // 2), name=LRA_WORKLOAD_C5,
+                                       compress="cp_als")
     if not args.no_cpu_baseline:
         U0r = [[m_u.astype(np.float32).astype(np.float64) for m_u in per] for per in U0]
         out["cpu_baseline"] = cpu_baseline(P, U0r, lam0)
