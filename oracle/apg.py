@@ -254,6 +254,18 @@ class Options:
     restart: bool = True
     update_core: bool = True      # False: the -NC variant (D kept at its initial value)
     reset_t: bool = False
+    # flexible coupling (Section III-C): per mode, the blocks that share the
+    # first L_n columns (None: every block); the others keep all R columns
+    # individual in that mode
+    coupled_blocks: Optional[tuple] = None
+
+    def group(self, n: int, S: int):
+        """Blocks sharing mode n's first L_n columns, in block order."""
+        if self.L[n] == 0:
+            return []
+        if self.coupled_blocks is None or self.coupled_blocks[n] is None:
+            return list(range(S))
+        return sorted(int(b) for b in self.coupled_blocks[n])
 
 
 @dataclass
@@ -321,7 +333,8 @@ def sweep(data, st: State, w_hat: float, extrapolate: bool, opt: Options):
     # (ii) factor matrices, eq. solUns / solUnC / solUnsI with the gradient of
     #      eq. solapgU and the extrapolated point of eq. eqextraPU
     for n in range(N):
-        Ln = opt.L[n]
+        grp = opt.group(n, S)
+        Ln = opt.L[n] if grp else 0
         P, Lu, K = [], [], []
         for s in range(S):
             Us = [U[m][s] for m in range(N)]
@@ -330,7 +343,7 @@ def sweep(data, st: State, w_hat: float, extrapolate: bool, opt: Options):
             Lu.append(spectral_norm(Ps))
             K.append(data.mttkrp(s, Us, n))
         rec.Lu[n] = list(Lu)
-        LC = float(sum(Lu))
+        LC = float(sum(Lu[s] for s in grp)) if grp else float(sum(Lu))
         rec.LC[n] = LC
 
         Uhat = []
@@ -339,9 +352,10 @@ def sweep(data, st: State, w_hat: float, extrapolate: bool, opt: Options):
             Uhat.append(st.U[n][s] + w * (st.U[n][s] - st.U_prev[n][s]))
         if Ln > 0:
             wC = extrapolation_weight(w_hat, st.LC_prev[n], LC, opt.delta_w) if extrapolate else 0.0
-            UC_old, UC_prev = st.U[n][0][:, :Ln], st.U_prev[n][0][:, :Ln]
+            g0 = grp[0]
+            UC_old, UC_prev = st.U[n][g0][:, :Ln], st.U_prev[n][g0][:, :Ln]
             UC_hat = UC_old + wC * (UC_old - UC_prev)
-            for s in range(S):
+            for s in grp:
                 Uhat[s][:, :Ln] = UC_hat
 
         G = [Uhat[s] @ P[s] - K[s] * lam[s][None, :] for s in range(S)]
@@ -350,16 +364,17 @@ def sweep(data, st: State, w_hat: float, extrapolate: bool, opt: Options):
 
         if Ln > 0:
             if LC > 0.0:
-                GC = sum(G[s][:, :Ln] for s in range(S))
+                GC = sum(G[s][:, :Ln] for s in grp)
                 UC_new = np.maximum(0.0, UC_hat - GC / LC)
             else:
-                UC_new = st.U[n][0][:, :Ln].copy()
+                UC_new = st.U[n][grp[0]][:, :Ln].copy()
         for s in range(S):
+            Ls = Ln if s in grp else 0          # blocks outside the group: all columns individual
             if Lu[s] > 0.0:
-                UI_new = np.maximum(0.0, Uhat[s][:, Ln:] - G[s][:, Ln:] / Lu[s])
+                UI_new = np.maximum(0.0, Uhat[s][:, Ls:] - G[s][:, Ls:] / Lu[s])
             else:
-                UI_new = st.U[n][s][:, Ln:].copy()
-            U[n][s] = np.concatenate([UC_new, UI_new], axis=1) if Ln > 0 else UI_new
+                UI_new = st.U[n][s][:, Ls:].copy()
+            U[n][s] = np.concatenate([UC_new, UI_new], axis=1) if Ls > 0 else UI_new
     return lam, U, rec
 
 

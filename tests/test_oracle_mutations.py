@@ -27,7 +27,7 @@ MUTATIONS = {
     "hadamard_skip": (("hadamard_of_grams", _skip_ignored), pins.test_gradients_match_finite_differences, ()),
     # step twice too long
     "half_lipschitz": (("spectral_norm", lambda A: 0.5 * _orig_sn(A)),
-                       pins.test_unextrapolated_sweep_is_exact_block_minimisation_rank1, ((1, 0, 1), True)),
+                       pins.test_unextrapolated_sweep_is_exact_block_minimisation_rank1, ((1, 0, 1), None, True)),
     # wrong t recursion
     "t_recursion": (("t_next", lambda t: 0.5 * (1.0 + np.sqrt(1.0 + 2.0 * t * t))),
                     pins.test_t_sequence_closed_forms, ()),
@@ -43,3 +43,11 @@ def test_planted_mistake_is_caught(name, monkeypatch):
     monkeypatch.setattr(apg, attr, fn)
     with pytest.raises(AssertionError):
         pin(*args)
+
+
+def test_planted_mistake_ignoring_coupling_groups_is_caught(monkeypatch):
+    # flexible coupling that ties the shared columns of every block instead of
+    # only the listed ones
+    monkeypatch.setattr(apg.Options, "group", lambda self, n, S: list(range(S)) if self.L[n] else [])
+    with pytest.raises(AssertionError):
+        pins.test_unextrapolated_sweep_is_exact_block_minimisation_rank1((1, 0, 1), ((0, 2), None, (1, 2)), True)

@@ -256,17 +256,33 @@ def _coord_min(Ffun, x0):
 
 
 @pytest.mark.parametrize("update_core", [True, False])
-@pytest.mark.parametrize("L", [(0, 0, 0), (1, 0, 1), (1, 1, 1)])
-def test_unextrapolated_sweep_is_exact_block_minimisation_rank1(L, update_core):
+@pytest.mark.parametrize("L,groups", [((0, 0, 0), None), ((1, 0, 1), None), ((1, 1, 1), None),
+                                      ((1, 0, 1), ((0, 2), None, (1, 2))), ((1, 1, 0), ((1,), (0, 1, 2), None))])
+def test_unextrapolated_sweep_is_exact_block_minimisation_rank1(L, groups, update_core):
     # update_core=False is the -NC variant (Section III-C, no core update): the lambda
-    # coordinates are skipped and only the factor blocks are minimised.
+    # coordinates are skipped and only the factor blocks are minimised.  groups:
+    # flexible coupling (Section III-C), the shared coordinate is tied only
+    # across the listed blocks of that mode.
     P = synth.coupled_problem([(3, 4, 2), (3, 4, 2), (3, 4, 2)], 1, L, 10.0, 11, dtype=np.float64)
     U0, lam0 = synth.uniform_init(P.dims, 1, L, 12)
+    opt = Options(L=L, update_core=update_core, coupled_blocks=groups)
+    S = 3
+
+    def group_of(n):
+        if not L[n]:
+            return []
+        return list(range(S)) if groups is None or groups[n] is None else sorted(groups[n])
+
+    for n in range(3):
+        # the start ties the shared column only inside the group
+        grp = group_of(n)
+        for s in range(S):
+            if L[n] and s not in grp:
+                U0[n][s] = U0[n][s] * (1.0 + 0.3 * (s + 1))
     data = DenseData(P.tensors)
     st = apg.initial_state(data, U0, lam0)
-    lam_new, U_new, _ = apg.sweep(data, st, 0.0, False, Options(L=L, update_core=update_core))
+    lam_new, U_new, _ = apg.sweep(data, st, 0.0, False, opt)
 
-    S = 3
     lam = [l.copy() for l in lam0]
     U = [[u.copy() for u in per] for per in U0]
     F = lambda lm, Uu: apg.objective(data, lm, Uu)  # noqa: E731
@@ -278,25 +294,27 @@ def test_unextrapolated_sweep_is_exact_block_minimisation_rank1(L, update_core):
         lam[s][0] = _coord_min(fl, lam[s][0])
     for n in range(3):
         newU = [u.copy() for u in U[n]]
+        grp = group_of(n)
         if L[n] == 1:
-            # shared column: one coordinate per row, set in every block at once
+            # shared column: one coordinate per row, set in every group block at once
             for i in range(P.dims[0][n]):
                 def fc(x, i=i):
                     Uu = [[u.copy() for u in per] for per in U]
-                    for s in range(S):
+                    for s in grp:
                         Uu[n][s][i, 0] = x
                     return F(lam, Uu)
-                v = _coord_min(fc, U[n][0][i, 0])
-                for s in range(S):
+                v = _coord_min(fc, U[n][grp[0]][i, 0])
+                for s in grp:
                     newU[s][i, 0] = v
-        else:
-            for s in range(S):
-                for i in range(P.dims[s][n]):
-                    def fi(x, i=i, s=s):
-                        Uu = [[u.copy() for u in per] for per in U]
-                        Uu[n][s][i, 0] = x
-                        return F(lam, Uu)
-                    newU[s][i, 0] = _coord_min(fi, U[n][s][i, 0])
+        for s in range(S):
+            if L[n] == 1 and s in grp:
+                continue
+            for i in range(P.dims[s][n]):
+                def fi(x, i=i, s=s):
+                    Uu = [[u.copy() for u in per] for per in U]
+                    Uu[n][s][i, 0] = x
+                    return F(lam, Uu)
+                newU[s][i, 0] = _coord_min(fi, U[n][s][i, 0])
         U[n] = newU
     for s in range(S):
         np.testing.assert_allclose(lam_new[s], lam[s], rtol=1e-9)
