@@ -163,6 +163,68 @@ def precision_leg(P, U0, lam0, w, steps, fit_fp32, k_fp32):
             "iterations": st["k"]}
 
 
+def workload_leg(name: str, steps: int):
+    """A second workload shape of the paper (face-image-shaped with per-block
+    ranks, or ERP-shaped fully coupled), FP32: iterations/s and the fit."""
+    import torch
+
+    import synth
+    from paper_2302_05119_amd import CoupledCP
+
+    dev = torch.device("cuda:0")
+    P = synth.make_workload(name)
+    U0, lam0 = synth.workload_init(name, P)
+    tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
+    m = CoupledCP(tens, P.R, P.L, compute="f32", init_U=U0, init_lambda=lam0, block_ranks=P.meta.get("block_ranks"))
+    m.autotune(20)
+    m.step(10)
+    k0 = m.stats()["k"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(steps, sync=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = m.stats()
+    return {"workload": name, "iter_per_s": (st["k"] - k0) / (t1 - t0), "iterations": st["k"],
+            "global_fit": m.global_fit(), "restarts": st["restarts"]}
+
+
+def sweep_leg(kind: str):
+    """The synthetic sweeps of the paper's Experiment 1 (20 blocks, R = 10,
+    L = [5, 5, 0], U[0,1] factors): SNR 0..20 dB in steps of 2 at 100^3
+    ("snr"), or sizes I = 10n, n = 1, 3, ..., 19 at 20 dB ("size").  Each point
+    runs CoNCPD-APG to the paper's stopping rule (|dRelErr| < 1e-8 or 1000
+    iterations) and lraCoNCPD-APG (CPD-ALS compression, then the same rule);
+    reported: fit, iterations and seconds of each."""
+    import torch
+
+    import synth
+    from paper_2302_05119_amd import CoupledCP
+
+    dev = torch.device("cuda:0")
+    pts = [(snr, 100) for snr in range(0, 21, 2)] if kind == "snr" else [(20, 10 * n) for n in range(1, 20, 2)]
+    out = []
+    for i, (snr, I) in enumerate(pts):
+        P = synth.coupled_problem([(I, I, I)] * 20, 10, (5, 5, 0), float(snr), 4000 + i)
+        U0, lam0 = synth.uniform_init(P.dims, 10, (5, 5, 0), 5000 + i)
+        tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
+        row = {"snr_db": snr, "I": I}
+        for lra in (False, True):
+            kw = {"tucker_ranks": (10, 10, 10)} if lra else {}
+            m = CoupledCP(tens, 10, (5, 5, 0), compute="f32", init_U=U0, init_lambda=lam0, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if lra:
+                m.lra_compress_cp(eps=1e-4, max_it=200, seed=6000 + i)
+            st = m.fit()
+            torch.cuda.synchronize()
+            key = "lra" if lra else "dense"
+            row[key] = {"fit": m.global_fit(), "iterations": st["k"], "seconds": time.perf_counter() - t0}
+        out.append(row)
+        print(f"[sweep {kind}] {row}", file=sys.stderr, flush=True)
+    return out
+
+
 def batched_leg(steps):
     """Batching form on the EEG-shaped workload (16 blocks 64 x 60 x T_s, T_s
     in [200, 2000], R = 30, channel and frequency factors shared): every mode
@@ -221,6 +283,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lra-steps", type=int, default=300, help="iterations of the lra leg (0: skip it)")
     ap.add_argument("--forms-steps", type=int, default=200, help="iterations of the BF16 and batched legs (0: skip)")
+    ap.add_argument("--sweeps", action="store_true", help="also run the SNR and size sweeps of the synthetic "
+                    "experiment (each point to the paper's stopping rule)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="time the default launch configuration instead of the autotuned one")
     ap.add_argument("--copy-calibration", action="store_true", help="only run the copy kernels used to "
@@ -311,6 +375,11 @@ def main():
     if args.forms_steps > 0:
         out["bf16_c2"] = precision_leg(P, U0, lam0, w, args.forms_steps, st["fit"], st["k"])
         out["batched_c4"] = batched_leg(args.forms_steps)
+        out["face"] = workload_leg("face_31x32x32x64_r22to26", args.forms_steps)
+        out["erp"] = workload_leg("erp_42x9x71x60_r36_full", args.forms_steps)
+    if args.sweeps:
+        out["sweep_snr"] = sweep_leg("snr")
+        out["sweep_size"] = sweep_leg("size")
     if args.lra_steps > 0:
         out["lra"] = lra_leg(args.lra_steps, max(1, args.warmup // 2))
         out["lra_c5"] = lra_leg(args.lra_steps, max(1, args.warmup // 2), name=LRA_WORKLOAD_C5)

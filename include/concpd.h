@@ -85,6 +85,12 @@ typedef struct concpd_config {
                                Lipschitz constant unchanged.  Host factor and lambda arrays
                                keep the stride R; columns >= R^(s) are ignored on input and
                                read back as zero. */
+    const uint64_t* coupled_blocks; /* [3] flexible coupling (Section III-C): bit s of
+                               coupled_blocks[n] set = block s shares mode n's first L_n
+                               columns; blocks left out keep all R columns of that mode
+                               individual.  A mode with L_n > 0 needs at least one bit set
+                               (bits >= S must be clear) and equal I_n over its group.
+                               NULL: every block shares (the model of Section II-C). */
 } concpd_config;
 
 typedef struct concpd_stats {

@@ -32,6 +32,7 @@ class Config(ctypes.Structure):
         ("max_it", ctypes.c_int32),
         ("tucker_ranks", ctypes.POINTER(ctypes.c_int32)),
         ("block_ranks", ctypes.POINTER(ctypes.c_int32)),
+        ("coupled_blocks", ctypes.POINTER(ctypes.c_uint64)),
     ]
 
 

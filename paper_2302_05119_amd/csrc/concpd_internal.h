@@ -37,6 +37,8 @@ struct Ctrl {
 struct Geo {
     int S, R, Rq;                 // Rq = R rounded up to a multiple of 4 (factor row stride)
     int L[3];
+    int ngrp[3];                  // blocks of mode n's coupling group (L_n > 0), else every block
+    int grp[3][CPD_MAXS];         // their indices, ascending
     int upd_core;
     int lra;                      // 1: gradients from the Tucker form
     int I[CPD_MAXS][3];
@@ -90,7 +92,9 @@ struct StateP {
 // Work items of the grouped kernels (host-built lists, one entry per workgroup).
 struct ItemP1 { int s, i1, rg, pad; };              // pass 1: block (< 0: empty), slab, 64-row group
 struct ItemP2 { int s, chunk, q0, pad; };           // pass 2: block, 4-slab chunk, i3 start
-struct ItemU  { int s0, ns, row0, nrows; };         // update: blocks [s0, s0+ns), rows
+// update: rows [row0, row0+nrows) of blocks [s0, s0+ns) (ns > 0, columns
+// individual), or of the -ns blocks of the mode's coupling group (ns < 0)
+struct ItemU  { int s0, ns, row0, nrows; }; 
 struct ItemK2 { int s, col0, chunk, pad; };         // mode-2 contraction: block, column tile start, i1 chunk
 
 // Kernel launchers (defined in the .hip files).

@@ -114,8 +114,9 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     }
     __syncthreads();
     if (tid < 3) {
+        // L_C over the mode's coupling group (every block when L_n = 0)
         double LC = 0.0;
-        for (int b2 = 0; b2 < S; ++b2) LC += lu[tid * S + b2];
+        for (int k = 0; k < g->ngrp[tid]; ++k) LC += lu[tid * S + g->grp[tid][k]];
         st.LC_prev[tid] = LC;
     }
     if (tid != 0) return;

@@ -23,21 +23,27 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
     apply_rot(st);
     extrapolate = extrapolating(c, extrapolate);
     const ItemU it = items[blockIdx.x];
-    const int s0 = it.s0, ns = it.ns, row0 = it.row0, nrows = it.nrows;
-    const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R, Ln = g->L[n];
+    // a coupling-group item (ns < 0) covers the -ns blocks of grp[n]; any other
+    // item covers blocks s0.. with every column individual
+    const bool cg = it.ns < 0;
+    const int s0 = it.s0, ns = cg ? -it.ns : it.ns, row0 = it.row0, nrows = it.nrows;
+    const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R, Ln = cg ? g->L[n] : 0;
+    const int* blk = cg ? g->grp[n] : nullptr;
     const int tid = threadIdx.x;
     extern __shared__ double sm[];
     double* uh = sm;                       // [ns][nrows][R]
     double* gc = uh + ns * nrows * R;      // [ns][nrows][Ln]
     const int tot = ns * nrows * R;
     const double what = c->w_hat, dw = c->delta_w;
-    const double LC = (Ln > 0) ? strided_sum(st.Lu_cur + n * S, 1, S) : 0.0;
+    double LC = 0.0;
+    if (Ln > 0)
+        for (int k = 0; k < ns; ++k) LC += st.Lu_cur[n * S + blk[k]];
     const double wC = (Ln > 0) ? extrap_weight(extrapolate, what, st.LC_prev[n], LC, dw) : 0.0;
 
     // extrapolated point
     for (int e = tid; e < tot; e += 256) {
         const int sl = e / (nrows * R), rem = e % (nrows * R), rr = rem / R, col = rem % R;
-        const int s = s0 + sl;
+        const int s = cg ? blk[sl] : s0 + sl;
         const long long off = g->uoff[n][s] + (long long)(row0 + rr) * Rq + col;
         const double x1 = (double)st.U[1][off], x2 = (double)st.U[2][off];
         const double w = (col < Ln) ? wC : extrap_weight(extrapolate, what, st.Lu_prev[n * S + s], st.Lu_cur[n * S + s], dw);
@@ -47,7 +53,7 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
     // gradient; individual columns are projected here
     for (int e = tid; e < tot; e += 256) {
         const int sl = e / (nrows * R), rem = e % (nrows * R), rr = rem / R, col = rem % R;
-        const int s = s0 + sl, i = row0 + rr;
+        const int s = cg ? blk[sl] : s0 + sl, i = row0 + rr;
         const double* P = st.P + (long long)s * RR;
         const double* u = uh + (sl * nrows + rr) * R;
         // four chains by r mod 4, then the remainder into the first; eight
@@ -85,10 +91,10 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
         const int rr = e / Ln, col = e % Ln, i = row0 + rr;
         double gsum = 0.0;
         for (int sl = 0; sl < ns; ++sl) gsum += gc[(sl * nrows + rr) * Ln + col];
-        const long long off0 = g->uoff[n][s0] + (long long)i * Rq + col;
+        const long long off0 = g->uoff[n][blk[0]] + (long long)i * Rq + col;
         const double un = (LC > 0.0) ? relu_keep_nan(uh[rr * R + col] - gsum / LC) : (double)st.U[1][off0];
         const T ut = (T)un;
-        for (int sl = 0; sl < ns; ++sl) st.U[0][g->uoff[n][s0 + sl] + (long long)i * Rq + col] = ut;
+        for (int sl = 0; sl < ns; ++sl) st.U[0][g->uoff[n][blk[sl]] + (long long)i * Rq + col] = ut;
     }
 }
 

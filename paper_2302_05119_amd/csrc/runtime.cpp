@@ -67,6 +67,15 @@ struct Lists {
     int p1_split;   // wavefronts per pass-1 item (1, 2 or 4)
 };
 
+// Blocks that share mode n's first L_n columns (bit s = block s; 0 when L_n = 0).
+uint64_t group_mask(const concpd_config* c, int n) {
+    if (c->coupled[n] <= 0) return 0;
+    const uint64_t all = c->num_blocks >= 64 ? ~0ull : ((1ull << c->num_blocks) - 1);
+    return c->coupled_blocks ? (c->coupled_blocks[n] & all) : all;
+}
+int first_member(uint64_t m) { return m ? __builtin_ctzll(m) : -1; }
+bool in_group(uint64_t m, int s) { return (m >> s) & 1ull; }
+
 concpd_status validate(const concpd_config* c) {
     if (!c) return fail(CONCPD_EINVAL, "config is NULL");
     if (c->order != 3) return fail(CONCPD_ENOTSUP, "order %d not supported (only 3)", c->order);
@@ -76,13 +85,23 @@ concpd_status validate(const concpd_config* c) {
     for (int n = 0; n < 3; ++n)
         if (c->coupled[n] < 0 || c->coupled[n] > c->rank)
             return fail(CONCPD_EINVAL, "coupled[%d] = %d not in [0, rank]", n, c->coupled[n]);
+    if (c->coupled_blocks) {
+        const uint64_t all = c->num_blocks >= 64 ? ~0ull : ((1ull << c->num_blocks) - 1);
+        for (int n = 0; n < 3; ++n) {
+            if (c->coupled_blocks[n] & ~all) return fail(CONCPD_EINVAL, "coupled_blocks[%d] names blocks >= S", n);
+            if (c->coupled[n] > 0 && !c->coupled_blocks[n])
+                return fail(CONCPD_EINVAL, "coupled_blocks[%d] selects no block for L = %d", n, c->coupled[n]);
+        }
+    }
     for (int s = 0; s < c->num_blocks; ++s)
         for (int n = 0; n < 3; ++n) {
             const int64_t d = c->dims[3 * s + n];
             if (d < 1 || d > (1 << 24)) return fail(CONCPD_EINVAL, "dims[%d] = %lld out of range", 3 * s + n, (long long)d);
-            if (c->coupled[n] > 0 && d != c->dims[n])
+            const uint64_t gm = group_mask(c, n);
+            const int f = first_member(gm);
+            if (in_group(gm, s) && d != c->dims[3 * f + n])
                 return fail(CONCPD_EINVAL, "mode %d is coupled but block %d has I=%lld != %lld", n, s, (long long)d,
-                            (long long)c->dims[n]);
+                            (long long)c->dims[3 * f + n]);
         }
     if (c->tensor_dtype != CONCPD_F64 && c->tensor_dtype != CONCPD_F32)
         return fail(CONCPD_EINVAL, "tensor_dtype must be F64 or F32");
@@ -105,10 +124,13 @@ concpd_status validate(const concpd_config* c) {
                     return fail(CONCPD_ENOTSUP, "lra compression supports I_n <= 512 (block %d mode %d)", s, n);
             }
     if (c->block_ranks) {
-        const int lmax = std::max(std::max(c->coupled[0], c->coupled[1]), std::max(c->coupled[2], 1));
-        for (int s = 0; s < c->num_blocks; ++s)
+        for (int s = 0; s < c->num_blocks; ++s) {
+            int lmax = 1;
+            for (int n = 0; n < 3; ++n)
+                if (in_group(group_mask(c, n), s)) lmax = std::max(lmax, c->coupled[n]);
             if (c->block_ranks[s] < lmax || c->block_ranks[s] > c->rank)
                 return fail(CONCPD_EINVAL, "block_ranks[%d] = %d not in [max(1, L_n), rank]", s, c->block_ranks[s]);
+        }
     }
     if (c->tucker_ranks && c->tensor_dtype != CONCPD_F32)
         return fail(CONCPD_ENOTSUP, "lra compression needs F32 tensors");
@@ -175,12 +197,23 @@ void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAU
         L->u[n].clear();
         int lds_rows = 1;
         if (c->coupled[n] > 0) {
-            const int I = (int)c->dims[n];
-            int nrows = std::max(1, 256 / (S * R));
+            // the coupling group's rows, all its blocks in one item (ns < 0),
+            // then the blocks outside the group with individual columns
+            const uint64_t gm = group_mask(c, n);
+            const int nm = __builtin_popcountll(gm);
+            const int I = (int)c->dims[3 * first_member(gm) + n];
+            int nrows = std::max(1, 256 / (nm * R));
             // LDS: ns * nrows * 2R doubles <= 48 KiB
-            while (nrows > 1 && (size_t)S * nrows * 2 * R * 8 > 49152) --nrows;
-            for (int r0 = 0; r0 < I; r0 += nrows) L->u[n].push_back({0, S, r0, std::min(nrows, I - r0)});
-            lds_rows = S * nrows;
+            while (nrows > 1 && (size_t)nm * nrows * 2 * R * 8 > 49152) --nrows;
+            for (int r0 = 0; r0 < I; r0 += nrows) L->u[n].push_back({0, -nm, r0, std::min(nrows, I - r0)});
+            lds_rows = nm * nrows;
+            const int nri = std::max(1, 256 / R);
+            for (int s = 0; s < S; ++s) {
+                if (in_group(gm, s)) continue;
+                const int Is = (int)c->dims[3 * s + n];
+                for (int r0 = 0; r0 < Is; r0 += nri) L->u[n].push_back({s, 1, r0, std::min(nri, Is - r0)});
+                lds_rows = std::max(lds_rows, nri);
+            }
         } else {
             const int nrows = std::max(1, 256 / R);
             for (int s = 0; s < S; ++s) {
@@ -202,7 +235,13 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     g->S = S;
     g->R = R;
     g->Rq = Rq;
-    for (int n = 0; n < 3; ++n) g->L[n] = c->coupled[n];
+    for (int n = 0; n < 3; ++n) {
+        g->L[n] = c->coupled[n];
+        const uint64_t gm = group_mask(c, n);
+        g->ngrp[n] = 0;
+        for (int s = 0; s < c->num_blocks; ++s)
+            if (c->coupled[n] <= 0 || in_group(gm, s)) g->grp[n][g->ngrp[n]++] = s;
+    }
     g->upd_core = c->update_core;
     g->mdtype = c->compute_dtype;
     g->k2rows = CPD_K2ROWS_DEFAULT;
@@ -374,6 +413,7 @@ struct concpd_ctx_s {
     std::vector<int32_t> tucker;
     int S, R, Rq, L[3];
     std::vector<int> rk;   // R^(s): block s uses columns 0..rk[s]-1, the rest stay zero
+    uint64_t cmask[3];     // the caller's coupling groups (copied)
     bool f64;
     int mdtype;
     std::vector<const void*> tensors;
@@ -634,11 +674,13 @@ void pack_factors(concpd_ctx c, const double* const* U, std::vector<T>& out) {
         for (int s = 0; s < c->S; ++s) {
             const int I = (int)c->dims[3 * s + n];
             const double* src = U[3 * s + n];
-            const double* shared = U[3 * 0 + n];
+            const uint64_t gm = group_mask(&c->cfg, n);
+            const int Ls = in_group(gm, s) ? c->L[n] : 0;
+            const double* shared = Ls ? U[3 * first_member(gm) + n] : src;
             T* dst = out.data() + c->geo.uoff[n][s];
             for (int i = 0; i < I; ++i)
                 for (int r = 0; r < c->rk[s]; ++r)
-                    dst[(size_t)i * c->Rq + r] = (T)(r < c->L[n] ? shared[(size_t)i * c->R + r] : src[(size_t)i * c->R + r]);
+                    dst[(size_t)i * c->Rq + r] = (T)(r < Ls ? shared[(size_t)i * c->R + r] : src[(size_t)i * c->R + r]);
         }
 }
 
@@ -893,6 +935,8 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
     c->R = cfg->rank;
     c->Rq = (c->R + 3) / 4 * 4;
     for (int n = 0; n < 3; ++n) c->L[n] = cfg->coupled[n];
+    for (int n = 0; n < 3; ++n) c->cmask[n] = cfg->coupled_blocks ? cfg->coupled_blocks[n] : ~0ull;
+    c->cfg.coupled_blocks = cfg->coupled_blocks ? c->cmask : nullptr;
     c->rk.assign(c->S, c->R);
     if (cfg->block_ranks) c->rk.assign(cfg->block_ranks, cfg->block_ranks + c->S);
     c->cfg.block_ranks = c->rk.data();
@@ -942,11 +986,14 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
         for (int n = 0; n < 3; ++n)
             for (int s = 0; s < c->S; ++s) {
                 const int I = (int)c->dims[3 * s + n];
+                const uint64_t gm = group_mask(&c->cfg, n);
+                const int f = first_member(gm);
+                const bool copy = in_group(gm, s) && s != f;   // shared columns drawn once, by the first member
                 std::vector<double>& v = hU[3 * s + n];
                 v.assign((size_t)I * c->R, 0.0);
                 for (int i = 0; i < I; ++i)
                     for (int r = 0; r < c->R; ++r) {
-                        if (r < c->L[n] && s > 0) v[(size_t)i * c->R + r] = hU[n][(size_t)i * c->R + r];
+                        if (r < c->L[n] && copy) v[(size_t)i * c->R + r] = hU[3 * f + n][(size_t)i * c->R + r];
                         else v[(size_t)i * c->R + r] = rng.uniform();
                     }
             }
@@ -1365,6 +1412,10 @@ concpd_status concpd_loss_grad(concpd_ctx c, const void* const* U_dev, const voi
                                double* loss, void* const* gU_dev, void* const* glam_dev) {
     if (!c || !U_dev || !lambda_dev || !loss || !gU_dev || !glam_dev) return fail(CONCPD_EINVAL, "NULL argument");
     if (c->lra) return fail(CONCPD_ESTATE, "concpd_loss_grad is not available in lra mode");
+    if (coupled && c->cfg.coupled_blocks)
+        for (int n = 0; n < 3; ++n)
+            if (c->L[n] > 0 && __builtin_popcountll(group_mask(&c->cfg, n)) != c->S)
+                return fail(CONCPD_ENOTSUP, "concpd_loss_grad with coupled = 1 needs every block in every coupling group");
     for (int i = 0; i < 3 * c->S; ++i)
         if (!U_dev[i] || !gU_dev[i]) return fail(CONCPD_EINVAL, "NULL factor pointer %d", i);
     for (int s = 0; s < c->S; ++s)

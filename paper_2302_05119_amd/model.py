@@ -55,11 +55,15 @@ class CoupledCP:
     tucker_ranks optional (J1, J2, J3) or [S][3] for lra_compress.
     block_ranks  optional [S] per-block ranks R^(s) <= rank (Section II-C);
                  factors and lambdas of block s then have R^(s) columns.
+    coupled_blocks optional [3] lists of the blocks that share mode n's
+                 first L_n columns (None entries: every block), the flexible
+                 coupling of Section III-C.
     """
 
     def __init__(self, tensors, rank: int, coupled=(0, 0, 0), compute: str = "f32", init_U=None, init_lambda=None,
                  seed: int = 0, update_core: bool = True, restart: bool = True, delta_w: float = 0.9999,
-                 tol: float = 1e-8, max_it: int = 1000, tucker_ranks=None, block_ranks=None, stream=None):
+                 tol: float = 1e-8, max_it: int = 1000, tucker_ranks=None, block_ranks=None, coupled_blocks=None,
+                 stream=None):
         import torch
 
         self._lib = load()
@@ -102,6 +106,14 @@ class CoupledCP:
             raise ValueError("block_ranks needs one rank per block")
         self._branks_c = (ctypes.c_int32 * S)(*self.block_ranks) if block_ranks is not None else None
         cfg.block_ranks = self._branks_c
+        self._cmask_c = None
+        if coupled_blocks is not None:
+            masks = []
+            for n in range(3):
+                grp = coupled_blocks[n]
+                masks.append((1 << S) - 1 if grp is None else sum(1 << int(b) for b in set(grp)))
+            self._cmask_c = (ctypes.c_uint64 * 3)(*masks)
+        cfg.coupled_blocks = self._cmask_c
         self.cfg = cfg
         self.compute = compute
         nbytes = ctypes.c_size_t()

@@ -71,12 +71,17 @@ class Problem:
         return len(self.dims)
 
 
-def coupled_problem(dims, R, L, snr_db, seed, dtype=np.float32, factor_draw=None) -> Problem:
+def coupled_problem(dims, R, L, snr_db, seed, dtype=np.float32, factor_draw=None, block_ranks=None,
+                    block_lam=None, noise="gaussian") -> Problem:
     """Blocks M^(s) = [[U^(1,s), U^(2,s), U^(3,s)]] (lambda = 1) plus noise.
 
     ``dims`` is a list of S (I1, I2, I3); a mode with L_n > 0 must have the same
     size in every block.  Factors are U[0,1] unless ``factor_draw(rng, n, s_or_None,
-    rows, cols)`` is given.
+    rows, cols)`` is given.  ``block_ranks`` (R^(s) <= R) keeps only the first
+    R^(s) components of block s; ``block_lam`` = (lo, hi) draws per-block
+    component weights U[lo, hi] (kept in ``meta['lam']``).  ``noise`` is
+    "gaussian" (energy SNR of ``snr_db``) or "salt_pepper" (the block scaled to
+    [0, 1], then a fraction ``snr_db`` of its entries set to 0 or 1).
     """
     rng = rng_for(seed)
     S = len(dims)
@@ -93,12 +98,34 @@ def coupled_problem(dims, R, L, snr_db, seed, dtype=np.float32, factor_draw=None
             truth.append(_shared_columns(rng, S, sizes[0], R, L[n], draw))
         else:
             truth.append([draw(rng, sizes[s], R) for s in range(S)])
+    meta = {}
+    if block_ranks is not None:
+        truth = [[u.copy() for u in per] for per in truth]
+        for s, r in enumerate(block_ranks):
+            for n in range(3):
+                truth[n][s][:, r:] = 0.0
+        meta["block_ranks"] = [int(r) for r in block_ranks]
+    lams = None
+    if block_lam is not None:
+        lams = [rng.uniform(block_lam[0], block_lam[1], size=R) for _ in range(S)]
+        meta["lam"] = lams
     tensors = []
     for s in range(S):
-        X = cp_tensor([truth[n][s] for n in range(3)])
-        X = add_noise(rng, X, snr_db)
+        X = cp_tensor([truth[n][s] for n in range(3)], None if lams is None else lams[s])
+        if noise == "salt_pepper":
+            X = salt_pepper(rng, X / np.max(X), snr_db)
+        else:
+            X = add_noise(rng, X, snr_db)
         tensors.append(np.ascontiguousarray(X.astype(dtype)))
-    return Problem(list(map(tuple, dims)), R, tuple(L), tensors, truth, snr_db)
+    return Problem(list(map(tuple, dims)), R, tuple(L), tensors, truth, snr_db, meta=meta)
+
+
+def salt_pepper(rng, X: np.ndarray, frac: float) -> np.ndarray:
+    """A fraction ``frac`` of the entries set to 0 or 1 (equally likely)."""
+    X = X.copy()
+    hit = rng.random(X.shape) < frac
+    X[hit] = (rng.random(int(hit.sum())) < 0.5).astype(np.float64)
+    return X
 
 
 def eeg_problem(S, T_range, R, snr_db, seed, channels=64, freqs=60, dtype=np.float32) -> Problem:
@@ -173,6 +200,16 @@ WORKLOADS = {
                                      iters=200, dtype="bf16", seed=1004),
     "c5_lra_4x512cube_r40": dict(dims=[(512, 512, 512)] * 4, R=40, L=(40, 0, 0), snr=15.0,
                                  iters=500, dtype="f32", seed=1005, tucker=(40, 40, 40)),
+    # face-image-shaped (Section IV, Experiment 2): 31 subjects of 32 x 32 pixels x
+    # 64 illuminations, per-subject ranks 22..26, 15 components coupled in the two
+    # pixel modes, salt-and-pepper noise on the [0, 1]-scaled blocks
+    "face_31x32x32x64_r22to26": dict(dims=[(32, 32, 64)] * 31, R=26, L=(15, 15, 0), snr=0.1,
+                                     noise="salt_pepper", rank_range=(22, 26), iters=200, dtype="f32", seed=1006),
+    # ERP-shaped (Section IV, Experiment 3): 42 subjects of 9 channels x 71
+    # frequency bins x 60 time points, R = 36 coupled in every mode; the blocks
+    # differ only through their core weights (drawn U[0.5, 1.5] per component)
+    "erp_42x9x71x60_r36_full": dict(dims=[(9, 71, 60)] * 42, R=36, L=(36, 36, 36), snr=10.0,
+                                    block_lam=(0.5, 1.5), iters=200, dtype="f32", seed=1007),
 }
 
 
@@ -182,9 +219,21 @@ def make_workload(name: str, dtype=None) -> Problem:
         return eeg_problem(w["S"], w["T_range"], w["R"], w["snr"], w["seed"],
                            dtype=dtype or np.float32)
     store = dtype or (np.float64 if w["dtype"] == "f64" else np.float32)
-    return coupled_problem(w["dims"], w["R"], w["L"], w["snr"], w["seed"], dtype=store)
+    ranks = None
+    if "rank_range" in w:
+        lo, hi = w["rank_range"]
+        ranks = rng_for(w["seed"] + 500).integers(lo, hi + 1, size=len(w["dims"])).tolist()
+    return coupled_problem(w["dims"], w["R"], w["L"], w["snr"], w["seed"], dtype=store, block_ranks=ranks,
+                           block_lam=w.get("block_lam"), noise=w.get("noise", "gaussian"))
 
 
 def workload_init(name: str, problem: Problem):
+    """U[0,1] start [n][s] and lambda [s]; with per-block ranks, block s keeps
+    its first R^(s) columns."""
     w = WORKLOADS[name]
-    return uniform_init(problem.dims, problem.R, problem.L, w["seed"] + 1000)
+    U, lam = uniform_init(problem.dims, problem.R, problem.L, w["seed"] + 1000)
+    ranks = problem.meta.get("block_ranks")
+    if ranks is not None:
+        U = [[u[:, :ranks[s]].copy() for s, u in enumerate(per)] for per in U]
+        lam = [l[:ranks[s]].copy() for s, l in enumerate(lam)]
+    return U, lam

@@ -94,6 +94,26 @@ def test_block_ranks_validated(lib, ranks, expect):
     assert st == expect, lib.concpd_last_error()
 
 
+@pytest.mark.parametrize("masks,expect", [((0b11, 0, 0), 0), ((0b01, 0, 0), 0), ((0, 0, 0), 1), ((0b111, 0, 0), 1)])
+def test_coupled_blocks_validated(lib, masks, expect):
+    # S = 2, L = (3, 0, 0): a coupled mode needs a non-empty group of existing blocks
+    c = _cfg(S=2, R=6, L=(3, 0, 0))
+    arr = (ctypes.c_uint64 * 3)(*masks)
+    c.coupled_blocks = ctypes.cast(arr, ctypes.POINTER(ctypes.c_uint64))
+    st, _ = query(lib, c)
+    assert st == expect, lib.concpd_last_error()
+
+
+def test_coupled_blocks_allow_other_sizes_outside_the_group(lib):
+    c = _cfg(S=2, R=6, L=(3, 0, 0), dims=[(10, 11, 12), (9, 11, 12)])
+    st, _ = query(lib, c)
+    assert st == 1                      # every block coupled: I_1 must agree
+    arr = (ctypes.c_uint64 * 3)(0b01, 0, 0)
+    c.coupled_blocks = ctypes.cast(arr, ctypes.POINTER(ctypes.c_uint64))
+    st, _ = query(lib, c)
+    assert st == 0, lib.concpd_last_error()
+
+
 def test_order_other_than_three_not_supported(lib):
     c = _cfg()
     c.order = 4

@@ -6,6 +6,9 @@ ABI against the FP64 oracle:
 * Uneven ranks R^(s) per block (the model of Section II-C): the library embeds
   block s at the common R with zero columns and lambda_r = 0; the oracle runs
   every block at its own rank, without padding.
+* Flexible coupling (Section III-C): a mode's shared columns tied only across
+  a listed group of blocks; the others keep every column individual (and may
+  differ in that mode's size).
 
 Tolerances as in the main parity tests: 1e-5 normwise for FP32 operands,
 1e-10 for FP64 (1e-8 for factors after a 50-iteration FP64 trajectory).
@@ -210,3 +213,99 @@ def test_uneven_ranks_padding_input_is_ignored(dev):
         np.testing.assert_array_equal(a.lam(s), b.lam(s))
         for n in range(3):
             np.testing.assert_array_equal(a.factor(n, s), b.factor(n, s))
+
+
+# ---------------------------------------------------------------------------
+# flexible coupling (Section III-C): coupling on specific blocks only
+# ---------------------------------------------------------------------------
+
+GROUPS = ((0, 2, 3), None, (1, 2))      # mode 1: blocks 0, 2, 3; mode 3: blocks 1, 2
+
+
+def group_init(P, R, L, groups, seed):
+    """U[0,1] start whose shared columns agree inside each group only."""
+    rng = np.random.default_rng(seed)
+    U = [[rng.random((d[n], R)) for d in P.dims] for n in range(3)]
+    for n in range(3):
+        if L[n]:
+            grp = range(P.S) if groups[n] is None else sorted(groups[n])
+            grp = list(grp)
+            for s in grp[1:]:
+                U[n][s][:, :L[n]] = U[n][grp[0]][:, :L[n]]
+    lam = [rng.random(R) for _ in range(P.S)]
+    return U, lam
+
+
+def group_problem(dtype):
+    # block 1 is outside mode 1's group, so its I_1 may differ
+    dims = [(17, 40, 30), (11, 45, 30), (17, 33, 30), (17, 40, 26)]
+    return synth.coupled_problem(dims, 6, (0, 0, 0), 10.0, 261, dtype=dtype)
+
+
+@pytest.mark.parametrize("compute,tol", [("f32", 1e-5), ("f64", 1e-10)])
+@pytest.mark.parametrize("k_before", [0, 3])
+def test_flexible_coupling_one_iteration_teacher_forced(dev, compute, tol, k_before):
+    say(f"[flex] teacher-forced compute={compute} k_before={k_before}")
+    dtype = np.float64 if compute == "f64" else np.float32
+    L = (3, 0, 2)
+    P = group_problem(dtype)
+    P.L = L
+    U0, lam0 = group_init(P, 6, L, GROUPS, 262)
+    opt = Options(L=L, coupled_blocks=GROUPS)
+    m, st, new, s1 = forced_step(dev, P, U0, lam0, compute, k_before, opt, 6, coupled_blocks=GROUPS)
+    say(f"   F gpu={s1['F']:.12e} oracle={new.F:.12e}")
+    assert bool(s1["restarted_last"]) == bool(new.last_restarted)
+    assert abs(s1["F"] - new.F) / new.F <= tol
+    Ld, Lu, LC = m.lipschitz()
+    ltol = 1e-6 if compute == "f32" else 1e-11
+    np.testing.assert_allclose(LC, new.LC_prev, rtol=ltol)
+    for s in range(P.S):
+        np.testing.assert_allclose(Lu[s], [new.Lu_prev[n][s] for n in range(3)], rtol=ltol)
+        assert rel(m.lam(s), new.lam[s]) <= tol
+        for n in range(3):
+            e = rel(m.factor(n, s), new.U[n][s])
+            assert e <= tol, (n, s, e)
+    # members share their columns bit for bit; the others are free
+    for n, grp in ((0, GROUPS[0]), (2, GROUPS[2])):
+        ref = m.factor(n, grp[0])[:, :L[n]]
+        for s in grp[1:]:
+            np.testing.assert_array_equal(m.factor(n, s)[:, :L[n]], ref)
+    assert not np.array_equal(m.factor(2, 0)[:, :2], m.factor(2, 1)[:, :2])
+
+
+def test_flexible_coupling_fp64_trajectory(dev):
+    say("[flex] fp64 trajectory")
+    L = (3, 0, 2)
+    P = group_problem(np.float64)
+    P.L = L
+    U0, lam0 = group_init(P, 6, L, GROUPS, 272)
+    m = make_model(P, U0, lam0, dev, "f64", R=6, coupled_blocks=GROUPS)
+    ref = apg.run(DenseData(P.tensors), U0, lam0, Options(L=L, coupled_blocks=GROUPS), iters=40)
+    s = m.step(40)
+    say(f"   F gpu={s['F']:.15e} oracle={ref.F:.15e} restarts gpu={s['restarts']} oracle={ref.restarts}")
+    assert s["restarts"] == ref.restarts
+    assert abs(s["F"] - ref.F) / ref.F <= 1e-10
+    for b in range(P.S):
+        assert rel(m.lam(b), ref.lam[b]) <= 1e-8
+        for n in range(3):
+            assert rel(m.factor(n, b), ref.U[n][b]) <= 1e-8
+
+
+def test_flexible_coupling_seeded_init_and_rejections(dev):
+    import torch
+    from paper_2302_05119_amd import ConcpdError, CoupledCP
+    say("[flex] seeded init, rejections")
+    P = group_problem(np.float32)
+    tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
+    m = CoupledCP(tens, 6, (3, 0, 2), seed=4, coupled_blocks=GROUPS)
+    for n, grp in ((0, GROUPS[0]), (2, GROUPS[2])):
+        L = (3, 0, 2)[n]
+        for s in grp[1:]:
+            np.testing.assert_array_equal(m.factor(n, s)[:, :L], m.factor(n, grp[0])[:, :L])
+    assert not np.array_equal(m.factor(2, 0)[:, :2], m.factor(2, 1)[:, :2])   # block 0 is outside mode 3's group
+    with pytest.raises(ConcpdError):
+        CoupledCP(tens, 6, (3, 0, 0))                               # block 1's I_1 differs
+    with pytest.raises(ConcpdError):
+        CoupledCP(tens, 6, (3, 0, 0), coupled_blocks=((), None, None))  # empty group
+    with pytest.raises(ConcpdError):
+        CoupledCP(tens, 6, (3, 0, 0), coupled_blocks=((0, 1), None, None))  # unequal I_1 inside the group
