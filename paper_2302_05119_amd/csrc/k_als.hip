@@ -14,7 +14,10 @@
 //
 //   ||M - X~||^2 = ||M||^2 - 2 <K_3, U~^(3)> + 1^T (⊛_m U~^(m)T U~^(m)) 1.
 //
-// Blocks stop independently: a block whose flag is 0 is skipped.
+// Blocks stop independently: a block whose flag is 0 is skipped.  K_3's chunk
+// partials are summed once into the K3 buffer (wide launch) before the mode-3
+// solve and the fit read it: a lane summing 100+ partials per entry itself
+// would wait on each group of loads in turn.
 #include "ksource.h"
 
 namespace cpd {
@@ -133,7 +136,12 @@ __global__ __launch_bounds__(64) void k_als_solve(const Geo* __restrict__ g, Sta
     for (int e = lane; e < R * R; e += 64) L[e] = Lg[e];
     const int i = row0 + lane;
     const int ic = min(i, I - 1);
-    for (int c = 0; c < R; ++c) x[c * 64 + lane] = k_value<T, KSRC>(g, st, s, ic, c);
+    if (KSRC == KSRC_PART) {
+        const T* K3 = st.K3 + g->koff[s] + (long long)ic * Rq;
+        for (int c = 0; c < R; ++c) x[c * 64 + lane] = (double)K3[c];
+    } else {
+        for (int c = 0; c < R; ++c) x[c * 64 + lane] = k_value<T, KSRC>(g, st, s, ic, c);
+    }
     __syncthreads();
     for (int j = 0; j < R; ++j) {
         double v = x[j * 64 + lane];
@@ -151,8 +159,9 @@ __global__ __launch_bounds__(64) void k_als_solve(const Geo* __restrict__ g, Sta
     }
 }
 
-// RelErr of every active block after its mode-3 update (K_3 from pass 2 on
-// the new U~^(1), U~^(2)); xx[s] = ||X~||^2.  Fixed-order tree reductions.
+// RelErr of every active block after its mode-3 update (K_3, summed into the
+// K3 buffer from pass 2 on the new U~^(1), U~^(2)); xx[s] = ||X~||^2.
+// Fixed-order tree reductions.
 template <typename T>
 __global__ __launch_bounds__(256) void k_als_fit(const Geo* __restrict__ g, StateP<T> st, const int* __restrict__ act,
                                                  double* __restrict__ relerr, double* __restrict__ xx) {
@@ -165,10 +174,12 @@ __global__ __launch_bounds__(256) void k_als_fit(const Geo* __restrict__ g, Stat
     __shared__ double red[2][256];
     const int I3 = g->I[s][2];
     const T* U3 = st.U[1] + g->uoff[2][s];
+    const T* K3 = st.K3 + g->koff[s];
     double ip = 0.0;
     for (long long e = tid; e < (long long)I3 * R; e += 256) {
-        const int i = (int)(e / R), c = (int)(e % R);
-        ip = fma(k_value<T, KSRC_PART>(g, st, s, i, c), (double)U3[(long long)i * Rq + c], ip);
+        const long long i = e / R;
+        const int c = (int)(e % R);
+        ip = fma((double)K3[i * Rq + c], (double)U3[i * Rq + c], ip);
     }
     als_hadamard_gram<T>(g, st, s, -1, R, H, stage);
     double hs = 0.0;

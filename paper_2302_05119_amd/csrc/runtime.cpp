@@ -849,8 +849,14 @@ concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, double eps, int max
     std::vector<double> prev(S), cur(S);
     HIPCHECK(hipMemcpyAsync(act, hact.data(), sizeof(int) * S, hipMemcpyHostToDevice, c->q));
     HIPCHECK(hipMemcpyAsync(bad, hbad.data(), sizeof(int) * S, hipMemcpyHostToDevice, c->q));
+    // K_3 = the pass-2 chunk partials summed into the K3 buffer, per block
+    auto k3_sum = [&]() {
+        for (int s = 0; s < S; ++s)
+            cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], R, st.K3 + c->geo.koff[s], c->Rq, 0, c->q);
+    };
     // RelErr_0 at the starting point
     debug_passes<T>(c, st);
+    k3_sum();
     cpd::launch_als_fit<T>(c->dgeo, st, S, R, act, rel, xx, c->q);
     HIPCHECK(hipMemcpyAsync(prev.data(), rel, sizeof(double) * S, hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipStreamSynchronize(c->q));
@@ -871,6 +877,7 @@ concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, double eps, int max
         cpd::launch_als_chol<T>(c->dgeo, st, S, R, 1, act, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 1, Imax[1], act, Lfac, c->q);
         cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
+        k3_sum();
         cpd::launch_als_chol<T>(c->dgeo, st, S, R, 2, act, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 2, Imax[2], act, Lfac, c->q);
         cpd::launch_als_fit<T>(c->dgeo, st, S, R, act, rel, xx, c->q);

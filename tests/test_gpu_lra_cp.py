@@ -192,3 +192,36 @@ def test_rejections(dev):
     m.lra_compress_cp()
     with pytest.raises(ConcpdError):
         m.lra_compress_cp()                                                  # already compressed
+
+
+def test_full_size_c5_cp_compression_and_fit(dev):
+    # 4 blocks of 512^3, R = 40, 15 dB, the launch configuration the benchmark
+    # times: properties that hold at any size.  The reported RelErr of block 0
+    # equals the direct one of its returned factors (X~_(1) = A_1 (A_3 ⊙ A_2)^T
+    # by a BLAS product); every block's fit stops near the noise level; the
+    # lra iterations on the Kruskal form reach the noise level too.
+    say("[cp-als c5 full] 4 x 512^3 compression and 200 lra iterations")
+    name = "c5_lra_4x512cube_r40"
+    w = synth.WORKLOADS[name]
+    P = synth.make_workload(name)
+    U0, lam0 = synth.workload_init(name, P)
+    m = make_model(P, dev, w["R"], w["L"], U0=U0, lam0=lam0, tucker=w["tucker"])
+    out = m.lra_compress_cp(eps=1e-4, max_it=200, seed=w["seed"] + 3000)
+    rho = 10 ** (-w["snr"] / 20)
+    noise_rel = rho / np.sqrt(1 + rho * rho)
+    say(f"   ALS iterations {out['als_iters']} RelErr {out['als_relerr']} (noise level {noise_rel:.5f})")
+    assert all(1 <= k < 200 for k in out["als_iters"])
+    assert all(abs(r - noise_rel) < 5e-3 for r in out["als_relerr"])
+    A, G = m.tucker(0)
+    kr = (A[2][:, None, :] * A[1][None, :, :]).reshape(-1, w["R"])     # row index i3 * I2 + i2
+    X0 = P.tensors[0].astype(np.float64)
+    Xu = X0.transpose(0, 2, 1).reshape(X0.shape[0], -1)                 # column index i3 * I2 + i2
+    direct = np.linalg.norm(Xu - A[0] @ kr.T) / np.linalg.norm(Xu)
+    del Xu, X0, kr
+    say(f"   block 0: reported {out['als_relerr'][0]:.8f} direct {direct:.8f}")
+    assert abs(out["als_relerr"][0] - direct) <= 1e-6
+    st = m.lra_step(200)
+    gf = m.global_fit()
+    say(f"   k={st['k']} restarts={st['restarts']} fit(X~)={st['fit']:.5f} global fit={gf:.5f}")
+    assert st["k"] == 200 and not st["nonfinite"]
+    assert 0.80 <= gf <= 0.85
