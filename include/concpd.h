@@ -278,7 +278,9 @@ concpd_status concpd_profile_read(concpd_ctx ctx, double* ms_pass1, double* ms_p
  *                            taken on the device, so a sweep is a fixed kernel
  *                            sequence); 0 (default): direct kernel launches.
  *   CONCPD_OPT_OVERLAP       1: the small FP64 kernels run on a second stream
- *                            beside the MTTKRP passes (default 0).
+ *                            beside the MTTKRP passes (default 0); with graph
+ *                            sweeps the two streams become parallel branches
+ *                            of the captured graph.
  *   CONCPD_OPT_K2_ROWS       i1 rows per workgroup of the mode-2 contraction
  *                            (8..64, default 16).
  *   CONCPD_OPT_P1_SPLIT      wavefronts that share one 64-row item of pass 1
@@ -311,13 +313,15 @@ typedef struct concpd_tuning {
     int32_t candidates;           /* configurations timed */
     int32_t p1_split;             /* chosen CONCPD_OPT_P1_SPLIT (the split in use) */
     int32_t p1_dma;               /* chosen CONCPD_OPT_P1_DMA */
+    int32_t overlap;              /* chosen CONCPD_OPT_OVERLAP */
 } concpd_tuning;
 
 /* Autotuner: times `sweeps` sweeps (HIP events on the context stream) of
  * candidate launch configurations from the same iterate, restoring the
  * iterate after each, and keeps the fastest: first the pass-1 split 1/2/4
  * (x DMA off/on where possible; dense path), then mode-2 chunk rows 8/16/32 x
- * graph sweeps 0/1/4.  The iterate is unchanged on return.  Synchronises.
+ * graph sweeps 0/1/4, then (dense path) the second-stream overlap inside
+ * graphs of 1 and 4 sweeps.  The iterate is unchanged on return.  Synchronises.
  * Errors: EINVAL (sweeps not in [1, 10000]), ESTATE (converged iterate), EHIP. */
 concpd_status concpd_autotune(concpd_ctx ctx, int32_t sweeps, concpd_tuning* out);
 

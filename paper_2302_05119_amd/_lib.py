@@ -62,6 +62,7 @@ class Tuning(ctypes.Structure):
         ("candidates", ctypes.c_int32),
         ("p1_split", ctypes.c_int32),
         ("p1_dma", ctypes.c_int32),
+        ("overlap", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -432,8 +432,10 @@ struct concpd_ctx_s {
     int profiling;
     // CONCPD_OVERLAP=1 runs the small FP64 kernels (core update, step
     // matrices) on a second stream beside the MTTKRP passes they do not depend
-    // on.  Off by default: the cross-stream event waits cost more than the
-    // overlap gains at the benchmark sizes.
+    // on.  Off by default: with direct launches the cross-stream event waits
+    // cost more than the overlap gains; inside a captured graph they are graph
+    // edges, and the autotuner tries that (measured: 8 % faster sweeps on the
+    // EEG-shaped blocks, neutral on the cubes).
     int overlap;
     hipStream_t q2;
     hipEvent_t fj[6];
@@ -586,7 +588,7 @@ void run_one_sweep(concpd_ctx c, const StateP<T>& st) {
 concpd_status launch_sweeps(concpd_ctx c, long long count) {
     const int gs = c->graph_sweeps;
     long long direct = count;
-    if (gs > 0 && !c->profiling && !c->overlap && count >= gs) {
+    if (gs > 0 && !c->profiling && count >= gs) {
         if (!c->gexec) {
             if (!c->qcap) HIPCHECK(hipStreamCreateWithFlags(&c->qcap, hipStreamNonBlocking));
             hipStream_t q = c->q;
@@ -1508,6 +1510,7 @@ concpd_status concpd_set_option(concpd_ctx c, int32_t option, int64_t value) {
             HIPCHECK(hipStreamCreateWithFlags(&c->q2, hipStreamNonBlocking));
             for (int i = 0; i < 6; ++i) HIPCHECK(hipEventCreateWithFlags(&c->fj[i], hipEventDisableTiming));
         }
+        if ((value != 0) != (c->overlap != 0)) c->drop_graph();
         c->overlap = value != 0;
         return CONCPD_OK;
     case CONCPD_OPT_P1_DMA:
@@ -1581,9 +1584,11 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
     };
     concpd_status r = snapshot();
     if (r != CONCPD_OK) return r;
-    const int prof = c->profiling, ov = c->overlap;
+    const int prof = c->profiling;
     c->profiling = 0;
-    c->overlap = 0;
+    r = concpd_set_option(c, CONCPD_OPT_OVERLAP, 0);
+    if (r != CONCPD_OK) return r;
+    int bo = 0;
     const int k2c[3] = {8, 16, 32};
     const int gsc[3] = {0, 1, 4};
     hipEvent_t e0, e1;
@@ -1653,10 +1658,28 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
         }
         if (r != CONCPD_OK) break;
     }
+    // the small kernels on a second stream beside the passes, as branches of
+    // the captured graph (dense path; measured: faster for the EEG-shaped
+    // blocks, even for cubes)
+    if (!c->lra && r == CONCPD_OK) {
+        r = concpd_set_option(c, CONCPD_OPT_K2_ROWS, bk);
+        if (r == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_OVERLAP, 1);
+        for (int gi = 1; gi < 3 && r == CONCPD_OK; ++gi) {
+            r = concpd_set_option(c, CONCPD_OPT_GRAPH_SWEEPS, gsc[gi]);
+            if (r != CONCPD_OK) break;
+            double us = 0.0;
+            if ((r = time_sweeps(us)) != CONCPD_OK) break;
+            if (us < best) {
+                best = us;
+                bg = gsc[gi];
+                bo = 1;
+            }
+        }
+        if (r == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_OVERLAP, bo);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->profiling = prof;
-    c->overlap = ov;
     if (r != CONCPD_OK) return r;
     if (!c->lra) {
         r = concpd_set_option(c, CONCPD_OPT_K2_ROWS, bk);
@@ -1672,6 +1695,7 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
         out->p1_split = c->lists.p1_split;
         out->p1_dma = c->p1dma;
         out->graph_sweeps = bg;
+        out->overlap = bo;
         out->us_per_sweep = best;
         out->us_per_sweep_default = dflt;
         out->candidates = ncand;

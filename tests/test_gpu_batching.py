@@ -44,17 +44,20 @@ def factors(m):
     return [m.factor(n, s) for n in range(3) for s in range(m.S)]
 
 
-@pytest.mark.parametrize("gs", [1, 4])
-def test_graph_replay_matches_eager(gs):
+@pytest.mark.parametrize("gs,overlap", [(1, 0), (4, 0), (1, 1), (4, 1)])
+def test_graph_replay_matches_eager(gs, overlap):
+    # overlap = 1: the small kernels on the second stream, captured as parallel
+    # branches of the graph
     import torch
-    say(f"[graph] sweeps per graph = {gs}")
+    say(f"[graph] sweeps per graph = {gs}, overlap = {overlap}")
     L = (2, 0, 0)
     P = synth.coupled_problem([(24, 40, 33), (24, 17, 50), (24, 29, 8)], 6, L, 10.0, 801)
     U0, lam0 = synth.uniform_init(P.dims, 6, L, 802)
     me = model(P, U0, lam0)
     mg = model(P, U0, lam0)
+    mg.set_option("overlap", overlap)
     mg.set_option("graph_sweeps", gs)
-    assert mg.get_option("graph_sweeps") == gs
+    assert mg.get_option("graph_sweeps") == gs and mg.get_option("overlap") == overlap
     scratch = torch.zeros(1 << 20, device="cuda:0")
     for rep in range(5):
         se = me.step(gs)
@@ -164,7 +167,9 @@ def test_autotune_keeps_the_iterate():
     t = m.autotune(8)
     say(f"   {t}")
     # 60-value FP32 rows are 16-byte aligned: the pass-1 DMA path is a candidate
-    assert t["candidates"] == 15 and t["k2_rows"] in (8, 16, 32) and t["graph_sweeps"] in (0, 1, 4)
+    assert t["candidates"] == 17 and t["k2_rows"] in (8, 16, 32) and t["graph_sweeps"] in (0, 1, 4)
+    assert t["overlap"] in (0, 1) and m.get_option("overlap") == t["overlap"]
+    assert t["overlap"] == 0 or t["graph_sweeps"] > 0
     assert t["p1_split"] in (1, 2, 4) and m.get_option("p1_split") == t["p1_split"]
     assert t["p1_dma"] in (0, 1) and m.get_option("p1_dma") == t["p1_dma"]
     assert t["us_per_sweep"] <= t["us_per_sweep_default"]
