@@ -9,8 +9,10 @@
 // the iterate's current slot while the fit runs), in the same dimension-tree
 // order: pass 1 gives K_1 and Y = M x_3 U~^(3); K_2 = Y contracted with the
 // new U~^(1); pass 2 gives K_3 from the new U~^(1), U~^(2).  The kernels here
-// form H_n and its Cholesky factor (FP64, one workgroup per block), solve the
-// I_n right-hand sides (one lane per row), and evaluate RelErr through
+// keep the Gram V_m = U~^(m)T U~^(m) of every factor (FP64, refreshed after
+// each solve), form H_n from two of them and its Cholesky factor (one
+// workgroup per block), solve the I_n right-hand sides (one lane per row), and
+// evaluate RelErr through
 //
 //   ||M - X~||^2 = ||M||^2 - 2 <K_3, U~^(3)> + 1^T (⊛_m U~^(m)T U~^(m)) 1.
 //
@@ -22,72 +24,69 @@
 
 namespace cpd {
 
-// Hadamard product of the Grams of the modes other than `skip` (skip = -1:
-// all three), R x R FP64, written to H (LDS).  Thread t owns the pairs
-// e = t + 256 j; rows of each factor are staged 32 at a time in LDS.
+// V_n = U~^(n)T U~^(n) (R x R, FP64) of every active block, at V + (3 s + n) R^2.
+// Thread t owns the pairs e = t + 256 j; rows are staged 32 at a time in LDS.
 template <typename T>
-__device__ void als_hadamard_gram(const Geo* __restrict__ g, const StateP<T>& st, int s, int skip, int R, double* H,
-                                  double* stage) {
+__global__ __launch_bounds__(256) void k_als_gram(const Geo* __restrict__ g, StateP<T> st, int n,
+                                                  const int* __restrict__ act, double* __restrict__ V) {
+    apply_rot(st);
     constexpr int CH = 32;
-    const int tid = threadIdx.x, Rq = g->Rq;
+    const int s = blockIdx.x, R = g->R, Rq = g->Rq, tid = threadIdx.x;
+    if (!act[s]) return;
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
+    double* stage = (double*)smraw;        // 32 x R
     const int npair = R * R;
-    double h[16];
+    const int I = g->I[s][n];
+    const T* U = st.U[1] + g->uoff[n][s];
+    double acc[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) h[j] = 1.0;
-    for (int m = 0; m < 3; ++m) {
-        if (m == skip) continue;
-        const int I = g->I[s][m];
-        const T* U = st.U[1] + g->uoff[m][s];
-        double acc[16];
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    for (int i0 = 0; i0 < I; i0 += CH) {
+        const int nr = min(CH, I - i0);
+        __syncthreads();
+        for (int e = tid; e < CH * R; e += 256) {
+            const int rr = e / R, c = e % R;
+            stage[e] = rr < nr ? (double)U[(long long)(i0 + rr) * Rq + c] : 0.0;
+        }
+        __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-        for (int i0 = 0; i0 < I; i0 += CH) {
-            const int nr = min(CH, I - i0);
-            __syncthreads();
-            for (int e = tid; e < CH * R; e += 256) {
-                const int rr = e / R, c = e % R;
-                stage[e] = rr < nr ? (double)U[(long long)(i0 + rr) * Rq + c] : 0.0;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int e = tid + 256 * j;
-                if (e < npair) {
-                    const int a = e / R, b = e % R;
-                    double v = acc[j];
-                    for (int rr = 0; rr < nr; ++rr) v = fma(stage[rr * R + a], stage[rr * R + b], v);
-                    acc[j] = v;
-                }
+        for (int j = 0; j < 16; ++j) {
+            const int e = tid + 256 * j;
+            if (e < npair) {
+                const int a = e / R, b = e % R;
+                double v = acc[j];
+                for (int rr = 0; rr < nr; ++rr) v = fma(stage[rr * R + a], stage[rr * R + b], v);
+                acc[j] = v;
             }
         }
-#pragma unroll
-        for (int j = 0; j < 16; ++j) h[j] *= acc[j];
     }
+    double* out = V + (3LL * s + n) * npair;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int e = tid + 256 * j;
-        if (e < npair) H[e] = h[j];
+        if (e < npair) out[e] = acc[j];
     }
-    __syncthreads();
 }
 
-// H_n and its Cholesky factor L (lower, row-major R x R) for every active
-// block; bad[s] = 1 if a pivot falls below 1e-13 of its starting diagonal
-// entry or is not finite (H_n numerically singular).
-template <typename T>
-__global__ __launch_bounds__(256) void k_als_chol(const Geo* __restrict__ g, StateP<T> st, int n,
-                                                  const int* __restrict__ act, double* __restrict__ Lout,
+// H_n = V_a ⊛ V_b (the kept Grams of the other two modes) and its Cholesky
+// factor L (lower, row-major R x R) for every active block; bad[s] = 1 if a
+// pivot falls below 1e-13 of its starting diagonal entry or is not finite
+// (H_n numerically singular).
+__global__ __launch_bounds__(256) void k_als_chol(const Geo* __restrict__ g, int n, const int* __restrict__ act,
+                                                  const double* __restrict__ V, double* __restrict__ Lout,
                                                   int* __restrict__ bad) {
-    apply_rot(st);
     const int s = blockIdx.x, R = g->R, tid = threadIdx.x;
     if (!act[s]) return;
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     double* H = (double*)smraw;            // R x R
-    double* stage = H + R * R;             // 32 x R
     __shared__ int flag;
     __shared__ double diag[CPD_MAXR];
     if (tid == 0) flag = 0;
-    als_hadamard_gram<T>(g, st, s, n, R, H, stage);
+    const int a = n == 0 ? 1 : 0, b = n == 2 ? 1 : 2;
+    const double* Va = V + (3LL * s + a) * R * R;
+    const double* Vb = V + (3LL * s + b) * R * R;
+    for (int e = tid; e < R * R; e += 256) H[e] = Va[e] * Vb[e];
+    __syncthreads();
     for (int j = tid; j < R; j += 256) diag[j] = H[j * R + j];
     __syncthreads();
     // right-looking Cholesky in place (lower triangle); a pivot below 1e-13 of
@@ -164,13 +163,11 @@ __global__ __launch_bounds__(64) void k_als_solve(const Geo* __restrict__ g, Sta
 // Fixed-order tree reductions.
 template <typename T>
 __global__ __launch_bounds__(256) void k_als_fit(const Geo* __restrict__ g, StateP<T> st, const int* __restrict__ act,
-                                                 double* __restrict__ relerr, double* __restrict__ xx) {
+                                                 const double* __restrict__ V, double* __restrict__ relerr,
+                                                 double* __restrict__ xx) {
     apply_rot(st);
     const int s = blockIdx.x, R = g->R, Rq = g->Rq, tid = threadIdx.x;
     if (!act[s]) return;
-    extern __shared__ __attribute__((aligned(16))) char smraw[];
-    double* H = (double*)smraw;
-    double* stage = H + R * R;
     __shared__ double red[2][256];
     const int I3 = g->I[s][2];
     const T* U3 = st.U[1] + g->uoff[2][s];
@@ -181,9 +178,11 @@ __global__ __launch_bounds__(256) void k_als_fit(const Geo* __restrict__ g, Stat
         const int c = (int)(e % R);
         ip = fma((double)K3[i * Rq + c], (double)U3[i * Rq + c], ip);
     }
-    als_hadamard_gram<T>(g, st, s, -1, R, H, stage);
+    const double* V0 = V + 3LL * s * R * R;
+    const double* V1 = V0 + R * R;
+    const double* V2 = V1 + R * R;
     double hs = 0.0;
-    for (int e = tid; e < R * R; e += 256) hs += H[e];
+    for (int e = tid; e < R * R; e += 256) hs += V0[e] * V1[e] * V2[e];
     red[0][tid] = ip;
     red[1][tid] = hs;
     __syncthreads();
@@ -229,12 +228,14 @@ __global__ __launch_bounds__(256) void k_als_export(const Geo* __restrict__ g, S
     if (blockIdx.x == 0 && threadIdx.x == 0) st.normM2[s] = xx[s];
 }
 
-inline size_t als_lds_bytes(int R) { return sizeof(double) * ((size_t)R * R + 32 * (size_t)R); }
-
 template <typename T>
-void launch_als_chol(const Geo* g, const StateP<T>& st, int S, int R, int n, const int* act, double* L, int* bad,
+void launch_als_gram(const Geo* g, const StateP<T>& st, int S, int R, int n, const int* act, double* V, hipStream_t q) {
+    hipLaunchKernelGGL((k_als_gram<T>), dim3(S), dim3(256), sizeof(double) * 32 * (size_t)R, q, g, st, n, act, V);
+}
+
+void launch_als_chol(const Geo* g, int S, int R, int n, const int* act, const double* V, double* L, int* bad,
                      hipStream_t q) {
-    hipLaunchKernelGGL((k_als_chol<T>), dim3(S), dim3(256), als_lds_bytes(R), q, g, st, n, act, L, bad);
+    hipLaunchKernelGGL(k_als_chol, dim3(S), dim3(256), sizeof(double) * (size_t)R * R, q, g, n, act, V, L, bad);
 }
 
 template <typename T>
@@ -248,9 +249,9 @@ void launch_als_solve(const Geo* g, const StateP<T>& st, int S, int R, int n, in
 }
 
 template <typename T>
-void launch_als_fit(const Geo* g, const StateP<T>& st, int S, int R, const int* act, double* relerr, double* xx,
-                    hipStream_t q) {
-    hipLaunchKernelGGL((k_als_fit<T>), dim3(S), dim3(256), als_lds_bytes(R), q, g, st, act, relerr, xx);
+void launch_als_fit(const Geo* g, const StateP<T>& st, int S, const int* act, const double* V, double* relerr,
+                    double* xx, hipStream_t q) {
+    hipLaunchKernelGGL((k_als_fit<T>), dim3(S), dim3(256), 0, q, g, st, act, V, relerr, xx);
 }
 
 template <typename T>
@@ -259,10 +260,11 @@ void launch_als_export(const Geo* g, const StateP<T>& st, int S, const double* x
 }
 
 #define CPD_ALS_INST(T)                                                                                              \
-    template void launch_als_chol<T>(const Geo*, const StateP<T>&, int, int, int, const int*, double*, int*, hipStream_t); \
+    template void launch_als_gram<T>(const Geo*, const StateP<T>&, int, int, int, const int*, double*, hipStream_t);    \
     template void launch_als_solve<T>(const Geo*, const StateP<T>&, int, int, int, int, const int*, const double*,      \
                                       hipStream_t);                                                                  \
-    template void launch_als_fit<T>(const Geo*, const StateP<T>&, int, int, const int*, double*, double*, hipStream_t);   \
+    template void launch_als_fit<T>(const Geo*, const StateP<T>&, int, const int*, const double*, double*, double*,     \
+                                    hipStream_t);                                                                    \
     template void launch_als_export<T>(const Geo*, const StateP<T>&, int, const double*, hipStream_t);
 CPD_ALS_INST(float)
 CPD_ALS_INST(double)

@@ -844,6 +844,7 @@ concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, double eps, int max
     double* xx = rel + S;
     int* act = (int*)(xx + S);
     int* bad = act + S;
+    double* V = rel + 4 * S;   // Grams of the three factors, [S][3][R*R]
     int Imax[3] = {1, 1, 1};
     for (int s = 0; s < S; ++s)
         for (int n = 0; n < 3; ++n) Imax[n] = std::max(Imax[n], (int)c->dims[3 * s + n]);
@@ -857,9 +858,10 @@ concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, double eps, int max
             cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], R, st.K3 + c->geo.koff[s], c->Rq, 0, c->q);
     };
     // RelErr_0 at the starting point
+    for (int n = 0; n < 3; ++n) cpd::launch_als_gram<T>(c->dgeo, st, S, R, n, act, V, c->q);
     debug_passes<T>(c, st);
     k3_sum();
-    cpd::launch_als_fit<T>(c->dgeo, st, S, R, act, rel, xx, c->q);
+    cpd::launch_als_fit<T>(c->dgeo, st, S, act, V, rel, xx, c->q);
     HIPCHECK(hipMemcpyAsync(prev.data(), rel, sizeof(double) * S, hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipStreamSynchronize(c->q));
     for (int s = 0; s < S; ++s) {
@@ -873,16 +875,19 @@ concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, double eps, int max
     int active = S;
     for (int it = 1; it <= max_it && active > 0; ++it) {
         cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->p1dma, c->q);
-        cpd::launch_als_chol<T>(c->dgeo, st, S, R, 0, act, Lfac, bad, c->q);
+        cpd::launch_als_chol(c->dgeo, S, R, 0, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 0, Imax[0], act, Lfac, c->q);
+        cpd::launch_als_gram<T>(c->dgeo, st, S, R, 0, act, V, c->q);
         cpd::launch_k2<T>(c->dgeo, st, itk, (int)c->lists.k2.size(), 1, c->q);
-        cpd::launch_als_chol<T>(c->dgeo, st, S, R, 1, act, Lfac, bad, c->q);
+        cpd::launch_als_chol(c->dgeo, S, R, 1, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 1, Imax[1], act, Lfac, c->q);
+        cpd::launch_als_gram<T>(c->dgeo, st, S, R, 1, act, V, c->q);
         cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
         k3_sum();
-        cpd::launch_als_chol<T>(c->dgeo, st, S, R, 2, act, Lfac, bad, c->q);
+        cpd::launch_als_chol(c->dgeo, S, R, 2, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 2, Imax[2], act, Lfac, c->q);
-        cpd::launch_als_fit<T>(c->dgeo, st, S, R, act, rel, xx, c->q);
+        cpd::launch_als_gram<T>(c->dgeo, st, S, R, 2, act, V, c->q);
+        cpd::launch_als_fit<T>(c->dgeo, st, S, act, V, rel, xx, c->q);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipMemcpyAsync(cur.data(), rel, sizeof(double) * S, hipMemcpyDeviceToHost, c->q));
         HIPCHECK(hipMemcpyAsync(hbad.data(), bad, sizeof(int) * S, hipMemcpyDeviceToHost, c->q));
