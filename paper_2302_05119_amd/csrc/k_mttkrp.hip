@@ -61,8 +61,11 @@ static void pass2_dispatch(int Rq, dim3 grid, int maxI2, hipStream_t q, const Ge
     const size_t va = 16 / sizeof(TA), rtp = ((size_t)Rq / 4 + va - 1) / va * va;
     const size_t red = sizeof(TA) * 4 * 64 * (size_t)Rq;
     const size_t bst = sizeof(TA) * (size_t)maxI2 * 4 * rtp;   // transposed U2
+    // chunked staging: whole 16-row groups within 32 KiB (as p2_chunk_rows)
+    const size_t chr = (32768 / (4 * rtp * sizeof(TA))) / 16 * 16;
+    const size_t cst = sizeof(TA) * chr * 4 * rtp;
     if (bst <= 49152) pass2_rt<TM, T, true>(Rq / 4, grid, bst > red ? bst : red, q, g, st, items, slot);
-    else pass2_rt<TM, T, false>(Rq / 4, grid, red, q, g, st, items, slot);
+    else pass2_rt<TM, T, false>(Rq / 4, grid, cst > red ? cst : red, q, g, st, items, slot);
 }
 
 template <typename T>

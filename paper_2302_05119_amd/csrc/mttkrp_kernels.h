@@ -486,8 +486,18 @@ __global__ __launch_bounds__(256) void k_pass1d(const Geo* __restrict__ g, State
 // pass 2: one workgroup per (block, chunk of 4 i1 slabs, 64 consecutive i3);
 // wavefront w takes slab 4*chunk + w.  Lanes run along i3 (the contiguous
 // index), so every tensor load is a coalesced 64-element row segment; NB rows
-// are loaded ahead of the matrix-core work.  U2 is staged in LDS when it fits.
+// are loaded ahead of the matrix-core work.  U2 is staged in LDS, whole when it
+// fits (BLDS), else in chunks of P2CHR rows shared by the four wavefronts.
 // ---------------------------------------------------------------------------
+// rows of U2 per staged chunk: a multiple of 16 within 32 KiB of LDS
+// (transposed rows of 4 x RTP operands)
+template <typename TA, int RT>
+constexpr int p2_chunk_rows() {
+    constexpr int VA = 16 / (int)sizeof(TA);
+    constexpr int RTP = (RT + VA - 1) / VA * VA;
+    return (32768 / (4 * RTP * (int)sizeof(TA))) / 16 * 16;
+}
+
 template <typename TM, typename T, int RT, bool BLDS>
 __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP<T> st, const ItemP2* __restrict__ items,
                                                int slot) {
@@ -532,59 +542,64 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
         const TA v = cvt<TA, TM>(Mp[(long long)min(j, I2 - 1) * ldm]);
         cur[j] = (live && valid && j < I2) ? v : (TA)0;
     }
-    if (BLDS) {
-        // U2 transposed so that lane l's operands U2[i2][4t + l%4], t < RT,
-        // are one contiguous run: [I2][4][RTP]
-        // (eight loads per thread in flight per step, clamped addresses)
-        const int nu = I2 * Rq;
+    // U2 rows [c0, c1) transposed into LDS so that lane l's operands
+    // U2[i2][4t + l%4], t < RT, are one contiguous run: [rows][4][RTP]
+    // (eight loads per thread in flight per step, clamped addresses)
+    auto stage_u2 = [&](int c0, int c1) {
+        const int nu = (c1 - c0) * Rq;
+        const CPD_GLOBAL T* __restrict__ src = U2g + (long long)c0 * Rq;
         for (int e0 = threadIdx.x; e0 < nu; e0 += 256 * 8) {
             T v[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = U2g[min(e0 + 256 * j, nu - 1)];
+            for (int j = 0; j < 8; ++j) v[j] = src[min(e0 + 256 * j, nu - 1)];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int e = e0 + 256 * j;
                 if (e < nu) {
-                    const int i2 = e / Rq, c = e % Rq;
-                    sm[(i2 * 4 + (c & 3)) * RTP + (c >> 2)] = (TA)v[j];
+                    const int r = e / Rq, c = e % Rq;
+                    sm[(r * 4 + (c & 3)) * RTP + (c >> 2)] = (TA)v[j];
                 }
             }
         }
+    };
+    constexpr int CHR = BLDS ? (1 << 30) : p2_chunk_rows<TA, RT>();
+    static_assert(CHR % NB == 0, "U2 chunks must hold whole NB-row groups");
+    for (int c0 = 0; c0 < I2; c0 += CHR) {
+        const int c1 = min(I2, c0 + CHR);
+        // every wavefront of the workgroup stages and waits (also those past I1)
         __syncthreads();
-    }
-    if (live) {
-        for (int i2b = 0; i2b < I2; i2b += NB) {
-            const int nb2 = i2b + NB;
+        stage_u2(c0, c1);
+        __syncthreads();
+        if (live) {
+            for (int i2b = c0; i2b < c1; i2b += NB) {
+                const int nb2 = i2b + NB;
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const TA v = cvt<TA, TM>(Mp[(long long)min(nb2 + j, I2 - 1) * ldm]);
-                nxt[j] = (valid && nb2 + j < I2) ? v : (TA)0;
-            }
-            const int jm = min(NB, I2 - i2b);
+                for (int j = 0; j < NB; ++j) {
+                    const TA v = cvt<TA, TM>(Mp[(long long)min(nb2 + j, I2 - 1) * ldm]);
+                    nxt[j] = (valid && nb2 + j < I2) ? v : (TA)0;
+                }
+                const int jm = min(NB, I2 - i2b);
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                if (j < jm) {
-                    const int i2 = i2b + j;
-                    TA bb[RTP];
-                    if (BLDS) {
-                        const TA* ur = sm + (i2 * 4 + (lane & 3)) * RTP;
+                for (int j = 0; j < NB; ++j) {
+                    if (j < jm) {
+                        const TA* ur = sm + ((i2b - c0 + j) * 4 + (lane & 3)) * RTP;
+                        TA bb[RTP];
 #pragma unroll
                         for (int v = 0; v < RTP / VA; ++v) *(u32x4*)&bb[v * VA] = *(const u32x4*)(ur + v * VA);
-                    } else {
 #pragma unroll
-                        for (int t = 0; t < RT; ++t) bb[t] = (TA)U2g[(long long)i2 * Rq + 4 * t + (lane & 3)];
+                        for (int t = 0; t < RT; ++t) z[t].mma(cur[j], bb[t]);
                     }
-#pragma unroll
-                    for (int t = 0; t < RT; ++t) z[t].mma(cur[j], bb[t]);
                 }
-            }
 #pragma unroll
-            for (int j = 0; j < NB; ++j) cur[j] = nxt[j];
+                for (int j = 0; j < NB; ++j) cur[j] = nxt[j];
+            }
         }
+    }
+    if (live) {
 #pragma unroll
         for (int t = 0; t < RT; ++t) z[t].scale(u1v[t]);
     }
-    if (BLDS) __syncthreads();
+    __syncthreads();
     TA* red = sm;  // [4 waves][64][Rq]
 #pragma unroll
     for (int t = 0; t < RT; ++t)

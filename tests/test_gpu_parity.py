@@ -54,6 +54,10 @@ MTTKRP_CASES = [
     ([(13, 20, 200)], 30, "f32"),
     ([(7, 9, 11), (7, 9, 11)], 5, "f64"),
     ([(5, 66, 70)], 12, "f64"),
+    # U2 too large for LDS: staged in row chunks (a ragged last chunk)
+    ([(3, 700, 40), (6, 300, 20)], 20, "f32"),
+    ([(5, 200, 37)], 64, "f32"),
+    ([(3, 300, 20)], 32, "f64"),
 ]
 
 
