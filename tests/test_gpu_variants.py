@@ -309,3 +309,37 @@ def test_flexible_coupling_seeded_init_and_rejections(dev):
         CoupledCP(tens, 6, (3, 0, 0), coupled_blocks=((), None, None))  # empty group
     with pytest.raises(ConcpdError):
         CoupledCP(tens, 6, (3, 0, 0), coupled_blocks=((0, 1), None, None))  # unequal I_1 inside the group
+
+
+def test_variants_together_on_the_lra_path(dev):
+    # -NC, uneven ranks and flexible coupling at once, on T-HOSVD compressed
+    # blocks (Algorithm 2): 30 iterations against the oracle on its own
+    # compression (fit of X~ and global fit at 1e-4)
+    from oracle import tucker
+    from oracle.apg import TuckerData
+    say("[variants] lra: -NC + uneven ranks + coupling groups")
+    L, ranks, J = (3, 0, 2), (6, 4, 5, 6), (8, 8, 8)
+    P = group_problem(np.float32)
+    P.L = L
+    U6, lam6 = group_init(P, 6, L, GROUPS, 282)
+    U0 = [[U6[n][s][:, :ranks[s]].copy() for s in range(P.S)] for n in range(3)]
+    lam0 = [lam6[s][:ranks[s]].copy() for s in range(P.S)]
+    cores, bases, _ = tucker.compress_all([X.astype(np.float64) for X in P.tensors], J)
+    opt = Options(L=L, coupled_blocks=GROUPS, update_core=False)
+    ref = apg.run(TuckerData(cores, bases), U0, lam0, opt, iters=30)
+    m = make_model(P, U0, lam0, dev, "f32", R=6, block_ranks=ranks, coupled_blocks=GROUPS, update_core=False,
+                   tucker_ranks=J)
+    m.lra_compress()
+    s = m.lra_step(30)
+    gf = m.global_fit()
+    rf = apg.fit(P.tensors, ref.lam, ref.U)
+    say(f"   fit(X~) gpu={s['fit']:.8f} oracle={1 - ref.relerr:.8f}; global gpu={gf:.8f} oracle={rf:.8f}")
+    assert s["k"] == 30
+    assert abs(s["fit"] - (1 - ref.relerr)) <= 1e-4
+    assert abs(gf - rf) <= 1e-4
+    for b in range(P.S):
+        np.testing.assert_array_equal(m.lam(b), lam0[b])
+    check_padding_zero(m, ranks)
+    for n, grp in ((0, GROUPS[0]), (2, GROUPS[2])):
+        for b in grp[1:]:
+            np.testing.assert_array_equal(m.factor(n, b)[:, :L[n]], m.factor(n, grp[0])[:, :L[n]])
