@@ -216,6 +216,17 @@ concpd_status concpd_get_lambda(concpd_ctx ctx, int32_t s, double* host_dst);
  * eqLipsLu): Ld [S], Lu [S*3] (index 3*s + n), LC [3] = sum_s Lu.  Synchronises. */
 concpd_status concpd_get_lipschitz(concpd_ctx ctx, double* Ld, double* Lu, double* LC);
 
+/* Read the iterate state for a checkpoint, in the layout concpd_set_state
+ * takes back: U, lam = x_{k-1} and U_prev, lam_prev = x_{k-2} ([S*3] host
+ * I_n x R arrays at index 3*s + n / [S] R-vectors, caller-allocated; any of
+ * the four may be NULL to skip it), Ld_prev [S], Lu_prev [S*3], LC_prev [3]
+ * (negative = none), t = t_{k-1}, k.  Restoring these into a context of the
+ * same configuration continues the run bit for bit (the restart count starts
+ * again from 0).  Synchronises.  Errors: EINVAL, EHIP. */
+concpd_status concpd_get_state(concpd_ctx ctx, double* const* U, double* const* U_prev, double* const* lam,
+                               double* const* lam_prev, double* Ld_prev, double* Lu_prev, double* LC_prev,
+                               double* t, int64_t* k);
+
 /* Replace the iterate state (checkpoint restore / teacher forcing):
  *   U, lam          x_{k-1}: [S*3] / [S] host arrays,
  *   U_prev, lam_prev x_{k-2} (NULL: same as x_{k-1}),

@@ -1422,6 +1422,67 @@ concpd_status concpd_set_state(concpd_ctx c, const double* const* U, const doubl
     return CONCPD_OK;
 }
 
+concpd_status concpd_get_state(concpd_ctx c, double* const* U, double* const* U_prev, double* const* lam,
+                               double* const* lam_prev, double* Ld_prev, double* Lu_prev, double* LC_prev, double* t,
+                               int64_t* k) {
+    if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    const int S = c->S, R = c->R, Rq = c->Rq;
+    Ctrl h;
+    HIPCHECK(hipMemcpyAsync(&h, c->ctrl, sizeof h, hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    // logical slot 1 holds x_{k-1} (the accepted iterate), slot 2 x_{k-2}
+    for (int l = 1; l <= 2; ++l) {
+        double* const* Ud = l == 1 ? U : U_prev;
+        double* const* Ld = l == 1 ? lam : lam_prev;
+        const int ph = (h.rot3 + l) % 3;
+        if (Ud) {
+            const size_t n = (size_t)c->lay.uslot;
+            std::vector<double> hv(n);
+            if (c->f64) {
+                HIPCHECK(hipMemcpyAsync(hv.data(), c->ws + c->lay.U[ph], n * 8, hipMemcpyDeviceToHost, c->q));
+            } else {
+                std::vector<float> hf(n);
+                HIPCHECK(hipMemcpyAsync(hf.data(), c->ws + c->lay.U[ph], n * 4, hipMemcpyDeviceToHost, c->q));
+                HIPCHECK(hipStreamSynchronize(c->q));
+                for (size_t i = 0; i < n; ++i) hv[i] = hf[i];
+            }
+            HIPCHECK(hipStreamSynchronize(c->q));
+            for (int s = 0; s < S; ++s)
+                for (int n2 = 0; n2 < 3; ++n2) {
+                    double* dst = Ud[3 * s + n2];
+                    if (!dst) return fail(CONCPD_EINVAL, "U / U_prev[%d] is NULL", 3 * s + n2);
+                    const double* src = hv.data() + c->geo.uoff[n2][s];
+                    for (int64_t i = 0; i < c->dims[3 * s + n2]; ++i)
+                        for (int r = 0; r < R; ++r) dst[i * R + r] = src[i * Rq + r];
+                }
+        }
+        if (Ld) {
+            std::vector<double> hl((size_t)S * Rq);
+            HIPCHECK(hipMemcpyAsync(hl.data(), c->ws + c->lay.lam[ph], hl.size() * 8, hipMemcpyDeviceToHost, c->q));
+            HIPCHECK(hipStreamSynchronize(c->q));
+            for (int s = 0; s < S; ++s) {
+                if (!Ld[s]) return fail(CONCPD_EINVAL, "lambda / lambda_prev[%d] is NULL", s);
+                for (int r = 0; r < R; ++r) Ld[s][r] = hl[(size_t)s * Rq + r];
+            }
+        }
+    }
+    std::vector<double> ld(S), lu(3 * S), lc(3);
+    HIPCHECK(hipMemcpyAsync(ld.data(), c->ws + c->lay.Ld_prev, 8 * ld.size(), hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipMemcpyAsync(lu.data(), c->ws + c->lay.Lu_prev, 8 * lu.size(), hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipMemcpyAsync(lc.data(), c->ws + c->lay.LC_prev, 8 * lc.size(), hipMemcpyDeviceToHost, c->q));
+    HIPCHECK(hipStreamSynchronize(c->q));
+    for (int s = 0; s < S; ++s) {
+        if (Ld_prev) Ld_prev[s] = ld[s];
+        for (int n2 = 0; n2 < 3; ++n2)
+            if (Lu_prev) Lu_prev[3 * s + n2] = lu[n2 * S + s];
+    }
+    for (int n2 = 0; n2 < 3; ++n2)
+        if (LC_prev) LC_prev[n2] = lc[n2];
+    if (t) *t = h.t;
+    if (k) *k = h.k;
+    return CONCPD_OK;
+}
+
 concpd_status concpd_loss_grad(concpd_ctx c, const void* const* U_dev, const void* const* lambda_dev, int32_t coupled,
                                double* loss, void* const* gU_dev, void* const* glam_dev) {
     if (!c || !U_dev || !lambda_dev || !loss || !gU_dev || !glam_dev) return fail(CONCPD_EINVAL, "NULL argument");

@@ -293,6 +293,30 @@ class CoupledCP:
         check(self._lib.concpd_debug_mttkrp(self.ctx, n, s, ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def get_state(self) -> dict:
+        """The iterate state for a checkpoint, as keyword arguments of
+        set_state: U, U_prev [n][s] (I_n x R^(s)), lam, lam_prev [s],
+        Ld_prev [s], Lu_prev [s][n], LC_prev [n] (None where unset), t, k."""
+        S = self.S
+        bufs = {key: [[np.zeros((self.dims[s][n], self.R)) for s in range(S)] for n in range(3)] for key in ("U", "U_prev")}
+        lams = {key: [np.zeros(self.R) for _ in range(S)] for key in ("lam", "lam_prev")}
+        P = ctypes.POINTER(ctypes.c_double)
+        flat = lambda UU: (P * (3 * S))(*[UU[n][s].ctypes.data_as(P) for s in range(S) for n in range(3)])  # noqa: E731
+        lptr = lambda LL: (P * S)(*[x.ctypes.data_as(P) for x in LL])  # noqa: E731
+        Ld, Lu, LC = np.zeros(S), np.zeros(3 * S), np.zeros(3)
+        t = ctypes.c_double()
+        k = ctypes.c_int64()
+        check(self._lib.concpd_get_state(self.ctx, flat(bufs["U"]), flat(bufs["U_prev"]), lptr(lams["lam"]),
+                                         lptr(lams["lam_prev"]), Ld.ctypes.data_as(P), Lu.ctypes.data_as(P),
+                                         LC.ctypes.data_as(P), ctypes.byref(t), ctypes.byref(k)))
+        r = self.block_ranks
+        none = lambda v: None if v < 0 else float(v)  # noqa: E731
+        return {"U": [[bufs["U"][n][s][:, :r[s]] for s in range(S)] for n in range(3)],
+                "U_prev": [[bufs["U_prev"][n][s][:, :r[s]] for s in range(S)] for n in range(3)],
+                "lam": [lams["lam"][s][:r[s]] for s in range(S)], "lam_prev": [lams["lam_prev"][s][:r[s]] for s in range(S)],
+                "Ld_prev": [none(v) for v in Ld], "Lu_prev": [[none(v) for v in Lu[3 * s:3 * s + 3]] for s in range(S)],
+                "LC_prev": [none(v) for v in LC], "t": t.value, "k": k.value}
+
     def set_state(self, U, lam, U_prev=None, lam_prev=None, Ld_prev=None, Lu_prev=None, LC_prev=None, t=1.0, k=0):
         """U, U_prev: [n][s] arrays; Lu_prev [s][n] (or [n][s] transposed by caller); None entries mean 'none'."""
         flat = lambda UU: [_stride_r(UU[n][s], self.R) for s in range(self.S) for n in range(3)]  # noqa: E731

@@ -218,3 +218,35 @@ def test_seeded_init_and_nonnegativity(dev):
             if n < 2:
                 np.testing.assert_array_equal(U, m.factor(n, 0))
     assert all(np.all(m.lam(s) >= 0) for s in range(2))
+
+
+@pytest.mark.parametrize("compute", ["f32", "f64"])
+def test_checkpoint_get_state_set_state_resumes_bit_for_bit(dev, compute):
+    # a checkpoint taken after 7 iterations, restored into a fresh context,
+    # continues exactly as the original run (iterate, objective, Lipschitz
+    # constants, extrapolation state)
+    say(f"[checkpoint] compute={compute}")
+    dtype = np.float64 if compute == "f64" else np.float32
+    L = (3, 0, 2)
+    P = synth.coupled_problem([(17, 40, 30), (17, 25, 30), (17, 33, 30)], 6, L, 10.0, 901, dtype=dtype)
+    U0, lam0 = synth.uniform_init(P.dims, 6, L, 902)
+    a = make_model(P, U0, lam0, dev, compute)
+    a.step(7)
+    st = a.get_state()
+    assert st["k"] == 7 and st["t"] > 1.0
+    for s in range(P.S):
+        np.testing.assert_array_equal(st["lam"][s], a.lam(s))
+        for n in range(3):
+            np.testing.assert_array_equal(st["U"][n][s], a.factor(n, s))
+    b = make_model(P, U0, lam0, dev, compute, seed=3)
+    b.set_state(**st)
+    assert b.stats()["F"] == a.stats()["F"]
+    sa, sb = a.step(10), b.step(10)
+    say(f"   F a={sa['F']:.15e} b={sb['F']:.15e} k {sa['k']} {sb['k']}")
+    assert sa["F"] == sb["F"] and sa["k"] == sb["k"] == 17
+    for s in range(P.S):
+        np.testing.assert_array_equal(a.lam(s), b.lam(s))
+        for n in range(3):
+            np.testing.assert_array_equal(a.factor(n, s), b.factor(n, s))
+    for x, y in zip(a.lipschitz(), b.lipschitz()):
+        np.testing.assert_array_equal(x, y)
