@@ -127,8 +127,11 @@ def lra_leg(steps: int, warmup: int, dense_steps: int = 30, name: str = LRA_WORK
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     st = m.stats()
+    from paper_2302_05119_amd import launch_floor
+    fl = launch_floor(13)   # kernels per compressed sweep
     return {"workload": name, "compression": compress, **extra, "compress_s": t1 - t0,
             "iter_per_s": (st["k"] - k0) / (t3 - t2),
+            "launch_floor": {"kernels_per_sweep": 13, "graph_us": fl["graph_us"], "direct_us": fl["direct_us"]},
             "dense_iter_per_s_same_blocks": dense_rate, "sweeps": steps,
             "warmup": warmup, "fit_compressed": st["fit"], "global_fit": m.global_fit(), "iterations": st["k"],
             "restarts": st["restarts"]}
@@ -372,6 +375,11 @@ def main():
                 "iterations": st["k"], "sweeps_timed": args.steps, "iterations_timed": accepted},
     }
     out["tuning"] = tuning
+    # the sweep's launch-latency floor: a graph of as many empty kernels
+    from paper_2302_05119_amd import launch_floor
+    fl = launch_floor(10)
+    out["launch_floor"] = {"kernels_per_sweep": 10, "graph_us": fl["graph_us"], "direct_us": fl["direct_us"],
+                           "sweep_us": elapsed / max(accepted, 1) * 1e6}
     if args.forms_steps > 0:
         out["bf16_c2"] = precision_leg(P, U0, lam0, w, args.forms_steps, st["fit"], st["k"])
         out["batched_c4"] = batched_leg(args.forms_steps)

@@ -270,6 +270,13 @@ concpd_status concpd_debug_mttkrp(concpd_ctx ctx, int32_t n, int32_t s, void* de
  * nonnegative matrices, Lanczos with Sturm multisection otherwise.  Results
  * to host_out [count].  1 <= n <= 64, 1 <= count <= 65535.  Needs no context;
  * allocates and synchronises.  Errors: EINVAL, EHIP. */
+/* Measurement hook: the launch-latency floor of a sweep of `kernels` kernels,
+ * timed with HIP events on a private stream: *us_graph per replay of a
+ * captured graph of that many empty one-wavefront kernels, *us_direct per
+ * `kernels` direct launches of them (after one untimed pass each).  Compare a
+ * latency-bound sweep against it.  Synchronises.  Errors: EINVAL, EHIP. */
+concpd_status concpd_launch_floor(int32_t kernels, int32_t reps, double* us_graph, double* us_direct);
+
 concpd_status concpd_debug_spectral_norm(const double* host_A, int32_t n, int32_t count, double* host_out);
 
 /* Per-kernel timing of the dense MTTKRP passes (pass 1: M x_3 U^(3); pass 2:

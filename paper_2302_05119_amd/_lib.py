@@ -86,6 +86,7 @@ SIGNATURES = {
     "concpd_fit": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "lra_compress": (ctypes.c_int, [_P, _I32P, ctypes.POINTER(Stats)]),
     "lra_step": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Stats)]),
+    "concpd_launch_floor": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _DP, _DP]),
     "concpd_get_state": (ctypes.c_int, [_P, _DPP, _DPP, _DPP, _DPP, _DP, _DP, _DP, _DP,
                                         ctypes.POINTER(ctypes.c_int64)]),
     "lra_compress_cp": (ctypes.c_int, [_P, _DPP, ctypes.c_uint64, ctypes.c_double, ctypes.c_int32,

@@ -123,6 +123,7 @@ void launch_grad(const Geo* g, const StateP<T>& st, int S, int R, int Rq, const 
 inline size_t lra_c_lds_bytes(int Jmax, int Rq) { return sizeof(double) * ((size_t)Jmax * Jmax + 2 * (size_t)Jmax * Rq + 256); }
 template <typename T> void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int Rq, int n, hipStream_t q);
 void launch_sum_parts(const double* part, int np, double* out, hipStream_t q);
+void launch_empty(hipStream_t q);
 void launch_pad_copy(const void* src, int src_dtype, void* dst, int dst_dtype, long long rows, int I3, int ld, hipStream_t q);
 void launch_finite_check(const void* src, int dtype, long long n, int* flag, hipStream_t q);
 template <typename T> void launch_als_gram(const Geo* g, const StateP<T>& st, int S, int R, int n, const int* act, double* V, hipStream_t q);

@@ -4,6 +4,12 @@
 
 namespace cpd {
 
+// A kernel that does nothing (one wavefront): the launch-latency floor of a
+// sweep is a graph of as many of these as the sweep has kernels.
+__global__ __launch_bounds__(64) void k_empty() {}
+
+void launch_empty(hipStream_t q) { hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, q); }
+
 template <typename TS> __device__ __forceinline__ double as_f64(TS x) { return (double)x; }
 template <> __device__ __forceinline__ double as_f64<__hip_bfloat16>(__hip_bfloat16 x) { return (double)__bfloat162float(x); }
 template <> __device__ __forceinline__ double as_f64<__half>(__half x) { return (double)__half2float(x); }

@@ -1515,6 +1515,64 @@ concpd_status concpd_debug_mttkrp(concpd_ctx c, int32_t n, int32_t s, void* dev_
     return CONCPD_OK;
 }
 
+concpd_status concpd_launch_floor(int32_t kernels, int32_t reps, double* us_graph, double* us_direct) {
+    if (kernels < 1 || kernels > 1024 || reps < 1 || reps > 100000 || !us_graph || !us_direct)
+        return fail(CONCPD_EINVAL, "launch floor: kernels in [1, 1024], reps in [1, 100000], non-NULL outputs");
+    hipStream_t q = nullptr, qc = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipGraphExec_t gx = nullptr;
+    concpd_status st = CONCPD_OK;
+    auto done = [&](concpd_status r) {
+        if (q) (void)hipStreamSynchronize(q);
+        if (gx) (void)hipGraphExecDestroy(gx);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (qc) (void)hipStreamDestroy(qc);
+        if (q) (void)hipStreamDestroy(q);
+        return r;
+    };
+#define FLOOR_HIP(x)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess) return done(fail(CONCPD_EHIP, "%s: %s", #x, hipGetErrorString(e_))); \
+    } while (0)
+    FLOOR_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    FLOOR_HIP(hipStreamCreateWithFlags(&qc, hipStreamNonBlocking));
+    FLOOR_HIP(hipEventCreate(&e0));
+    FLOOR_HIP(hipEventCreate(&e1));
+    FLOOR_HIP(hipStreamBeginCapture(qc, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < kernels; ++i) cpd::launch_empty(qc);
+    hipGraph_t graph = nullptr;
+    FLOOR_HIP(hipStreamEndCapture(qc, &graph));
+    const hipError_t ei = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        gx = nullptr;
+        return done(fail(CONCPD_EHIP, "graph instantiate: %s", hipGetErrorString(ei)));
+    }
+    float ms = 0.f;
+    for (int pass = 0; pass < 2; ++pass) {   // warm-up, then timed
+        FLOOR_HIP(hipEventRecord(e0, q));
+        for (int r = 0; r < reps; ++r) FLOOR_HIP(hipGraphLaunch(gx, q));
+        FLOOR_HIP(hipEventRecord(e1, q));
+        FLOOR_HIP(hipEventSynchronize(e1));
+    }
+    FLOOR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *us_graph = 1e3 * ms / reps;
+    for (int pass = 0; pass < 2; ++pass) {
+        FLOOR_HIP(hipEventRecord(e0, q));
+        for (int r = 0; r < reps; ++r)
+            for (int i = 0; i < kernels; ++i) cpd::launch_empty(q);
+        FLOOR_HIP(hipEventRecord(e1, q));
+        FLOOR_HIP(hipEventSynchronize(e1));
+    }
+    FLOOR_HIP(hipGetLastError());
+    FLOOR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *us_direct = 1e3 * ms / reps;
+#undef FLOOR_HIP
+    return done(st);
+}
+
 concpd_status concpd_debug_spectral_norm(const double* host_A, int32_t n, int32_t count, double* host_out) {
     if (!host_A || !host_out) return fail(CONCPD_EINVAL, "NULL argument");
     if (n < 1 || n > CPD_MAXR) return fail(CONCPD_EINVAL, "n = %d not in [1, %d]", n, CPD_MAXR);

@@ -362,6 +362,16 @@ class CoupledCP:
             pass
 
 
+def launch_floor(kernels: int, reps: int = 2000) -> dict:
+    """Launch-latency floor of a sweep of `kernels` kernels: microseconds per
+    replay of a graph of that many empty kernels, and per as many direct
+    launches (device-side HIP events)."""
+    lib = load()
+    g, d = ctypes.c_double(), ctypes.c_double()
+    check(lib.concpd_launch_floor(int(kernels), int(reps), ctypes.byref(g), ctypes.byref(d)))
+    return {"kernels": int(kernels), "graph_us": g.value, "direct_us": d.value}
+
+
 def spectral_norm(mats) -> np.ndarray:
     """Largest eigenvalues of symmetric n x n FP64 matrices ([count, n, n] or
     [n, n]) computed on the device by the sweep's spectral-norm code (the

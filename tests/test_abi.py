@@ -133,3 +133,10 @@ def test_calls_on_null_context_fail_cleanly(lib):
     assert lib.concpd_step(None, 1, ctypes.byref(Stats())) == 1
     assert lib.lra_step(None, 1, None) == 1
     assert lib.concpd_destroy(None) == 0
+
+
+def test_launch_floor_rejects_bad_arguments_without_device(lib):
+    g, d = ctypes.c_double(), ctypes.c_double()
+    assert lib.concpd_launch_floor(0, 10, ctypes.byref(g), ctypes.byref(d)) == 1
+    assert lib.concpd_launch_floor(10, 0, ctypes.byref(g), ctypes.byref(d)) == 1
+    assert lib.concpd_launch_floor(10, 10, None, ctypes.byref(d)) == 1

@@ -248,3 +248,11 @@ def test_full_size_c4_eeg_teacher_forced_fp32_and_bf16_fit():
     f32, fb = m.global_fit(), mb.global_fit()
     say(f"   60 iterations: global fit FP32 {f32:.6f}  BF16 {fb:.6f}")
     assert abs(f32 - fb) <= 1e-3
+
+
+def test_launch_floor_measures_empty_sweeps():
+    from paper_2302_05119_amd import launch_floor
+    say("[floor] 10 empty kernels")
+    f = launch_floor(10, 500)
+    say(f"   {f}")
+    assert 0.0 < f["graph_us"] < 1e4 and 0.0 < f["direct_us"] < 1e4
