@@ -169,7 +169,7 @@ concpd_status lra_compress(concpd_ctx ctx, const int32_t* ranks, concpd_stats* o
 /* concpd_step in lra mode.  Errors: ESTATE if lra_compress has not run. */
 concpd_status lra_step(concpd_ctx ctx, int32_t n_iter, concpd_stats* out);
 
-/* Compress every block by an unconstrained rank-R CPD fitted with alternating
+/* Compress every block by an unconstrained rank-R~ CPD fitted with alternating
  * least squares: the paper's own first step of Algorithm 2 (Section III-B;
  * ALS and its stopping rule per the experiment settings of Section IV: stop
  * once |RelErr_k - RelErr_{k-1}| < eps, or after max_it iterations; the paper
@@ -178,22 +178,24 @@ concpd_status lra_step(concpd_ctx ctx, int32_t n_iter, concpd_stats* out);
  * factors, H_n the Hadamard product of the other two Grams; Cholesky, FP64).
  * RelErr_0 is taken at the starting point; each block stops on its own.
  * Afterwards the context is in lra mode with X~^(s) = [[U~^(1,s), U~^(2,s),
- * U~^(3,s)]] held in Tucker form (A_n = U~^(n,s) as FP64 I_n x R, G = the
+ * U~^(3,s)]] held in Tucker form (A_n = U~^(n,s) as FP64 I_n x R~, G = the
  * super-diagonal core of ones, which lra_get_tucker returns), and lra_step
  * iterates on it (eq. eqlrau / eqlrag).  The APG iterate is left as it was.
- *   init    [S*3] host I_n x R row-major starting factors at index 3*s + n
+ *   cp_rank R~, 1 <= R~ <= R (eq. cosfunclra allows R~ <= R; the paper's
+ *           runs use R~ = R), or 0 for R.
+ *   init    [S*3] host I_n x R~ row-major starting factors at index 3*s + n
  *           (copied), or NULL for a seeded U[0,1] draw (SplitMix64(seed);
  *           order: n, then s, then row, then column).
  *   iters   [S] ALS iterations run per block, or NULL.
  *   relerr  [S] final ||M - X~|| / ||M|| per block (M: the operand copy the
  *           MTTKRP reads), or NULL.
- * Needs tucker_ranks with every J_n >= R (so R <= I_n; they reserve the compressed form's
+ * Needs tucker_ranks with every J_n >= R~ (so R~ <= I_n; they reserve the compressed form's
  * storage), R^(s) = R for every block, and a context not yet compressed.
  * Errors: EINVAL, ESTATE, ENOTSUP, ENONFINITE (a Gram H_n that is not
  * positive definite, e.g. a rank-deficient start, or a non-finite fit; the
  * context is then left uncompressed with its iterate intact), EHIP. */
 concpd_status lra_compress_cp(concpd_ctx ctx, const double* const* init, uint64_t seed, double eps, int32_t max_it,
-                              int32_t* iters, double* relerr, concpd_stats* out);
+                              int32_t cp_rank, int32_t* iters, double* relerr, concpd_stats* out);
 
 /* Copy one part of block s's compressed form to host memory (FP64):
  * n = 0, 1, 2: the basis A_n (I_n x J_n, row-major); n = 3: the core G

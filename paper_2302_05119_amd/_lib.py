@@ -89,7 +89,7 @@ SIGNATURES = {
     "concpd_launch_floor": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _DP, _DP]),
     "concpd_get_state": (ctypes.c_int, [_P, _DPP, _DPP, _DPP, _DPP, _DP, _DP, _DP, _DP,
                                         ctypes.POINTER(ctypes.c_int64)]),
-    "lra_compress_cp": (ctypes.c_int, [_P, _DPP, ctypes.c_uint64, ctypes.c_double, ctypes.c_int32,
+    "lra_compress_cp": (ctypes.c_int, [_P, _DPP, ctypes.c_uint64, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                        _I32P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(Stats)]),
     "lra_get_tucker": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _DP]),
     "concpd_set_option": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64]),

@@ -27,11 +27,11 @@ namespace cpd {
 // V_n = U~^(n)T U~^(n) (R x R, FP64) of every active block, at V + (3 s + n) R^2.
 // Thread t owns the pairs e = t + 256 j; rows are staged 32 at a time in LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void k_als_gram(const Geo* __restrict__ g, StateP<T> st, int n,
+__global__ __launch_bounds__(256) void k_als_gram(const Geo* __restrict__ g, StateP<T> st, int n, int R,
                                                   const int* __restrict__ act, double* __restrict__ V) {
     apply_rot(st);
     constexpr int CH = 32;
-    const int s = blockIdx.x, R = g->R, Rq = g->Rq, tid = threadIdx.x;
+    const int s = blockIdx.x, Rq = g->Rq, tid = threadIdx.x;
     if (!act[s]) return;
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     double* stage = (double*)smraw;        // 32 x R
@@ -72,10 +72,10 @@ __global__ __launch_bounds__(256) void k_als_gram(const Geo* __restrict__ g, Sta
 // factor L (lower, row-major R x R) for every active block; bad[s] = 1 if a
 // pivot falls below 1e-13 of its starting diagonal entry or is not finite
 // (H_n numerically singular).
-__global__ __launch_bounds__(256) void k_als_chol(const Geo* __restrict__ g, int n, const int* __restrict__ act,
+__global__ __launch_bounds__(256) void k_als_chol(int n, int R, const int* __restrict__ act,
                                                   const double* __restrict__ V, double* __restrict__ Lout,
                                                   int* __restrict__ bad) {
-    const int s = blockIdx.x, R = g->R, tid = threadIdx.x;
+    const int s = blockIdx.x, tid = threadIdx.x;
     if (!act[s]) return;
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     double* H = (double*)smraw;            // R x R
@@ -120,10 +120,10 @@ __global__ __launch_bounds__(256) void k_als_chol(const Geo* __restrict__ g, int
 // U~^(n) row i = K_n row i times H_n^{-1}: forward then back substitution with
 // L, one lane per row, the lane's vector in LDS column-major (col * 64 + lane).
 template <typename T, int KSRC>
-__global__ __launch_bounds__(64) void k_als_solve(const Geo* __restrict__ g, StateP<T> st, int n,
+__global__ __launch_bounds__(64) void k_als_solve(const Geo* __restrict__ g, StateP<T> st, int n, int R,
                                                   const int* __restrict__ act, const double* __restrict__ Lin) {
     apply_rot(st);
-    const int s = blockIdx.y, R = g->R, Rq = g->Rq, lane = threadIdx.x;
+    const int s = blockIdx.y, Rq = g->Rq, lane = threadIdx.x;
     if (!act[s]) return;
     const int I = g->I[s][n];
     const int row0 = blockIdx.x * 64;
@@ -162,11 +162,11 @@ __global__ __launch_bounds__(64) void k_als_solve(const Geo* __restrict__ g, Sta
 // K3 buffer from pass 2 on the new U~^(1), U~^(2)); xx[s] = ||X~||^2.
 // Fixed-order tree reductions.
 template <typename T>
-__global__ __launch_bounds__(256) void k_als_fit(const Geo* __restrict__ g, StateP<T> st, const int* __restrict__ act,
-                                                 const double* __restrict__ V, double* __restrict__ relerr,
-                                                 double* __restrict__ xx) {
+__global__ __launch_bounds__(256) void k_als_fit(const Geo* __restrict__ g, StateP<T> st, int R,
+                                                 const int* __restrict__ act, const double* __restrict__ V,
+                                                 double* __restrict__ relerr, double* __restrict__ xx) {
     apply_rot(st);
-    const int s = blockIdx.x, R = g->R, Rq = g->Rq, tid = threadIdx.x;
+    const int s = blockIdx.x, Rq = g->Rq, tid = threadIdx.x;
     if (!act[s]) return;
     __shared__ double red[2][256];
     const int I3 = g->I[s][2];
@@ -204,9 +204,10 @@ __global__ __launch_bounds__(256) void k_als_fit(const Geo* __restrict__ g, Stat
 // The fitted blocks in Tucker form for the lra path: A_n = U~^(n) (FP64,
 // I_n x R), G = super-diagonal ones (R x R x R), ||X~||^2 as the block norm.
 template <typename T>
-__global__ __launch_bounds__(256) void k_als_export(const Geo* __restrict__ g, StateP<T> st, const double* __restrict__ xx) {
+__global__ __launch_bounds__(256) void k_als_export(const Geo* __restrict__ g, StateP<T> st, int R,
+                                                    const double* __restrict__ xx) {
     apply_rot(st);
-    const int s = blockIdx.y, R = g->R, Rq = g->Rq;
+    const int s = blockIdx.y, Rq = g->Rq;
     double* L = st.lra;
     const long long stride = (long long)gridDim.x * 256;
     for (int n = 0; n < 3; ++n) {
@@ -230,12 +231,11 @@ __global__ __launch_bounds__(256) void k_als_export(const Geo* __restrict__ g, S
 
 template <typename T>
 void launch_als_gram(const Geo* g, const StateP<T>& st, int S, int R, int n, const int* act, double* V, hipStream_t q) {
-    hipLaunchKernelGGL((k_als_gram<T>), dim3(S), dim3(256), sizeof(double) * 32 * (size_t)R, q, g, st, n, act, V);
+    hipLaunchKernelGGL((k_als_gram<T>), dim3(S), dim3(256), sizeof(double) * 32 * (size_t)R, q, g, st, n, R, act, V);
 }
 
-void launch_als_chol(const Geo* g, int S, int R, int n, const int* act, const double* V, double* L, int* bad,
-                     hipStream_t q) {
-    hipLaunchKernelGGL(k_als_chol, dim3(S), dim3(256), sizeof(double) * (size_t)R * R, q, g, n, act, V, L, bad);
+void launch_als_chol(int S, int R, int n, const int* act, const double* V, double* L, int* bad, hipStream_t q) {
+    hipLaunchKernelGGL(k_als_chol, dim3(S), dim3(256), sizeof(double) * (size_t)R * R, q, n, R, act, V, L, bad);
 }
 
 template <typename T>
@@ -243,29 +243,29 @@ void launch_als_solve(const Geo* g, const StateP<T>& st, int S, int R, int n, in
                       hipStream_t q) {
     const size_t lds = sizeof(double) * ((size_t)R * R + 64 * (size_t)R);
     const dim3 grid((unsigned)((Imax + 63) / 64), (unsigned)S);
-    if (n == 0) hipLaunchKernelGGL((k_als_solve<T, KSRC_K1P>), grid, dim3(64), lds, q, g, st, n, act, L);
-    else if (n == 1) hipLaunchKernelGGL((k_als_solve<T, KSRC_K2>), grid, dim3(64), lds, q, g, st, n, act, L);
-    else hipLaunchKernelGGL((k_als_solve<T, KSRC_PART>), grid, dim3(64), lds, q, g, st, n, act, L);
+    if (n == 0) hipLaunchKernelGGL((k_als_solve<T, KSRC_K1P>), grid, dim3(64), lds, q, g, st, n, R, act, L);
+    else if (n == 1) hipLaunchKernelGGL((k_als_solve<T, KSRC_K2>), grid, dim3(64), lds, q, g, st, n, R, act, L);
+    else hipLaunchKernelGGL((k_als_solve<T, KSRC_PART>), grid, dim3(64), lds, q, g, st, n, R, act, L);
 }
 
 template <typename T>
-void launch_als_fit(const Geo* g, const StateP<T>& st, int S, const int* act, const double* V, double* relerr,
+void launch_als_fit(const Geo* g, const StateP<T>& st, int S, int R, const int* act, const double* V, double* relerr,
                     double* xx, hipStream_t q) {
-    hipLaunchKernelGGL((k_als_fit<T>), dim3(S), dim3(256), 0, q, g, st, act, V, relerr, xx);
+    hipLaunchKernelGGL((k_als_fit<T>), dim3(S), dim3(256), 0, q, g, st, R, act, V, relerr, xx);
 }
 
 template <typename T>
-void launch_als_export(const Geo* g, const StateP<T>& st, int S, const double* xx, hipStream_t q) {
-    hipLaunchKernelGGL((k_als_export<T>), dim3(64, S), dim3(256), 0, q, g, st, xx);
+void launch_als_export(const Geo* g, const StateP<T>& st, int S, int R, const double* xx, hipStream_t q) {
+    hipLaunchKernelGGL((k_als_export<T>), dim3(64, S), dim3(256), 0, q, g, st, R, xx);
 }
 
 #define CPD_ALS_INST(T)                                                                                              \
     template void launch_als_gram<T>(const Geo*, const StateP<T>&, int, int, int, const int*, double*, hipStream_t);    \
     template void launch_als_solve<T>(const Geo*, const StateP<T>&, int, int, int, int, const int*, const double*,      \
                                       hipStream_t);                                                                  \
-    template void launch_als_fit<T>(const Geo*, const StateP<T>&, int, const int*, const double*, double*, double*,     \
+    template void launch_als_fit<T>(const Geo*, const StateP<T>&, int, int, const int*, const double*, double*, double*, \
                                     hipStream_t);                                                                    \
-    template void launch_als_export<T>(const Geo*, const StateP<T>&, int, const double*, hipStream_t);
+    template void launch_als_export<T>(const Geo*, const StateP<T>&, int, int, const double*, hipStream_t);
 CPD_ALS_INST(float)
 CPD_ALS_INST(double)
 

@@ -836,8 +836,9 @@ concpd_status loss_grad_t(concpd_ctx c, const StateP<T>& st, const void* const* 
 // while the fit runs, so the sweep's MTTKRP passes serve it unchanged; the
 // APG iterate is saved to the host before and put back after.
 template <typename T>
-concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, double eps, int max_it, int32_t* iters, double* relerr_out) {
-    const int S = c->S, R = c->R;
+concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, int R, double eps, int max_it, int32_t* iters,
+                          double* relerr_out) {
+    const int S = c->S;
     double* L = (double*)(c->ws + c->lay.lra);
     double* Lfac = L + c->lay.l_sig;
     double* rel = L + c->lay.l_work;
@@ -861,7 +862,7 @@ concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, double eps, int max
     for (int n = 0; n < 3; ++n) cpd::launch_als_gram<T>(c->dgeo, st, S, R, n, act, V, c->q);
     debug_passes<T>(c, st);
     k3_sum();
-    cpd::launch_als_fit<T>(c->dgeo, st, S, act, V, rel, xx, c->q);
+    cpd::launch_als_fit<T>(c->dgeo, st, S, R, act, V, rel, xx, c->q);
     HIPCHECK(hipMemcpyAsync(prev.data(), rel, sizeof(double) * S, hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipStreamSynchronize(c->q));
     for (int s = 0; s < S; ++s) {
@@ -875,19 +876,19 @@ concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, double eps, int max
     int active = S;
     for (int it = 1; it <= max_it && active > 0; ++it) {
         cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->p1dma, c->q);
-        cpd::launch_als_chol(c->dgeo, S, R, 0, act, V, Lfac, bad, c->q);
+        cpd::launch_als_chol(S, R, 0, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 0, Imax[0], act, Lfac, c->q);
         cpd::launch_als_gram<T>(c->dgeo, st, S, R, 0, act, V, c->q);
         cpd::launch_k2<T>(c->dgeo, st, itk, (int)c->lists.k2.size(), 1, c->q);
-        cpd::launch_als_chol(c->dgeo, S, R, 1, act, V, Lfac, bad, c->q);
+        cpd::launch_als_chol(S, R, 1, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 1, Imax[1], act, Lfac, c->q);
         cpd::launch_als_gram<T>(c->dgeo, st, S, R, 1, act, V, c->q);
         cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
         k3_sum();
-        cpd::launch_als_chol(c->dgeo, S, R, 2, act, V, Lfac, bad, c->q);
+        cpd::launch_als_chol(S, R, 2, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 2, Imax[2], act, Lfac, c->q);
         cpd::launch_als_gram<T>(c->dgeo, st, S, R, 2, act, V, c->q);
-        cpd::launch_als_fit<T>(c->dgeo, st, S, act, V, rel, xx, c->q);
+        cpd::launch_als_fit<T>(c->dgeo, st, S, R, act, V, rel, xx, c->q);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipMemcpyAsync(cur.data(), rel, sizeof(double) * S, hipMemcpyDeviceToHost, c->q));
         HIPCHECK(hipMemcpyAsync(hbad.data(), bad, sizeof(int) * S, hipMemcpyDeviceToHost, c->q));
@@ -906,7 +907,7 @@ concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, double eps, int max
         }
         HIPCHECK(hipMemcpyAsync(act, hact.data(), sizeof(int) * S, hipMemcpyHostToDevice, c->q));
     }
-    cpd::launch_als_export<T>(c->dgeo, st, S, xx, c->q);
+    cpd::launch_als_export<T>(c->dgeo, st, S, R, xx, c->q);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(c->q));
     return CONCPD_OK;
@@ -1226,19 +1227,21 @@ concpd_status lra_compress(concpd_ctx c, const int32_t* ranks, concpd_stats* out
 }
 
 concpd_status lra_compress_cp(concpd_ctx c, const double* const* init, uint64_t seed, double eps, int32_t max_it,
-                              int32_t* iters, double* relerr, concpd_stats* out) {
+                              int32_t cp_rank, int32_t* iters, double* relerr, concpd_stats* out) {
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
     if (c->lra) return fail(CONCPD_ESTATE, "lra_compress_cp: the context is already compressed");
     if (c->tucker.empty()) return fail(CONCPD_ESTATE, "lra_compress_cp: needs tucker_ranks (J_n >= R reserves the storage)");
+    if (cp_rank < 0 || cp_rank > c->R) return fail(CONCPD_EINVAL, "cp_rank %d not in [0, rank]", cp_rank);
+    const int Rt = cp_rank ? cp_rank : c->R;
     for (int i = 0; i < 3 * c->S; ++i)
-        if (c->tucker[i] < c->R)
-            return fail(CONCPD_EINVAL, "lra_compress_cp: tucker_ranks[%d] = %d < rank %d", i, c->tucker[i], c->R);
+        if (c->tucker[i] < Rt)
+            return fail(CONCPD_EINVAL, "lra_compress_cp: tucker_ranks[%d] = %d < CP rank %d", i, c->tucker[i], Rt);
     for (int s = 0; s < c->S; ++s)
         if (c->rk[s] != c->R) return fail(CONCPD_ENOTSUP, "lra_compress_cp: block ranks below R are not supported");
     if (!(eps >= 0.0) || !isfinite(eps)) return fail(CONCPD_EINVAL, "eps must be finite and >= 0");
     if (max_it < 0) return fail(CONCPD_EINVAL, "max_it must be >= 0");
-    const int S = c->S, R = c->R;
-    // starting factors (host, FP64): the caller's, or a seeded U[0,1] draw
+    const int S = c->S, R = Rt;
+    // starting factors (host, FP64, I_n x R~): the caller's, or a seeded U[0,1] draw
     std::vector<std::vector<double>> h(3 * S);
     if (!init) {
         SplitMix64 rng{seed};
@@ -1284,8 +1287,8 @@ concpd_status lra_compress_cp(concpd_ctx c, const double* const* init, uint64_t 
         HIPCHECK(hipStreamSynchronize(c->q));
     }
     c->drop_graph();
-    concpd_status st = c->f64 ? als_fit_all<double>(c, c->sd, eps, max_it, iters, relerr)
-                              : als_fit_all<float>(c, c->sf, eps, max_it, iters, relerr);
+    concpd_status st = c->f64 ? als_fit_all<double>(c, c->sd, Rt, eps, max_it, iters, relerr)
+                              : als_fit_all<float>(c, c->sf, Rt, eps, max_it, iters, relerr);
     // the APG iterate and the control block back in place
     hipStreamSynchronize(c->q);
     hc.stop = 0;

@@ -160,18 +160,19 @@ class CoupledCP:
         check(self._lib.lra_compress(self.ctx, pr, ctypes.byref(st)))
         return st.as_dict()
 
-    def lra_compress_cp(self, init=None, eps: float = 1e-4, max_it: int = 200, seed: int = 0) -> dict:
-        """Compress every block by a rank-R CPD fitted with ALS (the paper's own
-        first step of Algorithm 2).  init: optional [n][s] I_n x R arrays.
-        Returns the statistics plus 'als_iters' and 'als_relerr' per block."""
+    def lra_compress_cp(self, init=None, eps: float = 1e-4, max_it: int = 200, seed: int = 0, rank: int = 0) -> dict:
+        """Compress every block by a rank-R~ CPD fitted with ALS (the paper's own
+        first step of Algorithm 2); rank R~ <= R (0: R).  init: optional [n][s]
+        I_n x R~ arrays.  Returns the statistics plus 'als_iters' and
+        'als_relerr' per block."""
         st = Stats()
         keep = pI = None
         if init is not None:
             keep, pI = _dbl_ptr_array([init[n][s] for s in range(self.S) for n in range(3)])
         its = (ctypes.c_int32 * self.S)()
         rel = (ctypes.c_double * self.S)()
-        check(self._lib.lra_compress_cp(self.ctx, pI, ctypes.c_uint64(seed), float(eps), int(max_it), its, rel,
-                                        ctypes.byref(st)))
+        check(self._lib.lra_compress_cp(self.ctx, pI, ctypes.c_uint64(seed), float(eps), int(max_it), int(rank), its,
+                                        rel, ctypes.byref(st)))
         del keep
         out = st.as_dict()
         out["als_iters"] = list(its)

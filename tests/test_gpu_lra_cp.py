@@ -225,3 +225,39 @@ def test_full_size_c5_cp_compression_and_fit(dev):
     say(f"   k={st['k']} restarts={st['restarts']} fit(X~)={st['fit']:.5f} global fit={gf:.5f}")
     assert st["k"] == 200 and not st["nonfinite"]
     assert 0.80 <= gf <= 0.85
+
+
+def test_cp_rank_below_r(dev):
+    # eq. cosfunclra allows R~ < R: a rank-4 CPD compression under a rank-6
+    # model, one ALS iteration against the oracle, then one teacher-forced
+    # lra iteration on the oracle's own R~ = 4 Kruskal form
+    say("[cp-als] R~ = 4 < R = 6")
+    L, R, Rt = (2, 0, 0), 6, 4
+    P = synth.coupled_problem([(20, 24, 18), (20, 30, 22)], R, L, 15.0, 361, dtype=np.float32)
+    rng = np.random.default_rng(362)
+    init = [[rng.random((d[n], Rt)).astype(np.float32).astype(np.float64) for d in P.dims] for n in range(3)]
+    U0, lam0 = synth.uniform_init(P.dims, R, L, 363)
+    m = make_model(P, dev, R, L, U0=U0, lam0=lam0, tucker=(Rt, Rt, Rt))
+    out = m.lra_compress_cp(init=init, eps=0.0, max_it=1, rank=Rt)
+    facs = []
+    for s in range(P.S):
+        X = P.tensors[s].astype(np.float64)
+        want = cpals.als_iteration(X, [init[n][s] for n in range(3)])
+        facs.append(want)
+        A, G = m.tucker(s)
+        assert G.shape == (Rt, Rt, Rt) and all(a.shape == (P.dims[s][n], Rt) for n, a in enumerate(A))
+        for n in range(3):
+            assert rel(A[n], want[n]) <= 1e-4, (s, n)
+        assert out["als_relerr"][s] == pytest.approx(cpals.relerr(X, want), abs=1e-6)
+    cores, bases = zip(*[cpals.kruskal_as_tucker(U) for U in facs])
+    data = TuckerData(list(cores), list(bases))
+    U32 = [[u.astype(np.float32).astype(np.float64) for u in per] for per in U0]
+    st0 = apg.initial_state(data, U32, lam0)
+    st1 = apg.iterate(data, st0, Options(L=L))
+    s1 = m.lra_step(1)
+    say(f"   F1 gpu={s1['F']:.10e} oracle={st1.F:.10e}")
+    assert abs(s1["F"] - st1.F) / st1.F <= 1e-4
+    for s in range(P.S):
+        assert rel(m.lam(s), st1.lam[s]) <= 1e-4
+        for n in range(3):
+            assert rel(m.factor(n, s), st1.U[n][s]) <= 1e-4
