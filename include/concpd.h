@@ -9,8 +9,19 @@
  * Problem (Section II-C, eq. tensormodel and eq. costfunc): given blocks
  * M^(s) (s = 1..S) of size I1 x I2 x I3, find lambda^(s) >= 0 (the
  * super-diagonal of the core D^(s)) and factors U^(n,s) >= 0 of size
- * I_n x R whose first L_n columns are shared by every block, minimising
+ * I_n x R whose first L_n columns are shared by every block (or by a chosen
+ * group of blocks per mode, concpd_config.coupled_blocks; each block may have
+ * its own rank R^(s) <= R, concpd_config.block_ranks), minimising
  * 1/2 sum_s || M^(s) - [[D^(s); U^(1,s), U^(2,s), U^(3,s)]] ||_F^2.
+ *
+ * Entry points: configuration and workspace (concpd_query_workspace,
+ * concpd_init, concpd_destroy); Algorithm 1 (concpd_step, concpd_fit);
+ * Algorithm 2 (lra_compress_cp: the paper's CPD-ALS compression,
+ * lra_compress: truncated HOSVD, lra_step, lra_get_tucker); results and
+ * checkpoints (concpd_global_fit, concpd_get_factor, concpd_get_lambda,
+ * concpd_get_lipschitz, concpd_get_state, concpd_set_state); the autograd
+ * form (concpd_loss_grad); launch options and autotuning; measurement and
+ * test hooks (concpd_profile*, concpd_launch_floor, concpd_debug_*).
  *
  * Conventions used by every call:
  *  - Tensors are device buffers, C-contiguous (i3 fastest):
