@@ -48,7 +48,8 @@ def cpu_baseline(P, U0, lam0, budget_s=12.0):
     rest = time.perf_counter() - t1
     n = 1 + n_more
     return {"value": n / (first + rest), "unit": "iter/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n} oracle iterations (NumPy FP64) of the same 10x100^3 R=20 workload from the same init"}
+            "sample": f"{n} oracle iterations (NumPy FP64) of the same 10x100^3 R=20 workload from the same init"}, \
+        (n, apg.fit(P.tensors, st.lam, st.U))
 
 
 LRA_WORKLOAD = "c3_lra_10x256cube_r20"
@@ -401,7 +402,14 @@ def main():
                                        compress="cp_als")
     if not args.no_cpu_baseline:
         U0r = [[m_u.astype(np.float32).astype(np.float64) for m_u in per] for per in U0]
-        out["cpu_baseline"] = cpu_baseline(P, U0r, lam0)
+        out["cpu_baseline"], (n_or, fit_or) = cpu_baseline(P, U0r, lam0)
+        # the fit gate: the GPU path from the same start after as many
+        # iterations as the oracle sample ran, global fit within 1e-3
+        g = CoupledCP(tens, w["R"], w["L"], compute="f32", init_U=U0, init_lambda=lam0)
+        g.step(n_or)
+        fit_gpu = g.global_fit()
+        out["fit_gate"] = {"iterations": n_or, "gpu_global_fit": fit_gpu, "oracle_global_fit": fit_or,
+                           "delta": fit_gpu - fit_or, "pass": abs(fit_gpu - fit_or) <= 1e-3}
     print(json.dumps(out), flush=True)
 
 
