@@ -47,8 +47,17 @@ def cpu_baseline(P, U0, lam0, budget_s=12.0):
         st = apg.iterate(data, st, opt)
     rest = time.perf_counter() - t1
     n = 1 + n_more
+    host = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                host = line.split(":", 1)[1].strip()
+                break
+    except OSError:  # pragma: no cover
+        pass
     return {"value": n / (first + rest), "unit": "iter/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n} oracle iterations (NumPy FP64) of the same 10x100^3 R=20 workload from the same init"}, \
+            "sample": f"{n} oracle iterations (NumPy FP64) of the same 10x100^3 R=20 workload from the same init",
+            "host_cpu": host}, \
         (n, apg.fit(P.tensors, st.lam, st.U))
 
 
