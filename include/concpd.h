@@ -260,9 +260,11 @@ concpd_status concpd_set_state(concpd_ctx ctx, const double* const* U, const dou
  *   U_dev      [S*3] device I_n x R row-major arrays (index 3*s + n) in the
  *              context's factor type (double for compute_dtype F64, else float).
  *   lambda_dev [S] device double R-vectors.
- *   coupled    1: the first L_n columns of every mode-n factor are the shared
- *              U_C, read from block 0, and every block's gU receives the
- *              gradient with respect to U_C (the sum over s, eq. solbpgUCI);
+ *   coupled    1: the first L_n columns of every mode-n factor of the mode's
+ *              coupling group (every block unless coupled_blocks says
+ *              otherwise) are the shared U_C, read from the group's first
+ *              block, and every member's gU receives the gradient with
+ *              respect to U_C (the sum over the group, eq. solbpgUCI);
  *              0: every block's factors are taken as given and gU holds each
  *              block's own gradient (a caller that ties parameters sums them).
  *   gU_dev     [S*3] device outputs shaped like U_dev.

@@ -417,7 +417,7 @@ def run(data, U0, lam0, opt: Options, iters: Optional[int] = None, state: Option
 # ---------------------------------------------------------------------------
 
 
-def loss_and_grads(data, lam, U, L):
+def loss_and_grads(data, lam, U, L, coupled_blocks=None):
     """F and its partial gradients at (lam, U): d/dlam^(s) = H lam - b
     (eq. solbpgG) and d/dU^(n,s) = U D H_{-n} D - M_(n) U^{⊙-n} D
     (eq. solbpgU).  The shared columns' gradient is the sum over s
@@ -432,7 +432,8 @@ def loss_and_grads(data, lam, U, L):
             P = np.outer(lam[s], lam[s]) * hadamard_of_grams(Us, skip=n)
             g_U[n][s] = U[n][s] @ P - data.mttkrp(s, Us, n) * lam[s][None, :]
     g_C = []
+    grp = Options(L=tuple(L), coupled_blocks=coupled_blocks)
     for n in range(N):
         Ln = L[n]
-        g_C.append(sum(g_U[n][s][:, :Ln] for s in range(S)) if Ln > 0 else None)
+        g_C.append(sum(g_U[n][s][:, :Ln] for s in grp.group(n, S)) if Ln > 0 else None)
     return F, g_lam, g_U, g_C

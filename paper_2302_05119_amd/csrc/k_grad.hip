@@ -65,16 +65,18 @@ __global__ __launch_bounds__(256) void k_grad_u(const Geo* __restrict__ g, State
 }
 
 // Shared columns of a coupled mode: the gradient with respect to U_C is the
-// sum over blocks (block order), written to every block.
+// sum over the mode's coupling group (block order), written to every member.
 template <typename T>
 __global__ __launch_bounds__(256) void k_grad_shared(const Geo* __restrict__ g, int n, T* const* __restrict__ out) {
-    const int S = g->S, R = g->R, Ln = g->L[n], I = g->I[0][n];
+    const int R = g->R, Ln = g->L[n], ng = g->ngrp[n];
+    const int* grp = g->grp[n];
+    const int I = g->I[grp[0]][n];
     const long long e = blockIdx.x * 256LL + threadIdx.x;
     if (e >= (long long)I * Ln) return;
     const long long o = (e / Ln) * R + e % Ln;
     double acc = 0.0;
-    for (int s = 0; s < S; ++s) acc += (double)out[s][o];
-    for (int s = 0; s < S; ++s) out[s][o] = (T)acc;
+    for (int k = 0; k < ng; ++k) acc += (double)out[grp[k]][o];
+    for (int k = 0; k < ng; ++k) out[grp[k]][o] = (T)acc;
 }
 
 // In: largest I_n over the blocks, per mode.

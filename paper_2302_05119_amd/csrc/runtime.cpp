@@ -786,14 +786,18 @@ concpd_status loss_grad_t(concpd_ctx c, const StateP<T>& st, const void* const* 
     HIPCHECK(hipMemsetAsync(c->ws + P.gctrl, 0, sizeof(Ctrl), c->q));
     HIPCHECK(hipMemsetAsync(Ug, 0, (size_t)P.uslot * esz, c->q));
     HIPCHECK(hipMemsetAsync(sg.lam[0], 0, sizeof(double) * c->S * c->Rq, c->q));
-    // pack: I_n x R (row stride R) -> I_n x Rq; shared columns from block 0 when coupled
+    // pack: I_n x R (row stride R) -> I_n x Rq; shared columns from the first
+    // block of each coupling group when coupled
     for (int s = 0; s < c->S; ++s) {
         for (int n = 0; n < 3; ++n) {
             const int I = (int)c->dims[3 * s + n];
             T* dst = Ug + c->geo.uoff[n][s];
             HIPCHECK(hipMemcpy2DAsync(dst, c->Rq * esz, U_dev[3 * s + n], c->R * esz, c->R * esz, I, hipMemcpyDeviceToDevice, c->q));
-            if (coupled && c->L[n] > 0 && s > 0)
-                HIPCHECK(hipMemcpy2DAsync(dst, c->Rq * esz, U_dev[n], c->R * esz, c->L[n] * esz, I, hipMemcpyDeviceToDevice, c->q));
+            const uint64_t gm = group_mask(&c->cfg, n);
+            const int f = first_member(gm);
+            if (coupled && c->L[n] > 0 && in_group(gm, s) && s != f)
+                HIPCHECK(hipMemcpy2DAsync(dst, c->Rq * esz, U_dev[3 * f + n], c->R * esz, c->L[n] * esz, I,
+                                          hipMemcpyDeviceToDevice, c->q));
         }
         HIPCHECK(hipMemcpyAsync(sg.lam[0] + (size_t)s * c->Rq, lam_dev[s], sizeof(double) * c->R, hipMemcpyDeviceToDevice, c->q));
     }
@@ -1490,10 +1494,6 @@ concpd_status concpd_loss_grad(concpd_ctx c, const void* const* U_dev, const voi
                                double* loss, void* const* gU_dev, void* const* glam_dev) {
     if (!c || !U_dev || !lambda_dev || !loss || !gU_dev || !glam_dev) return fail(CONCPD_EINVAL, "NULL argument");
     if (c->lra) return fail(CONCPD_ESTATE, "concpd_loss_grad is not available in lra mode");
-    if (coupled && c->cfg.coupled_blocks)
-        for (int n = 0; n < 3; ++n)
-            if (c->L[n] > 0 && __builtin_popcountll(group_mask(&c->cfg, n)) != c->S)
-                return fail(CONCPD_ENOTSUP, "concpd_loss_grad with coupled = 1 needs every block in every coupling group");
     for (int i = 0; i < 3 * c->S; ++i)
         if (!U_dev[i] || !gU_dev[i]) return fail(CONCPD_EINVAL, "NULL factor pointer %d", i);
     for (int s = 0; s < c->S; ++s)

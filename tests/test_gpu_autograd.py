@@ -152,3 +152,40 @@ def test_loss_grad_leaves_the_iterate_alone():
     for n in range(3):
         for s in range(P.S):
             np.testing.assert_array_equal(m.factor(n, s), m2.factor(n, s))
+
+
+@pytest.mark.parametrize("compute,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_loss_and_gradients_with_coupling_groups(compute, tol):
+    # flexible coupling (Section III-C): mode 1 shared by blocks 0 and 2 only,
+    # mode 3 by blocks 1 and 2; the shared gradient is the group's sum
+    import torch
+    from paper_2302_05119_amd import CoupledCP
+    say(f"[loss_grad] coupling groups compute={compute}")
+    dtype = np.float64 if compute == "f64" else np.float32
+    L, R, groups = (2, 0, 1), 4, ((0, 2), None, (1, 2))
+    P = synth.coupled_problem([(9, 10, 11), (7, 12, 11), (9, 8, 11)], R, (0, 0, 0), 10.0, 741, dtype=dtype)
+    dev = torch.device("cuda:0")
+    m = CoupledCP([torch.from_numpy(X).to(dev) for X in P.tensors], R, L, compute=compute, seed=3,
+                  coupled_blocks=groups)
+    rng = np.random.default_rng(742)
+    U = [[rng.random((d[n], R)) for d in P.dims] for n in range(3)]
+    for n, grp in ((0, groups[0]), (2, groups[2])):
+        for b in grp[1:]:
+            U[n][b][:, :L[n]] = U[n][grp[0]][:, :L[n]]
+    if compute != "f64":
+        U = [[u.astype(np.float32).astype(np.float64) for u in per] for per in U]
+    lam = [rng.random(R) + 0.5 for _ in range(P.S)]
+    F_ref, gl_ref, gU_ref, gC_ref = apg.loss_and_grads(DenseData(P.tensors), lam, U, L, coupled_blocks=groups)
+    Ut, lt = to_dev(U, lam, compute, dev)
+    F, gU, gl = m.loss_grad(Ut, lt, coupled=True)
+    say(f"   F gpu={F:.15e} oracle={F_ref:.15e}")
+    assert abs(F - F_ref) / F_ref <= tol
+    for s in range(P.S):
+        assert rel(gl[s].cpu().numpy(), gl_ref[s]) <= tol
+        for n in range(3):
+            g = gU[n][s].cpu().numpy()
+            member = L[n] > 0 and s in (groups[n] or range(P.S))
+            Ls = L[n] if member else 0
+            assert rel(g[:, Ls:], gU_ref[n][s][:, Ls:]) <= tol, (n, s)
+            if member:
+                assert rel(g[:, :Ls], gC_ref[n]) <= tol, (n, s)
