@@ -193,15 +193,16 @@ concpd_status lra_step(concpd_ctx ctx, int32_t n_iter, concpd_stats* out);
  * super-diagonal core of ones, which lra_get_tucker returns), and lra_step
  * iterates on it (eq. eqlrau / eqlrag).  The APG iterate is left as it was.
  *   cp_rank R~, 1 <= R~ <= R (eq. cosfunclra allows R~ <= R; the paper's
- *           runs use R~ = R), or 0 for R.
- *   init    [S*3] host I_n x R~ row-major starting factors at index 3*s + n
+ *           runs use R~ = R), or 0 for R; block s is fitted at rank
+ *           R~_s = min(R~, R^(s)).
+ *   init    [S*3] host I_n x R~_s row-major starting factors at index 3*s + n
  *           (copied), or NULL for a seeded U[0,1] draw (SplitMix64(seed);
  *           order: n, then s, then row, then column).
  *   iters   [S] ALS iterations run per block, or NULL.
  *   relerr  [S] final ||M - X~|| / ||M|| per block (M: the operand copy the
  *           MTTKRP reads), or NULL.
- * Needs tucker_ranks with every J_n >= R~ (so R~ <= I_n; they reserve the compressed form's
- * storage), R^(s) = R for every block, and a context not yet compressed.
+ * Needs tucker_ranks with every J_n >= R~_s (so R~_s <= I_n; they reserve the compressed form's
+ * storage) and a context not yet compressed.
  * Errors: EINVAL, ESTATE, ENOTSUP, ENONFINITE (a Gram H_n that is not
  * positive definite, e.g. a rank-deficient start, or a non-finite fit; the
  * context is then left uncompressed with its iterate intact), EHIP. */

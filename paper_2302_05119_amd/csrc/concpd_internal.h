@@ -37,6 +37,7 @@ struct Ctrl {
 struct Geo {
     int S, R, Rq;                 // Rq = R rounded up to a multiple of 4 (factor row stride)
     int L[3];
+    int rk[CPD_MAXS];             // R^(s): columns in use per block (the rest stay zero)
     int ngrp[3];                  // blocks of mode n's coupling group (L_n > 0), else every block
     int grp[3][CPD_MAXS];         // their indices, ascending
     int upd_core;
@@ -127,7 +128,7 @@ void launch_empty(hipStream_t q);
 void launch_pad_copy(const void* src, int src_dtype, void* dst, int dst_dtype, long long rows, int I3, int ld, hipStream_t q);
 void launch_finite_check(const void* src, int dtype, long long n, int* flag, hipStream_t q);
 template <typename T> void launch_als_gram(const Geo* g, const StateP<T>& st, int S, int R, int n, const int* act, double* V, hipStream_t q);
-void launch_als_chol(int S, int R, int n, const int* act, const double* V, double* L, int* bad, hipStream_t q);
+void launch_als_chol(const Geo* g, int S, int R, int n, const int* act, const double* V, double* L, int* bad, hipStream_t q);
 template <typename T> void launch_als_solve(const Geo* g, const StateP<T>& st, int S, int R, int n, int Imax, const int* act, const double* L, hipStream_t q);
 template <typename T> void launch_als_fit(const Geo* g, const StateP<T>& st, int S, int R, const int* act, const double* V, double* relerr, double* xx, hipStream_t q);
 template <typename T> void launch_als_export(const Geo* g, const StateP<T>& st, int S, int R, const double* xx, hipStream_t q);

@@ -33,6 +33,8 @@ __global__ __launch_bounds__(256) void k_als_gram(const Geo* __restrict__ g, Sta
     constexpr int CH = 32;
     const int s = blockIdx.x, Rq = g->Rq, tid = threadIdx.x;
     if (!act[s]) return;
+    const int Rs = R;                      // the block's stride in V
+    R = min(R, g->rk[s]);                  // its CP rank
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     double* stage = (double*)smraw;        // 32 x R
     const int npair = R * R;
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(256) void k_als_gram(const Geo* __restrict__ g, Sta
             }
         }
     }
-    double* out = V + (3LL * s + n) * npair;
+    double* out = V + (3LL * s + n) * Rs * Rs;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int e = tid + 256 * j;
@@ -72,19 +74,21 @@ __global__ __launch_bounds__(256) void k_als_gram(const Geo* __restrict__ g, Sta
 // factor L (lower, row-major R x R) for every active block; bad[s] = 1 if a
 // pivot falls below 1e-13 of its starting diagonal entry or is not finite
 // (H_n numerically singular).
-__global__ __launch_bounds__(256) void k_als_chol(int n, int R, const int* __restrict__ act,
+__global__ __launch_bounds__(256) void k_als_chol(const Geo* __restrict__ g, int n, int R, const int* __restrict__ act,
                                                   const double* __restrict__ V, double* __restrict__ Lout,
                                                   int* __restrict__ bad) {
     const int s = blockIdx.x, tid = threadIdx.x;
     if (!act[s]) return;
+    const long long RR = (long long)R * R;  // per-block storage
+    R = min(R, g->rk[s]);
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     double* H = (double*)smraw;            // R x R
     __shared__ int flag;
     __shared__ double diag[CPD_MAXR];
     if (tid == 0) flag = 0;
     const int a = n == 0 ? 1 : 0, b = n == 2 ? 1 : 2;
-    const double* Va = V + (3LL * s + a) * R * R;
-    const double* Vb = V + (3LL * s + b) * R * R;
+    const double* Va = V + (3LL * s + a) * RR;
+    const double* Vb = V + (3LL * s + b) * RR;
     for (int e = tid; e < R * R; e += 256) H[e] = Va[e] * Vb[e];
     __syncthreads();
     for (int j = tid; j < R; j += 256) diag[j] = H[j * R + j];
@@ -109,7 +113,7 @@ __global__ __launch_bounds__(256) void k_als_chol(int n, int R, const int* __res
         }
         __syncthreads();
     }
-    double* L = Lout + (long long)s * R * R;
+    double* L = Lout + (long long)s * RR;
     for (int e = tid; e < R * R; e += 256) {
         const int i = e / R, k = e % R;
         L[e] = k <= i ? H[e] : 0.0;
@@ -125,13 +129,15 @@ __global__ __launch_bounds__(64) void k_als_solve(const Geo* __restrict__ g, Sta
     apply_rot(st);
     const int s = blockIdx.y, Rq = g->Rq, lane = threadIdx.x;
     if (!act[s]) return;
+    const long long RR = (long long)R * R;
+    R = min(R, g->rk[s]);
     const int I = g->I[s][n];
     const int row0 = blockIdx.x * 64;
     if (row0 >= I) return;
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     double* L = (double*)smraw;            // R x R
     double* x = L + R * R;                 // R x 64
-    const double* Lg = Lin + (long long)s * R * R;
+    const double* Lg = Lin + (long long)s * RR;
     for (int e = lane; e < R * R; e += 64) L[e] = Lg[e];
     const int i = row0 + lane;
     const int ic = min(i, I - 1);
@@ -168,6 +174,8 @@ __global__ __launch_bounds__(256) void k_als_fit(const Geo* __restrict__ g, Stat
     apply_rot(st);
     const int s = blockIdx.x, Rq = g->Rq, tid = threadIdx.x;
     if (!act[s]) return;
+    const long long RR = (long long)R * R;
+    R = min(R, g->rk[s]);
     __shared__ double red[2][256];
     const int I3 = g->I[s][2];
     const T* U3 = st.U[1] + g->uoff[2][s];
@@ -178,9 +186,9 @@ __global__ __launch_bounds__(256) void k_als_fit(const Geo* __restrict__ g, Stat
         const int c = (int)(e % R);
         ip = fma((double)K3[i * Rq + c], (double)U3[i * Rq + c], ip);
     }
-    const double* V0 = V + 3LL * s * R * R;
-    const double* V1 = V0 + R * R;
-    const double* V2 = V1 + R * R;
+    const double* V0 = V + 3LL * s * RR;
+    const double* V1 = V0 + RR;
+    const double* V2 = V1 + RR;
     double hs = 0.0;
     for (int e = tid; e < R * R; e += 256) hs += V0[e] * V1[e] * V2[e];
     red[0][tid] = ip;
@@ -208,6 +216,7 @@ __global__ __launch_bounds__(256) void k_als_export(const Geo* __restrict__ g, S
                                                     const double* __restrict__ xx) {
     apply_rot(st);
     const int s = blockIdx.y, Rq = g->Rq;
+    R = min(R, g->rk[s]);
     double* L = st.lra;
     const long long stride = (long long)gridDim.x * 256;
     for (int n = 0; n < 3; ++n) {
@@ -234,8 +243,9 @@ void launch_als_gram(const Geo* g, const StateP<T>& st, int S, int R, int n, con
     hipLaunchKernelGGL((k_als_gram<T>), dim3(S), dim3(256), sizeof(double) * 32 * (size_t)R, q, g, st, n, R, act, V);
 }
 
-void launch_als_chol(int S, int R, int n, const int* act, const double* V, double* L, int* bad, hipStream_t q) {
-    hipLaunchKernelGGL(k_als_chol, dim3(S), dim3(256), sizeof(double) * (size_t)R * R, q, n, R, act, V, L, bad);
+void launch_als_chol(const Geo* g, int S, int R, int n, const int* act, const double* V, double* L, int* bad,
+                     hipStream_t q) {
+    hipLaunchKernelGGL(k_als_chol, dim3(S), dim3(256), sizeof(double) * (size_t)R * R, q, g, n, R, act, V, L, bad);
 }
 
 template <typename T>

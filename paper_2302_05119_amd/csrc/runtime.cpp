@@ -880,16 +880,16 @@ concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, int R, double eps, 
     int active = S;
     for (int it = 1; it <= max_it && active > 0; ++it) {
         cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->p1dma, c->q);
-        cpd::launch_als_chol(S, R, 0, act, V, Lfac, bad, c->q);
+        cpd::launch_als_chol(c->dgeo, S, R, 0, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 0, Imax[0], act, Lfac, c->q);
         cpd::launch_als_gram<T>(c->dgeo, st, S, R, 0, act, V, c->q);
         cpd::launch_k2<T>(c->dgeo, st, itk, (int)c->lists.k2.size(), 1, c->q);
-        cpd::launch_als_chol(S, R, 1, act, V, Lfac, bad, c->q);
+        cpd::launch_als_chol(c->dgeo, S, R, 1, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 1, Imax[1], act, Lfac, c->q);
         cpd::launch_als_gram<T>(c->dgeo, st, S, R, 1, act, V, c->q);
         cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
         k3_sum();
-        cpd::launch_als_chol(S, R, 2, act, V, Lfac, bad, c->q);
+        cpd::launch_als_chol(c->dgeo, S, R, 2, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 2, Imax[2], act, Lfac, c->q);
         cpd::launch_als_gram<T>(c->dgeo, st, S, R, 2, act, V, c->q);
         cpd::launch_als_fit<T>(c->dgeo, st, S, R, act, V, rel, xx, c->q);
@@ -989,6 +989,7 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
     }
     build_lists(&c->cfg, &c->lists);
     plan(&c->cfg, c->lists, &c->lay, &c->geo);
+    for (int s = 0; s < c->S; ++s) c->geo.rk[s] = c->rk[s];
     if (ws_bytes < c->lay.total) {
         const size_t need = c->lay.total;
         delete c;
@@ -1237,28 +1238,29 @@ concpd_status lra_compress_cp(concpd_ctx c, const double* const* init, uint64_t 
     if (c->tucker.empty()) return fail(CONCPD_ESTATE, "lra_compress_cp: needs tucker_ranks (J_n >= R reserves the storage)");
     if (cp_rank < 0 || cp_rank > c->R) return fail(CONCPD_EINVAL, "cp_rank %d not in [0, rank]", cp_rank);
     const int Rt = cp_rank ? cp_rank : c->R;
-    for (int i = 0; i < 3 * c->S; ++i)
-        if (c->tucker[i] < Rt)
-            return fail(CONCPD_EINVAL, "lra_compress_cp: tucker_ranks[%d] = %d < CP rank %d", i, c->tucker[i], Rt);
-    for (int s = 0; s < c->S; ++s)
-        if (c->rk[s] != c->R) return fail(CONCPD_ENOTSUP, "lra_compress_cp: block ranks below R are not supported");
+    const int S = c->S;
+    // block s is fitted at rank min(R~, R^(s))
+    std::vector<int> rb(S);
+    for (int s = 0; s < S; ++s) rb[s] = std::min(Rt, c->rk[s]);
+    for (int i = 0; i < 3 * S; ++i)
+        if (c->tucker[i] < rb[i / 3])
+            return fail(CONCPD_EINVAL, "lra_compress_cp: tucker_ranks[%d] = %d < CP rank %d", i, c->tucker[i], rb[i / 3]);
     if (!(eps >= 0.0) || !isfinite(eps)) return fail(CONCPD_EINVAL, "eps must be finite and >= 0");
     if (max_it < 0) return fail(CONCPD_EINVAL, "max_it must be >= 0");
-    const int S = c->S, R = Rt;
-    // starting factors (host, FP64, I_n x R~): the caller's, or a seeded U[0,1] draw
+    // starting factors (host, FP64, I_n x min(R~, R^(s))): the caller's, or a seeded U[0,1] draw
     std::vector<std::vector<double>> h(3 * S);
     if (!init) {
         SplitMix64 rng{seed};
         for (int n = 0; n < 3; ++n)
             for (int s = 0; s < S; ++s) {
-                h[3 * s + n].resize((size_t)c->dims[3 * s + n] * R);
+                h[3 * s + n].resize((size_t)c->dims[3 * s + n] * rb[s]);
                 for (double& v : h[3 * s + n]) v = rng.uniform();
             }
     }
     for (int i = 0; i < 3 * S; ++i) {
         const double* p = init ? init[i] : h[i].data();
         if (!p) return fail(CONCPD_EINVAL, "init[%d] is NULL", i);
-        if (!all_finite(p, (size_t)c->dims[i] * R)) return fail(CONCPD_ENONFINITE, "init[%d] is not finite", i);
+        if (!all_finite(p, (size_t)c->dims[i] * rb[i / 3])) return fail(CONCPD_ENONFINITE, "init[%d] is not finite", i);
     }
     // save the APG iterate's current slot and the control block
     const int phys = phys_slot3(c, 1);
@@ -1275,7 +1277,7 @@ concpd_status lra_compress_cp(concpd_ctx c, const double* const* init, uint64_t 
         for (int s = 0; s < S; ++s)
             for (int n = 0; n < 3; ++n) {
                 const double* src = init ? init[3 * s + n] : h[3 * s + n].data();
-                const int I = (int)c->dims[3 * s + n];
+                const int I = (int)c->dims[3 * s + n], R = rb[s];
                 for (int i = 0; i < I; ++i)
                     for (int r = 0; r < R; ++r) {
                         const size_t e = (size_t)c->geo.uoff[n][s] + (size_t)i * c->Rq + r;
@@ -1302,7 +1304,7 @@ concpd_status lra_compress_cp(concpd_ctx c, const double* const* init, uint64_t 
     HIPCHECK(hipStreamSynchronize(c->q));
     if (st != CONCPD_OK) return st;
     for (int s = 0; s < S; ++s)
-        for (int n = 0; n < 3; ++n) c->geo.J[s][n] = R;
+        for (int n = 0; n < 3; ++n) c->geo.J[s][n] = rb[s];
     c->geo.lra = 1;
     c->lra = 1;
     HIPCHECK(hipMemcpyAsync(c->dgeo, &c->geo, sizeof(Geo), hipMemcpyHostToDevice, c->q));

@@ -174,6 +174,9 @@ class CoupledCP:
         check(self._lib.lra_compress_cp(self.ctx, pI, ctypes.c_uint64(seed), float(eps), int(max_it), int(rank), its,
                                         rel, ctypes.byref(st)))
         del keep
+        # the Kruskal form of block s has min(R~, R^(s)) columns in every mode
+        rt = int(rank) or self.R
+        self._ranks_c = (ctypes.c_int32 * (3 * self.S))(*[min(rt, r) for r in self.block_ranks for _ in range(3)])
         out = st.as_dict()
         out["als_iters"] = list(its)
         out["als_relerr"] = list(rel)

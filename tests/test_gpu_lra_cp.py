@@ -173,8 +173,6 @@ def test_rejections(dev):
         CoupledCP(tens, 4, (0, 0, 0)).lra_compress_cp()                        # no compressed-form storage
     with pytest.raises(ConcpdError):
         CoupledCP(tens, 4, (0, 0, 0), tucker_ranks=(3, 4, 4)).lra_compress_cp()  # J_1 < R
-    with pytest.raises(ConcpdError):
-        CoupledCP(tens, 4, (0, 0, 0), tucker_ranks=(4, 4, 4), block_ranks=(4, 3)).lra_compress_cp()
     m = CoupledCP(tens, 4, (0, 0, 0), tucker_ranks=(4, 4, 4))
     with pytest.raises(ConcpdError):
         m.lra_compress_cp(eps=-1.0)
@@ -261,3 +259,42 @@ def test_cp_rank_below_r(dev):
         assert rel(m.lam(s), st1.lam[s]) <= 1e-4
         for n in range(3):
             assert rel(m.factor(n, s), st1.U[n][s]) <= 1e-4
+
+
+def test_cp_compression_with_block_ranks(dev):
+    # uneven R^(s) (5, 3): block s is fitted at rank R^(s); one ALS iteration
+    # against the oracle per block, then one teacher-forced lra iteration of
+    # the rank-(5, 3) model on the oracle's own Kruskal forms
+    say("[cp-als] block ranks (5, 3)")
+    L, R, ranks = (2, 0, 0), 5, (5, 3)
+    P = synth.coupled_problem([(20, 24, 18), (20, 30, 22)], R, L, 15.0, 371, dtype=np.float32)
+    rng = np.random.default_rng(372)
+    init = [[rng.random((d[n], ranks[s])).astype(np.float32).astype(np.float64) for s, d in enumerate(P.dims)]
+            for n in range(3)]
+    U5, l5 = synth.uniform_init(P.dims, R, L, 373)
+    U0 = [[U5[n][s][:, :ranks[s]].copy() for s in range(P.S)] for n in range(3)]
+    lam0 = [l5[s][:ranks[s]].copy() for s in range(P.S)]
+    m = make_model(P, dev, R, L, U0=U0, lam0=lam0, tucker=(5, 5, 5), block_ranks=ranks)
+    out = m.lra_compress_cp(init=init, eps=0.0, max_it=1)
+    facs = []
+    for s in range(P.S):
+        X = P.tensors[s].astype(np.float64)
+        want = cpals.als_iteration(X, [init[n][s] for n in range(3)])
+        facs.append(want)
+        A, G = m.tucker(s)
+        assert G.shape == (ranks[s],) * 3
+        for n in range(3):
+            assert A[n].shape == (P.dims[s][n], ranks[s]) and rel(A[n], want[n]) <= 1e-4, (s, n)
+        assert out["als_relerr"][s] == pytest.approx(cpals.relerr(X, want), abs=1e-6)
+    cores, bases = zip(*[cpals.kruskal_as_tucker(U) for U in facs])
+    data = TuckerData(list(cores), list(bases))
+    U32 = [[u.astype(np.float32).astype(np.float64) for u in per] for per in U0]
+    st1 = apg.iterate(data, apg.initial_state(data, U32, lam0), Options(L=L))
+    s1 = m.lra_step(1)
+    say(f"   F1 gpu={s1['F']:.10e} oracle={st1.F:.10e}")
+    assert abs(s1["F"] - st1.F) / st1.F <= 1e-4
+    for s in range(P.S):
+        assert rel(m.lam(s), st1.lam[s]) <= 1e-4
+        for n in range(3):
+            assert rel(m.factor(n, s), st1.U[n][s]) <= 1e-4
+            assert np.all(m.factor(n, s, padded=True)[:, ranks[s]:] == 0.0)
