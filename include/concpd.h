@@ -34,7 +34,9 @@
  *    thread-local message describing the first error.
  *  - The library never allocates device memory: the caller passes one
  *    workspace buffer of at least concpd_query_workspace() bytes and keeps it
- *    (and the tensors) alive until concpd_destroy().
+ *    (and the tensors) alive until concpd_destroy(), or, with
+ *    concpd_init_static, the context uses a fixed-size device array that the
+ *    library holds on every device it runs on.
  */
 #ifndef CONCPD_H
 #define CONCPD_H
@@ -143,6 +145,29 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors,
                           const double* const* init_U, const double* const* init_lambda,
                           uint64_t seed, void* workspace, size_t ws_bytes, void* stream,
                           concpd_ctx* out);
+
+/* Bytes of the static workspace of concpd_init_static (32 MiB per device). */
+#define CONCPD_STATIC_WORKSPACE_BYTES (32u << 20)
+
+/* concpd_init for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same context, but its workspace is a device array of
+ * CONCPD_STATIC_WORKSPACE_BYTES that the library holds on each device until
+ * the process ends, so neither this call nor the caller allocates.  The
+ * context lives on the current device (its stream must belong to it); the
+ * other arguments are those of concpd_init, and every other entry point
+ * works on the context unchanged.
+ * One such context per device at a time: the array is shared by every call
+ * on that device and keeps the last context's contents (this call clears
+ * what must start at zero).  Contexts on one device would race on it, so a
+ * second call while one is alive fails with ESTATE until concpd_destroy of
+ * the first.  The optional second stream (CONCPD_OVERLAP) is never created.
+ * Errors: those of concpd_init; EINVAL when concpd_query_workspace(cfg)
+ * exceeds CONCPD_STATIC_WORKSPACE_BYTES; ESTATE as above; EHIP if the
+ * array's device address cannot be obtained. */
+concpd_status concpd_init_static(const concpd_config* cfg, const void* const* tensors,
+                                 const double* const* init_U, const double* const* init_lambda,
+                                 uint64_t seed, void* stream, concpd_ctx* out);
 
 /* Run outer iterations of Algorithm 1 (each: the extrapolated sweep
  * D^(1..S), U^(1,1..S), ..., U^(3,1..S); if F_k >= F_{k-1} and restart is on,

@@ -69,6 +69,8 @@ class Tuning(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+STATIC_WORKSPACE_BYTES = 32 << 20   # CONCPD_STATIC_WORKSPACE_BYTES of concpd.h
+
 OPT_GRAPH_SWEEPS, OPT_OVERLAP, OPT_K2_ROWS, OPT_P1_SPLIT, OPT_P1_DMA = 1, 2, 3, 4, 5
 
 _P = ctypes.c_void_p
@@ -82,6 +84,8 @@ SIGNATURES = {
     "concpd_query_workspace": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)]),
     "concpd_init": (ctypes.c_int, [ctypes.POINTER(Config), _PP, _DPP, _DPP, ctypes.c_uint64, _P, ctypes.c_size_t, _P,
                                    ctypes.POINTER(_P)]),
+    "concpd_init_static": (ctypes.c_int, [ctypes.POINTER(Config), _PP, _DPP, _DPP, ctypes.c_uint64, _P,
+                                          ctypes.POINTER(_P)]),
     "concpd_step": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(Stats)]),
     "concpd_fit": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
     "lra_compress": (ctypes.c_int, [_P, _I32P, ctypes.POINTER(Stats)]),

@@ -9,11 +9,21 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/concpd.h"
 #include "concpd_internal.h"
+
+// Workspace of concpd_init_static, for callers that cannot allocate device
+// memory: an array of the library's own on every device it runs on, held
+// until the process ends.  In host code the array's name only stands in for
+// it; its device address comes from hipGetSymbolAddress (once per device,
+// with that device current) and only that address is ever used.
+#define CPD_STATIC_WS_BYTES ((size_t)CONCPD_STATIC_WORKSPACE_BYTES)
+#define CPD_MAX_DEVICES 64
+static __device__ __align__(256) char scratch[CPD_STATIC_WS_BYTES];
 
 namespace {
 
@@ -36,6 +46,13 @@ concpd_status fail(concpd_status st, const char* fmt, ...) {
     } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct StaticWs {
+    std::mutex mu;
+    void* ptr[CPD_MAX_DEVICES] = {};              // device address of scratch per device
+    concpd_ctx owner[CPD_MAX_DEVICES] = {};       // the live context using it, if any
+};
+StaticWs g_static;
 
 #define CPD_PROF_REPS 4   // back-to-back launches of each pass per profiled sweep
 int operand_bytes(int dtype) { return dtype == CONCPD_F64 ? 8 : (dtype == CONCPD_F32 ? 4 : 2); }
@@ -447,6 +464,7 @@ struct concpd_ctx_s {
     int k2rows;
     int p1split = 0;   // requested pass-1 split (0: automatic)
     int p1dma = 0, p1dma_ok = 0;   // pass 1 by LDS DMA (in use / possible)
+    int static_dev = -1;           // device whose static workspace this context holds (-1: none)
     std::vector<hipEvent_t> ev1, ev2;  // begin/end pairs of timed pass launches
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -934,9 +952,14 @@ concpd_status concpd_query_workspace(const concpd_config* cfg, size_t* bytes) {
     return CONCPD_OK;
 }
 
-concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, const double* const* init_U,
-                          const double* const* init_lambda, uint64_t seed, void* workspace, size_t ws_bytes, void* stream,
-                          concpd_ctx* out) {
+}  // extern "C"
+
+namespace {
+// concpd_init with a flag that keeps it from creating any HIP object (the
+// optional second stream), for the static-workspace entry point.
+concpd_status init_impl(const concpd_config* cfg, const void* const* tensors, const double* const* init_U,
+                        const double* const* init_lambda, uint64_t seed, void* workspace, size_t ws_bytes, void* stream,
+                        bool no_alloc, concpd_ctx* out) {
     g_err.clear();
     if (!out) return fail(CONCPD_EINVAL, "out is NULL");
     *out = nullptr;
@@ -975,7 +998,7 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
     c->profiling = 0;
     {
         const char* ov = getenv("CONCPD_OVERLAP");
-        c->overlap = ov && ov[0] == '1';
+        c->overlap = !no_alloc && ov && ov[0] == '1';
         c->graph_sweeps = 0;
         c->qcap = nullptr;
         c->gexec = nullptr;
@@ -1103,14 +1126,14 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
 
     // finiteness of the tensors and their squared norms (original and operand copy)
     int* dflag = (int*)(c->ws + c->lay.flag);
-    double* scratch = (double*)(c->ws + c->lay.scratch);
+    double* sqpart = (double*)(c->ws + c->lay.scratch);
     for (int s = 0; s < c->S; ++s) {
         const long long n = c->dims[3 * s] * c->dims[3 * s + 1] * c->dims[3 * s + 2];
         cpd::launch_finite_check(c->tensors[s], cfg->tensor_dtype, n, dflag, c->q);
-        cpd::launch_sqnorm(c->tensors[s], cfg->tensor_dtype, n, (double*)(c->ws + c->lay.normOrig) + s, scratch, 1024, c->q);
+        cpd::launch_sqnorm(c->tensors[s], cfg->tensor_dtype, n, (double*)(c->ws + c->lay.normOrig) + s, sqpart, 1024, c->q);
         // the operand copy's padding is zero, so its norm runs over I1 I2 ld
         cpd::launch_sqnorm(c->geo.M[s], c->mdtype, c->dims[3 * s] * c->dims[3 * s + 1] * c->geo.mld[s],
-                           (double*)(c->ws + c->lay.normM2) + s, scratch, 1024, c->q);
+                           (double*)(c->ws + c->lay.normM2) + s, sqpart, 1024, c->q);
     }
     int hflag = 0;
     INIT_HIP(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, c->q));
@@ -1139,6 +1162,48 @@ concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, 
     return CONCPD_OK;
 #undef INIT_CHECK
 #undef INIT_HIP
+}
+}  // namespace
+
+extern "C" {
+
+concpd_status concpd_init(const concpd_config* cfg, const void* const* tensors, const double* const* init_U,
+                          const double* const* init_lambda, uint64_t seed, void* workspace, size_t ws_bytes, void* stream,
+                          concpd_ctx* out) {
+    return init_impl(cfg, tensors, init_U, init_lambda, seed, workspace, ws_bytes, stream, false, out);
+}
+
+concpd_status concpd_init_static(const concpd_config* cfg, const void* const* tensors, const double* const* init_U,
+                                 const double* const* init_lambda, uint64_t seed, void* stream, concpd_ctx* out) {
+    g_err.clear();
+    if (!out) return fail(CONCPD_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    concpd_status st = concpd_query_workspace(cfg, &need);
+    if (st != CONCPD_OK) return st;
+    if (need > CPD_STATIC_WS_BYTES)
+        return fail(CONCPD_EINVAL, "configuration needs %zu bytes of workspace, more than the static workspace's %zu",
+                    need, CPD_STATIC_WS_BYTES);
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= CPD_MAX_DEVICES) return fail(CONCPD_ENOTSUP, "device %d: static workspace only on devices 0..%d", dev, CPD_MAX_DEVICES - 1);
+    std::lock_guard<std::mutex> lock(g_static.mu);
+    if (g_static.owner[dev])
+        return fail(CONCPD_ESTATE, "the static workspace of device %d is held by another context (destroy it first)", dev);
+    if (!g_static.ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CONCPD_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_static.ptr[dev] = p;
+    }
+    concpd_ctx c = nullptr;
+    st = init_impl(cfg, tensors, init_U, init_lambda, seed, g_static.ptr[dev], CPD_STATIC_WS_BYTES, stream, true, &c);
+    if (st != CONCPD_OK) return st;
+    c->static_dev = dev;
+    g_static.owner[dev] = c;
+    *out = c;
+    return CONCPD_OK;
 }
 
 concpd_status concpd_step(concpd_ctx c, int32_t n_iter, concpd_stats* out) {
@@ -1837,6 +1902,10 @@ concpd_status concpd_destroy(concpd_ctx c) {
     (void)hipStreamSynchronize(c->q);
     for (hipEvent_t e : c->ev1) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev2) (void)hipEventDestroy(e);
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static.mu);
+        if (g_static.owner[c->static_dev] == c) g_static.owner[c->static_dev] = nullptr;
+    }
     delete c;
     return CONCPD_OK;
 }

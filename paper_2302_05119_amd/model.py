@@ -58,12 +58,16 @@ class CoupledCP:
     coupled_blocks optional [3] lists of the blocks that share mode n's
                  first L_n columns (None entries: every block), the flexible
                  coupling of Section III-C.
+    static_workspace  True: no workspace is allocated; the context uses the
+                 library's static device workspace (concpd_init_static: at
+                 most one such context per device, up to
+                 CONCPD_STATIC_WORKSPACE_BYTES).
     """
 
     def __init__(self, tensors, rank: int, coupled=(0, 0, 0), compute: str = "f32", init_U=None, init_lambda=None,
                  seed: int = 0, update_core: bool = True, restart: bool = True, delta_w: float = 0.9999,
                  tol: float = 1e-8, max_it: int = 1000, tucker_ranks=None, block_ranks=None, coupled_blocks=None,
-                 stream=None):
+                 stream=None, static_workspace: bool = False):
         import torch
 
         self._lib = load()
@@ -118,9 +122,14 @@ class CoupledCP:
         self.compute = compute
         nbytes = ctypes.c_size_t()
         check(self._lib.concpd_query_workspace(ctypes.byref(cfg), ctypes.byref(nbytes)))
-        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
-        base = self.workspace.data_ptr()
-        self._ws_ptr = (base + 255) // 256 * 256
+        self.static_workspace = bool(static_workspace)
+        if self.static_workspace:
+            self.workspace = None
+            self._ws_ptr = None
+        else:
+            self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         tptrs = _void_ptr_array([t.data_ptr() for t in self.tensors])
         keepU = keepL = None
@@ -131,9 +140,14 @@ class CoupledCP:
         if init_lambda is not None:
             keepL, pL = _dbl_ptr_array([_stride_r(x, self.R) for x in init_lambda])
         ctx = ctypes.c_void_p()
-        check(self._lib.concpd_init(ctypes.byref(cfg), tptrs, pU, pL, ctypes.c_uint64(seed), ctypes.c_void_p(self._ws_ptr),
-                                    ctypes.c_size_t(int(nbytes.value)), ctypes.c_void_p(self.stream.cuda_stream),
-                                    ctypes.byref(ctx)))
+        if self.static_workspace:
+            with torch.cuda.device(dev):
+                check(self._lib.concpd_init_static(ctypes.byref(cfg), tptrs, pU, pL, ctypes.c_uint64(seed),
+                                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        else:
+            check(self._lib.concpd_init(ctypes.byref(cfg), tptrs, pU, pL, ctypes.c_uint64(seed), ctypes.c_void_p(self._ws_ptr),
+                                        ctypes.c_size_t(int(nbytes.value)), ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.byref(ctx)))
         self.ctx = ctx
         del keepU, keepL
 
