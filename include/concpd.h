@@ -353,13 +353,24 @@ concpd_status concpd_profile_read(concpd_ctx ctx, double* ms_pass1, double* ms_p
  *                            every operand row is 16-byte aligned and the
  *                            compute type is FP32 or 16-bit (EINVAL
  *                            otherwise); default 1 for 16-bit storage.
+ *   CONCPD_OPT_FUSE          1: the dense sweep runs its R x R work in the
+ *                            launches of the passes it does not depend on
+ *                            (core update beside pass 1, the mode-2 and mode-3
+ *                            step matrices beside the mode-2 contraction and
+ *                            pass 2): three launches fewer per sweep, fewer
+ *                            wavefronts per SIMD for those passes.  Results
+ *                            are bit-identical to the unfused sweep.  R > 32
+ *                            (and the register path of 16-bit storage) runs
+ *                            unfused whatever the value; default 1 when pass 1
+ *                            has at most two wavefronts per SIMD, else 0.
  * Synchronises.  Errors: EINVAL (unknown option or value), EHIP. */
 typedef enum concpd_option {
     CONCPD_OPT_GRAPH_SWEEPS = 1,
     CONCPD_OPT_OVERLAP = 2,
     CONCPD_OPT_K2_ROWS = 3,
     CONCPD_OPT_P1_SPLIT = 4,
-    CONCPD_OPT_P1_DMA = 5
+    CONCPD_OPT_P1_DMA = 5,
+    CONCPD_OPT_FUSE = 6
 } concpd_option;
 concpd_status concpd_set_option(concpd_ctx ctx, int32_t option, int64_t value);
 concpd_status concpd_get_option(concpd_ctx ctx, int32_t option, int64_t* value);
@@ -373,6 +384,7 @@ typedef struct concpd_tuning {
     int32_t p1_split;             /* chosen CONCPD_OPT_P1_SPLIT (the split in use) */
     int32_t p1_dma;               /* chosen CONCPD_OPT_P1_DMA */
     int32_t overlap;              /* chosen CONCPD_OPT_OVERLAP */
+    int32_t fuse;                 /* chosen CONCPD_OPT_FUSE */
 } concpd_tuning;
 
 /* Autotuner: times `sweeps` sweeps (HIP events on the context stream) of
@@ -380,7 +392,9 @@ typedef struct concpd_tuning {
  * iterate after each, and keeps the fastest: first the pass-1 split 1/2/4
  * (x DMA off/on where possible; dense path), then mode-2 chunk rows 8/16/32 x
  * graph sweeps 0/1/4, then (dense path) the second-stream overlap inside
- * graphs of 1 and 4 sweeps.  The iterate is unchanged on return.  Synchronises.
+ * graphs of 1 and 4 sweeps, then (dense path, R <= 32) the fused launches
+ * (CONCPD_OPT_FUSE) with direct launches and with the best graph length.
+ * The iterate is unchanged on return.  Synchronises.
  * Errors: EINVAL (sweeps not in [1, 10000]), ESTATE (converged iterate), EHIP. */
 concpd_status concpd_autotune(concpd_ctx ctx, int32_t sweeps, concpd_tuning* out);
 

@@ -63,6 +63,7 @@ class Tuning(ctypes.Structure):
         ("p1_split", ctypes.c_int32),
         ("p1_dma", ctypes.c_int32),
         ("overlap", ctypes.c_int32),
+        ("fuse", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -71,7 +72,7 @@ class Tuning(ctypes.Structure):
 
 STATIC_WORKSPACE_BYTES = 32 << 20   # CONCPD_STATIC_WORKSPACE_BYTES of concpd.h
 
-OPT_GRAPH_SWEEPS, OPT_OVERLAP, OPT_K2_ROWS, OPT_P1_SPLIT, OPT_P1_DMA = 1, 2, 3, 4, 5
+OPT_GRAPH_SWEEPS, OPT_OVERLAP, OPT_K2_ROWS, OPT_P1_SPLIT, OPT_P1_DMA, OPT_FUSE = 1, 2, 3, 4, 5, 6
 
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)

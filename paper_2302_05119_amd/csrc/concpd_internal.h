@@ -102,6 +102,10 @@ struct ItemK2 { int s, col0, chunk, pad; };         // mode-2 contraction: block
 namespace cpd {
 void launch_spectral_norm(const double* mats, int n, int count, double* out, hipStream_t q);
 template <typename T> void launch_core(const Geo* g, const StateP<T>& st, int S, int R, int extrap, hipStream_t q);
+// fused launches (R x R work beside independent MTTKRP work); false when R > 32
+template <typename T> bool launch_core_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int P, int R, int slot, int mdtype, int dma, int extrap, int S, hipStream_t q);
+template <typename T> bool launch_prep_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int R, int slot, int S, hipStream_t q);
+template <typename T> bool launch_prep_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int R, int slot, int mdtype, int maxI2, int S, hipStream_t q);
 template <typename T> void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, hipStream_t q);
 template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
 template <typename T> void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);

@@ -45,27 +45,13 @@ static void pass2_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g,
 #undef CPD_P2
 }
 
-// pass 1 LDS: four staging areas (64-byte chunk x 4 x RTP operands), then,
-// when P > 1, the partial accumulators of the four wavefronts (RT x 4 x 64)
-template <typename TM>
-static size_t pass1_lds(int RT, int P) {
-    typedef typename AccType<TM>::type TA;
-    const size_t kc = 64 / sizeof(typename Raw<TM>::type), va = 16 / sizeof(TA), rtp = ((size_t)RT + va - 1) / va * va;
-    return sizeof(TA) * (4 * kc * 4 * rtp + (P > 1 ? 4 * (size_t)RT * 4 * 64 : 0));
-}
-
 template <typename TM, typename T>
 static void pass2_dispatch(int Rq, dim3 grid, int maxI2, hipStream_t q, const Geo* g, const StateP<T>& st,
                            const ItemP2* items, int slot) {
-    typedef typename AccType<TM>::type TA;
-    const size_t va = 16 / sizeof(TA), rtp = ((size_t)Rq / 4 + va - 1) / va * va;
-    const size_t red = sizeof(TA) * 4 * 64 * (size_t)Rq;
-    const size_t bst = sizeof(TA) * (size_t)maxI2 * 4 * rtp;   // transposed U2
-    // chunked staging: whole 16-row groups within 32 KiB (as p2_chunk_rows)
-    const size_t chr = (32768 / (4 * rtp * sizeof(TA))) / 16 * 16;
-    const size_t cst = sizeof(TA) * chr * 4 * rtp;
-    if (bst <= 49152) pass2_rt<TM, T, true>(Rq / 4, grid, bst > red ? bst : red, q, g, st, items, slot);
-    else pass2_rt<TM, T, false>(Rq / 4, grid, cst > red ? cst : red, q, g, st, items, slot);
+    bool blds = true;
+    const size_t lds = pass2_lds<TM>(Rq, maxI2, &blds);
+    if (blds) pass2_rt<TM, T, true>(Rq / 4, grid, lds, q, g, st, items, slot);
+    else pass2_rt<TM, T, false>(Rq / 4, grid, lds, q, g, st, items, slot);
 }
 
 template <typename T>

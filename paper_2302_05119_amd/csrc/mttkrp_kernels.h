@@ -101,12 +101,10 @@ __device__ __forceinline__ void load_run(const TA* __restrict__ p, TA (&bb)[RT])
 }
 
 template <typename TM, typename T, int RT>
-__global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP<T> st, const ItemP1* __restrict__ items,
-                                               int nitems, int P, int slot) {
+__device__ __forceinline__ void pass1_item(const Geo* __restrict__ g, StateP<T> st, const ItemP1* __restrict__ items,
+                                               int nitems, int P, int slot, int bid) {
     typedef typename AccType<TM>::type TA;
     typedef typename Raw<TM>::type TR;
-    if (st.ctrl->stop) return;
-    apply_rot(st);
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     constexpr int KC = 64 / (int)sizeof(TR);          // chunk: 64 bytes of a row
     constexpr int NV = 4;                             // 16-byte words per chunk
@@ -114,7 +112,7 @@ __global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP
     constexpr int RTP = (RT + VA - 1) / VA * VA;      // padded operand run
     constexpr int UPL = (KC * 4 * RT + 63) / 64;      // U3 chunk elements per lane
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int ii = blockIdx.x * (4 / P) + wave / P, part = wave % P;
+    const int ii = bid * (4 / P) + wave / P, part = wave % P;
     const ItemP1 it = items[min(ii, nitems - 1)];
     const bool live = ii < nitems && it.s >= 0;
     const int s = live ? it.s : 0, i1 = it.i1, rg = it.rg, row0 = rg * 64;
@@ -245,6 +243,13 @@ __global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP
     }
 }
 
+template <typename TM, typename T, int RT>
+__global__ __launch_bounds__(256) void k_pass1(const Geo* __restrict__ g, StateP<T> st, const ItemP1* __restrict__ items, int nitems, int P, int slot) {
+    if (st.ctrl->stop) return;
+    apply_rot(st);
+    pass1_item<TM, T, RT>(g, st, items, nitems, P, slot, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // pass 1 with the tensor streamed straight into LDS (same items, splits and
 // outputs as k_pass1; every block's operand rows 16-byte aligned; FP32 or
@@ -326,16 +331,14 @@ struct P1D {
 };
 
 template <typename TM, int RT>
-__global__ __launch_bounds__(256) void k_pass1d(const Geo* __restrict__ g, StateP<float> st, const ItemP1* __restrict__ items,
-                                                int nitems, int P, int slot) {
+__device__ __forceinline__ void pass1d_item(const Geo* __restrict__ g, StateP<float> st, const ItemP1* __restrict__ items,
+                                                int nitems, int P, int slot, int bid) {
     typedef P1D<TM, RT> D;
     typedef typename D::TR TR;
     constexpr int KC = D::KC, EPP = 16 / (int)sizeof(TR);   // values per 16-byte piece
-    if (st.ctrl->stop) return;
-    apply_rot(st);
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, q = lane & 3;
-    const int ii = blockIdx.x * (4 / P) + wave / P, part = wave % P;
+    const int ii = bid * (4 / P) + wave / P, part = wave % P;
     const ItemP1 it = items[min(ii, nitems - 1)];
     const bool live = ii < nitems && it.s >= 0;
     const int s = live ? it.s : 0, i1 = it.i1, rg = it.rg, row0 = rg * 64;
@@ -482,6 +485,13 @@ __global__ __launch_bounds__(256) void k_pass1d(const Geo* __restrict__ g, State
     }
 }
 
+template <typename TM, int RT>
+__global__ __launch_bounds__(256) void k_pass1d(const Geo* __restrict__ g, StateP<float> st, const ItemP1* __restrict__ items, int nitems, int P, int slot) {
+    if (st.ctrl->stop) return;
+    apply_rot(st);
+    pass1d_item<TM, RT>(g, st, items, nitems, P, slot, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // pass 2: one workgroup per (block, chunk of 4 i1 slabs, 64 consecutive i3);
 // wavefront w takes slab 4*chunk + w.  Lanes run along i3 (the contiguous
@@ -499,13 +509,11 @@ constexpr int p2_chunk_rows() {
 }
 
 template <typename TM, typename T, int RT, bool BLDS>
-__global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP<T> st, const ItemP2* __restrict__ items,
-                                               int slot) {
+__device__ __forceinline__ void pass2_item(const Geo* __restrict__ g, StateP<T> st, const ItemP2* __restrict__ items,
+                                               int slot, int bid) {
     typedef typename AccType<TM>::type TA;
-    if (st.ctrl->stop) return;
-    apply_rot(st);
     extern __shared__ __attribute__((aligned(16))) char smraw[];
-    const ItemP2 it = items[blockIdx.x];
+    const ItemP2 it = items[bid];
     const int s = it.s, chunk = it.chunk, q0 = it.q0;
     const int I1 = g->I[s][0], I2 = g->I[s][1], I3 = g->I[s][2], Rq = g->Rq;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -617,6 +625,13 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
     }
 }
 
+template <typename TM, typename T, int RT, bool BLDS>
+__global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP<T> st, const ItemP2* __restrict__ items, int slot) {
+    if (st.ctrl->stop) return;
+    apply_rot(st);
+    pass2_item<TM, T, RT, BLDS>(g, st, items, slot, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // mode 2: K2[i2][r] = sum_i1 Y[i1][i2][r] U1[i1][r] with the new U^(1).  One
 // thread per element e = i2*Rq + r of a 256-wide column tile, one workgroup
@@ -625,10 +640,8 @@ __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP
 // factor update.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_k2(const Geo* __restrict__ g, StateP<T> st, const ItemK2* __restrict__ items, int slot) {
-    if (st.ctrl->stop) return;
-    apply_rot(st);
-    const ItemK2 it = items[blockIdx.x];
+__device__ __forceinline__ void k2_item(const Geo* __restrict__ g, StateP<T> st, const ItemK2* __restrict__ items, int slot, int bid) {
+    const ItemK2 it = items[bid];
     const int s = it.s, Rq = g->Rq;
     const int I1 = g->I[s][0], I2 = g->I[s][1];
     const long long ys = (long long)I2 * Rq;
@@ -648,6 +661,38 @@ __global__ __launch_bounds__(256) void k_k2(const Geo* __restrict__ g, StateP<T>
     }
     if (i1 < i1b) a0 += Y[i1 * ys] * U1[(long long)i1 * Rq];
     gptr_w(st.K2)[g->k2off[s] + (long long)it.chunk * ys + e] = a0 + a1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_k2(const Geo* __restrict__ g, StateP<T> st, const ItemK2* __restrict__ items, int slot) {
+    if (st.ctrl->stop) return;
+    apply_rot(st);
+    k2_item<T>(g, st, items, slot, blockIdx.x);
+}
+
+// pass 1 LDS: four staging areas (64-byte chunk x 4 x RTP operands), then,
+// when P > 1, the partial accumulators of the four wavefronts (RT x 4 x 64)
+template <typename TM>
+inline size_t pass1_lds(int RT, int P) {
+    typedef typename AccType<TM>::type TA;
+    const size_t kc = 64 / sizeof(typename Raw<TM>::type), va = 16 / sizeof(TA), rtp = ((size_t)RT + va - 1) / va * va;
+    return sizeof(TA) * (4 * kc * 4 * rtp + (P > 1 ? 4 * (size_t)RT * 4 * 64 : 0));
+}
+
+// pass 2 LDS: U2 staged whole when it fits 48 KiB (*whole = true), else in
+// chunks of whole 16-row groups within 32 KiB (as p2_chunk_rows); at least
+// the partial sums of the four wavefronts
+template <typename TM>
+inline size_t pass2_lds(int Rq, int maxI2, bool* whole) {
+    typedef typename AccType<TM>::type TA;
+    const size_t va = 16 / sizeof(TA), rtp = ((size_t)Rq / 4 + va - 1) / va * va;
+    const size_t red = sizeof(TA) * 4 * 64 * (size_t)Rq;
+    const size_t bst = sizeof(TA) * (size_t)maxI2 * 4 * rtp;   // transposed U2
+    const size_t chr = (32768 / (4 * rtp * sizeof(TA))) / 16 * 16;
+    const size_t cst = sizeof(TA) * chr * 4 * rtp;
+    *whole = bst <= 49152;
+    const size_t st = *whole ? bst : cst;
+    return st > red ? st : red;
 }
 
 }  // namespace cpd

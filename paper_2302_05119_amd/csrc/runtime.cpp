@@ -464,6 +464,8 @@ struct concpd_ctx_s {
     int k2rows;
     int p1split = 0;   // requested pass-1 split (0: automatic)
     int p1dma = 0, p1dma_ok = 0;   // pass 1 by LDS DMA (in use / possible)
+    int fuse = 0;                  // R x R work fused into the launches of independent passes
+    int fuse_dflt = 0;             // its default (pass 1 with few wavefronts per SIMD)
     int static_dev = -1;           // device whose static workspace this context holds (-1: none)
     std::vector<hipEvent_t> ev1, ev2;  // begin/end pairs of timed pass launches
     void drop_graph() {
@@ -525,6 +527,39 @@ void run_sweep(concpd_ctx c, const StateP<T>& st) {
     hipEvent_t e[4];
     if (prof)
         for (int i = 0; i < 4; ++i) (void)hipEventCreate(&e[i]);
+    if (c->fuse) {
+        // the R x R work beside the passes it does not depend on, in the same launches
+        const int ni1 = (int)c->lists.p1.size(), P = c->lists.p1_split;
+        if (prof) (void)hipEventRecord(e[0], q);
+        for (int rep = 0; rep < (prof ? CPD_PROF_REPS : 1); ++rep)
+            if (!cpd::launch_core_pass1<T>(g, st, it1, ni1, P, R, 1, c->mdtype, c->p1dma, extrap, S, q)) {
+                cpd::launch_core<T>(g, st, S, R, extrap, q);
+                cpd::launch_pass1<T>(g, st, it1, ni1, P, Rq, 1, c->mdtype, c->p1dma, q);
+            }
+        if (prof) (void)hipEventRecord(e[1], q);
+        cpd::launch_update<T>(g, st, itu[0], (int)c->lists.u[0].size(), 0, R, extrap, c->lists.lds_rows[0], 0, q);
+        if (!cpd::launch_prep_k2<T>(g, st, itk, (int)c->lists.k2.size(), R, 0, S, q)) {
+            cpd::launch_prep<T>(g, st, S, R, 1, q);
+            cpd::launch_k2<T>(g, st, itk, (int)c->lists.k2.size(), 0, q);
+        }
+        cpd::launch_update<T>(g, st, itu[1], (int)c->lists.u[1].size(), 1, R, extrap, c->lists.lds_rows[1], 0, q);
+        if (prof) (void)hipEventRecord(e[2], q);
+        for (int rep = 0; rep < (prof ? CPD_PROF_REPS : 1); ++rep)
+            if (!cpd::launch_prep_pass2<T>(g, st, it2, (int)c->lists.p2.size(), R, 0, c->mdtype, c->lists.maxI2, S, q)) {
+                cpd::launch_prep<T>(g, st, S, R, 2, q);
+                cpd::launch_pass2<T>(g, st, it2, (int)c->lists.p2.size(), Rq, 0, c->mdtype, c->lists.maxI2, q);
+            }
+        if (prof) {
+            (void)hipEventRecord(e[3], q);
+            c->ev1.push_back(e[0]);
+            c->ev1.push_back(e[1]);
+            c->ev2.push_back(e[2]);
+            c->ev2.push_back(e[3]);
+        }
+        cpd::launch_update<T>(g, st, itu[2], (int)c->lists.u[2].size(), 2, R, extrap, c->lists.lds_rows[2], 0, q);
+        cpd::launch_finish<T>(g, st, S, R, q);
+        return;
+    }
     // the second stream (if any) takes the small FP64 kernels
     hipStream_t qa = c->overlap ? c->q2 : q;
     auto fork = [&](int i) {
@@ -1107,6 +1142,15 @@ concpd_status init_impl(const concpd_config* cfg, const void* const* tensors, co
         // shape, slower for FP32 rows of a few thousand values)
         c->p1dma_ok = all && !c->f64;
         c->p1dma = c->p1dma_ok && c->mdtype != 1;
+    }
+    // the fused launches by default while pass 1 has at most two wavefronts
+    // per SIMD (they keep two or three resident; measured: 10 x 100^3 R = 20
+    // 120 -> 97 us per sweep, the EEG-shaped blocks 420 -> 408 us)
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            c->fuse = c->R <= 32 && (long long)c->lists.p1.size() * c->lists.p1_split <= 8LL * ncu;
+        c->fuse_dflt = c->fuse;
     }
     c->dgeo = (Geo*)(c->ws + c->lay.geo);
     INIT_HIP(hipMemcpyAsync(c->dgeo, &c->geo, sizeof(Geo), hipMemcpyHostToDevice, c->q));
@@ -1713,6 +1757,11 @@ concpd_status concpd_set_option(concpd_ctx c, int32_t option, int64_t value) {
         if (value != c->p1dma) c->drop_graph();
         c->p1dma = (int)value;
         return CONCPD_OK;
+    case CONCPD_OPT_FUSE:
+        if (value != 0 && value != 1) return fail(CONCPD_EINVAL, "fuse %lld not 0 or 1", (long long)value);
+        if (value != c->fuse) c->drop_graph();
+        c->fuse = (int)value;
+        return CONCPD_OK;
     case CONCPD_OPT_P1_SPLIT: {
         if (value != 0 && value != 1 && value != 2 && value != 4)
             return fail(CONCPD_EINVAL, "pass-1 split %lld not 0, 1, 2 or 4", (long long)value);
@@ -1752,6 +1801,7 @@ concpd_status concpd_get_option(concpd_ctx c, int32_t option, int64_t* value) {
     case CONCPD_OPT_K2_ROWS: *value = c->k2rows; return CONCPD_OK;
     case CONCPD_OPT_P1_SPLIT: *value = c->lists.p1_split; return CONCPD_OK;
     case CONCPD_OPT_P1_DMA: *value = c->p1dma; return CONCPD_OK;
+    case CONCPD_OPT_FUSE: *value = c->fuse; return CONCPD_OK;
     default: return fail(CONCPD_EINVAL, "unknown option %d", option);
     }
 }
@@ -1805,14 +1855,26 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
         ++ncand;
         return CONCPD_OK;
     };
-    if (!c->lra) {
+    // the default configuration of a fresh context first (it competes too)
+    const int dma_dflt = c->p1dma_ok && c->mdtype != 1;
+    auto set_default = [&]() -> concpd_status {
+        concpd_status q;
+        if ((q = concpd_set_option(c, CONCPD_OPT_GRAPH_SWEEPS, 0)) != CONCPD_OK) return q;
+        if ((q = concpd_set_option(c, CONCPD_OPT_OVERLAP, 0)) != CONCPD_OK) return q;
+        if (!c->lra && (q = concpd_set_option(c, CONCPD_OPT_K2_ROWS, CPD_K2ROWS_DEFAULT)) != CONCPD_OK) return q;
+        if ((q = concpd_set_option(c, CONCPD_OPT_P1_DMA, dma_dflt)) != CONCPD_OK) return q;
+        if ((q = concpd_set_option(c, CONCPD_OPT_P1_SPLIT, 0)) != CONCPD_OK) return q;
+        return concpd_set_option(c, CONCPD_OPT_FUSE, c->fuse_dflt);
+    };
+    if ((r = set_default()) == CONCPD_OK) r = time_sweeps(dflt);
+    if (r == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_FUSE, 0);
+    if (!c->lra && r == CONCPD_OK) {
         // the pass-1 split of i3 over wavefronts (direct launches, default chunk rows)
         Lists La;
         build_lists(&c->cfg, &La, CPD_K2ROWS_DEFAULT, 0);
         const int p_auto = La.p1_split;
         double bpu = INFINITY;
         const int psc[3] = {1, 2, 4};
-        const int dma_dflt = c->p1dma_ok && c->mdtype != 1;
         int bd = c->p1dma;
         if ((r = concpd_set_option(c, CONCPD_OPT_GRAPH_SWEEPS, 0)) == CONCPD_OK)
             r = concpd_set_option(c, CONCPD_OPT_K2_ROWS, CPD_K2ROWS_DEFAULT);
@@ -1823,7 +1885,6 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
                 if ((r = concpd_set_option(c, CONCPD_OPT_P1_SPLIT, psc[pi])) != CONCPD_OK) break;
                 double us = 0.0;
                 if ((r = time_sweeps(us)) != CONCPD_OK) break;
-                if (psc[pi] == p_auto && dma == dma_dflt) dflt = us;
                 if (us < bpu) {
                     bpu = us;
                     bp = psc[pi];
@@ -1843,7 +1904,6 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
             if (r != CONCPD_OK) break;
             double us = 0.0;
             if ((r = time_sweeps(us)) != CONCPD_OK) break;
-            if (c->lra && k2c[ki] == CPD_K2ROWS_DEFAULT && gsc[gi] == 0) dflt = us;
             if (us < best) {
                 best = us;
                 bk = k2c[ki];
@@ -1871,10 +1931,49 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
         }
         if (r == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_OVERLAP, bo);
     }
+    // the R x R work fused into the launches of the passes (dense path, R <= 32),
+    // with direct launches and with the best graph length
+    // (direct launches also with the other pass-1 split of 1 and 2: the fused
+    // pass keeps fewer wavefronts resident, so shorter items can pay off)
+    int bf = 0;
+    if (!c->lra && c->R <= 32 && r == CONCPD_OK) {
+        const int ov = bo, gbest = bg, pbest = c->lists.p1_split;
+        int bsplit = pbest;
+        if ((r = concpd_set_option(c, CONCPD_OPT_OVERLAP, 0)) == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_FUSE, 1);
+        for (int gi = 0; gi < 3 && r == CONCPD_OK; ++gi) {
+            const int gsv = gi == 2 ? gbest : 0;
+            const int sp = gi == 1 ? (pbest == 1 ? 2 : 1) : pbest;
+            if (gi == 2 && gsv == 0) break;
+            if (gi == 1 && c->f64) continue;
+            if ((r = concpd_set_option(c, CONCPD_OPT_P1_SPLIT, sp)) != CONCPD_OK) break;
+            if ((r = concpd_set_option(c, CONCPD_OPT_GRAPH_SWEEPS, gsv)) != CONCPD_OK) break;
+            double us = 0.0;
+            if ((r = time_sweeps(us)) != CONCPD_OK) break;
+            if (us < best) {
+                best = us;
+                bg = gsv;
+                bf = 1;
+                bo = 0;
+                bsplit = sp;
+            }
+        }
+        if (r == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_P1_SPLIT, bf ? bsplit : pbest);
+        if (r == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_FUSE, bf);
+        if (r == CONCPD_OK) r = concpd_set_option(c, CONCPD_OPT_OVERLAP, bf ? 0 : ov);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->profiling = prof;
     if (r != CONCPD_OK) return r;
+    if (dflt <= best) {
+        // no candidate beat the default configuration
+        if ((r = set_default()) != CONCPD_OK) return r;
+        best = dflt;
+        bk = CPD_K2ROWS_DEFAULT;
+        bg = 0;
+        bo = 0;
+        bf = c->fuse;
+    }
     if (!c->lra) {
         r = concpd_set_option(c, CONCPD_OPT_K2_ROWS, bk);
         if (r != CONCPD_OK) return r;
@@ -1890,6 +1989,7 @@ concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) 
         out->p1_dma = c->p1dma;
         out->graph_sweeps = bg;
         out->overlap = bo;
+        out->fuse = bf;
         out->us_per_sweep = best;
         out->us_per_sweep_default = dflt;
         out->candidates = ncand;

@@ -224,7 +224,7 @@ __host__ __device__ inline int sq_lp(int n) { return (sq_np(n) & 31) == 16 ? sq_
 
 // Size class of the R x R spectral-norm work (the NMAX template argument of
 // the small kernels): 16, 24, 32, 48 or 64.
-__host__ __device__ inline int nmax_class(int R) { return R <= 16 ? 16 : R <= 24 ? 24 : R <= 32 ? 32 : R <= 48 ? 48 : 64; }
+__host__ __device__ constexpr int nmax_class(int R) { return R <= 16 ? 16 : R <= 24 ? 24 : R <= 32 ? 32 : R <= 48 ? 48 : 64; }
 
 // Squaring buffers of the vector-ALU path (n <= NPM <= 32): NPM rows of
 // NPM + 2 doubles.  The stride is an odd multiple of four dwords, so the
