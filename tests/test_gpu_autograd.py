@@ -189,3 +189,87 @@ def test_loss_and_gradients_with_coupling_groups(compute, tol):
             assert rel(g[:, Ls:], gU_ref[n][s][:, Ls:]) <= tol, (n, s)
             if member:
                 assert rel(g[:, :Ls], gC_ref[n]) <= tol, (n, s)
+
+
+def bf16_round(X):
+    """FP32 values rounded to the nearest BF16 (ties to even), as FP64."""
+    b = np.ascontiguousarray(X, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def maxrel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def test_loss_grad_bf16_full_eeg_workload():
+    # the autograd form at its own configuration: 16 EEG-shaped blocks
+    # (64 x 60 x T_s, T_s ~ U{200..2000}), R = 30, channel and frequency
+    # factors fully coupled, BF16 tensor operands.  Against the FP64 oracle on
+    # the FP32 tensors: 2e-2 normwise and elementwise-max (the per-step BF16
+    # bound); against the oracle on the BF16-rounded tensors: 1e-5 (what is
+    # left is FP32 accumulation).
+    import torch
+    from paper_2302_05119_amd import CoupledCP
+    say("[loss_grad] BF16, full 16-block EEG-shaped workload")
+    P = synth.make_workload("c4_eeg_bf16_16blocks_r30")
+    dev = torch.device("cuda:0")
+    tens = [torch.from_numpy(np.ascontiguousarray(X)).to(dev) for X in P.tensors]
+    m = CoupledCP(tens, P.R, P.L, compute="bf16", seed=5)
+    U, lam = synth.uniform_init(P.dims, P.R, P.L, 1741)
+    lam = [l + 0.5 for l in lam]
+    U = [[u.astype(np.float32).astype(np.float64) for u in per] for per in U]
+    Ut, lt = to_dev(U, lam, "bf16", dev)
+    ref32 = apg.loss_and_grads(DenseData(P.tensors), lam, U, P.L)
+    ref16 = apg.loss_and_grads(DenseData([bf16_round(X) for X in P.tensors]), lam, U, P.L)
+    for coupled in (False, True):
+        F, gU, gl = m.loss_grad(Ut, lt, coupled=coupled)
+        for name, (F_ref, gl_ref, gU_ref, gC_ref), tol in (("fp32 data", ref32, 2e-2), ("bf16 data", ref16, 1e-5)):
+            eF = abs(F - F_ref) / F_ref
+            worst = (eF, 0.0)
+            for s in range(P.S):
+                worst = max(worst, (rel(gl[s].cpu().numpy(), gl_ref[s]), maxrel(gl[s].cpu().numpy(), gl_ref[s])))
+                for n in range(3):
+                    g = gU[n][s].cpu().numpy().astype(np.float64)
+                    want = gU_ref[n][s].copy()
+                    if coupled and P.L[n] > 0:
+                        want[:, :P.L[n]] = gC_ref[n]
+                    worst = max(worst, (rel(g, want), maxrel(g, want)))
+            say(f"   coupled={coupled} vs oracle on {name}: F rel {eF:.2e}, worst gradient normwise/elementwise "
+                f"{worst[0]:.2e} / {worst[1]:.2e}")
+            assert eF <= tol and worst[0] <= tol and worst[1] <= (tol if tol >= 1e-3 else 1e-3)
+
+
+def test_loss_grad_bf16_finite_differences():
+    # central differences of the library's own BF16 loss along random
+    # directions, against its gradient (EEG-shaped small case)
+    import torch
+    from paper_2302_05119_amd import CoupledCP
+    say("[loss_grad] BF16 finite differences")
+    P = synth.eeg_problem(4, (20, 60), 6, 5.0, 1751, channels=16, freqs=12)
+    dev = torch.device("cuda:0")
+    tens = [torch.from_numpy(np.ascontiguousarray(X)).to(dev) for X in P.tensors]
+    m = CoupledCP(tens, P.R, P.L, compute="bf16", seed=5)
+    U, lam = synth.uniform_init(P.dims, P.R, P.L, 1752)
+    lam = [l + 0.5 for l in lam]
+    Ut, lt = to_dev(U, lam, "bf16", dev)
+    F0, gU, gl = m.loss_grad(Ut, lt)
+    rng = np.random.default_rng(9)
+    h = 1e-2
+    for trial in range(3):
+        dU = [[torch.tensor(rng.standard_normal(u.shape), dtype=torch.float32, device=dev) for u in per] for per in Ut]
+        dl = [torch.tensor(rng.standard_normal(l.shape), device=dev) for l in lt]
+        Up = [[u + h * d for u, d in zip(pu, pd)] for pu, pd in zip(Ut, dU)]
+        Um = [[u - h * d for u, d in zip(pu, pd)] for pu, pd in zip(Ut, dU)]
+        Fp, _, _ = m.loss_grad(Up, [l + h * d for l, d in zip(lt, dl)])
+        Fm, _, _ = m.loss_grad(Um, [l - h * d for l, d in zip(lt, dl)])
+        fd = (Fp - Fm) / 2
+        # the FP32 steps actually taken (u + h d rounds), so only the loss's own
+        # accuracy and the O(h^2) term remain
+        an = sum(float(((up - um).double() * g.double()).sum()) / 2 for pg, pu_, pm_ in zip(gU, Up, Um)
+                 for g, up, um in zip(pg, pu_, pm_))
+        an += sum(float((g * d).sum()) * h for g, d in zip(gl, dl))
+        say(f"   trial {trial}: fd={fd:.10e} analytic={an:.10e}")
+        assert abs(fd - an) <= 2e-3 * abs(an)
