@@ -76,7 +76,12 @@ typedef struct concpd_config {
     int32_t compute_dtype;  /* MTTKRP operand type.  CONCPD_F64 needs F64 tensors and keeps
                                every quantity in FP64.  CONCPD_F32 runs FP32 MFMA.
                                CONCPD_BF16 / CONCPD_F16 keep a 16-bit shadow of the tensors
-                               in the workspace and run 16-bit MFMA with FP32 accumulation.
+                               in the workspace.  BF16 runs the MTTKRP passes on the BF16
+                               matrix cores (v_mfma_f32_4x4x4_16b_bf16, FP32 accumulation;
+                               pass 1 by LDS DMA, the default for 16-bit storage) with each
+                               FP32 factor value split into hi + lo BF16 parts, so only the
+                               tensor is rounded to 16 bits; FP16 widens its tensor values
+                               to FP32 for the FP32 matrix cores.
                                Grams, Lipschitz constants, the core update, the objective
                                and the restart test are FP64 in every mode. */
     int32_t update_core;    /* 1: update D^(s) (CoNCPD-APG); 0: keep lambda fixed, the -NC

@@ -24,10 +24,15 @@
 namespace cpd {
 
 template <typename TA> struct Acc4;
+typedef short v4i16 __attribute__((ext_vector_type(4)));   // four BF16 values (raw bits)
 template <> struct Acc4<float> {
     v4f v;
     __device__ void zero() { v = (v4f){0.f, 0.f, 0.f, 0.f}; }
     __device__ void mma(float a, float b) { v = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, v, 0, 0, 0); }
+    // v_mfma_f32_4x4x4_16b_bf16: block b of 16, lane 4b+i gives four k values
+    // of A's row i and lane 4b+j four k values (same k order) of B's column j;
+    // the result layout is that of the 4x4x1 form
+    __device__ void mma_bf16(v4i16 a, v4i16 b) { v = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, v, 0, 0, 0); }
     __device__ float get(int i) const { return v[i]; }
     __device__ void scale(float u) { v *= u; }
     __device__ void set(const float (&x)[4]) { v = (v4f){x[0], x[1], x[2], x[3]}; }
@@ -64,6 +69,16 @@ template <> __device__ __forceinline__ float cvt<float, float>(float x) { return
 template <> __device__ __forceinline__ double cvt<double, double>(double x) { return x; }
 template <> __device__ __forceinline__ float cvt<float, __hip_bfloat16>(unsigned short x) { return __uint_as_float((unsigned)x << 16); }
 template <> __device__ __forceinline__ float cvt<float, __half>(unsigned short x) { return __half2float(__ushort_as_half(x)); }
+
+// An FP32 factor value as the sum of two BF16 values, hi = bf16(u) and
+// lo = bf16(u - hi) (round to nearest even), so that two BF16 matrix-core
+// products carry it to about 2^-16 relative (the tensor operand is BF16
+// storage already).
+__device__ __forceinline__ void split_bf16(float u, unsigned short& hi, unsigned short& lo) {
+    const __hip_bfloat16 h = __float2bfloat16(u);
+    hi = __bfloat16_as_ushort(h);
+    lo = __bfloat16_as_ushort(__float2bfloat16(u - __bfloat162float(h)));
+}
 
 // ---------------------------------------------------------------------------
 // pass 1: one wavefront per (block, i1 slab, 64-row group of i2) item, or P
@@ -417,6 +432,51 @@ __device__ __forceinline__ void pass1d_item(const Geo* __restrict__ g, StateP<fl
             }
             wave_sync();
             request(c + D::NSTG - 1, stage == 0 ? D::NSTG - 1 : stage - 1);
+            if constexpr (std::is_same<TM, __hip_bfloat16>::value) {
+                // BF16 matrix cores: the stage's U3 rows become hi and lo BF16
+                // operands in place, [group of 4 k][lane class j][tile t][4 k]
+                // each (a lane's RT operands of a group are one run); the
+                // tensor's 16-byte pieces give two 4-k groups of a row per lane
+                constexpr int RQ = 4 * RT, NPAIR = (KC / 4) * RQ, NPL = (NPAIR + 63) / 64;
+                float uv[NPL][4];
+#pragma unroll
+                for (int r = 0; r < NPL; ++r) {
+                    const int p = min(lane + 64 * r, NPAIR - 1), gk = p / RQ, col = p % RQ;
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) uv[r][kk] = ur[(4 * gk + kk) * RQ + col];
+                }
+                wave_sync();
+                unsigned short* hb = (unsigned short*)ur;
+                unsigned short* lb = hb + (KC / 4) * 4 * RT * 4;
+#pragma unroll
+                for (int r = 0; r < NPL; ++r) {
+                    const int p = lane + 64 * r;
+                    if (p < NPAIR) {
+                        const int gk = p / RQ, col = p % RQ, jc = col / RT, t = col % RT;
+                        const int o = ((gk * 4 + jc) * RT + t) * 4;
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) split_bf16(uv[r][kk], hb[o + kk], lb[o + kk]);
+                    }
+                }
+                wave_sync();
+#pragma unroll
+                for (int pc = 0; pc < KC / EPP; ++pc) {
+                    const u32x4 w = *(const u32x4*)(sp + pc * 1024 + lane * 16);
+#pragma unroll
+                    for (int h2 = 0; h2 < EPP / 4; ++h2) {
+                        const int gk = pc * (EPP / 4) + h2;
+                        v4i16 a;
+                        *(unsigned long long*)&a = ((unsigned long long)w[2 * h2 + 1] << 32) | w[2 * h2];
+                        const v4i16* bh = (const v4i16*)(hb + (gk * 4 + q) * RT * 4);
+                        const v4i16* bl = (const v4i16*)(lb + (gk * 4 + q) * RT * 4);
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) {
+                            acc[t].mma_bf16(a, bh[t]);
+                            acc[t].mma_bf16(a, bl[t]);
+                        }
+                    }
+                }
+            } else {
 #pragma unroll
             for (int pc = 0; pc < KC / EPP; ++pc) {
                 const u32x4 w = *(const u32x4*)(sp + pc * 1024 + lane * 16);
@@ -430,6 +490,7 @@ __device__ __forceinline__ void pass1d_item(const Geo* __restrict__ g, StateP<fl
 #pragma unroll
                     for (int t = 0; t < RT; ++t) acc[t].mma(a, bb[t]);
                 }
+            }
             }
             // (the wait before the next request also retires this chunk's
             // LDS reads before its stage is overwritten)
@@ -572,6 +633,73 @@ __device__ __forceinline__ void pass2_item(const Geo* __restrict__ g, StateP<T> 
     };
     constexpr int CHR = BLDS ? (1 << 30) : p2_chunk_rows<TA, RT>();
     static_assert(CHR % NB == 0, "U2 chunks must hold whole NB-row groups");
+    if constexpr (std::is_same<TM, __hip_bfloat16>::value) {
+        // BF16 matrix cores: four consecutive i2 rows of a lane's tensor column
+        // form the A operand of v_mfma_f32_4x4x4_16b_bf16; U2 is staged as hi
+        // and lo BF16 parts, [group of 4 rows][lane class j][tile t][4 rows]
+        // (column 4t + j), rows past I2 zero.  Tensor loads are never masked
+        // (clamped addresses, finite values): a row past I2 meets zero U2
+        // operands, and a lane past I3 only feeds its own output row, which is
+        // never stored
+        unsigned short cb[NB], nb[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) cb[j] = Mp[(long long)min(j, I2 - 1) * ldm];
+        unsigned short* hb = (unsigned short*)smraw;
+        for (int c0 = 0; c0 < I2; c0 += CHR) {
+            const int c1 = min(I2, c0 + CHR), nr = c1 - c0, nr4 = (nr + 3) & ~3;
+            unsigned short* lb = hb + nr4 * Rq;
+            __syncthreads();
+            {
+                const int nu = nr4 * Rq;
+                const CPD_GLOBAL T* __restrict__ src = U2g + (long long)c0 * Rq;
+                for (int e0 = threadIdx.x; e0 < nu; e0 += 256 * 8) {
+                    T v[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) v[j] = src[min(e0 + 256 * j, nr * Rq - 1)];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int e = e0 + 256 * j;
+                        if (e < nu) {
+                            const int r = e / Rq, c = e % Rq;
+                            const int o = (((r >> 2) * 4 + (c & 3)) * RT + (c >> 2)) * 4 + (r & 3);
+                            unsigned short h = 0, l = 0;
+                            if (r < nr) split_bf16((float)v[j], h, l);
+                            hb[o] = h;
+                            lb[o] = l;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (live) {
+                for (int i2b = c0; i2b < c1; i2b += NB) {
+                    const int nb2 = i2b + NB;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) nb[j] = Mp[(long long)min(nb2 + j, I2 - 1) * ldm];
+                    const int jm = min(NB, I2 - i2b);
+#pragma unroll
+                    for (int gg = 0; gg < NB / 4; ++gg) {
+                        if (4 * gg < jm) {
+                            v4i16 a;
+                            *(unsigned long long*)&a = (unsigned long long)cb[4 * gg] | ((unsigned long long)cb[4 * gg + 1] << 16) |
+                                                       ((unsigned long long)cb[4 * gg + 2] << 32) |
+                                                       ((unsigned long long)cb[4 * gg + 3] << 48);
+                            const int gk = (i2b - c0) / 4 + gg;
+                            const v4i16* bh = (const v4i16*)(hb + (gk * 4 + (lane & 3)) * RT * 4);
+                            const v4i16* bl = (const v4i16*)(lb + (gk * 4 + (lane & 3)) * RT * 4);
+#pragma unroll
+                            for (int t = 0; t < RT; ++t) {
+                                z[t].mma_bf16(a, bh[t]);
+                                z[t].mma_bf16(a, bl[t]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) cb[j] = nb[j];
+                }
+            }
+        }
+    } else
     for (int c0 = 0; c0 < I2; c0 += CHR) {
         const int c1 = min(I2, c0 + CHR);
         // every wavefront of the workgroup stages and waits (also those past I1)
@@ -691,7 +819,12 @@ inline size_t pass2_lds(int Rq, int maxI2, bool* whole) {
     const size_t chr = (32768 / (4 * rtp * sizeof(TA))) / 16 * 16;
     const size_t cst = sizeof(TA) * chr * 4 * rtp;
     *whole = bst <= 49152;
-    const size_t st = *whole ? bst : cst;
+    size_t st = *whole ? bst : cst;
+    if (std::is_same<TM, __hip_bfloat16>::value && *whole) {
+        // hi and lo BF16 parts of the whole U2, rows rounded up to 4
+        const size_t hl = 4 * (size_t)Rq * (((size_t)maxI2 + 3) & ~(size_t)3);
+        st = st > hl ? st : hl;
+    }
     return st > red ? st : red;
 }
 
