@@ -27,7 +27,8 @@
  *  - Tensors are device buffers, C-contiguous (i3 fastest):
  *    element (i1,i2,i3) of block s at offset (i1*I2 + i2)*I3 + i3.
  *  - Host factor arrays are row-major I_n x R doubles (column r fastest).
- *  - Block s, mode n (0-based) is addressed as index 3*s + n in [S*3] arrays.
+ *  - Block s, mode n (0-based) is addressed as index N*s + n in [S*N] arrays
+ *    (N = 3: index 3*s + n in [S*3] arrays).
  *  - All device work is queued on the stream given to concpd_init.
  *  - Every call returns a concpd_status; no C++ exception crosses the ABI.
  *    On error the context is unchanged and concpd_last_error() returns a
@@ -51,7 +52,7 @@ extern "C" {
 typedef enum concpd_status {
     CONCPD_OK = 0,
     CONCPD_EINVAL = 1,     /* invalid argument or configuration */
-    CONCPD_ENOTSUP = 2,    /* valid but not supported by this build (e.g. order != 3) */
+    CONCPD_ENOTSUP = 2,    /* valid but not supported by this build (e.g. lra at order > 3) */
     CONCPD_ENONFINITE = 3, /* NaN or Inf in an input */
     CONCPD_EHIP = 4,       /* a HIP runtime call failed */
     CONCPD_ESTATE = 5      /* call not valid in the context's current state */
@@ -64,14 +65,25 @@ typedef enum concpd_dtype {
     CONCPD_F16 = 3
 } concpd_dtype;
 
+#define CONCPD_MAX_ORDER 6   /* largest tensor order N */
+
 typedef struct concpd_config {
-    int32_t order;          /* N, the tensor order; only 3 is supported */
+    int32_t order;          /* N, the tensor order, 3..CONCPD_MAX_ORDER.  Order 3 has every
+                               entry point; order N > 3 (the N-way model of Section II-C) has
+                               the dense path with FP32 or FP64 compute: concpd_init(_static),
+                               concpd_step, concpd_fit, concpd_global_fit, concpd_get_factor,
+                               concpd_get_lambda, concpd_get_lipschitz, concpd_get_state,
+                               concpd_set_state, concpd_debug_mttkrp, concpd_get_option,
+                               concpd_set_option(CONCPD_OPT_GRAPH_SWEEPS), concpd_destroy;
+                               the others return ENOTSUP */
     int32_t num_blocks;     /* S >= 1, at most 64 */
     int32_t rank;           /* R, components per block, 1..64 */
-    int32_t coupled[3];     /* L_n, 0 <= L_n <= R: the first L_n columns of every
-                               mode-n factor are shared by all blocks (Section II-C);
-                               a mode with L_n > 0 needs equal I_n in every block */
-    const int64_t* dims;    /* [S*3]: I_n of block s at dims[3*s + n], each >= 1 */
+    int32_t coupled[CONCPD_MAX_ORDER]; /* L_n for n < N (later entries ignored), 0 <= L_n <= R:
+                               the first L_n columns of every mode-n factor are shared by all
+                               blocks (Section II-C); a mode with L_n > 0 needs equal I_n in
+                               every block */
+    const int64_t* dims;    /* [S*N]: I_n of block s at dims[N*s + n], each >= 1; C-contiguous
+                               tensors, the last mode fastest */
     int32_t tensor_dtype;   /* element type of the caller's tensors: CONCPD_F64 or CONCPD_F32 */
     int32_t compute_dtype;  /* MTTKRP operand type.  CONCPD_F64 needs F64 tensors and keeps
                                every quantity in FP64.  CONCPD_F32 runs FP32 MFMA.
@@ -103,7 +115,7 @@ typedef struct concpd_config {
                                Lipschitz constant unchanged.  Host factor and lambda arrays
                                keep the stride R; columns >= R^(s) are ignored on input and
                                read back as zero. */
-    const uint64_t* coupled_blocks; /* [3] flexible coupling (Section III-C): bit s of
+    const uint64_t* coupled_blocks; /* [N] flexible coupling (Section III-C): bit s of
                                coupled_blocks[n] set = block s shares mode n's first L_n
                                columns; blocks left out keep all R columns of that mode
                                individual.  A mode with L_n > 0 needs at least one bit set
@@ -136,7 +148,7 @@ concpd_status concpd_query_workspace(const concpd_config* cfg, size_t* bytes);
  * iterate and computes its Grams, core data term b, F_0 and RelErr_0 on the
  * device (Algorithm 1, initialisation).
  *   tensors      [S] device pointers to the blocks (borrowed, read-only).
- *   init_U       [S*3] host I_n x R row-major arrays (copied), or NULL for a
+ *   init_U       [S*N] host I_n x R row-major arrays (copied), or NULL for a
  *                seeded U[0,1] draw (SplitMix64, order: n, then s, then row,
  *                then column; shared columns drawn once).  Shared columns are
  *                taken from block 0.
@@ -257,13 +269,13 @@ concpd_status concpd_get_factor(concpd_ctx ctx, int32_t n, int32_t s, double* ho
 concpd_status concpd_get_lambda(concpd_ctx ctx, int32_t s, double* host_dst);
 
 /* Lipschitz constants used by the last accepted sweep (eq. eqLipsLd /
- * eqLipsLu): Ld [S], Lu [S*3] (index 3*s + n), LC [3] = sum_s Lu.  Synchronises. */
+ * eqLipsLu): Ld [S], Lu [S*N] (index N*s + n), LC [N] = sum_s Lu.  Synchronises. */
 concpd_status concpd_get_lipschitz(concpd_ctx ctx, double* Ld, double* Lu, double* LC);
 
 /* Read the iterate state for a checkpoint, in the layout concpd_set_state
- * takes back: U, lam = x_{k-1} and U_prev, lam_prev = x_{k-2} ([S*3] host
- * I_n x R arrays at index 3*s + n / [S] R-vectors, caller-allocated; any of
- * the four may be NULL to skip it), Ld_prev [S], Lu_prev [S*3], LC_prev [3]
+ * takes back: U, lam = x_{k-1} and U_prev, lam_prev = x_{k-2} ([S*N] host
+ * I_n x R arrays at index N*s + n / [S] R-vectors, caller-allocated; any of
+ * the four may be NULL to skip it), Ld_prev [S], Lu_prev [S*N], LC_prev [N]
  * (negative = none), t = t_{k-1}, k.  Restoring these into a context of the
  * same configuration continues the run bit for bit (the restart count starts
  * again from 0).  Synchronises.  Errors: EINVAL, EHIP. */
@@ -272,9 +284,9 @@ concpd_status concpd_get_state(concpd_ctx ctx, double* const* U, double* const* 
                                double* t, int64_t* k);
 
 /* Replace the iterate state (checkpoint restore / teacher forcing):
- *   U, lam          x_{k-1}: [S*3] / [S] host arrays,
+ *   U, lam          x_{k-1}: [S*N] / [S] host arrays,
  *   U_prev, lam_prev x_{k-2} (NULL: same as x_{k-1}),
- *   Ld_prev [S], Lu_prev [S*3], LC_prev [3]: constants of the previous sweep,
+ *   Ld_prev [S], Lu_prev [S*N], LC_prev [N]: constants of the previous sweep,
  *                   NULL or negative entries meaning "none" (weight 0),
  *   t               t_{k-1} of eq. eqextrawu (t_0 = 1), k the iteration count.
  * Recomputes Grams, b, F_{k-1}, RelErr_{k-1}; clears the converged flag.
@@ -306,7 +318,9 @@ concpd_status concpd_loss_grad(concpd_ctx ctx, const void* const* U_dev, const v
                                double* loss, void* const* gU_dev, void* const* glam_dev);
 
 /* Test hook: K = M^(s)_(n) U^{⊙-n} at the current iterate, I_n x R row-major
- * float (double in F64 mode) written to dev_out.  Synchronises. */
+ * float (double in F64 mode) written to dev_out, by the launches a sweep uses
+ * (at order N > 3 the dimension-tree pass of mode n's half and its
+ * contraction, every factor from x_{k-1}).  Synchronises. */
 concpd_status concpd_debug_mttkrp(concpd_ctx ctx, int32_t n, int32_t s, void* dev_out);
 
 /* Test hook: the largest eigenvalue of each of `count` symmetric n x n FP64

@@ -16,12 +16,15 @@ OK, EINVAL, ENOTSUP, ENONFINITE, EHIP, ESTATE = 0, 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTSUP", 3: "ENONFINITE", 4: "EHIP", 5: "ESTATE"}
 
 
+MAX_ORDER = 6   # CONCPD_MAX_ORDER
+
+
 class Config(ctypes.Structure):
     _fields_ = [
         ("order", ctypes.c_int32),
         ("num_blocks", ctypes.c_int32),
         ("rank", ctypes.c_int32),
-        ("coupled", ctypes.c_int32 * 3),
+        ("coupled", ctypes.c_int32 * MAX_ORDER),
         ("dims", ctypes.POINTER(ctypes.c_int64)),
         ("tensor_dtype", ctypes.c_int32),
         ("compute_dtype", ctypes.c_int32),

@@ -5,6 +5,7 @@
 
 #define CPD_MAXS 64   // blocks per context
 #define CPD_MAXR 64   // components per block
+#define CPD_MAXN 6    // tensor order (CONCPD_MAX_ORDER)
 
 // Device-side control block: scalars of the outer iteration (Algorithm 1).
 #define CPD_K2ROWS_DEFAULT 16   // i1 rows per mode-2 contraction chunk
@@ -35,16 +36,17 @@ struct Ctrl {
 
 // Per-context geometry, resident in the workspace.
 struct Geo {
+    int N;                        // tensor order
     int S, R, Rq;                 // Rq = R rounded up to a multiple of 4 (factor row stride)
-    int L[3];
+    int L[CPD_MAXN];
     int rk[CPD_MAXS];             // R^(s): columns in use per block (the rest stay zero)
-    int ngrp[3];                  // blocks of mode n's coupling group (L_n > 0), else every block
-    int grp[3][CPD_MAXS];         // their indices, ascending
+    int ngrp[CPD_MAXN];           // blocks of mode n's coupling group (L_n > 0), else every block
+    int grp[CPD_MAXN][CPD_MAXS];  // their indices, ascending
     int upd_core;
     int lra;                      // 1: gradients from the Tucker form
-    int I[CPD_MAXS][3];
+    int I[CPD_MAXS][CPD_MAXN];
     int J[CPD_MAXS][3];           // Tucker ranks (lra)
-    long long uoff[3][CPD_MAXS];  // element offset of U^(n,s) inside one factor slot
+    long long uoff[CPD_MAXN][CPD_MAXS];  // element offset of U^(n,s) inside one factor slot
     long long yoff[CPD_MAXS];     // Y^(s) = M^(s) x_3 U^(3,s): I1 x I2 x Rq
     long long koff[CPD_MAXS];     // K^(3,s) buffer (I3 x Rq)
     long long poff[CPD_MAXS];     // mode-3 MTTKRP partials: nchunk x I3 x Rq
@@ -63,6 +65,18 @@ struct Geo {
     int nrg[CPD_MAXS];            // ceil(I2 / 64)
     const void* M[CPD_MAXS];      // block tensors in the MTTKRP operand type
     int mdtype;                   // operand type of M (concpd_dtype)
+    // order N > 3: two-level dimension tree.  M^(s) is viewed as an A x B
+    // matrix, A = I_0 ... I_{h-1} rows (modes 0..h-1), B = I_h ... I_{N-1}
+    // columns (the rest, contiguous).  Pass A forms T_A = M KR_B (A x Rq), pass
+    // B forms T_B = M^T KR_A (B x Rq); each mode's MTTKRP is a short
+    // contraction of T_A or T_B with the other factors of its half.
+    int nh;                       // h
+    long long nwA[CPD_MAXS], nwB[CPD_MAXS];
+    int npa[CPD_MAXS], npb[CPD_MAXS];     // contraction parts of pass A / pass B
+    long long kpa[CPD_MAXS], kpb[CPD_MAXS];   // contraction length per part (multiple of 16)
+    long long taoff[CPD_MAXS];    // pass-A partials: npa x A x Rq (in the Y region)
+    long long tboff[CPD_MAXS];    // pass-B partials: npb x B x Rq (in the Y region)
+    long long kroff[CPD_MAXS];    // Khatri-Rao operand: max(A, B) x Rq (in the part region)
 };
 
 // Device pointers of the iterate state.  Slot 0 = x_k being built,
@@ -71,18 +85,18 @@ template <typename T>
 struct StateP {
     T* U[3];            // factors, one slot = sum_{n,s} I_n * Rq elements
     double* lam[3];     // [S][Rq]
-    double* V[2];       // Grams U^T U, [3][S][R*R], slots 0 and 1
+    double* V[2];       // Grams U^T U, [N][S][R*R], slots 0 and 1
     double* b[2];       // core data term (U^⊙)^T vec(M), [S][Rq]
     double* P;          // D H_{-n} D of the mode being updated, [S][R*R]
     double* Ld_cur;     // [S]
     double* Ld_prev;
-    double* Lu_cur;     // [3][S]
+    double* Lu_cur;     // [N][S]
     double* Lu_prev;
-    double* LC_prev;    // [3]
+    double* LC_prev;    // [N]
     double* Fblk;       // [S]
     double* normM2;     // [S] ||M^(s)||_F^2 (or ||G^(s)||^2 in lra mode)
     T* Y;               // pass-1 output
-    T* K3;              // reduced mode-3 MTTKRP
+    T* K3;              // reduced mode-3 MTTKRP (order N > 3: the MTTKRP of the mode in work)
     T* part;            // mode-3 partials
     T* K1p;             // mode-1 partials
     T* K2;              // mode-2 MTTKRP
@@ -97,6 +111,7 @@ struct ItemP2 { int s, chunk, q0, pad; };           // pass 2: block, 4-slab chu
 // individual), or of the -ns blocks of the mode's coupling group (ns < 0)
 struct ItemU  { int s0, ns, row0, nrows; }; 
 struct ItemK2 { int s, col0, chunk, pad; };         // mode-2 contraction: block, column tile start, i1 chunk
+struct ItemNW { int s, og, part, pad; };            // order-N pass: block (< 0: empty), 64-output group, contraction part
 
 // Kernel launchers (defined in the .hip files).
 namespace cpd {
@@ -112,7 +127,15 @@ template <typename T> void launch_init_stats(const Geo* g, const StateP<T>& st, 
 template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int P, int Rq, int slot, int mdtype, int dma, hipStream_t q);
 template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int mdtype, int maxI2, hipStream_t q);
 template <typename T> void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, hipStream_t q);
-template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int lds_rows, int lra, hipStream_t q);
+// ksrc: 0 the order-3 pass outputs, 1 the Tucker form, 2 the plain K buffer (order N > 3)
+template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int lds_rows, int ksrc, hipStream_t q);
+// order N > 3 (dimension tree): Khatri-Rao operand of one half from factor
+// slot `slot`, pass A (half = 0) or B (half = 1), and the MTTKRP of mode n
+// from that pass's partials (modes before n of its half from slot lo_slot)
+// (check_stop: the sweep's launches do nothing once the stopping rule has fired)
+template <typename T> void launch_nw_kr(const Geo* g, const StateP<T>& st, int S, int half, int slot, long long maxrows, int Rq, int check_stop, hipStream_t q);
+template <typename T> void launch_nw_pass(const Geo* g, const StateP<T>& st, const ItemNW* items, int nitems, int half, int Rq, int check_stop, hipStream_t q);
+template <typename T> void launch_nw_contract(const Geo* g, const StateP<T>& st, int S, int n, int lo_slot, int maxI, int Rq, int check_stop, hipStream_t q);
 template <typename T> void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, int R, T* out, int ld_out, int lra, hipStream_t q);
 template <typename T> void launch_resid(const Geo* g, const StateP<T>& st, const void* M, int dtype, int s, int I1, double* part, hipStream_t q);
 void launch_sqnorm(const void* src, int dtype, long long n, double* out, double* part, int npart, hipStream_t q);

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_finite(const TS* __restrict__ x, long l
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
-// ||M^(s) - [[lambda; U^(1), U^(2), U^(3)]]||^2 for the slab i1 = blockIdx.x of
+// ||M^(s) - [[lambda; U^(1), ..., U^(N)]]||^2 for the slab i1 = blockIdx.x of
 // block s (the accepted iterate in slot 1), FP64 accumulation.
 template <typename TS, typename T>
 __global__ __launch_bounds__(256) void k_resid_slab(const Geo* __restrict__ g, StateP<T> st, const TS* __restrict__ M, int s,
@@ -69,21 +69,44 @@ __global__ __launch_bounds__(256) void k_resid_slab(const Geo* __restrict__ g, S
     __shared__ double w[CPD_MAXR];
     apply_rot(st);
     const int i1 = blockIdx.x;
-    const int I2 = g->I[s][1], I3 = g->I[s][2], R = g->R, Rq = g->Rq;
+    const int N = g->N, R = g->R, Rq = g->Rq;
     const T* U1 = st.U[1] + g->uoff[0][s] + (long long)i1 * Rq;
-    const T* U2 = st.U[1] + g->uoff[1][s];
-    const T* U3 = st.U[1] + g->uoff[2][s];
     const double* lam = st.lam[1] + s * Rq;
     if (threadIdx.x < R) w[threadIdx.x] = lam[threadIdx.x] * (double)U1[threadIdx.x];
     __syncthreads();
     double acc = 0.0;
-    const TS* Ms = M + (long long)i1 * I2 * I3;
-    for (long long e = threadIdx.x; e < (long long)I2 * I3; e += 256) {
-        const int i2 = (int)(e / I3), i3 = (int)(e % I3);
-        double m = 0.0;
-        for (int r = 0; r < R; ++r) m += w[r] * (double)U2[(long long)i2 * Rq + r] * (double)U3[(long long)i3 * Rq + r];
-        const double d = as_f64<TS>(Ms[e]) - m;
-        acc += d * d;
+    long long slab = 1;
+    for (int m = 1; m < N; ++m) slab *= g->I[s][m];
+    const TS* Ms = M + (long long)i1 * slab;
+    if (N == 3) {
+        const int I2 = g->I[s][1], I3 = g->I[s][2];
+        const T* U2 = st.U[1] + g->uoff[1][s];
+        const T* U3 = st.U[1] + g->uoff[2][s];
+        for (long long e = threadIdx.x; e < (long long)I2 * I3; e += 256) {
+            const int i2 = (int)(e / I3), i3 = (int)(e % I3);
+            double m = 0.0;
+            for (int r = 0; r < R; ++r) m += w[r] * (double)U2[(long long)i2 * Rq + r] * (double)U3[(long long)i3 * Rq + r];
+            const double d = as_f64<TS>(Ms[e]) - m;
+            acc += d * d;
+        }
+    } else {
+        // order N > 3: the element's row offsets in modes 2 .. N, last mode fastest
+        for (long long e = threadIdx.x; e < slab; e += 256) {
+            long long off[CPD_MAXN];
+            long long x = e;
+            for (int m = N - 1; m >= 1; --m) {
+                off[m] = g->uoff[m][s] + (x % g->I[s][m]) * Rq;
+                x /= g->I[s][m];
+            }
+            double m = 0.0;
+            for (int r = 0; r < R; ++r) {
+                double p = w[r];
+                for (int q = 1; q < N; ++q) p *= (double)st.U[1][off[q] + r];
+                m += p;
+            }
+            const double d = as_f64<TS>(Ms[e]) - m;
+            acc += d * d;
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();

@@ -23,8 +23,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 }
 
 
-// After the mode-3 update: Gram of U^(3), b (the data term (U^⊙)^T vec(M) of
-// eq. solapgG, reused by the next core update) and F^(s).  The last workgroup
+// After the last mode's update: Gram of U^(N), b (the data term (U^⊙)^T vec(M)
+// of eq. solapgG, reused by the next core update) and F^(s).  The last workgroup
 // sums F over the blocks in block order, applies the restart test of
 // Algorithm 1 and, for an accepted sweep, commits it: Lipschitz constants,
 // k, t, w_hat, the stopping rule and the slot rotation.
@@ -34,21 +34,24 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     if (c->stop) return;
     apply_rot(st);
     const int s = blockIdx.x, tid = threadIdx.x;
-    const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R;
+    const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R, N = g->N, NS = N * S;
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     __shared__ int last;
     __shared__ double fb[CPD_MAXS], nb[CPD_MAXS];
     // what the last workgroup needs, read now so that its latency overlaps the
-    // Gram (no workgroup of this launch writes any of it before the last one)
+    // Gram (no workgroup of this launch writes any of it before the last one);
+    // N S Lipschitz constants, up to two per thread
     const double nrm = (tid < S) ? st.normM2[tid] : 1.0;
     const double ldc = (tid < S) ? st.Ld_cur[tid] : 0.0;
-    const double luc = (tid < 3 * S) ? st.Lu_cur[tid] : 0.0;
+    const double luc = (tid < NS) ? st.Lu_cur[tid] : 0.0;
+    const double luc2 = (tid + 256 < NS) ? st.Lu_cur[tid + 256] : 0.0;
     const int redo0 = c->redo, restart_on = c->restart_on, reset_t = c->reset_t;
     const double F_prev = c->F_prev, rel_old = c->rel_prev, t_old = c->t, tol = c->tol;
     const long long k_old = c->k;
     const long long restarts = c->restarts;
     const int rot3 = c->rot3, rot2 = c->rot2;
-    // the objective's other inputs (Grams of the new modes 1 and 2, lambda)
+    // the objective's other inputs (Grams of the new modes 1 .. N-1, lambda;
+    // at order N > 3 v1 carries V_2 * ... * V_{N-1})
     constexpr int EP = (NMAX * NMAX + 255) / 256;
     double v0[EP], v1[EP];
     {
@@ -60,15 +63,20 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
             v0[q] = V0[i];
             v1[q] = V1[i];
         }
+        for (int m = 2; m < N - 1; ++m) {
+            const double* Vx = st.V[0] + (m * S + s) * RR;
+#pragma unroll
+            for (int q = 0; q < EP; ++q) v1[q] *= Vx[min(tid + 256 * q, RR - 1)];
+        }
     }
     __shared__ double lam[64];
     if (tid < 64) lam[tid] = st.lam[0][s * Rq + min(tid, R - 1)];
     const double nrm_s = st.normM2[s];
-    double* V2 = st.V[0] + (2 * S + s) * RR;
+    double* V2 = st.V[0] + ((N - 1) * S + s) * RR;
     double* b = st.b[0] + s * Rq;
     double* V2l = (double*)(smraw + gram_lds_bytes<T>(Rq, 1));
     double* bl = V2l + RR;
-    block_gram<T>(st.U[0] + g->uoff[2][s], g->I[s][2], R, Rq, V2, st.K3 + g->koff[s], b, smraw, V2l, bl);
+    block_gram<T>(st.U[0] + g->uoff[N - 1][s], g->I[s][N - 1], R, Rq, V2, st.K3 + g->koff[s], b, smraw, V2l, bl);
     const double F = block_objective_pf<EP>(lam, v0, v1, V2l, bl, nrm_s, R);
     if (tid == 0) {
         store_agent(&st.Fblk[s], F);
@@ -106,14 +114,18 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     __syncthreads();
     if (!accept) return;
     // accept: the Lipschitz constants of this sweep become the previous ones
-    __shared__ double lu[3 * CPD_MAXS];
+    __shared__ double lu[CPD_MAXN * CPD_MAXS];
     if (tid < S) st.Ld_prev[tid] = ldc;
-    if (tid < 3 * S) {
+    if (tid < NS) {
         st.Lu_prev[tid] = luc;
         lu[tid] = luc;
     }
+    if (tid + 256 < NS) {
+        st.Lu_prev[tid + 256] = luc2;
+        lu[tid + 256] = luc2;
+    }
     __syncthreads();
-    if (tid < 3) {
+    if (tid < N) {
         // L_C over the mode's coupling group (every block when L_n = 0)
         double LC = 0.0;
         for (int k = 0; k < g->ngrp[tid]; ++k) LC += lu[tid * S + g->grp[tid][k]];
@@ -137,7 +149,7 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
 }
 
 // Iterate in slot 1 (initial or restored): Grams of every factor, b from the
-// reduced mode-3 MTTKRP, F and RelErr; sets F_prev / rel_prev.
+// reduced MTTKRP of the last mode, F and RelErr; sets F_prev / rel_prev.
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_stats(const Geo* __restrict__ g, StateP<T> st) {
     Ctrl* c = st.ctrl;
@@ -147,15 +159,17 @@ __global__ __launch_bounds__(256) void k_init_stats(const Geo* __restrict__ g, S
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     __shared__ int last;
     __shared__ double fb[CPD_MAXS], nb[CPD_MAXS];
-    for (int m = 0; m < 2; ++m)
+    const int N = g->N;
+    for (int m = 0; m < N - 1; ++m)
         block_gram<T>(st.U[1] + g->uoff[m][s], g->I[s][m], R, Rq, st.V[1] + (m * S + s) * RR, nullptr, nullptr, smraw);
-    double* V2 = st.V[1] + (2 * S + s) * RR;
+    double* V2 = st.V[1] + ((N - 1) * S + s) * RR;
     double* b = st.b[1] + s * Rq;
-    block_gram<T>(st.U[1] + g->uoff[2][s], g->I[s][2], R, Rq, V2, st.K3 + g->koff[s], b, smraw);
+    block_gram<T>(st.U[1] + g->uoff[N - 1][s], g->I[s][N - 1], R, Rq, V2, st.K3 + g->koff[s], b, smraw);
     __threadfence_block();
     __syncthreads();
-    const double F = block_objective(st.lam[1] + s * Rq, st.V[1] + (0 * S + s) * RR, st.V[1] + (1 * S + s) * RR, V2, b,
-                                     st.normM2[s], R);
+    const double F = (N == 3) ? block_objective(st.lam[1] + s * Rq, st.V[1] + (0 * S + s) * RR, st.V[1] + (1 * S + s) * RR, V2,
+                                                b, st.normM2[s], R)
+                              : block_objective_n(st.lam[1] + s * Rq, st.V[1] + s * RR, (long long)S * RR, N, b, st.normM2[s], R);
     if (tid == 0) {
         store_agent(&st.Fblk[s], F);
         wait_stores();

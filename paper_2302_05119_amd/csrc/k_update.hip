@@ -5,9 +5,10 @@
 //   individual columns:  U_I = max(0, U_hat_I - G_I / L_u^(n,s))
 //   shared columns:      U_C = max(0, U_hat_C - sum_s G_C^(s) / sum_s L_u^(n,s))
 //
-// K = M_(n) U^{⊙-n} comes from the MTTKRP kernels: the mode-1 partials of
-// pass 1 (one per 64 rows of i2), the mode-2 contraction, and the pass-2 chunk
-// partials for mode 3, each summed here in fixed order.
+// K = M_(n) U^{⊙-n} comes from the MTTKRP kernels: at order 3 the mode-1
+// partials of pass 1 (one per 64 rows of i2), the mode-2 contraction, and the
+// pass-2 chunk partials for mode 3, each summed here in fixed order; at order
+// N > 3 the plain buffer of the dimension-tree contraction.
 // All of the small arithmetic is FP64; the new factor is rounded to the
 // storage type once.  A workgroup owns a row tile of every block that shares
 // the mode's columns, so the coupled sum runs in LDS in block order.
@@ -130,15 +131,17 @@ template void launch_extract_k<double>(const Geo*, const StateP<double>&, int, i
 
 template <typename T>
 void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int lds_rows,
-                   int lra, hipStream_t q) {
+                   int ksrc, hipStream_t q) {
     if (nitems <= 0) return;
     // lds_rows = max over items of ns * nrows; the shared-gradient buffer uses at most as much
     const size_t lds = sizeof(double) * (size_t)lds_rows * (size_t)(2 * R);
-    const int ks = lra ? KSRC_LRA0 + n : (n == 0 ? KSRC_K1P : (n == 1 ? KSRC_K2 : KSRC_PART));
+    const int ks = ksrc == 2 ? KSRC_PLAIN
+                             : (ksrc == 1 ? KSRC_LRA0 + n : (n == 0 ? KSRC_K1P : (n == 1 ? KSRC_K2 : KSRC_PART)));
 #define CPD_UPD(KS) \
     case KS: hipLaunchKernelGGL((k_update<T, KS>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap); break;
     switch (ks) {
         CPD_UPD(KSRC_K1P) CPD_UPD(KSRC_K2) CPD_UPD(KSRC_PART) CPD_UPD(KSRC_LRA0) CPD_UPD(KSRC_LRA1) CPD_UPD(KSRC_LRA2)
+        CPD_UPD(KSRC_PLAIN)
         default: break;
     }
 #undef CPD_UPD

@@ -1,12 +1,13 @@
 // Sources of the MTTKRP result K = M_(n) U^{⊙-n} used by the factor update,
 // the statistics and the gradient kernels: the pass partials of the dense
-// path (summed in fixed order) or the Tucker form of the lra path.
+// path (summed in fixed order), the Tucker form of the lra path, or the plain
+// I_n x Rq buffer that the order-N contraction writes.
 #pragma once
 #include "dev_common.h"
 
 namespace cpd {
 
-enum { KSRC_K1P = 0, KSRC_K2 = 1, KSRC_PART = 2, KSRC_LRA0 = 3, KSRC_LRA1 = 4, KSRC_LRA2 = 5 };
+enum { KSRC_K1P = 0, KSRC_K2 = 1, KSRC_PART = 2, KSRC_LRA0 = 3, KSRC_LRA1 = 4, KSRC_LRA2 = 5, KSRC_PLAIN = 6 };
 
 // Sum of n strided values p[0], p[st], ..., p[(n-1) st] in index order, eight
 // loads in flight per step (clamped addresses, zeros past n): a loop with one
@@ -35,6 +36,8 @@ __device__ __forceinline__ double k_value(const Geo* __restrict__ g, const State
         acc = strided_sum(st.K1p + g->k1off[s] + (long long)i * nrg * Rq + col, Rq, nrg);
     } else if (KSRC == KSRC_K2) {
         acc = strided_sum(st.K2 + g->k2off[s] + (long long)i * Rq + col, (long long)g->I[s][1] * Rq, g->nk2[s]);
+    } else if (KSRC == KSRC_PLAIN) {
+        acc = (double)st.K3[g->koff[s] + (long long)i * Rq + col];
     } else if (KSRC >= KSRC_LRA0) {
         // Tucker form: K_n[i][col] = sum_j A_n[i][j] C_n[j][col] (four chains
         // by j mod 4, then the remainder; eight terms in flight per step)

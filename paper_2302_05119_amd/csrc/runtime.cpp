@@ -55,11 +55,18 @@ struct StaticWs {
 StaticWs g_static;
 
 #define CPD_PROF_REPS 4   // back-to-back launches of each pass per profiled sweep
+// Entry points that exist at order 3 only (the Tucker/ALS path, state
+// transfer, autograd, tuning and profiling hooks).
+#define NEED_ORDER3(c, what)                                                                   \
+    do {                                                                                       \
+        if ((c)->N != 3) return fail(CONCPD_ENOTSUP, "%s needs a 3-way context", what);        \
+    } while (0)
+
 int operand_bytes(int dtype) { return dtype == CONCPD_F64 ? 8 : (dtype == CONCPD_F32 ? 4 : 2); }
 
 struct Layout {
     size_t geo, ctrl, U[3], lam[3], V[2], b[2], P, Ld_cur, Ld_prev, Lu_cur, Lu_prev, LC_prev, Fblk, normM2, normOrig, Y,
-        K3, part, K1p, K2, it1, it2, itk2, itu[3], scratch, shadow, lra, flag, total;
+        K3, part, K1p, K2, it1, it2, itk2, itu[CPD_MAXN], itna, itnb, scratch, shadow, lra, flag, total;
     // loss/gradient evaluation point (autograd form): factors, lambda, Grams,
     // b, step matrices, per-block F, control block, output pointer tables
     size_t gU, glam, gV, gb, gP, gF, gctrl, gptr;
@@ -78,9 +85,10 @@ struct Lists {
     std::vector<ItemP1> p1;
     std::vector<ItemP2> p2;
     std::vector<ItemK2> k2;
-    std::vector<ItemU> u[3];
+    std::vector<ItemU> u[CPD_MAXN];
+    std::vector<ItemNW> na, nb;   // order N > 3: the two passes of the dimension tree
     int maxI2;
-    int lds_rows[3];
+    int lds_rows[CPD_MAXN];
     int p1_split;   // wavefronts per pass-1 item (1, 2 or 4)
 };
 
@@ -95,31 +103,41 @@ bool in_group(uint64_t m, int s) { return (m >> s) & 1ull; }
 
 concpd_status validate(const concpd_config* c) {
     if (!c) return fail(CONCPD_EINVAL, "config is NULL");
-    if (c->order != 3) return fail(CONCPD_ENOTSUP, "order %d not supported (only 3)", c->order);
+    if (c->order < 3 || c->order > CPD_MAXN) return fail(CONCPD_EINVAL, "order %d not in [3, %d]", c->order, CPD_MAXN);
+    const int N = c->order;
     if (c->num_blocks < 1 || c->num_blocks > CPD_MAXS) return fail(CONCPD_EINVAL, "num_blocks %d not in [1, %d]", c->num_blocks, CPD_MAXS);
     if (c->rank < 1 || c->rank > CPD_MAXR) return fail(CONCPD_EINVAL, "rank %d not in [1, %d]", c->rank, CPD_MAXR);
     if (!c->dims) return fail(CONCPD_EINVAL, "dims is NULL");
-    for (int n = 0; n < 3; ++n)
+    for (int n = 0; n < N; ++n)
         if (c->coupled[n] < 0 || c->coupled[n] > c->rank)
             return fail(CONCPD_EINVAL, "coupled[%d] = %d not in [0, rank]", n, c->coupled[n]);
     if (c->coupled_blocks) {
         const uint64_t all = c->num_blocks >= 64 ? ~0ull : ((1ull << c->num_blocks) - 1);
-        for (int n = 0; n < 3; ++n) {
+        for (int n = 0; n < N; ++n) {
             if (c->coupled_blocks[n] & ~all) return fail(CONCPD_EINVAL, "coupled_blocks[%d] names blocks >= S", n);
             if (c->coupled[n] > 0 && !c->coupled_blocks[n])
                 return fail(CONCPD_EINVAL, "coupled_blocks[%d] selects no block for L = %d", n, c->coupled[n]);
         }
     }
-    for (int s = 0; s < c->num_blocks; ++s)
-        for (int n = 0; n < 3; ++n) {
-            const int64_t d = c->dims[3 * s + n];
-            if (d < 1 || d > (1 << 24)) return fail(CONCPD_EINVAL, "dims[%d] = %lld out of range", 3 * s + n, (long long)d);
+    for (int s = 0; s < c->num_blocks; ++s) {
+        long long nel = 1;
+        for (int n = 0; n < N; ++n) {
+            const int64_t d = c->dims[N * s + n];
+            if (d < 1 || d > (1 << 24)) return fail(CONCPD_EINVAL, "dims[%d] = %lld out of range", N * s + n, (long long)d);
+            nel *= d;
+            if (nel > (1LL << 40)) return fail(CONCPD_EINVAL, "block %d has more than 2^40 elements", s);
             const uint64_t gm = group_mask(c, n);
             const int f = first_member(gm);
-            if (in_group(gm, s) && d != c->dims[3 * f + n])
+            if (in_group(gm, s) && d != c->dims[N * f + n])
                 return fail(CONCPD_EINVAL, "mode %d is coupled but block %d has I=%lld != %lld", n, s, (long long)d,
-                            (long long)c->dims[3 * f + n]);
+                            (long long)c->dims[N * f + n]);
         }
+    }
+    if (N > 3) {
+        if (c->compute_dtype != CONCPD_F32 && c->compute_dtype != CONCPD_F64)
+            return fail(CONCPD_ENOTSUP, "order %d supports compute_dtype F32 or F64", N);
+        if (c->tucker_ranks) return fail(CONCPD_ENOTSUP, "lra compression needs order 3");
+    }
     if (c->tensor_dtype != CONCPD_F64 && c->tensor_dtype != CONCPD_F32)
         return fail(CONCPD_EINVAL, "tensor_dtype must be F64 or F32");
     if (c->compute_dtype < CONCPD_F64 || c->compute_dtype > CONCPD_F16) return fail(CONCPD_EINVAL, "bad compute_dtype");
@@ -143,7 +161,7 @@ concpd_status validate(const concpd_config* c) {
     if (c->block_ranks) {
         for (int s = 0; s < c->num_blocks; ++s) {
             int lmax = 1;
-            for (int n = 0; n < 3; ++n)
+            for (int n = 0; n < N; ++n)
                 if (in_group(group_mask(c, n), s)) lmax = std::max(lmax, c->coupled[n]);
             if (c->block_ranks[s] < lmax || c->block_ranks[s] > c->rank)
                 return fail(CONCPD_EINVAL, "block_ranks[%d] = %d not in [max(1, L_n), rank]", s, c->block_ranks[s]);
@@ -176,13 +194,79 @@ void xcd_order(std::vector<Item>& v, size_t grp = 1) {
     v.swap(out);
 }
 
+// Order N > 3: the split h of the dimension tree (the one with the smallest
+// intermediates sum_s A_s + B_s) and the contraction parts of both passes:
+// each pass gets about 2048 wavefronts (eight per CU), a part covers at least
+// 64 values of the contraction, in whole chunks of 16.
+struct NwPlan {
+    int h = 0;
+    long long A[CPD_MAXS], B[CPD_MAXS], kpa[CPD_MAXS], kpb[CPD_MAXS];
+    int npa[CPD_MAXS], npb[CPD_MAXS];
+};
+void nw_plan(const concpd_config* c, NwPlan* P) {
+    const int S = c->num_blocks, N = c->order;
+    long long best = -1;
+    for (int h = 1; h < N; ++h) {
+        long long tot = 0;
+        for (int s = 0; s < S; ++s) {
+            long long a = 1, b = 1;
+            for (int m = 0; m < N; ++m) (m < h ? a : b) *= c->dims[N * s + m];
+            tot += a + b;
+        }
+        if (best < 0 || tot < best) {
+            best = tot;
+            P->h = h;
+        }
+    }
+    long long oga = 0, ogb = 0;
+    for (int s = 0; s < S; ++s) {
+        long long a = 1, b = 1;
+        for (int m = 0; m < N; ++m) (m < P->h ? a : b) *= c->dims[N * s + m];
+        P->A[s] = a;
+        P->B[s] = b;
+        oga += (a + 63) / 64;
+        ogb += (b + 63) / 64;
+    }
+    const long long want = 2048;
+    auto parts = [&](long long og, long long K, int* np, long long* kp) {
+        long long p = std::max(1LL, (want + og - 1) / og);
+        p = std::min(p, std::max(1LL, K / 64));
+        long long per = (K + p - 1) / p;
+        per = (per + 15) / 16 * 16;
+        *kp = per;
+        *np = (int)((K + per - 1) / per);
+    };
+    for (int s = 0; s < S; ++s) {
+        parts(oga, P->B[s], &P->npa[s], &P->kpa[s]);
+        parts(ogb, P->A[s], &P->npb[s], &P->kpb[s]);
+    }
+}
+
 void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAULT, int p1split = 0) {
-    const int S = c->num_blocks, R = c->rank, Rq = (R + 3) / 4 * 4;
+    const int S = c->num_blocks, R = c->rank, Rq = (R + 3) / 4 * 4, N = c->order;
     L->p1.clear();
     L->p2.clear();
     L->k2.clear();
+    L->na.clear();
+    L->nb.clear();
     L->maxI2 = 1;
-    for (int s = 0; s < S; ++s) {
+    L->p1_split = 1;
+    if (N > 3) {
+        NwPlan W;
+        nw_plan(c, &W);
+        for (int s = 0; s < S; ++s) {
+            for (int og = 0; og * 64LL < W.A[s]; ++og)
+                for (int p = 0; p < W.npa[s]; ++p) L->na.push_back({s, og, p, 0});
+            for (int og = 0; og * 64LL < W.B[s]; ++og)
+                for (int p = 0; p < W.npb[s]; ++p) L->nb.push_back({s, og, p, 0});
+        }
+        while (L->na.size() % 4) L->na.push_back({-1, 0, 0, 0});
+        while (L->nb.size() % 4) L->nb.push_back({-1, 0, 0, 0});
+        xcd_order(L->na, 4);
+        xcd_order(L->nb, 4);
+    }
+    // the two-pass MTTKRP work lists exist at order 3 only
+    for (int s = 0; s < S && N == 3; ++s) {
         const int I1 = (int)c->dims[3 * s], I2 = (int)c->dims[3 * s + 1], I3 = (int)c->dims[3 * s + 2];
         L->maxI2 = std::max(L->maxI2, I2);
         for (int ch = 0; ch * k2rows < I1; ++ch)
@@ -197,7 +281,7 @@ void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAU
     // stream best unsplit, 1024 items split in two), no more than the 64-byte
     // chunks of the shortest row;
     // the list is padded to whole workgroups (4 / P items) with empty items
-    {
+    if (N == 3) {
         int minck = 1 << 30;
         for (int s = 0; s < S; ++s) minck = std::min(minck, (int)((c->dims[3 * s + 2] + 15) / 16));
         int P = 1;
@@ -210,7 +294,7 @@ void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAU
     }
     xcd_order(L->p2);
     xcd_order(L->k2);
-    for (int n = 0; n < 3; ++n) {
+    for (int n = 0; n < N; ++n) {
         L->u[n].clear();
         int lds_rows = 1;
         if (c->coupled[n] > 0) {
@@ -218,7 +302,7 @@ void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAU
             // then the blocks outside the group with individual columns
             const uint64_t gm = group_mask(c, n);
             const int nm = __builtin_popcountll(gm);
-            const int I = (int)c->dims[3 * first_member(gm) + n];
+            const int I = (int)c->dims[N * first_member(gm) + n];
             int nrows = std::max(1, 256 / (nm * R));
             // LDS: ns * nrows * 2R doubles <= 48 KiB
             while (nrows > 1 && (size_t)nm * nrows * 2 * R * 8 > 49152) --nrows;
@@ -227,14 +311,14 @@ void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAU
             const int nri = std::max(1, 256 / R);
             for (int s = 0; s < S; ++s) {
                 if (in_group(gm, s)) continue;
-                const int Is = (int)c->dims[3 * s + n];
+                const int Is = (int)c->dims[N * s + n];
                 for (int r0 = 0; r0 < Is; r0 += nri) L->u[n].push_back({s, 1, r0, std::min(nri, Is - r0)});
                 lds_rows = std::max(lds_rows, nri);
             }
         } else {
             const int nrows = std::max(1, 256 / R);
             for (int s = 0; s < S; ++s) {
-                const int I = (int)c->dims[3 * s + n];
+                const int I = (int)c->dims[N * s + n];
                 for (int r0 = 0; r0 < I; r0 += nrows) L->u[n].push_back({s, 1, r0, std::min(nrows, I - r0)});
             }
             lds_rows = nrows;
@@ -246,13 +330,14 @@ void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAU
 void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     memset(P, 0, sizeof *P);
     memset(g, 0, sizeof *g);
-    const int S = c->num_blocks, R = c->rank, Rq = (R + 3) / 4 * 4;
+    const int S = c->num_blocks, R = c->rank, Rq = (R + 3) / 4 * 4, N = c->order;
     const bool f64 = c->compute_dtype == CONCPD_F64;
     P->esz = f64 ? 8 : 4;
+    g->N = N;
     g->S = S;
     g->R = R;
     g->Rq = Rq;
-    for (int n = 0; n < 3; ++n) {
+    for (int n = 0; n < N; ++n) {
         g->L[n] = c->coupled[n];
         const uint64_t gm = group_mask(c, n);
         g->ngrp[n] = 0;
@@ -263,12 +348,39 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     g->mdtype = c->compute_dtype;
     g->k2rows = CPD_K2ROWS_DEFAULT;
     long long u = 0, y = 0, k = 0, p = 0, k1 = 0, k2 = 0;
-    for (int n = 0; n < 3; ++n)
+    for (int n = 0; n < N; ++n)
         for (int s = 0; s < S; ++s) {
             g->uoff[n][s] = u;
-            u += c->dims[3 * s + n] * Rq;
+            u += c->dims[N * s + n] * Rq;
         }
-    for (int s = 0; s < S; ++s) {
+    if (N > 3) {
+        // order N > 3: one MTTKRP buffer per block (the mode in work), the
+        // partials of both passes in the Y region, the Khatri-Rao operand in
+        // the part region
+        NwPlan W;
+        nw_plan(c, &W);
+        g->nh = W.h;
+        for (int s = 0; s < S; ++s) {
+            for (int n = 0; n < N; ++n) g->I[s][n] = (int)c->dims[N * s + n];
+            long long im = 1;
+            for (int n = 0; n < N; ++n) im = std::max<long long>(im, c->dims[N * s + n]);
+            g->koff[s] = k;
+            k += im * Rq;
+            g->nwA[s] = W.A[s];
+            g->nwB[s] = W.B[s];
+            g->npa[s] = W.npa[s];
+            g->npb[s] = W.npb[s];
+            g->kpa[s] = W.kpa[s];
+            g->kpb[s] = W.kpb[s];
+            g->taoff[s] = y;
+            y += (long long)W.npa[s] * W.A[s] * Rq;
+            g->tboff[s] = y;
+            y += (long long)W.npb[s] * W.B[s] * Rq;
+            g->kroff[s] = p;
+            p += std::max(W.A[s], W.B[s]) * Rq;
+        }
+    }
+    for (int s = 0; s < S && N == 3; ++s) {
         const long long I1 = c->dims[3 * s], I2 = c->dims[3 * s + 1], I3 = c->dims[3 * s + 2];
         for (int n = 0; n < 3; ++n) g->I[s][n] = (int)c->dims[3 * s + n];
         g->yoff[s] = y;
@@ -299,14 +411,14 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     P->ctrl = take(sizeof(Ctrl));
     for (int i = 0; i < 3; ++i) P->U[i] = take((size_t)u * P->esz);
     for (int i = 0; i < 3; ++i) P->lam[i] = take(sizeof(double) * S * Rq);
-    for (int i = 0; i < 2; ++i) P->V[i] = take(sizeof(double) * 3 * S * R * R);
+    for (int i = 0; i < 2; ++i) P->V[i] = take(sizeof(double) * N * S * R * R);
     for (int i = 0; i < 2; ++i) P->b[i] = take(sizeof(double) * S * Rq);
     P->P = take(sizeof(double) * S * R * R);
     P->Ld_cur = take(sizeof(double) * S);
     P->Ld_prev = take(sizeof(double) * S);
-    P->Lu_cur = take(sizeof(double) * 3 * S);
-    P->Lu_prev = take(sizeof(double) * 3 * S);
-    P->LC_prev = take(sizeof(double) * 3);
+    P->Lu_cur = take(sizeof(double) * N * S);
+    P->Lu_prev = take(sizeof(double) * N * S);
+    P->LC_prev = take(sizeof(double) * N);
     P->Fblk = take(sizeof(double) * S);
     P->normM2 = take(sizeof(double) * S);
     P->normOrig = take(sizeof(double) * S);
@@ -322,9 +434,11 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
         build_lists(c, &Lmin, CPD_K2ROWS_MIN);
         P->itk2 = take(sizeof(ItemK2) * std::max<size_t>(1, std::max(L.k2.size(), Lmin.k2.size())));
     }
-    for (int n = 0; n < 3; ++n) P->itu[n] = take(sizeof(ItemU) * std::max<size_t>(1, L.u[n].size()));
+    for (int n = 0; n < N; ++n) P->itu[n] = take(sizeof(ItemU) * std::max<size_t>(1, L.u[n].size()));
+    P->itna = take(sizeof(ItemNW) * std::max<size_t>(1, L.na.size()));
+    P->itnb = take(sizeof(ItemNW) * std::max<size_t>(1, L.nb.size()));
     size_t scr = 4096;
-    for (int s = 0; s < S; ++s) scr = std::max<size_t>(scr, (size_t)c->dims[3 * s]);
+    for (int s = 0; s < S; ++s) scr = std::max<size_t>(scr, (size_t)c->dims[N * s]);
     P->scratch_len = scr;
     P->scratch = take(sizeof(double) * scr);
     P->flag = take(sizeof(int) * 4);
@@ -346,7 +460,8 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
         const int me = operand_bytes(c->compute_dtype), ve = 16 / me;
         const bool half = c->compute_dtype == CONCPD_BF16 || c->compute_dtype == CONCPD_F16;
         size_t tot = 0;
-        for (int s = 0; s < S; ++s) {
+        // (order N > 3 reads the caller's tensors directly)
+        for (int s = 0; s < S && N == 3; ++s) {
             const long long I3 = c->dims[3 * s + 2];
             const bool copy = half || I3 % ve != 0;
             const long long ld = (I3 + ve - 1) / ve * ve;
@@ -428,9 +543,10 @@ struct concpd_ctx_s {
     concpd_config cfg;
     std::vector<int64_t> dims;
     std::vector<int32_t> tucker;
-    int S, R, Rq, L[3];
+    int N;                 // tensor order
+    int S, R, Rq, L[CPD_MAXN];
     std::vector<int> rk;   // R^(s): block s uses columns 0..rk[s]-1, the rest stay zero
-    uint64_t cmask[3];     // the caller's coupling groups (copied)
+    uint64_t cmask[CPD_MAXN];   // the caller's coupling groups (copied)
     bool f64;
     int mdtype;
     std::vector<const void*> tensors;
@@ -628,11 +744,52 @@ void run_sweep_lra(concpd_ctx c, const StateP<T>& st) {
     cpd::launch_finish<T>(g, st, S, R, q);
 }
 
+// Largest A_s, B_s and I_n of an order-N context (launch grids).
+void nw_extents(concpd_ctx c, long long* maxA, long long* maxB, int* maxI) {
+    *maxA = *maxB = 1;
+    *maxI = 1;
+    for (int s = 0; s < c->S; ++s) {
+        *maxA = std::max(*maxA, c->geo.nwA[s]);
+        *maxB = std::max(*maxB, c->geo.nwB[s]);
+        for (int n = 0; n < c->N; ++n) *maxI = std::max(*maxI, c->geo.I[s][n]);
+    }
+}
+
+// The sweep at order N > 3: core update, then modes 0..h-1 from pass A (x_{k-1}
+// factors of modes h..N-1), pass B with the new modes 0..h-1, modes h..N-1.
+template <typename T>
+void run_sweep_nw(concpd_ctx c, const StateP<T>& st) {
+    const int extrap = 1;
+    const Geo* g = c->dgeo;
+    const int S = c->S, R = c->R, Rq = c->Rq, N = c->N, h = c->geo.nh;
+    hipStream_t q = c->q;
+    long long maxA, maxB;
+    int maxI;
+    nw_extents(c, &maxA, &maxB, &maxI);
+    const ItemNW* ita = (const ItemNW*)(c->ws + c->lay.itna);
+    const ItemNW* itb = (const ItemNW*)(c->ws + c->lay.itnb);
+    cpd::launch_core<T>(g, st, S, R, extrap, q);
+    cpd::launch_nw_kr<T>(g, st, S, 0, 1, maxB, Rq, 1, q);
+    cpd::launch_nw_pass<T>(g, st, ita, (int)c->lists.na.size(), 0, Rq, 1, q);
+    for (int n = 0; n < N; ++n) {
+        if (n == h) {
+            cpd::launch_nw_kr<T>(g, st, S, 1, 0, maxA, Rq, 1, q);
+            cpd::launch_nw_pass<T>(g, st, itb, (int)c->lists.nb.size(), 1, Rq, 1, q);
+        }
+        if (n > 0) cpd::launch_prep<T>(g, st, S, R, n, q);
+        cpd::launch_nw_contract<T>(g, st, S, n, 0, maxI, Rq, 1, q);
+        cpd::launch_update<T>(g, st, (const ItemU*)(c->ws + c->lay.itu[n]), (int)c->lists.u[n].size(), n, R, extrap,
+                              c->lists.lds_rows[n], 2, q);
+    }
+    cpd::launch_finish<T>(g, st, S, R, q);
+}
+
 // One sweep: either an accepted iteration, or an extrapolated sweep that the
 // restart test rejects (then the next sweep redoes it and is accepted).
 template <typename T>
 void run_one_sweep(concpd_ctx c, const StateP<T>& st) {
-    if (c->lra) run_sweep_lra<T>(c, st);
+    if (c->N > 3) run_sweep_nw<T>(c, st);
+    else if (c->lra) run_sweep_lra<T>(c, st);
     else run_sweep<T>(c, st);
 }
 
@@ -677,6 +834,18 @@ concpd_status launch_sweeps(concpd_ctx c, long long count) {
 // Grams, b, F and RelErr of the iterate in slot 1.
 template <typename T>
 void recompute_stats(concpd_ctx c, const StateP<T>& st) {
+    if (c->N > 3) {
+        // K of the last mode with every factor from slot 1: pass B on the
+        // Khatri-Rao product of modes 0..h-1, then the contraction
+        long long maxA, maxB;
+        int maxI;
+        nw_extents(c, &maxA, &maxB, &maxI);
+        cpd::launch_nw_kr<T>(c->dgeo, st, c->S, 1, 1, maxA, c->Rq, 0, c->q);
+        cpd::launch_nw_pass<T>(c->dgeo, st, (const ItemNW*)(c->ws + c->lay.itnb), (int)c->lists.nb.size(), 1, c->Rq, 0, c->q);
+        cpd::launch_nw_contract<T>(c->dgeo, st, c->S, c->N - 1, 1, maxI, c->Rq, 0, c->q);
+        cpd::launch_init_stats<T>(c->dgeo, st, c->S, c->R, c->q);
+        return;
+    }
     if (c->lra) {
         // W of the iterate in both slots, then K3 = A_3 C_3 and the statistics
         for (int n = 0; n < 3; ++n)
@@ -725,13 +894,14 @@ concpd_status read_stats(concpd_ctx c, concpd_stats* out) {
 template <typename T>
 void pack_factors(concpd_ctx c, const double* const* U, std::vector<T>& out) {
     out.assign((size_t)c->lay.uslot, (T)0);
-    for (int n = 0; n < 3; ++n)
+    const int N = c->N;
+    for (int n = 0; n < N; ++n)
         for (int s = 0; s < c->S; ++s) {
-            const int I = (int)c->dims[3 * s + n];
-            const double* src = U[3 * s + n];
+            const int I = (int)c->dims[N * s + n];
+            const double* src = U[N * s + n];
             const uint64_t gm = group_mask(&c->cfg, n);
             const int Ls = in_group(gm, s) ? c->L[n] : 0;
-            const double* shared = Ls ? U[3 * first_member(gm) + n] : src;
+            const double* shared = Ls ? U[N * first_member(gm) + n] : src;
             T* dst = out.data() + c->geo.uoff[n][s];
             for (int i = 0; i < I; ++i)
                 for (int r = 0; r < c->rk[s]; ++r)
@@ -776,13 +946,14 @@ concpd_status upload_iterate(concpd_ctx c, const double* const* U, const double*
 }
 
 concpd_status set_lipschitz_prev(concpd_ctx c, const double* Ld, const double* Lu, const double* LC) {
-    std::vector<double> ld(c->S, -1.0), lu(3 * c->S, -1.0), lc(3, -1.0);
+    const int N = c->N;
+    std::vector<double> ld(c->S, -1.0), lu((size_t)N * c->S, -1.0), lc(N, -1.0);
     for (int s = 0; s < c->S; ++s) {
         if (Ld) ld[s] = Ld[s];
-        for (int n = 0; n < 3; ++n)
-            if (Lu) lu[n * c->S + s] = Lu[3 * s + n];
+        for (int n = 0; n < N; ++n)
+            if (Lu) lu[n * c->S + s] = Lu[N * s + n];
     }
-    for (int n = 0; n < 3; ++n)
+    for (int n = 0; n < N; ++n)
         if (LC) lc[n] = LC[n];
     HIPCHECK(hipMemcpyAsync(c->ws + c->lay.Ld_prev, ld.data(), ld.size() * 8, hipMemcpyHostToDevice, c->q));
     HIPCHECK(hipMemcpyAsync(c->ws + c->lay.Lu_prev, lu.data(), lu.size() * 8, hipMemcpyHostToDevice, c->q));
@@ -1011,13 +1182,16 @@ concpd_status init_impl(const concpd_config* cfg, const void* const* tensors, co
     c->S = cfg->num_blocks;
     c->R = cfg->rank;
     c->Rq = (c->R + 3) / 4 * 4;
-    for (int n = 0; n < 3; ++n) c->L[n] = cfg->coupled[n];
-    for (int n = 0; n < 3; ++n) c->cmask[n] = cfg->coupled_blocks ? cfg->coupled_blocks[n] : ~0ull;
+    c->N = cfg->order;
+    const int N = c->N;
+    for (int n = 0; n < CPD_MAXN; ++n) c->L[n] = n < N ? cfg->coupled[n] : 0;
+    for (int n = 0; n < CPD_MAXN; ++n) c->cmask[n] = (cfg->coupled_blocks && n < N) ? cfg->coupled_blocks[n] : ~0ull;
+    for (int n = N; n < CPD_MAXN; ++n) c->cfg.coupled[n] = 0;
     c->cfg.coupled_blocks = cfg->coupled_blocks ? c->cmask : nullptr;
     c->rk.assign(c->S, c->R);
     if (cfg->block_ranks) c->rk.assign(cfg->block_ranks, cfg->block_ranks + c->S);
     c->cfg.block_ranks = c->rk.data();
-    c->dims.assign(cfg->dims, cfg->dims + 3 * c->S);
+    c->dims.assign(cfg->dims, cfg->dims + (size_t)N * c->S);
     c->cfg.dims = c->dims.data();
     if (cfg->tucker_ranks) {
         c->tucker.assign(cfg->tucker_ranks, cfg->tucker_ranks + 3 * c->S);
@@ -1055,23 +1229,23 @@ concpd_status init_impl(const concpd_config* cfg, const void* const* tensors, co
     }
 
     // host-side initial iterate
-    std::vector<std::vector<double>> hU(3 * c->S);
-    std::vector<const double*> pU(3 * c->S);
+    std::vector<std::vector<double>> hU((size_t)N * c->S);
+    std::vector<const double*> pU((size_t)N * c->S);
     std::vector<std::vector<double>> hl(c->S);
     std::vector<const double*> pl(c->S);
     if (!init_U || !init_lambda) {
         SplitMix64 rng{seed};
-        for (int n = 0; n < 3; ++n)
+        for (int n = 0; n < N; ++n)
             for (int s = 0; s < c->S; ++s) {
-                const int I = (int)c->dims[3 * s + n];
+                const int I = (int)c->dims[N * s + n];
                 const uint64_t gm = group_mask(&c->cfg, n);
                 const int f = first_member(gm);
                 const bool copy = in_group(gm, s) && s != f;   // shared columns drawn once, by the first member
-                std::vector<double>& v = hU[3 * s + n];
+                std::vector<double>& v = hU[N * s + n];
                 v.assign((size_t)I * c->R, 0.0);
                 for (int i = 0; i < I; ++i)
                     for (int r = 0; r < c->R; ++r) {
-                        if (r < c->L[n] && copy) v[(size_t)i * c->R + r] = hU[3 * f + n][(size_t)i * c->R + r];
+                        if (r < c->L[n] && copy) v[(size_t)i * c->R + r] = hU[N * f + n][(size_t)i * c->R + r];
                         else v[(size_t)i * c->R + r] = rng.uniform();
                     }
             }
@@ -1082,13 +1256,13 @@ concpd_status init_impl(const concpd_config* cfg, const void* const* tensors, co
             for (int r = 0; r < c->R; ++r) hl[s][r] = cfg->update_core ? rng.uniform() : 1.0;
         }
     }
-    for (int i = 0; i < 3 * c->S; ++i) pU[i] = init_U ? init_U[i] : hU[i].data();
+    for (int i = 0; i < N * c->S; ++i) pU[i] = init_U ? init_U[i] : hU[i].data();
     for (int s = 0; s < c->S; ++s) pl[s] = init_lambda ? init_lambda[s] : hl[s].data();
     for (int s = 0; s < c->S; ++s) {
-        for (int n = 0; n < 3; ++n)
-            if (!pU[3 * s + n] || !cols_finite(pU[3 * s + n], c->dims[3 * s + n], c->R, c->rk[s])) {
+        for (int n = 0; n < N; ++n)
+            if (!pU[N * s + n] || !cols_finite(pU[N * s + n], c->dims[N * s + n], c->R, c->rk[s])) {
                 delete c;
-                return fail(pU[3 * s + n] ? CONCPD_ENONFINITE : CONCPD_EINVAL, "init_U[%d] missing or not finite", 3 * s + n);
+                return fail(pU[N * s + n] ? CONCPD_ENONFINITE : CONCPD_EINVAL, "init_U[%d] missing or not finite", N * s + n);
             }
         if (!pl[s] || !all_finite(pl[s], c->rk[s])) {
             delete c;
@@ -1119,7 +1293,7 @@ concpd_status init_impl(const concpd_config* cfg, const void* const* tensors, co
     // operand copies of the tensors
     for (int s = 0; s < c->S; ++s) {
         c->geo.M[s] = c->tensors[s];
-        c->geo.mld[s] = c->dims[3 * s + 2];
+        c->geo.mld[s] = c->dims[N * s + N - 1];
         if (c->lay.shadow_ld[s] > 0) {
             char* dst = c->ws + c->lay.shadow + c->lay.shadow_off[s];
             cpd::launch_pad_copy(c->tensors[s], cfg->tensor_dtype, dst, c->mdtype, c->dims[3 * s] * c->dims[3 * s + 1],
@@ -1140,7 +1314,10 @@ concpd_status init_impl(const concpd_config* cfg, const void* const* tensors, co
         // aligned; by default it does so for 16-bit storage, whose 32-byte
         // chunks carry twice the values (measured: faster for BF16 at every
         // shape, slower for FP32 rows of a few thousand values)
-        c->p1dma_ok = all && !c->f64;
+        // order N > 3: pass A reads rows of B = I_h ... I_N values
+        for (int s = 0; s < c->S && N > 3; ++s)
+            c->geo.mvec[s] = (c->geo.nwB[s] % (16 / me) == 0) && ((uintptr_t)c->geo.M[s] % 16 == 0);
+        c->p1dma_ok = all && !c->f64 && N == 3;
         c->p1dma = c->p1dma_ok && c->mdtype != 1;
     }
     // the fused launches by default while pass 1 has at most two wavefronts
@@ -1149,7 +1326,7 @@ concpd_status init_impl(const concpd_config* cfg, const void* const* tensors, co
     {
         int dev = 0, ncu = 0;
         if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-            c->fuse = c->R <= 32 && (long long)c->lists.p1.size() * c->lists.p1_split <= 8LL * ncu;
+            c->fuse = N == 3 && c->R <= 32 && (long long)c->lists.p1.size() * c->lists.p1_split <= 8LL * ncu;
         c->fuse_dflt = c->fuse;
     }
     c->dgeo = (Geo*)(c->ws + c->lay.geo);
@@ -1160,10 +1337,14 @@ concpd_status init_impl(const concpd_config* cfg, const void* const* tensors, co
         INIT_HIP(hipMemcpyAsync(c->ws + c->lay.it2, c->lists.p2.data(), c->lists.p2.size() * sizeof(ItemP2), hipMemcpyHostToDevice, c->q));
     if (!c->lists.k2.empty())
         INIT_HIP(hipMemcpyAsync(c->ws + c->lay.itk2, c->lists.k2.data(), c->lists.k2.size() * sizeof(ItemK2), hipMemcpyHostToDevice, c->q));
-    for (int n = 0; n < 3; ++n)
+    for (int n = 0; n < N; ++n)
         if (!c->lists.u[n].empty())
             INIT_HIP(hipMemcpyAsync(c->ws + c->lay.itu[n], c->lists.u[n].data(), c->lists.u[n].size() * sizeof(ItemU),
                                     hipMemcpyHostToDevice, c->q));
+    if (!c->lists.na.empty())
+        INIT_HIP(hipMemcpyAsync(c->ws + c->lay.itna, c->lists.na.data(), c->lists.na.size() * sizeof(ItemNW), hipMemcpyHostToDevice, c->q));
+    if (!c->lists.nb.empty())
+        INIT_HIP(hipMemcpyAsync(c->ws + c->lay.itnb, c->lists.nb.data(), c->lists.nb.size() * sizeof(ItemNW), hipMemcpyHostToDevice, c->q));
     c->sf = make_state<float>(c->ws, c->lay);
     c->sd = make_state<double>(c->ws, c->lay);
     c->ctrl = (Ctrl*)(c->ws + c->lay.ctrl);
@@ -1172,11 +1353,12 @@ concpd_status init_impl(const concpd_config* cfg, const void* const* tensors, co
     int* dflag = (int*)(c->ws + c->lay.flag);
     double* sqpart = (double*)(c->ws + c->lay.scratch);
     for (int s = 0; s < c->S; ++s) {
-        const long long n = c->dims[3 * s] * c->dims[3 * s + 1] * c->dims[3 * s + 2];
+        long long n = 1;
+        for (int m = 0; m < N; ++m) n *= c->dims[N * s + m];
         cpd::launch_finite_check(c->tensors[s], cfg->tensor_dtype, n, dflag, c->q);
         cpd::launch_sqnorm(c->tensors[s], cfg->tensor_dtype, n, (double*)(c->ws + c->lay.normOrig) + s, sqpart, 1024, c->q);
-        // the operand copy's padding is zero, so its norm runs over I1 I2 ld
-        cpd::launch_sqnorm(c->geo.M[s], c->mdtype, c->dims[3 * s] * c->dims[3 * s + 1] * c->geo.mld[s],
+        // the operand copy's padding is zero, so its norm runs over all rows of length ld
+        cpd::launch_sqnorm(c->geo.M[s], c->mdtype, n / c->dims[N * s + N - 1] * c->geo.mld[s],
                            (double*)(c->ws + c->lay.normM2) + s, sqpart, 1024, c->q);
     }
     int hflag = 0;
@@ -1291,6 +1473,7 @@ concpd_status concpd_fit(concpd_ctx c, concpd_stats* out) {
 }
 
 concpd_status lra_compress(concpd_ctx c, const int32_t* ranks, concpd_stats* out) {
+    if (c) NEED_ORDER3(c, "lra_compress");
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
     if (c->tucker.empty()) return fail(CONCPD_ESTATE, "lra_compress: no Tucker ranks configured");
     if (ranks)
@@ -1343,6 +1526,7 @@ concpd_status lra_compress(concpd_ctx c, const int32_t* ranks, concpd_stats* out
 concpd_status lra_compress_cp(concpd_ctx c, const double* const* init, uint64_t seed, double eps, int32_t max_it,
                               int32_t cp_rank, int32_t* iters, double* relerr, concpd_stats* out) {
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    NEED_ORDER3(c, "lra_compress_cp");
     if (c->lra) return fail(CONCPD_ESTATE, "lra_compress_cp: the context is already compressed");
     if (c->tucker.empty()) return fail(CONCPD_ESTATE, "lra_compress_cp: needs tucker_ranks (J_n >= R reserves the storage)");
     if (cp_rank < 0 || cp_rank > c->R) return fail(CONCPD_EINVAL, "cp_rank %d not in [0, rank]", cp_rank);
@@ -1435,7 +1619,7 @@ concpd_status concpd_global_fit(concpd_ctx c, double* fit) {
     double* res = scratch + c->lay.scratch_len - 1;
     double acc = 0.0;
     for (int s = 0; s < c->S; ++s) {
-        const int I1 = (int)c->dims[3 * s];
+        const int I1 = (int)c->dims[(size_t)c->N * s];
         if (c->f64) cpd::launch_resid<double>(c->dgeo, c->sd, c->tensors[s], c->cfg.tensor_dtype, s, I1, scratch, c->q);
         else cpd::launch_resid<float>(c->dgeo, c->sf, c->tensors[s], c->cfg.tensor_dtype, s, I1, scratch, c->q);
         cpd::launch_sum_parts(scratch, I1, res, c->q);
@@ -1450,8 +1634,8 @@ concpd_status concpd_global_fit(concpd_ctx c, double* fit) {
 
 concpd_status concpd_get_factor(concpd_ctx c, int32_t n, int32_t s, double* dst) {
     if (!c || !dst) return fail(CONCPD_EINVAL, "NULL argument");
-    if (n < 0 || n > 2 || s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "n/s out of range");
-    const int I = (int)c->dims[3 * s + n];
+    if (n < 0 || n >= c->N || s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "n/s out of range");
+    const int I = (int)c->dims[(size_t)c->N * s + n];
     const size_t cnt = (size_t)I * c->Rq;
     const char* src = c->ws + c->lay.U[phys_slot3(c, 1)] + (size_t)c->geo.uoff[n][s] * c->lay.esz;
     if (c->f64) {
@@ -1481,6 +1665,7 @@ concpd_status concpd_get_lambda(concpd_ctx c, int32_t s, double* dst) {
 
 concpd_status lra_get_tucker(concpd_ctx c, int32_t s, int32_t n, double* dst) {
     if (!c || !dst) return fail(CONCPD_EINVAL, "NULL argument");
+    NEED_ORDER3(c, "lra_get_tucker");
     if (s < 0 || s >= c->S || n < 0 || n > 3) return fail(CONCPD_EINVAL, "block or mode out of range");
     if (!c->lra) return fail(CONCPD_ESTATE, "lra_get_tucker before lra_compress");
     const double* L = (const double*)(c->ws + c->lay.lra);
@@ -1494,18 +1679,19 @@ concpd_status lra_get_tucker(concpd_ctx c, int32_t s, int32_t n, double* dst) {
 
 concpd_status concpd_get_lipschitz(concpd_ctx c, double* Ld, double* Lu, double* LC) {
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
-    std::vector<double> ld(c->S), lu(3 * c->S), lc(3);
+    const int N = c->N;
+    std::vector<double> ld(c->S), lu((size_t)N * c->S), lc(N);
     HIPCHECK(hipMemcpyAsync(ld.data(), c->ws + c->lay.Ld_prev, 8 * ld.size(), hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipMemcpyAsync(lu.data(), c->ws + c->lay.Lu_prev, 8 * lu.size(), hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipMemcpyAsync(lc.data(), c->ws + c->lay.LC_prev, 8 * lc.size(), hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipStreamSynchronize(c->q));
     for (int s = 0; s < c->S; ++s) {
         if (Ld) Ld[s] = ld[s];
-        for (int n = 0; n < 3; ++n)
-            if (Lu) Lu[3 * s + n] = lu[n * c->S + s];
+        for (int n = 0; n < N; ++n)
+            if (Lu) Lu[N * s + n] = lu[n * c->S + s];
     }
     if (LC)
-        for (int n = 0; n < 3; ++n) LC[n] = lc[n];
+        for (int n = 0; n < N; ++n) LC[n] = lc[n];
     return CONCPD_OK;
 }
 
@@ -1514,14 +1700,15 @@ concpd_status concpd_set_state(concpd_ctx c, const double* const* U, const doubl
                                const double* Lu_prev, const double* LC_prev, double t, int64_t k) {
     if (!c || !U || !lam) return fail(CONCPD_EINVAL, "NULL argument");
     if (!(t >= 1.0) || k < 0) return fail(CONCPD_EINVAL, "t must be >= 1 and k >= 0");
+    const int N = c->N;
     for (int s = 0; s < c->S; ++s) {
-        for (int n = 0; n < 3; ++n) {
-            const int64_t I = c->dims[3 * s + n];
+        for (int n = 0; n < N; ++n) {
+            const int e = N * s + n;
+            const int64_t I = c->dims[e];
             const int rk = c->rk[s];
-            if (!U[3 * s + n]) return fail(CONCPD_EINVAL, "U[%d] is NULL", 3 * s + n);
-            if (!cols_finite(U[3 * s + n], I, c->R, rk) ||
-                (U_prev && (!U_prev[3 * s + n] || !cols_finite(U_prev[3 * s + n], I, c->R, rk))))
-                return fail(CONCPD_ENONFINITE, "U / U_prev[%d] missing or not finite", 3 * s + n);
+            if (!U[e]) return fail(CONCPD_EINVAL, "U[%d] is NULL", e);
+            if (!cols_finite(U[e], I, c->R, rk) || (U_prev && (!U_prev[e] || !cols_finite(U_prev[e], I, c->R, rk))))
+                return fail(CONCPD_ENONFINITE, "U / U_prev[%d] missing or not finite", e);
         }
         if (!lam[s] || !all_finite(lam[s], c->rk[s]) || (lam_prev && (!lam_prev[s] || !all_finite(lam_prev[s], c->rk[s]))))
             return fail(CONCPD_ENONFINITE, "lambda / lambda_prev[%d] missing or not finite", s);
@@ -1544,7 +1731,7 @@ concpd_status concpd_get_state(concpd_ctx c, double* const* U, double* const* U_
                                double* const* lam_prev, double* Ld_prev, double* Lu_prev, double* LC_prev, double* t,
                                int64_t* k) {
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
-    const int S = c->S, R = c->R, Rq = c->Rq;
+    const int S = c->S, R = c->R, Rq = c->Rq, N = c->N;
     Ctrl h;
     HIPCHECK(hipMemcpyAsync(&h, c->ctrl, sizeof h, hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipStreamSynchronize(c->q));
@@ -1566,11 +1753,11 @@ concpd_status concpd_get_state(concpd_ctx c, double* const* U, double* const* U_
             }
             HIPCHECK(hipStreamSynchronize(c->q));
             for (int s = 0; s < S; ++s)
-                for (int n2 = 0; n2 < 3; ++n2) {
-                    double* dst = Ud[3 * s + n2];
-                    if (!dst) return fail(CONCPD_EINVAL, "U / U_prev[%d] is NULL", 3 * s + n2);
+                for (int n2 = 0; n2 < N; ++n2) {
+                    double* dst = Ud[N * s + n2];
+                    if (!dst) return fail(CONCPD_EINVAL, "U / U_prev[%d] is NULL", N * s + n2);
                     const double* src = hv.data() + c->geo.uoff[n2][s];
-                    for (int64_t i = 0; i < c->dims[3 * s + n2]; ++i)
+                    for (int64_t i = 0; i < c->dims[N * s + n2]; ++i)
                         for (int r = 0; r < R; ++r) dst[i * R + r] = src[i * Rq + r];
                 }
         }
@@ -1584,17 +1771,17 @@ concpd_status concpd_get_state(concpd_ctx c, double* const* U, double* const* U_
             }
         }
     }
-    std::vector<double> ld(S), lu(3 * S), lc(3);
+    std::vector<double> ld(S), lu((size_t)N * S), lc(N);
     HIPCHECK(hipMemcpyAsync(ld.data(), c->ws + c->lay.Ld_prev, 8 * ld.size(), hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipMemcpyAsync(lu.data(), c->ws + c->lay.Lu_prev, 8 * lu.size(), hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipMemcpyAsync(lc.data(), c->ws + c->lay.LC_prev, 8 * lc.size(), hipMemcpyDeviceToHost, c->q));
     HIPCHECK(hipStreamSynchronize(c->q));
     for (int s = 0; s < S; ++s) {
         if (Ld_prev) Ld_prev[s] = ld[s];
-        for (int n2 = 0; n2 < 3; ++n2)
-            if (Lu_prev) Lu_prev[3 * s + n2] = lu[n2 * S + s];
+        for (int n2 = 0; n2 < N; ++n2)
+            if (Lu_prev) Lu_prev[N * s + n2] = lu[n2 * S + s];
     }
-    for (int n2 = 0; n2 < 3; ++n2)
+    for (int n2 = 0; n2 < N; ++n2)
         if (LC_prev) LC_prev[n2] = lc[n2];
     if (t) *t = h.t;
     if (k) *k = h.k;
@@ -1604,6 +1791,7 @@ concpd_status concpd_get_state(concpd_ctx c, double* const* U, double* const* U_
 concpd_status concpd_loss_grad(concpd_ctx c, const void* const* U_dev, const void* const* lambda_dev, int32_t coupled,
                                double* loss, void* const* gU_dev, void* const* glam_dev) {
     if (!c || !U_dev || !lambda_dev || !loss || !gU_dev || !glam_dev) return fail(CONCPD_EINVAL, "NULL argument");
+    NEED_ORDER3(c, "concpd_loss_grad");
     if (c->lra) return fail(CONCPD_ESTATE, "concpd_loss_grad is not available in lra mode");
     for (int i = 0; i < 3 * c->S; ++i)
         if (!U_dev[i] || !gU_dev[i]) return fail(CONCPD_EINVAL, "NULL factor pointer %d", i);
@@ -1615,7 +1803,31 @@ concpd_status concpd_loss_grad(concpd_ctx c, const void* const* U_dev, const voi
 
 concpd_status concpd_debug_mttkrp(concpd_ctx c, int32_t n, int32_t s, void* dev_out) {
     if (!c || !dev_out) return fail(CONCPD_EINVAL, "NULL argument");
-    if (n < 0 || n > 2 || s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "n/s out of range");
+    if (n < 0 || n >= c->N || s < 0 || s >= c->S) return fail(CONCPD_EINVAL, "n/s out of range");
+    if (c->N > 3) {
+        // the sweep's own launches for mode n, every other factor from slot 1
+        const int I = (int)c->dims[(size_t)c->N * s + n], half = n >= c->geo.nh;
+        long long maxA, maxB;
+        int maxI;
+        nw_extents(c, &maxA, &maxB, &maxI);
+        const size_t es = c->lay.esz;
+        const ItemNW* items = (const ItemNW*)(c->ws + (half ? c->lay.itnb : c->lay.itna));
+        const int nit = (int)(half ? c->lists.nb.size() : c->lists.na.size());
+        if (c->f64) {
+            cpd::launch_nw_kr<double>(c->dgeo, c->sd, c->S, half, 1, half ? maxA : maxB, c->Rq, 0, c->q);
+            cpd::launch_nw_pass<double>(c->dgeo, c->sd, items, nit, half, c->Rq, 0, c->q);
+            cpd::launch_nw_contract<double>(c->dgeo, c->sd, c->S, n, 1, maxI, c->Rq, 0, c->q);
+        } else {
+            cpd::launch_nw_kr<float>(c->dgeo, c->sf, c->S, half, 1, half ? maxA : maxB, c->Rq, 0, c->q);
+            cpd::launch_nw_pass<float>(c->dgeo, c->sf, items, nit, half, c->Rq, 0, c->q);
+            cpd::launch_nw_contract<float>(c->dgeo, c->sf, c->S, n, 1, maxI, c->Rq, 0, c->q);
+        }
+        HIPCHECK(hipMemcpy2DAsync(dev_out, (size_t)c->R * es, c->ws + c->lay.K3 + (size_t)c->geo.koff[s] * es,
+                                  (size_t)c->Rq * es, (size_t)c->R * es, (size_t)I, hipMemcpyDeviceToDevice, c->q));
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(c->q));
+        return CONCPD_OK;
+    }
     const int I = (int)c->dims[3 * s + n];
     if (c->f64) {
         debug_passes<double>(c, c->sd);
@@ -1708,12 +1920,14 @@ concpd_status concpd_debug_spectral_norm(const double* host_A, int32_t n, int32_
 
 concpd_status concpd_profile(concpd_ctx c, int32_t enable) {
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    NEED_ORDER3(c, "concpd_profile");
     c->profiling = enable != 0;
     return CONCPD_OK;
 }
 
 concpd_status concpd_profile_read(concpd_ctx c, double* ms1, double* ms2, int64_t* launches) {
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    NEED_ORDER3(c, "concpd_profile_read");
     HIPCHECK(hipStreamSynchronize(c->q));
     double a = 0.0, b = 0.0;
     for (size_t i = 0; i + 1 < c->ev1.size(); i += 2) {
@@ -1736,6 +1950,8 @@ concpd_status concpd_profile_read(concpd_ctx c, double* ms1, double* ms2, int64_
 
 concpd_status concpd_set_option(concpd_ctx c, int32_t option, int64_t value) {
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    if (c->N != 3 && option != CONCPD_OPT_GRAPH_SWEEPS)
+        return fail(CONCPD_ENOTSUP, "option %d needs a 3-way context (order N > 3 has graph sweeps only)", option);
     HIPCHECK(hipStreamSynchronize(c->q));
     switch (option) {
     case CONCPD_OPT_GRAPH_SWEEPS:
@@ -1808,6 +2024,7 @@ concpd_status concpd_get_option(concpd_ctx c, int32_t option, int64_t* value) {
 
 concpd_status concpd_autotune(concpd_ctx c, int32_t sweeps, concpd_tuning* out) {
     if (!c) return fail(CONCPD_EINVAL, "ctx is NULL");
+    NEED_ORDER3(c, "concpd_autotune");
     if (sweeps < 1 || sweeps > 10000) return fail(CONCPD_EINVAL, "sweeps %d not in [1, 10000]", sweeps);
     Ctrl h;
     HIPCHECK(hipMemcpyAsync(&h, c->ctrl, sizeof h, hipMemcpyDeviceToHost, c->q));

@@ -753,6 +753,27 @@ __device__ __forceinline__ double block_objective(const double* lam, const doubl
     return 0.5 * (normM2 + red[0]);
 }
 
+// The objective at order N > 3: H = V_1 * V_2 * ... * V_N (Grams at stride gs).
+__device__ __forceinline__ double block_objective_n(const double* lam, const double* V, long long gs, int N, const double* b,
+                                                    double normM2, int R) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x, RR = R * R;
+    double part = 0.0;
+    for (int i = tid; i < RR; i += 256) {
+        double h = lam[i / R] * lam[i % R];
+        for (int m = 0; m < N; ++m) h *= V[m * gs + i];
+        part += h;
+    }
+    if (tid < R) part -= 2.0 * lam[tid] * b[tid];
+    red[tid] = part;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    return 0.5 * (normM2 + red[0]);
+}
+
 // The same objective from values already at hand: V0, V1 entries tid + 256 q
 // in registers, lambda, V2 (row stride R) and b in LDS.  Same products and
 // the same summation order as block_objective.
@@ -811,6 +832,8 @@ __host__ __device__ inline size_t prep_lds_bytes(int R, int Rq) {
 // Core tensor update (eq. solD with the gradient of eq. solapgG at the
 // extrapolated point of eq. eqextraPG), then P = D H_{-1} D and its spectral
 // norm for the mode-1 update.  All 256 threads of the workgroup take part.
+// H is the Hadamard product of the N Grams of x_{k-1}, taken as
+// V_1 * (V_2 * V_3 * ... * V_N).
 template <typename T, int NMAX>
 __device__ __forceinline__ void core_block(const Geo* __restrict__ g, const StateP<T>& st, int s, int extrapolate, char* smraw) {
     const Ctrl* c = st.ctrl;
@@ -831,6 +854,12 @@ __device__ __forceinline__ void core_block(const Geo* __restrict__ g, const Stat
         const int i = min(tid + 256 * m, RR - 1);
         v0[m] = V0[i];
         v12[m] = V1[i] * V2[i];
+    }
+    // order N > 3: the Grams of modes 4.. join the product H_{-1}
+    for (int mm = 3; mm < g->N; ++mm) {
+        const double* Vx = st.V[1] + (mm * S + s) * RR;
+#pragma unroll
+        for (int m = 0; m < EP; ++m) v12[m] *= Vx[min(tid + 256 * m, RR - 1)];
     }
     const double* l1 = st.lam[1] + s * Rq;
     const double* l2 = st.lam[2] + s * Rq;
@@ -895,25 +924,35 @@ __device__ __forceinline__ void core_block(const Geo* __restrict__ g, const Stat
 // threads of the workgroup enter; the eigenvalue runs on the first wavefront.
 template <typename T, int NMAX>
 __device__ __forceinline__ void prep_block(const Geo* __restrict__ g, const StateP<T>& st, int s, int n, char* smraw) {
-    const int S = g->S, R = g->R, Rq = g->Rq, ld = R | 1, RR = R * R;
+    const int S = g->S, R = g->R, Rq = g->Rq, ld = R | 1, RR = R * R, N = g->N;
     const int m = n - 1, tid = threadIdx.x;
     double* Vm = st.V[0] + (m * S + s) * RR;
-    // the other Gram of the step matrix (mode 3 of x_{k-1} for n = 1, the new
-    // mode 1 for n = 2) and lambda, read before the Gram so their latency
-    // overlaps it; the new Gram comes back through LDS
-    const double* Vo = (n == 1) ? st.V[1] + (2 * S + s) * RR : st.V[0] + (0 * S + s) * RR;
+    // the other Grams of the step matrix (every mode but n - 1 and n, in mode
+    // order: at order 3 mode 3 of x_{k-1} for n = 1, the new mode 1 for n = 2)
+    // and lambda, read before the Gram so their latency overlaps it; the new
+    // Gram comes back through LDS
     constexpr int EP = (NMAX * NMAX + 255) / 256;
     double vo[EP];
+    {
+        const int q0 = (n == 1) ? 2 : 0;
+        const double* Vo = (q0 < n ? st.V[0] : st.V[1]) + (q0 * S + s) * RR;
 #pragma unroll
-    for (int q = 0; q < EP; ++q) vo[q] = Vo[min(tid + 256 * q, RR - 1)];
+        for (int q = 0; q < EP; ++q) vo[q] = Vo[min(tid + 256 * q, RR - 1)];
+        for (int mm = q0 + 1; mm < N; ++mm) {
+            if (mm == n - 1 || mm == n) continue;
+            const double* Vx = (mm < n ? st.V[0] : st.V[1]) + (mm * S + s) * RR;
+#pragma unroll
+            for (int q = 0; q < EP; ++q) vo[q] *= Vx[min(tid + 256 * q, RR - 1)];
+        }
+    }
     __shared__ double lam[64];
     if (tid < 64) lam[tid] = st.lam[0][s * Rq + min(tid, R - 1)];
     double* A = (double*)smraw;
     double* Vl = (double*)(smraw + prep_lds_bytes<T>(R, Rq) - sizeof(double) * (size_t)RR);   // new Gram (LDS)
     block_gram<T>(st.U[0] + g->uoff[m][s], g->I[s][m], R, Rq, Vm, nullptr, nullptr, smraw, Vl);
     double* work = eig_work(A, R);
-    // P = D (Va * Vb) D with Va = Gram of mode 1, Vb = Gram of mode 3 (n = 1)
-    // or of mode 2 (n = 2)
+    // P = D (Va * Vb) D: at order 3 Va = Gram of mode 1, Vb = Gram of mode 3
+    // (n = 1) or of mode 2 (n = 2)
 #pragma unroll
     for (int q = 0; q < EP; ++q) {
         const int i = tid + 256 * q;

@@ -45,11 +45,17 @@ def _stride_r(a, R):
 
 
 class CoupledCP:
-    """Coupled nonnegative CP decomposition of S third-order blocks on one GPU.
+    """Coupled nonnegative CP decomposition of S blocks of order N on one GPU.
 
-    tensors      list of S contiguous 3-way torch tensors on one HIP device
-                 (float32, or float64 with compute="f64"); borrowed.
-    rank         R; coupled = (L1, L2, L3) shared leading columns per mode.
+    tensors      list of S contiguous N-way torch tensors on one HIP device
+                 (float32, or float64 with compute="f64"); borrowed.  N = 3
+                 has every method; N = 4..6 (the N-way model of Section II-C)
+                 has the dense sweep with compute "f32" or "f64": step, fit,
+                 factor(s), lam(s), lipschitz, global_fit, get/set_state,
+                 debug_mttkrp and the graph_sweeps option (the others raise
+                 ENOTSUP).
+    rank         R; coupled = (L1, ..., LN) shared leading columns per mode
+                 (default none).
     compute      "f64" | "f32" | "bf16" | "f16": MTTKRP operand type.
     init_U       optional [n][s] arrays (I_n x R); init_lambda optional [s] arrays.
     tucker_ranks optional (J1, J2, J3) or [S][3] for lra_compress.
@@ -64,7 +70,7 @@ class CoupledCP:
                  CONCPD_STATIC_WORKSPACE_BYTES).
     """
 
-    def __init__(self, tensors, rank: int, coupled=(0, 0, 0), compute: str = "f32", init_U=None, init_lambda=None,
+    def __init__(self, tensors, rank: int, coupled=None, compute: str = "f32", init_U=None, init_lambda=None,
                  seed: int = 0, update_core: bool = True, restart: bool = True, delta_w: float = 0.9999,
                  tol: float = 1e-8, max_it: int = 1000, tucker_ranks=None, block_ranks=None, coupled_blocks=None,
                  stream=None, static_workspace: bool = False):
@@ -74,16 +80,22 @@ class CoupledCP:
         self.tensors = list(tensors)
         S = len(self.tensors)
         dev = self.tensors[0].device
+        N = self.tensors[0].dim()
         for t in self.tensors:
-            if t.device != dev or t.dim() != 3 or not t.is_contiguous():
-                raise ValueError("tensors must be contiguous 3-way tensors on one device")
+            if t.device != dev or t.dim() != N or not t.is_contiguous():
+                raise ValueError("tensors must be contiguous tensors of one order on one device")
+        if not 3 <= N <= _lib.MAX_ORDER:
+            raise ValueError(f"tensor order {N} not in [3, {_lib.MAX_ORDER}]")
+        self.N = N
         tdt = _lib.F64 if self.tensors[0].dtype == torch.float64 else _lib.F32
         if any(t.dtype not in (torch.float32, torch.float64) or t.dtype != self.tensors[0].dtype for t in self.tensors):
             raise ValueError("tensors must all be float32 or all float64")
         self.S, self.R = S, int(rank)
-        self.coupled = tuple(int(x) for x in coupled)
+        self.coupled = (0,) * N if coupled is None else tuple(int(x) for x in coupled)
+        if len(self.coupled) != N:
+            raise ValueError(f"coupled needs one L_n per mode ({N})")
         self.dims = [tuple(int(d) for d in t.shape) for t in self.tensors]
-        self._dims_c = (ctypes.c_int64 * (3 * S))(*[d for dims in self.dims for d in dims])
+        self._dims_c = (ctypes.c_int64 * (N * S))(*[d for dims in self.dims for d in dims])
         self._tucker_c = None
         if tucker_ranks is not None:
             tr = np.asarray(tucker_ranks, dtype=np.int32)
@@ -91,10 +103,10 @@ class CoupledCP:
                 tr = np.tile(tr, (S, 1))
             self._tucker_c = (ctypes.c_int32 * (3 * S))(*tr.reshape(-1).tolist())
         cfg = Config()
-        cfg.order = 3
+        cfg.order = N
         cfg.num_blocks = S
         cfg.rank = self.R
-        for n in range(3):
+        for n in range(N):
             cfg.coupled[n] = self.coupled[n]
         cfg.dims = self._dims_c
         cfg.tensor_dtype = tdt
@@ -113,10 +125,10 @@ class CoupledCP:
         self._cmask_c = None
         if coupled_blocks is not None:
             masks = []
-            for n in range(3):
+            for n in range(N):
                 grp = coupled_blocks[n]
                 masks.append((1 << S) - 1 if grp is None else sum(1 << int(b) for b in set(grp)))
-            self._cmask_c = (ctypes.c_uint64 * 3)(*masks)
+            self._cmask_c = (ctypes.c_uint64 * N)(*masks)
         cfg.coupled_blocks = self._cmask_c
         self.cfg = cfg
         self.compute = compute
@@ -135,7 +147,7 @@ class CoupledCP:
         keepU = keepL = None
         pU = pL = None
         if init_U is not None:
-            flat = [_stride_r(init_U[n][s], self.R) for s in range(S) for n in range(3)]
+            flat = [_stride_r(init_U[n][s], self.R) for s in range(S) for n in range(N)]
             keepU, pU = _dbl_ptr_array(flat)
         if init_lambda is not None:
             keepL, pL = _dbl_ptr_array([_stride_r(x, self.R) for x in init_lambda])
@@ -280,7 +292,7 @@ class CoupledCP:
         return out if padded else out[:, :self.block_ranks[s]].copy()
 
     def factors(self):
-        return [[self.factor(n, s) for s in range(self.S)] for n in range(3)]
+        return [[self.factor(n, s) for s in range(self.S)] for n in range(self.N)]
 
     def lam(self, s: int, padded: bool = False) -> np.ndarray:
         out = np.empty(self.R, dtype=np.float64)
@@ -292,11 +304,11 @@ class CoupledCP:
 
     def lipschitz(self):
         Ld = np.empty(self.S)
-        Lu = np.empty(3 * self.S)
-        LC = np.empty(3)
+        Lu = np.empty(self.N * self.S)
+        LC = np.empty(self.N)
         P = ctypes.POINTER(ctypes.c_double)
         check(self._lib.concpd_get_lipschitz(self.ctx, Ld.ctypes.data_as(P), Lu.ctypes.data_as(P), LC.ctypes.data_as(P)))
-        return Ld, Lu.reshape(self.S, 3), LC
+        return Ld, Lu.reshape(self.S, self.N), LC
 
     def global_fit(self) -> float:
         f = ctypes.c_double()
@@ -315,13 +327,13 @@ class CoupledCP:
         """The iterate state for a checkpoint, as keyword arguments of
         set_state: U, U_prev [n][s] (I_n x R^(s)), lam, lam_prev [s],
         Ld_prev [s], Lu_prev [s][n], LC_prev [n] (None where unset), t, k."""
-        S = self.S
-        bufs = {key: [[np.zeros((self.dims[s][n], self.R)) for s in range(S)] for n in range(3)] for key in ("U", "U_prev")}
+        S, N = self.S, self.N
+        bufs = {key: [[np.zeros((self.dims[s][n], self.R)) for s in range(S)] for n in range(N)] for key in ("U", "U_prev")}
         lams = {key: [np.zeros(self.R) for _ in range(S)] for key in ("lam", "lam_prev")}
         P = ctypes.POINTER(ctypes.c_double)
-        flat = lambda UU: (P * (3 * S))(*[UU[n][s].ctypes.data_as(P) for s in range(S) for n in range(3)])  # noqa: E731
+        flat = lambda UU: (P * (N * S))(*[UU[n][s].ctypes.data_as(P) for s in range(S) for n in range(N)])  # noqa: E731
         lptr = lambda LL: (P * S)(*[x.ctypes.data_as(P) for x in LL])  # noqa: E731
-        Ld, Lu, LC = np.zeros(S), np.zeros(3 * S), np.zeros(3)
+        Ld, Lu, LC = np.zeros(S), np.zeros(N * S), np.zeros(N)
         t = ctypes.c_double()
         k = ctypes.c_int64()
         check(self._lib.concpd_get_state(self.ctx, flat(bufs["U"]), flat(bufs["U_prev"]), lptr(lams["lam"]),
@@ -329,15 +341,15 @@ class CoupledCP:
                                          LC.ctypes.data_as(P), ctypes.byref(t), ctypes.byref(k)))
         r = self.block_ranks
         none = lambda v: None if v < 0 else float(v)  # noqa: E731
-        return {"U": [[bufs["U"][n][s][:, :r[s]] for s in range(S)] for n in range(3)],
-                "U_prev": [[bufs["U_prev"][n][s][:, :r[s]] for s in range(S)] for n in range(3)],
+        return {"U": [[bufs["U"][n][s][:, :r[s]] for s in range(S)] for n in range(N)],
+                "U_prev": [[bufs["U_prev"][n][s][:, :r[s]] for s in range(S)] for n in range(N)],
                 "lam": [lams["lam"][s][:r[s]] for s in range(S)], "lam_prev": [lams["lam_prev"][s][:r[s]] for s in range(S)],
-                "Ld_prev": [none(v) for v in Ld], "Lu_prev": [[none(v) for v in Lu[3 * s:3 * s + 3]] for s in range(S)],
+                "Ld_prev": [none(v) for v in Ld], "Lu_prev": [[none(v) for v in Lu[N * s:N * s + N]] for s in range(S)],
                 "LC_prev": [none(v) for v in LC], "t": t.value, "k": k.value}
 
     def set_state(self, U, lam, U_prev=None, lam_prev=None, Ld_prev=None, Lu_prev=None, LC_prev=None, t=1.0, k=0):
         """U, U_prev: [n][s] arrays; Lu_prev [s][n] (or [n][s] transposed by caller); None entries mean 'none'."""
-        flat = lambda UU: [_stride_r(UU[n][s], self.R) for s in range(self.S) for n in range(3)]  # noqa: E731
+        flat = lambda UU: [_stride_r(UU[n][s], self.R) for s in range(self.S) for n in range(N)]  # noqa: E731
         kU, pU = _dbl_ptr_array(flat(U))
         kL, pL = _dbl_ptr_array([_stride_r(x, self.R) for x in lam])
         kUp = pUp = kLp = pLp = None
@@ -354,8 +366,8 @@ class CoupledCP:
             return _opt_dbl(a)
 
         kd, pd = _arr(Ld_prev, (self.S,))
-        ku, pu = _arr(Lu_prev, (self.S, 3))
-        kc, pc = _arr(LC_prev, (3,))
+        ku, pu = _arr(Lu_prev, (self.S, self.N))
+        kc, pc = _arr(LC_prev, (self.N,))
         check(self._lib.concpd_set_state(self.ctx, pU, pUp, pL, pLp, pd, pu, pc, float(t), int(k)))
         del kU, kL, kUp, kLp, kd, ku, kc
 

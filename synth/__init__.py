@@ -41,11 +41,15 @@ def _uniform(rng, rows, cols):
 
 
 def cp_tensor(factors: Sequence[np.ndarray], lam=None) -> np.ndarray:
-    """Dense 3-way tensor sum_r lam_r a_r o b_r o c_r (C-contiguous, float64)."""
-    A, B, C = factors
-    R = A.shape[1]
+    """Dense N-way tensor sum_r lam_r u1_r o u2_r o ... o uN_r (C-contiguous, float64)."""
+    R = factors[0].shape[1]
     w = np.ones(R) if lam is None else np.asarray(lam, dtype=np.float64)
-    return np.einsum("ir,jr,kr,r->ijk", A, B, C, w, optimize=True)
+    if len(factors) == 3:
+        A, B, C = factors
+        return np.einsum("ir,jr,kr,r->ijk", A, B, C, w, optimize=True)
+    idx = "ijklmn"[:len(factors)]
+    spec = ",".join(c + "r" for c in idx) + ",r->" + idx
+    return np.einsum(spec, *factors, w, optimize=True)
 
 
 def add_noise(rng, X: np.ndarray, snr_db: float | None) -> np.ndarray:
@@ -58,9 +62,9 @@ def add_noise(rng, X: np.ndarray, snr_db: float | None) -> np.ndarray:
 
 @dataclass
 class Problem:
-    dims: List[Tuple[int, int, int]]
+    dims: List[Tuple[int, ...]]
     R: int
-    L: Tuple[int, int, int]
+    L: Tuple[int, ...]
     tensors: List[np.ndarray]          # storage dtype (float32 or float64), C-contiguous
     true_factors: List[List[np.ndarray]]  # [n][s], float64
     snr_db: float | None
@@ -73,9 +77,10 @@ class Problem:
 
 def coupled_problem(dims, R, L, snr_db, seed, dtype=np.float32, factor_draw=None, block_ranks=None,
                     block_lam=None, noise="gaussian") -> Problem:
-    """Blocks M^(s) = [[U^(1,s), U^(2,s), U^(3,s)]] (lambda = 1) plus noise.
+    """Blocks M^(s) = [[U^(1,s), ..., U^(N,s)]] (lambda = 1) plus noise.
 
-    ``dims`` is a list of S (I1, I2, I3); a mode with L_n > 0 must have the same
+    ``dims`` is a list of S (I1, ..., IN) (N = 3..6, the N-way model of
+    Section II-C); a mode with L_n > 0 must have the same
     size in every block.  Factors are U[0,1] unless ``factor_draw(rng, n, s_or_None,
     rows, cols)`` is given.  ``block_ranks`` (R^(s) <= R) keeps only the first
     R^(s) components of block s; ``block_lam`` = (lo, hi) draws per-block
@@ -85,8 +90,9 @@ def coupled_problem(dims, R, L, snr_db, seed, dtype=np.float32, factor_draw=None
     """
     rng = rng_for(seed)
     S = len(dims)
+    N = len(dims[0])
     truth = []
-    for n in range(3):
+    for n in range(N):
         sizes = [d[n] for d in dims]
         if L[n] > 0:
             assert len(set(sizes)) == 1, "coupled mode needs equal sizes"
@@ -102,7 +108,7 @@ def coupled_problem(dims, R, L, snr_db, seed, dtype=np.float32, factor_draw=None
     if block_ranks is not None:
         truth = [[u.copy() for u in per] for per in truth]
         for s, r in enumerate(block_ranks):
-            for n in range(3):
+            for n in range(N):
                 truth[n][s][:, r:] = 0.0
         meta["block_ranks"] = [int(r) for r in block_ranks]
     lams = None
@@ -111,7 +117,7 @@ def coupled_problem(dims, R, L, snr_db, seed, dtype=np.float32, factor_draw=None
         meta["lam"] = lams
     tensors = []
     for s in range(S):
-        X = cp_tensor([truth[n][s] for n in range(3)], None if lams is None else lams[s])
+        X = cp_tensor([truth[n][s] for n in range(N)], None if lams is None else lams[s])
         if noise == "salt_pepper":
             X = salt_pepper(rng, X / np.max(X), snr_db)
         else:
@@ -166,7 +172,7 @@ def uniform_init(dims, R, L, seed):
     rng = rng_for(seed)
     S = len(dims)
     U = []
-    for n in range(3):
+    for n in range(len(dims[0])):
         sizes = [d[n] for d in dims]
         if len(set(sizes)) == 1:
             U.append(_shared_columns(rng, S, sizes[0], R, L[n], _uniform))
