@@ -349,7 +349,7 @@ class CoupledCP:
 
     def set_state(self, U, lam, U_prev=None, lam_prev=None, Ld_prev=None, Lu_prev=None, LC_prev=None, t=1.0, k=0):
         """U, U_prev: [n][s] arrays; Lu_prev [s][n] (or [n][s] transposed by caller); None entries mean 'none'."""
-        flat = lambda UU: [_stride_r(UU[n][s], self.R) for s in range(self.S) for n in range(N)]  # noqa: E731
+        flat = lambda UU: [_stride_r(UU[n][s], self.R) for s in range(self.S) for n in range(self.N)]  # noqa: E731
         kU, pU = _dbl_ptr_array(flat(U))
         kL, pL = _dbl_ptr_array([_stride_r(x, self.R) for x in lam])
         kUp = pUp = kLp = pLp = None
