@@ -225,6 +225,38 @@ def pass_roofline(dims, R, avg1, avg2, tensor_bytes=4):
             "pass2": {"bytes": b2, "avg_us": avg2 * 1e6, "gbs": b2 / avg2 / 1e9, "frac": b2 / avg2 / 1e9 / HBM_PEAK_GBS}}
 
 
+NWAY_WORKLOAD = "n4_fp32_10x32x4_r20"
+
+
+def nway_leg(steps: int):
+    """The N-way model at N = 4 (10 blocks of 32^4, R = 20, FP32): iterations/s
+    of the dense sweep (two dimension-tree passes per sweep) and the fit."""
+    import torch
+
+    import synth
+    from paper_2302_05119_amd import CoupledCP
+
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS[NWAY_WORKLOAD]
+    P = synth.make_workload(NWAY_WORKLOAD)
+    U0, lam0 = synth.workload_init(NWAY_WORKLOAD, P)
+    tens = [torch.from_numpy(X).to(dev) for X in P.tensors]
+    m = CoupledCP(tens, w["R"], w["L"], compute="f32", init_U=U0, init_lambda=lam0)
+    m.set_option("graph_sweeps", 8)
+    m.step(8, sync=False)
+    k0 = m.stats()["k"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(steps, sync=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = m.stats()
+    acc = st["k"] - k0
+    return {"workload": NWAY_WORKLOAD, "order": 4, "iter_per_s": acc / (t1 - t0),
+            "sweep_us": (t1 - t0) / max(acc, 1) * 1e6, "tensor_bytes": sum(4 * X.size for X in P.tensors),
+            "fit": st["fit"], "global_fit": m.global_fit(), "iterations": st["k"], "restarts": st["restarts"]}
+
+
 def workload_leg(name: str, steps: int):
     """A second workload shape of the paper (face-image-shaped with per-block
     ranks, or ERP-shaped fully coupled), FP32: iterations/s and the fit."""
@@ -454,6 +486,7 @@ def main():
         out["batched_c4"] = batched_leg(args.forms_steps)
         out["face"] = workload_leg("face_31x32x32x64_r22to26", args.forms_steps)
         out["erp"] = workload_leg("erp_42x9x71x60_r36_full", args.forms_steps)
+        out["nway_n4"] = nway_leg(args.forms_steps)
     if args.sweeps:
         out["sweep_snr"] = sweep_leg("snr")
         out["sweep_size"] = sweep_leg("size")

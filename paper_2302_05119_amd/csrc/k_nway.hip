@@ -152,24 +152,21 @@ __global__ __launch_bounds__(256) void k_nw_pass(const Geo* __restrict__ g, Stat
         }
 }
 
-// K_n of every block from the partials of its half (FP64 sums: the parts in
-// part order inside each term, the terms in index order), rounded once into
-// the plain K buffer.  Thread per (i, r); grid y = block.
+// K_n of every block from the partials of its half, one workgroup per (i, block):
+// thread (j, r) takes the terms q = j, j + J, ... of column r (J = 256 / Rq
+// stripes; each term sums the parts in part order and multiplies by the other
+// factors of the half), then thread r adds the J stripe sums in stripe order;
+// FP64 throughout, rounded once into the plain K buffer.
 template <typename T>
 __global__ __launch_bounds__(256) void k_nw_contract(const Geo* __restrict__ g, StateP<T> st, int n, int lo_slot,
                                                      int check_stop) {
     if (check_stop && st.ctrl->stop) return;
-    apply_rot(st);
-    const int s = blockIdx.y, N = g->N, h = g->nh, Rq = g->Rq, R = g->R;
+    const int s = blockIdx.y, i = blockIdx.x;
     const int In = g->I[s][n];
-    const long long e = blockIdx.x * 256LL + threadIdx.x;
-    if (e >= (long long)In * Rq) return;
-    const int i = (int)(e / Rq), r = (int)(e % Rq);
-    T* Kout = st.K3 + g->koff[s];
-    if (r >= R) {
-        Kout[e] = (T)0;
-        return;
-    }
+    if (i >= In) return;   // uniform over the workgroup
+    apply_rot(st);
+    const int N = g->N, h = g->nh, Rq = g->Rq, R = g->R, tid = threadIdx.x;
+    const int J = 256 / Rq, r = tid % Rq, j = tid / Rq;
     const int half = n >= h;
     const int m0 = half ? h : 0, m1 = half ? N : h;
     const long long O = half ? g->nwB[s] : g->nwA[s];
@@ -178,30 +175,40 @@ __global__ __launch_bounds__(256) void k_nw_contract(const Geo* __restrict__ g, 
     const T* Ulo = pick3(st.U, lo_slot);
     const T* Uhi = st.U[1];
     const long long cnt = O / In, pst = O * Rq;
+    __shared__ double red[256];
     double acc = 0.0;
-    for (long long q = 0; q < cnt; ++q) {
-        // q runs over the half's other modes (row-major); mode n is pinned to i
-        long long x = q, o = 0, mult = 1;
-        double w = 1.0;
-        for (int m = m1 - 1; m >= m0; --m) {
-            const int Im = g->I[s][m];
-            long long im;
-            if (m == n) {
-                im = i;
-            } else {
-                im = x % Im;
-                x /= Im;
-                w *= (double)(m < n ? Ulo : Uhi)[g->uoff[m][s] + im * Rq + r];
+    if (j < J && r < R) {
+        for (long long q = j; q < cnt; q += J) {
+            // q runs over the half's other modes (row-major); mode n is pinned to i
+            long long x = q, o = 0, mult = 1;
+            double w = 1.0;
+            for (int m = m1 - 1; m >= m0; --m) {
+                const int Im = g->I[s][m];
+                long long im;
+                if (m == n) {
+                    im = i;
+                } else {
+                    im = x % Im;
+                    x /= Im;
+                    w *= (double)(m < n ? Ulo : Uhi)[g->uoff[m][s] + im * Rq + r];
+                }
+                o += im * mult;
+                mult *= Im;
             }
-            o += im * mult;
-            mult *= Im;
+            const T* pp = part + o * Rq;
+            double tv = 0.0;
+#pragma unroll 4
+            for (int p = 0; p < np; ++p) tv += (double)pp[p * pst];
+            acc = fma(tv, w, acc);
         }
-        const T* pp = part + o * Rq;
-        double tv = 0.0;
-        for (int p = 0; p < np; ++p) tv += (double)pp[p * pst];
-        acc = fma(tv, w, acc);
     }
-    Kout[e] = (T)acc;
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < Rq) {
+        double sum = 0.0;
+        for (int jj = 0; jj < J; ++jj) sum += red[jj * Rq + tid];
+        st.K3[g->koff[s] + (long long)i * Rq + tid] = (T)(tid < R ? sum : 0.0);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -244,8 +251,8 @@ void launch_nw_pass(const Geo* g, const StateP<T>& st, const ItemNW* items, int 
 template <typename T>
 void launch_nw_contract(const Geo* g, const StateP<T>& st, int S, int n, int lo_slot, int maxI, int Rq, int check_stop,
                         hipStream_t q) {
-    const unsigned gx = (unsigned)(((long long)maxI * Rq + 255) / 256);
-    hipLaunchKernelGGL(k_nw_contract<T>, dim3(gx, S), dim3(256), 0, q, g, st, n, lo_slot, check_stop);
+    (void)Rq;
+    hipLaunchKernelGGL(k_nw_contract<T>, dim3(maxI, S), dim3(256), 0, q, g, st, n, lo_slot, check_stop);
 }
 
 #define CPD_INST_NW(T)                                                                                                    \

@@ -216,6 +216,10 @@ WORKLOADS = {
     # differ only through their core weights (drawn U[0.5, 1.5] per component)
     "erp_42x9x71x60_r36_full": dict(dims=[(9, 71, 60)] * 42, R=36, L=(36, 36, 36), snr=10.0,
                                     block_lam=(0.5, 1.5), iters=200, dtype="f32", seed=1007),
+    # the N-way model (Section II-C) at N = 4 with the byte count of the
+    # 10 x 100^3 case: 10 blocks of 32^4, R = 20, five shared mode-1 columns
+    "n4_fp32_10x32x4_r20": dict(dims=[(32, 32, 32, 32)] * 10, R=20, L=(5, 0, 0, 0), snr=10.0,
+                                iters=200, dtype="f32", seed=1008),
 }
 
 
