@@ -476,10 +476,12 @@ def main():
                 "iterations": st["k"], "sweeps_timed": args.steps, "iterations_timed": accepted},
     }
     out["tuning"] = tuning
-    # the sweep's launch-latency floor: a graph of as many empty kernels
+    # the sweep's launch-latency floor: a graph of as many empty kernels (7 with
+    # the R x R work fused into the pass launches, else 10)
     from paper_2302_05119_amd import launch_floor
-    fl = launch_floor(10)
-    out["launch_floor"] = {"kernels_per_sweep": 10, "graph_us": fl["graph_us"], "direct_us": fl["direct_us"],
+    nk = 7 if m.get_option("fuse") else 10
+    fl = launch_floor(nk)
+    out["launch_floor"] = {"kernels_per_sweep": nk, "graph_us": fl["graph_us"], "direct_us": fl["direct_us"],
                            "sweep_us": elapsed / max(accepted, 1) * 1e6}
     if args.forms_steps > 0:
         out["bf16_c2"] = precision_leg(P, U0, lam0, w, args.forms_steps)
@@ -496,6 +498,15 @@ def main():
         out["lra_cp_als"] = lra_leg(args.lra_steps, max(1, args.warmup // 2), compress="cp_als")
         out["lra_c5_cp_als"] = lra_leg(args.lra_steps, max(1, args.warmup // 2), name=LRA_WORKLOAD_C5,
                                        compress="cp_als")
+        # the dense passes on tensors that do not fit the 256 MB Infinity Cache
+        # (10 x 256^3 FP32, 671 MB): the same roofline object for their
+        # dominant pass
+        dp = out["lra"]["dense_passes_same_blocks"]
+        k = "pass2" if dp["pass2"]["avg_us"] >= dp["pass1"]["avg_us"] else "pass1"
+        out["roofline_10x256cube_dense"] = {
+            "bound": "hbm", "kernel": {"pass1": "pass1_ttm_mode3", "pass2": "pass2_mode3_mttkrp"}[k],
+            "achieved": dp[k]["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dp[k]["frac"], "traffic": None,
+            "avg_launch_us": dp[k]["avg_us"], "algorithmic_bytes_per_launch": dp[k]["bytes"]}
     n_gate, fit_or = 25, None
     if not args.no_cpu_baseline:
         U0r = [[m_u.astype(np.float32).astype(np.float64) for m_u in per] for per in U0]

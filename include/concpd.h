@@ -33,11 +33,12 @@
  *  - Every call returns a concpd_status; no C++ exception crosses the ABI.
  *    On error the context is unchanged and concpd_last_error() returns a
  *    thread-local message describing the first error.
- *  - The library never allocates device memory: the caller passes one
+ *  - A context never allocates device memory: the caller passes one
  *    workspace buffer of at least concpd_query_workspace() bytes and keeps it
  *    (and the tensors) alive until concpd_destroy(), or, with
  *    concpd_init_static, the context uses a fixed-size device array that the
- *    library holds on every device it runs on.
+ *    library holds on every device it runs on.  (The context-free test hook
+ *    concpd_debug_spectral_norm allocates and frees its own device buffers.)
  */
 #ifndef CONCPD_H
 #define CONCPD_H
@@ -323,13 +324,6 @@ concpd_status concpd_loss_grad(concpd_ctx ctx, const void* const* U_dev, const v
  * contraction, every factor from x_{k-1}).  Synchronises. */
 concpd_status concpd_debug_mttkrp(concpd_ctx ctx, int32_t n, int32_t s, void* dev_out);
 
-/* Test hook: the largest eigenvalue of each of `count` symmetric n x n FP64
- * matrices (host, row-major, packed one after another), computed on the
- * device by the same code that gives the spectral norms of eq. eqLipsLd /
- * eqLipsLu in a sweep: repeated squaring with Collatz-Wielandt bounds for
- * nonnegative matrices, Lanczos with Sturm multisection otherwise.  Results
- * to host_out [count].  1 <= n <= 64, 1 <= count <= 65535.  Needs no context;
- * allocates and synchronises.  Errors: EINVAL, EHIP. */
 /* Measurement hook: the launch-latency floor of a sweep of `kernels` kernels,
  * timed with HIP events on a private stream: *us_graph per replay of a
  * captured graph of that many empty one-wavefront kernels, *us_direct per
@@ -337,6 +331,13 @@ concpd_status concpd_debug_mttkrp(concpd_ctx ctx, int32_t n, int32_t s, void* de
  * latency-bound sweep against it.  Synchronises.  Errors: EINVAL, EHIP. */
 concpd_status concpd_launch_floor(int32_t kernels, int32_t reps, double* us_graph, double* us_direct);
 
+/* Test hook: the largest eigenvalue of each of `count` symmetric n x n FP64
+ * matrices (host, row-major, packed one after another), computed on the
+ * device by the same code that gives the spectral norms of eq. eqLipsLd /
+ * eqLipsLu in a sweep: repeated squaring with Collatz-Wielandt bounds for
+ * nonnegative matrices, Lanczos with Sturm multisection otherwise.  Results
+ * to host_out [count].  1 <= n <= 64, 1 <= count <= 65535.  Needs no context;
+ * allocates and synchronises.  Errors: EINVAL, EHIP. */
 concpd_status concpd_debug_spectral_norm(const double* host_A, int32_t n, int32_t count, double* host_out);
 
 /* Per-kernel timing of the dense MTTKRP passes (pass 1: M x_3 U^(3); pass 2:

@@ -141,7 +141,7 @@ template <typename T> void launch_resid(const Geo* g, const StateP<T>& st, const
 void launch_sqnorm(const void* src, int dtype, long long n, double* out, double* part, int npart, hipStream_t q);
 void launch_mode_gram(const float* X, int mode, int I1, int I2, int I3, double* part, int nsplit, hipStream_t q);
 void launch_sum_split(const double* part, int nsplit, long long n, double* out, hipStream_t q);
-void launch_eig_top(const Geo* g, double* lra, double* sig, long long sig_stride, double* work, long long work_stride, int nmat, hipStream_t q);
+void launch_eig_top(const Geo* g, double* lra, double* sig, long long sig_stride, double* work, long long work_stride, int nmat, int nmax, hipStream_t q);
 void launch_ttm_chain(const float* M, int I1, int I2, int I3, const double* A1, const double* A2, const double* A3, int J1, int J2, int J3, double* T1, double* T2, double* G, hipStream_t q);
 template <typename T> void launch_lra_w(const Geo* g, const StateP<T>& st, int S, int Jmax, int n, int uslot, int wslot, hipStream_t q);
 template <typename T>

@@ -77,8 +77,22 @@ __device__ __forceinline__ void store_agent(double* p, double v) {
 __device__ __forceinline__ double load_agent(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// s_waitcnt vmcnt(0): every global load and store of the wavefront has completed.
-__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// s_waitcnt vmcnt(0): every global load and store of the wavefront has
+// completed.  The compiler fences on both sides keep the compiler from moving
+// a memory access across the wait; the wait itself orders the hardware: an
+// agent-scope store has reached the coherence point shared by all XCDs when
+// its completion is counted.
+__device__ __forceinline__ void wait_stores() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// Arrival count of a last-workgroup reduction, at agent scope (the counter
+// lives at the coherence point; the value returned orders nothing by itself:
+// the handed-over data travels by store_agent / wait_stores / load_agent).
+__device__ __forceinline__ unsigned arrive_agent(unsigned* counter) {
+    return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // An accepted sweep rotates the slots instead of copying them: logical slot l
 // of the factors and lambda (0: x_k being built, 1: x_{k-1}, 2: x_{k-2}) is

@@ -20,79 +20,101 @@ namespace cpd {
 
 // ---------------------------------------------------------------------------
 // Mode Gram Sigma_n[a][b] = sum_t X_n(a, t) X_n(b, t) of one block, as a tiled
-// SYRK: a 64 x 64 output tile per workgroup (upper triangle of tiles only),
-// 4 x 4 outputs per thread, the contraction index t staged through LDS in
-// chunks of 32.  Products and sums are FP64 (the FP32 inputs convert exactly),
+// SYRK on the FP64 matrix cores: a 64 x 64 output tile per workgroup (upper
+// triangle of tiles only), a 32 x 32 quarter per wavefront (2 x 2 tiles of
+// v_mfma_f64_16x16x4f64), the contraction index t staged through LDS in
+// chunks of 32 (the next chunk's loads in flight while the current one is
+// consumed).  Products and sums are FP64 (the FP32 inputs convert exactly),
 // so the Gram carries no rounding beyond FP64 summation.
 // Element (a, t) of the unfolding sits at
 //   mode 0: a*I2*I3 + t                        (t = i2*I3 + i3)
 //   mode 1: (t / I3)*I2*I3 + a*I3 + t % I3     (t = i1*I3 + i3)
 //   mode 2: t*I3 + a                           (t = i1*I2 + i2)
-// A split-K grid dimension (blockIdx.y) writes partial tiles, summed later.
+// (every index fits 32 bits: I_n <= 512).  A split-K grid dimension
+// (blockIdx.y) writes partial tiles, summed later.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ long long unfold_addr(int mode, int a, long long t, int I2, int I3) {
+__device__ __forceinline__ long long unfold_addr(int mode, int a, unsigned t, int I2, int I3) {
     if (mode == 0) return (long long)a * I2 * I3 + t;
-    if (mode == 1) return (t / I3) * (long long)I2 * I3 + (long long)a * I3 + (t % I3);
-    return t * I3 + a;
+    if (mode == 1) return (long long)(t / (unsigned)I3) * I2 * I3 + (long long)a * I3 + (t % (unsigned)I3);
+    return (long long)t * I3 + a;
 }
 
 __global__ __launch_bounds__(256) void k_mode_gram(const float* __restrict__ X, int mode, int I1, int I2, int I3,
                                                    int ntile, double* __restrict__ part) {
     const int In = mode == 0 ? I1 : (mode == 1 ? I2 : I3);
-    const long long T = (long long)I1 * I2 * I3 / In;
+    const unsigned T = (unsigned)((long long)I1 * I2 * I3 / In);
     // tile pair (ta <= tb) from blockIdx.x
     int ta = 0, rem = blockIdx.x;
     while (rem >= ntile - ta) { rem -= ntile - ta; ++ta; }
     const int tb = ta + rem;
     const int nsplit = gridDim.y, sp = blockIdx.y;
-    const long long tb0 = T * sp / nsplit, tb1 = T * (sp + 1) / nsplit;
-    __shared__ double sa[32][65];
-    __shared__ double sb[32][65];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    double acc[4][4];
+    const unsigned tb0 = (unsigned)((long long)T * sp / nsplit), tb1 = (unsigned)((long long)T * (sp + 1) / nsplit);
+    __shared__ double sa[32][66];
+    __shared__ double sb[32][66];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;   // the wavefront's quarter of the tile
+    const int li = lane & 15, lk = lane >> 4;
+    v4d acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (long long t0 = tb0; t0 < tb1; t0 += 32) {
-        // stage X_n(ta*64 + r, t0 + k) and X_n(tb*64 + r, t0 + k), r < 64, k < 32;
-        // the fastest-varying thread index follows the contiguous direction
-        for (int e = tid; e < 64 * 32; e += 256) {
+        for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+    // staging: 8 elements of each operand per thread; the fastest-varying
+    // thread index follows the contiguous direction
+    float na[8], nb[8];
+    auto load = [&](unsigned t0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;
             const int r = mode == 2 ? (e & 63) : (e >> 5);
             const int k = mode == 2 ? (e >> 6) : (e & 31);
-            const long long t = t0 + k;
+            const unsigned t = t0 + k;
             const int ra = ta * 64 + r, rb = tb * 64 + r;
-            sa[k][r] = (ra < In && t < tb1) ? (double)X[unfold_addr(mode, ra, t, I2, I3)] : 0.0;
-            sb[k][r] = (rb < In && t < tb1) ? (double)X[unfold_addr(mode, rb, t, I2, I3)] : 0.0;
+            const bool tin = t < tb1;
+            na[q] = (ra < In && tin) ? X[unfold_addr(mode, ra, t, I2, I3)] : 0.0f;
+            nb[q] = (rb < In && tin) ? X[unfold_addr(mode, rb, t, I2, I3)] : 0.0f;
+        }
+    };
+    if (tb0 < tb1) load(tb0);
+    for (unsigned t0 = tb0; t0 < tb1; t0 += 32) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;
+            const int r = mode == 2 ? (e & 63) : (e >> 5);
+            const int k = mode == 2 ? (e >> 6) : (e & 31);
+            sa[k][r] = (double)na[q];
+            sb[k][r] = (double)nb[q];
         }
         __syncthreads();
-#pragma unroll 4
-        for (int k = 0; k < 32; ++k) {
-            double av[4], bv[4];
+        if (t0 + 32 < tb1) load(t0 + 32);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = sa[k][ty * 4 + i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = sb[k][tx * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        for (int k0 = 0; k0 < 32; k0 += 4) {
+            // lane l: A[l % 16][l / 16] = X_a(row, k0 + l / 16), B likewise
+            const double a0 = sa[k0 + lk][wr + li], a1 = sa[k0 + lk][wr + 16 + li];
+            const double b0 = sb[k0 + lk][wc + li], b1 = sb[k0 + lk][wc + 16 + li];
+            acc[0][0] = mfma64(a0, b0, acc[0][0]);
+            acc[0][1] = mfma64(a0, b1, acc[0][1]);
+            acc[1][0] = mfma64(a1, b0, acc[1][0]);
+            acc[1][1] = mfma64(a1, b1, acc[1][1]);
         }
         __syncthreads();
     }
     // partial tile sp of Sigma (full In x In storage, both triangles; on a
-    // diagonal tile the mirrored writes carry identical values)
+    // diagonal tile the mirrored writes carry identical values).  Register v of
+    // lane l holds D[4v + l / 16][l % 16].
     double* out = part + (long long)sp * In * In;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int a = ta * 64 + ty * 4 + i, b = tb * 64 + tx * 4 + j;
-            if (a < In && b < In) {
-                out[(long long)a * In + b] = acc[i][j];
-                out[(long long)b * In + a] = acc[i][j];
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = ta * 64 + wr + 16 * i + 4 * v + lk, b = tb * 64 + wc + 16 * j + li;
+                if (a < In && b < In) {
+                    out[(long long)a * In + b] = acc[i][j][v];
+                    out[(long long)b * In + a] = acc[i][j][v];
+                }
             }
-        }
 }
 
 __global__ __launch_bounds__(256) void k_sum_split(const double* __restrict__ part, int nsplit, long long n,
@@ -149,9 +171,155 @@ __device__ __forceinline__ int sturm_count(const double* d, const double* e2, in
     return cnt;
 }
 
+// Householder reflector of step k from row k of A (= column k): v (v_0 = 1)
+// into sv, beta, mu = ||x||, alpha = x_0; false when the row below the
+// diagonal is already zero (no reflection).  Every workgroup that calls it on
+// the same row gets the same bits (same loads, same summation order).
+__device__ bool tri_reflector(const double* __restrict__ A, int n, int k, double* sv, double* red, double& beta,
+                              double& mu, double& alpha) {
+    const int tid = threadIdx.x, m = n - k - 1;
+    const double* xrow = A + (long long)k * n + k + 1;
+    double ss = 0.0;
+    for (int i = tid; i < m; i += 256) {
+        const double x = xrow[i];
+        sv[i] = x;
+        if (i > 0) ss = fma(x, x, ss);
+    }
+    const double sigma = block_sum256(ss, red);
+    alpha = sv[0];
+    if (!(sigma > 0.0)) {
+        __syncthreads();
+        return false;
+    }
+    mu = sqrt(fma(alpha, alpha, sigma));
+    const double v1 = alpha <= 0.0 ? alpha - mu : -sigma / (alpha + mu);
+    beta = 2.0 * v1 * v1 / (sigma + v1 * v1);
+    __syncthreads();
+    for (int i = tid; i < m; i += 256) sv[i] = i == 0 ? 1.0 : sv[i] / v1;
+    __syncthreads();
+    return true;
+}
+
+// p[r] = beta (B v)[r] for rows r0 <= r < r1 of the trailing block B of step
+// k: four rows per wavefront at a time, the lanes along the rows (coalesced;
+// m <= 511, so the eight 64-column pieces of all four rows, 32 loads a lane,
+// are in flight together), then wavefront sums in fixed butterfly order.
+__device__ void tri_matvec(const double* __restrict__ A, int n, int k, int r0, int r1, double beta, const double* sv,
+                           double* p) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, m = n - k - 1;
+    const double* B = A + (long long)(k + 1) * n + k + 1;
+    for (int rb = r0 + 4 * wv; rb < r1; rb += 16) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const int c = lane + 64 * cc;
+            if (64 * cc < m) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = min(rb + j, r1 - 1);
+                    const double x = B[(long long)r * n + min(c, m - 1)];
+                    if (c < m) a[j] = fma(x, sv[c], a[j]);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double t = wave_sum(a[j]);
+            if (lane == 0 && rb + j < r1) p[rb + j] = beta * t;
+        }
+    }
+}
+
+// B -= v w^T + w v^T for rows r0 <= r < r1, evaluated in a symmetric order so
+// B stays exactly symmetric (four rows per wavefront, loads first).
+__device__ void tri_update(double* __restrict__ A, int n, int k, int r0, int r1, const double* sv, const double* sw) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, m = n - k - 1;
+    double* Bw = A + (long long)(k + 1) * n + k + 1;
+    for (int rb = r0 + 4 * wv; rb < r1; rb += 16) {
+        double x[4][8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc) {
+                const int r = min(rb + j, r1 - 1), c = min(lane + 64 * cc, m - 1);
+                x[j][cc] = (64 * cc < m) ? Bw[(long long)r * n + c] : 0.0;
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = rb + j;
+            if (r >= r1) continue;
+            const double vr = sv[r], wr = sw[r];
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc) {
+                const int c = lane + 64 * cc;
+                if (c < m) {
+                    const double f = c < r ? fma(sv[c], wr, sw[c] * vr) : fma(vr, sw[c], wr * sv[c]);
+                    Bw[(long long)r * n + c] = x[j][cc] - f;
+                }
+            }
+        }
+    }
+}
+
+// Step k of the tridiagonalisation of every matrix, spread over workgroups of
+// TRI_ROWS trailing rows each (grid: row slices x matrices).  k_tri_p writes
+// d, e, tau of step k and p = beta B v; k_tri_update forms w = p - K v with
+// K = beta p.v / 2 (every workgroup from the whole of p, in the same order),
+// updates its rows and stores its part of the reflector below the diagonal.
+#define TRI_ROWS 32
+__global__ __launch_bounds__(256) void k_tri_p(const Geo* __restrict__ g, double* __restrict__ sig, long long sig_stride,
+                                               double* __restrict__ work, long long work_stride, int k) {
+    const int mat = blockIdx.y, s = mat / 3, mode = mat % 3;
+    const int n = g->I[s][mode];
+    if (k + 2 >= n) return;
+    const int m = n - k - 1, r0 = blockIdx.x * TRI_ROWS;
+    if (r0 >= m) return;
+    double* A = sig + (long long)mat * sig_stride;
+    double* W = work + (long long)mat * work_stride;
+    double* pbuf = W + 4 * n + 64;   // the inverse-iteration factors' space, free until then
+    __shared__ double sv[512], red[4];
+    double beta, mu, alpha;
+    const bool refl = tri_reflector(A, n, k, sv, red, beta, mu, alpha);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        W[k] = A[(long long)k * n + k];         // d
+        W[n + k] = refl ? mu : alpha;           // e
+        W[3 * n + k] = refl ? beta : 0.0;       // tau
+    }
+    if (refl) tri_matvec(A, n, k, r0, min(r0 + TRI_ROWS, m), beta, sv, pbuf);
+}
+
+__global__ __launch_bounds__(256) void k_tri_update(const Geo* __restrict__ g, double* __restrict__ sig, long long sig_stride,
+                                                    double* __restrict__ work, long long work_stride, int k) {
+    const int mat = blockIdx.y, s = mat / 3, mode = mat % 3;
+    const int n = g->I[s][mode];
+    if (k + 2 >= n) return;
+    const int m = n - k - 1, r0 = blockIdx.x * TRI_ROWS, r1 = min(r0 + TRI_ROWS, m);
+    if (r0 >= m) return;
+    double* A = sig + (long long)mat * sig_stride;
+    const double* pbuf = work + (long long)mat * work_stride + 4 * n + 64;
+    __shared__ double sv[512], sw[512], red[4];
+    const int tid = threadIdx.x;
+    double beta, mu, alpha;
+    if (!tri_reflector(A, n, k, sv, red, beta, mu, alpha)) {
+        for (int i = r0 + tid; i < r1; i += 256) A[(long long)(k + 1 + i) * n + k] = 0.0;
+        return;
+    }
+    double pv = 0.0;
+    for (int r = tid; r < m; r += 256) {
+        const double p = pbuf[r];
+        sw[r] = p;
+        pv = fma(p, sv[r], pv);
+    }
+    const double K = 0.5 * beta * block_sum256(pv, red);
+    for (int r = tid; r < m; r += 256) sw[r] = fma(-K, sv[r], sw[r]);
+    __syncthreads();
+    tri_update(A, n, k, r0, r1, sv, sw);
+    for (int i = r0 + tid; i < r1; i += 256) A[(long long)(k + 1 + i) * n + k] = sv[i];
+}
+
 __global__ __launch_bounds__(256) void k_eig_top(const Geo* __restrict__ g, double* __restrict__ lra,
                                                  double* __restrict__ sig, long long sig_stride,
-                                                 double* __restrict__ work, long long work_stride) {
+                                                 double* __restrict__ work, long long work_stride, int tri_done) {
     const int mat = blockIdx.x, s = mat / 3, mode = mat % 3;
     const int n = g->I[s][mode], J = g->J[s][mode];
     double* A = sig + (long long)mat * sig_stride;
@@ -169,64 +337,30 @@ __global__ __launch_bounds__(256) void k_eig_top(const Geo* __restrict__ g, doub
     __shared__ double tinfo[3];
     const int tid = threadIdx.x;
 
-    // ---- 1. tridiagonalisation -------------------------------------------
-    for (int k = 0; k + 2 < n; ++k) {
+    // ---- 1. tridiagonalisation (done by k_tri_p / k_tri_update, one launch
+    // pair per step, when tri_done is set) ---------------------------------
+    for (int k = 0; k + 2 < n && !tri_done; ++k) {
         const int m = n - k - 1;
-        const double* xrow = A + (long long)k * n + k + 1;   // row k == column k
-        double ss = 0.0;
-        for (int i = tid; i < m; i += 256) {
-            const double x = xrow[i];
-            sv[i] = x;
-            if (i > 0) ss = fma(x, x, ss);
+        double beta, mu, alpha;
+        const bool refl = tri_reflector(A, n, k, sv, red, beta, mu, alpha);
+        if (tid == 0) {
+            d[k] = A[(long long)k * n + k];
+            e[k] = refl ? mu : alpha;
+            tau[k] = refl ? beta : 0.0;
         }
-        const double sigma = block_sum256(ss, red);
-        const double alpha = sv[0];
-        if (tid == 0) d[k] = A[(long long)k * n + k];
-        if (!(sigma > 0.0)) {
-            if (tid == 0) {
-                e[k] = alpha;
-                tau[k] = 0.0;
-            }
+        if (!refl) {
             for (int i = tid; i < m; i += 256) A[(long long)(k + 1 + i) * n + k] = 0.0;
             __syncthreads();
             continue;
         }
-        const double mu = sqrt(fma(alpha, alpha, sigma));
-        const double v1 = alpha <= 0.0 ? alpha - mu : -sigma / (alpha + mu);
-        const double beta = 2.0 * v1 * v1 / (sigma + v1 * v1);
+        tri_matvec(A, n, k, 0, m, beta, sv, sw);
         __syncthreads();
-        for (int i = tid; i < m; i += 256) sv[i] = i == 0 ? 1.0 : sv[i] / v1;
-        if (tid == 0) {
-            e[k] = mu;
-            tau[k] = beta;
-        }
-        __syncthreads();
-        // p = beta B v (B = trailing block, read by columns for coalescing)
-        const double* B = A + (long long)(k + 1) * n + k + 1;
         double pv = 0.0;
-        for (int r = tid; r < m; r += 256) {
-            double a0 = 0.0, a1 = 0.0;
-            int c = 0;
-            for (; c + 1 < m; c += 2) {
-                a0 = fma(B[(long long)c * n + r], sv[c], a0);
-                a1 = fma(B[(long long)(c + 1) * n + r], sv[c + 1], a1);
-            }
-            if (c < m) a0 = fma(B[(long long)c * n + r], sv[c], a0);
-            const double p = beta * (a0 + a1);
-            sw[r] = p;
-            pv = fma(p, sv[r], pv);
-        }
+        for (int r = tid; r < m; r += 256) pv = fma(sw[r], sv[r], pv);
         const double K = 0.5 * beta * block_sum256(pv, red);
         for (int r = tid; r < m; r += 256) sw[r] = fma(-K, sv[r], sw[r]);
         __syncthreads();
-        // B -= v w^T + w v^T, evaluated in a symmetric order so B stays
-        // exactly symmetric
-        double* Bw = A + (long long)(k + 1) * n + k + 1;
-        for (long long q = tid; q < (long long)m * m; q += 256) {
-            const int r = (int)(q / m), c = (int)(q % m);
-            const int lo = min(r, c), hi = max(r, c);
-            Bw[(long long)r * n + c] -= fma(sv[lo], sw[hi], sw[lo] * sv[hi]);
-        }
+        tri_update(A, n, k, 0, m, sv, sw);
         // reflector vector below the subdiagonal of column k
         for (int i = tid; i < m; i += 256) A[(long long)(k + 1 + i) * n + k] = sv[i];
         __syncthreads();
@@ -319,28 +453,60 @@ __global__ __launch_bounds__(256) void k_eig_top(const Geo* __restrict__ g, doub
     for (int it = 0; it < 5; ++it) {
         if (tid < J) {
             const int j = tid;
-            // forward elimination of the right-hand side (in place)
+            // forward elimination of the right-hand side (in place); the
+            // loads of eight steps are issued before the recurrence runs
+            // through them (a step writes Z[i] and reads Z[i + 1], so every
+            // value read is the one the plain loop would read)
             double rw = Z[j];
-            for (int i = 0; i + 1 < n; ++i) {
-                const double l = F[(0LL * n + i) * J + j], y1 = Z[(long long)(i + 1) * J + j];
-                if (F[(4LL * n + i) * J + j] == 0.0) {
-                    Z[(long long)i * J + j] = rw;
-                    rw = y1 - l * rw;
-                } else {
-                    Z[(long long)i * J + j] = y1;
-                    rw = rw - l * y1;
+            for (int i0 = 0; i0 + 1 < n; i0 += 8) {
+                double lv[8], yv[8], sv8[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int i = min(i0 + q, n - 2);
+                    lv[q] = F[(0LL * n + i) * J + j];
+                    sv8[q] = F[(4LL * n + i) * J + j];
+                    yv[q] = Z[(long long)(i + 1) * J + j];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int i = i0 + q;
+                    if (i + 1 < n) {
+                        if (sv8[q] == 0.0) {
+                            Z[(long long)i * J + j] = rw;
+                            rw = yv[q] - lv[q] * rw;
+                        } else {
+                            Z[(long long)i * J + j] = yv[q];
+                            rw = rw - lv[q] * yv[q];
+                        }
+                    }
                 }
             }
             Z[(long long)(n - 1) * J + j] = rw;
-            // back substitution, tiny pivots replaced by +-eps ||T||
+            // back substitution, tiny pivots replaced by +-eps ||T|| (eight
+            // steps of loads ahead; a step reads and writes only its own Z[i])
             double x1 = 0.0, x2 = 0.0;
-            for (int i = n - 1; i >= 0; --i) {
-                double u0 = F[(1LL * n + i) * J + j];
-                if (fabs(u0) < pivtol) u0 = u0 < 0.0 ? -pivtol : pivtol;
-                const double x = (Z[(long long)i * J + j] - F[(2LL * n + i) * J + j] * x1 - F[(3LL * n + i) * J + j] * x2) / u0;
-                Z[(long long)i * J + j] = x;
-                x2 = x1;
-                x1 = x;
+            for (int i0 = n - 1; i0 >= 0; i0 -= 8) {
+                double u0v[8], u1v[8], u2v[8], zv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int i = max(i0 - q, 0);
+                    u0v[q] = F[(1LL * n + i) * J + j];
+                    u1v[q] = F[(2LL * n + i) * J + j];
+                    u2v[q] = F[(3LL * n + i) * J + j];
+                    zv[q] = Z[(long long)i * J + j];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int i = i0 - q;
+                    if (i >= 0) {
+                        double u0 = u0v[q];
+                        if (fabs(u0) < pivtol) u0 = u0 < 0.0 ? -pivtol : pivtol;
+                        const double x = (zv[q] - u1v[q] * x1 - u2v[q] * x2) / u0;
+                        Z[(long long)i * J + j] = x;
+                        x2 = x1;
+                        x1 = x;
+                    }
+                }
             }
         }
         __syncthreads();
@@ -349,6 +515,7 @@ __global__ __launch_bounds__(256) void k_eig_top(const Geo* __restrict__ g, doub
             const int j = tid & 63, grp = tid >> 6;
             double mx = 0.0;
             if (j < J)
+#pragma unroll 8
                 for (int i = grp; i < n; i += 4) mx = fmax(mx, fabs(Z[(long long)i * J + j]));
             part[grp][j] = mx;
             __syncthreads();
@@ -368,14 +535,24 @@ __global__ __launch_bounds__(256) void k_eig_top(const Geo* __restrict__ g, doub
                 const int jj = c0 + (tid & 63), grp = tid >> 6;
                 double dt = 0.0;
                 if (jj < j)
+#pragma unroll 8
                     for (int i = grp; i < n; i += 4) dt = fma(Z[(long long)i * J + jj], Z[(long long)i * J + j], dt);
                 part[grp][tid & 63] = dt;
                 __syncthreads();
                 if (tid < 64) sw[tid] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
                 __syncthreads();
                 for (int i = tid; i < n; i += 256) {
-                    double z = Z[(long long)i * J + j];
-                    for (int q = c0; q < j; ++q) z = fma(-sw[q - c0], Z[(long long)i * J + q], z);
+                    // the row's earlier columns, eight loads ahead
+                    const double* zr = Z + (long long)i * J;
+                    double z = zr[j];
+                    for (int q0 = c0; q0 < j; q0 += 8) {
+                        double zq[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) zq[q] = zr[min(q0 + q, j - 1)];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (q0 + q < j) z = fma(-sw[q0 + q - c0], zq[q], z);
+                    }
                     Z[(long long)i * J + j] = z;
                 }
                 __syncthreads();
@@ -395,17 +572,32 @@ __global__ __launch_bounds__(256) void k_eig_top(const Geo* __restrict__ g, doub
         if (tk == 0.0) continue;
         const int m = n - k - 1;
         const double* v = A + (long long)(k + 1) * n + k;   // v_i at row k+1+i, v_0 = 1
+        for (int i = tid; i < m; i += 256) sv[i] = i == 0 ? 1.0 : v[(long long)i * n];
+        __syncthreads();
         const int j = tid & 63, grp = tid >> 6;
+        double* Zk = Z + (long long)(k + 1) * J + j;
         double dt = 0.0;
         if (j < J)
-            for (int i = grp; i < m; i += 4)
-                dt = fma(i == 0 ? 1.0 : v[(long long)i * n], Z[(long long)(k + 1 + i) * J + j], dt);
+            for (int i0 = grp; i0 < m; i0 += 32) {
+                double zv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) zv[q] = Zk[(long long)min(i0 + 4 * q, m - 1) * J];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (i0 + 4 * q < m) dt = fma(sv[i0 + 4 * q], zv[q], dt);
+            }
         part[grp][j] = dt;
         __syncthreads();
         if (j < J) {
             const double f = tk * (part[0][j] + part[1][j] + part[2][j] + part[3][j]);
-            for (int i = grp; i < m; i += 4)
-                Z[(long long)(k + 1 + i) * J + j] = fma(-f, i == 0 ? 1.0 : v[(long long)i * n], Z[(long long)(k + 1 + i) * J + j]);
+            for (int i0 = grp; i0 < m; i0 += 32) {
+                double zv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) zv[q] = Zk[(long long)min(i0 + 4 * q, m - 1) * J];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (i0 + 4 * q < m) Zk[(long long)(i0 + 4 * q) * J] = fma(-f, sv[i0 + 4 * q], zv[q]);
+            }
         }
         __syncthreads();
     }
@@ -441,27 +633,68 @@ __global__ __launch_bounds__(256) void k_eig_top(const Geo* __restrict__ g, doub
 
 // ---------------------------------------------------------------------------
 // TTM chain for G = M x_1 A_1^T x_2 A_2^T x_3 A_3^T (FP64 accumulation)
-//   T1[i1][i2][j3] = sum_i3 M[i1][i2][i3] A3[i3][j3]          (one slab per workgroup)
+//   T1[i1][i2][j3] = sum_i3 M[i1][i2][i3] A3[i3][j3]          (matrix cores, 64 rows per workgroup)
 //   T2[i1][j2][j3] = sum_i2 A2[i2][j2] T1[i1][i2][j3]
 //   G [j1][j2][j3] = sum_i1 A1[i1][j1] T2[i1][j2][j3]
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ttm3(const float* __restrict__ M, int I2, int I3, const double* __restrict__ A3,
-                                              int J3, double* __restrict__ T1) {
-    const int i1 = blockIdx.x;
-    __shared__ float xs[4][512];
-    const int tid = threadIdx.x;
-    for (int i2b = 0; i2b < I2; i2b += 4) {
-        const int nr = min(4, I2 - i2b);
-        __syncthreads();
-        for (int e = tid; e < nr * I3; e += 256) xs[e / I3][e % I3] = M[((long long)i1 * I2 + i2b + e / I3) * I3 + e % I3];
-        __syncthreads();
-        for (int e = tid; e < nr * J3; e += 256) {
-            const int r = e / J3, j = e % J3;
-            double a = 0.0;
-            for (int k = 0; k < I3; ++k) a = fma((double)xs[r][k], A3[(long long)k * J3 + j], a);
-            T1[((long long)i1 * I2 + i2b + r) * J3 + j] = a;
+// T1 = M_(3) A3 as a GEMM over the rows (i1, i2) of the tensor on the FP64
+// matrix cores: a workgroup takes 64 rows, wavefront w rows 16w .. 16w + 15
+// and every 16-column tile of J3 (<= 64); the contraction over i3 is staged
+// through LDS in chunks of 32 (tensor rows converted to FP64, the matching
+// rows of A3), the next chunk's loads in flight while one is consumed.
+__global__ __launch_bounds__(256) void k_ttm3(const float* __restrict__ M, long long rows, int I3,
+                                              const double* __restrict__ A3, int J3, double* __restrict__ T1) {
+    __shared__ double xs[64][33];
+    __shared__ double as[32][66];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const long long row0 = (long long)blockIdx.x * 64;
+    const int nct = (J3 + 15) >> 4;
+    v4d acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = (v4d){0.0, 0.0, 0.0, 0.0};
+    float mx[8];
+    double ax[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;
+            const int r = e >> 5, kk = e & 31;                       // tensor: 64 rows x 32 values
+            const long long row = row0 + r;
+            const int k = k0 + kk;
+            mx[q] = (row < rows && k < I3) ? M[row * I3 + k] : 0.0f;
+            const int ka = e >> 6, j = e & 63;                       // A3: 32 rows x 64 columns
+            ax[q] = (k0 + ka < I3 && j < J3) ? A3[(long long)(k0 + ka) * J3 + j] : 0.0;
         }
+    };
+    load(0);
+    for (int k0 = 0; k0 < I3; k0 += 32) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;
+            xs[e >> 5][e & 31] = (double)mx[q];
+            as[e >> 6][e & 63] = ax[q];
+        }
+        __syncthreads();
+        if (k0 + 32 < I3) load(k0 + 32);
+#pragma unroll
+        for (int kk = 0; kk < 32; kk += 4) {
+            const double a = xs[16 * wv + li][kk + lk];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (t < nct) acc[t] = mfma64(a, as[kk + lk][16 * t + li], acc[t]);
+        }
+        __syncthreads();
     }
+    // register v of lane l holds D[4v + l / 16][l % 16]
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const long long row = row0 + 16 * wv + 4 * v + lk;
+            const int col = 16 * t + li;
+            if (t < nct && row < rows && col < J3) T1[row * J3 + col] = acc[t][v];
+        }
 }
 
 __global__ __launch_bounds__(256) void k_ttm2(const double* __restrict__ T1, int I2, int J3, const double* __restrict__ A2,
@@ -603,12 +836,22 @@ void launch_sum_split(const double* part, int nsplit, long long n, double* out, 
     hipLaunchKernelGGL(k_sum_split, dim3((unsigned)nb), dim3(256), 0, q, part, nsplit, n, out);
 }
 void launch_eig_top(const Geo* g, double* lra, double* sig, long long sig_stride, double* work, long long work_stride,
-                    int nmat, hipStream_t q) {
-    hipLaunchKernelGGL(k_eig_top, dim3(nmat), dim3(256), 0, q, g, lra, sig, sig_stride, work, work_stride);
+                    int nmat, int nmax, hipStream_t q) {
+    // the tridiagonalisation step by step over row slices of every matrix
+    // (each step is a pass over an n x n matrix: spread over workgroups, the
+    // steps run at the memory system's rate instead of one CU's latency),
+    // then the rest of the solver with one workgroup per matrix
+    const dim3 grid((unsigned)((nmax + TRI_ROWS - 1) / TRI_ROWS), (unsigned)nmat);
+    for (int k = 0; k + 2 < nmax; ++k) {
+        hipLaunchKernelGGL(k_tri_p, grid, dim3(256), 0, q, g, sig, sig_stride, work, work_stride, k);
+        hipLaunchKernelGGL(k_tri_update, grid, dim3(256), 0, q, g, sig, sig_stride, work, work_stride, k);
+    }
+    hipLaunchKernelGGL(k_eig_top, dim3(nmat), dim3(256), 0, q, g, lra, sig, sig_stride, work, work_stride, 1);
 }
 void launch_ttm_chain(const float* M, int I1, int I2, int I3, const double* A1, const double* A2, const double* A3, int J1,
                       int J2, int J3, double* T1, double* T2, double* G, hipStream_t q) {
-    hipLaunchKernelGGL(k_ttm3, dim3(I1), dim3(256), 0, q, M, I2, I3, A3, J3, T1);
+    const long long rows = (long long)I1 * I2;
+    hipLaunchKernelGGL(k_ttm3, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, q, M, rows, I3, A3, J3, T1);
     hipLaunchKernelGGL(k_ttm2, dim3(I1), dim3(256), 0, q, T1, I2, J3, A2, J2, T2);
     long long nb = ((long long)J1 * J2 * J3 + 255) / 256;
     if (nb > 1024) nb = 1024;

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     if (tid == 0) {
         store_agent(&st.Fblk[s], F);
         wait_stores();
-        last = (atomicAdd(&c->counter_finish, 1u) == (unsigned)(gridDim.x - 1));
+        last = (arrive_agent(&c->counter_finish) == (unsigned)(gridDim.x - 1));
     }
     __syncthreads();
     if (!last) return;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_init_stats(const Geo* __restrict__ g, S
     if (tid == 0) {
         store_agent(&st.Fblk[s], F);
         wait_stores();
-        last = (atomicAdd(&c->counter_aux, 1u) == (unsigned)(gridDim.x - 1));
+        last = (arrive_agent(&c->counter_aux) == (unsigned)(gridDim.x - 1));
     }
     __syncthreads();
     if (!last) return;

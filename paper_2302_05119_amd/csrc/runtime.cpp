@@ -1496,7 +1496,7 @@ concpd_status lra_compress(concpd_ctx c, const int32_t* ranks, concpd_stats* out
                                   c->q);
         }
     }
-    cpd::launch_eig_top(c->dgeo, L, L + P.l_sig, P.sig_stride, L + P.l_work, P.work_stride, 3 * c->S, c->q);
+    cpd::launch_eig_top(c->dgeo, L, L + P.l_sig, P.sig_stride, L + P.l_work, P.work_stride, 3 * c->S, P.Imax, c->q);
     for (int s = 0; s < c->S; ++s) {
         const int I[3] = {(int)c->dims[3 * s], (int)c->dims[3 * s + 1], (int)c->dims[3 * s + 2]};
         const float* X = (const float*)c->tensors[s];
