@@ -12,7 +12,9 @@ normwise; RelErr is compared at 1e-6 absolute and the
 iteration counts exactly (the CPU model of FP32 factor rounding moves RelErr
 by < 1e-9 on these problems, far inside eps = 1e-4).  The lra iterations are
 compared teacher-forced (both sides from the same point, the oracle on its own
-compression) at 1e-4, a bound set by the two compressions' difference.
+compression) at 1e-4, a bound set by the two compressions' difference, and
+against the oracle run on the library's own exported compressed form at the
+FP32 bound of one step, 1e-5.
 """
 import sys
 
@@ -57,6 +59,25 @@ def als_inits(P, R, seed):
     # [n][s], rounded to FP32 (the device holds the factors in FP32)
     per = [[rng.random((d[n], R)).astype(np.float32).astype(np.float64) for n in range(3)] for d in P.dims]
     return [[per[s][n] for s in range(P.S)] for n in range(3)]
+
+
+def check_step_on_gpu_form(m, P, U32, lam0, L, s1, tol=1e-5):
+    """The teacher-forced lra step against the oracle run on the compressed
+    form the library exported (m.tucker): the two sides then share the data
+    term, so the FP32 bound of one step applies (eq. eqlrau / eqlrag)."""
+    cores, bases = [], []
+    for s in range(P.S):
+        A, G = m.tucker(s)
+        cores.append(G)
+        bases.append(list(A))
+    data = TuckerData(cores, bases)
+    st1 = apg.iterate(data, apg.initial_state(data, U32, lam0), Options(L=L))
+    say(f"   on the exported form: F1 gpu={s1['F']:.10e} oracle={st1.F:.10e}")
+    assert abs(s1["F"] - st1.F) / st1.F <= tol
+    for s in range(P.S):
+        assert rel(m.lam(s), st1.lam[s]) <= tol
+        for n in range(3):
+            assert rel(m.factor(n, s), st1.U[n][s]) <= tol, (n, s)
 
 
 @pytest.mark.parametrize("dims,R", [([(20, 24, 18), (16, 30, 22)], 5), ([(40, 36, 50)] * 2, 8), ([(21, 70, 100)], 20)])
@@ -133,6 +154,7 @@ def test_lra_iterations_on_cp_compression(dev):
         assert rel(m.lam(s), st1.lam[s]) <= 1e-4
         for n in range(3):
             assert rel(m.factor(n, s), st1.U[n][s]) <= 1e-4
+    check_step_on_gpu_form(m, P, U32, lam0, L, s1)
     ref = apg.run(data, None, None, Options(L=L), iters=59, state=st1)
     s60 = m.lra_step(59)
     gf = m.global_fit()
@@ -259,6 +281,7 @@ def test_cp_rank_below_r(dev):
         assert rel(m.lam(s), st1.lam[s]) <= 1e-4
         for n in range(3):
             assert rel(m.factor(n, s), st1.U[n][s]) <= 1e-4
+    check_step_on_gpu_form(m, P, U32, lam0, L, s1)
 
 
 def test_cp_compression_with_block_ranks(dev):
@@ -298,3 +321,4 @@ def test_cp_compression_with_block_ranks(dev):
         for n in range(3):
             assert rel(m.factor(n, s), st1.U[n][s]) <= 1e-4
             assert np.all(m.factor(n, s, padded=True)[:, ranks[s]:] == 0.0)
+    check_step_on_gpu_form(m, P, U32, lam0, L, s1)

@@ -136,6 +136,9 @@ def test_nway_one_iteration_teacher_forced(dev, compute, tol, k_before, order):
         for n in range(order):
             e = rel(m.factor(n, s), new.U[n][s])
             assert e <= tol, (n, s, e)
+            # elementwise, relative to the factor's largest entry
+            d = np.max(np.abs(m.factor(n, s) - new.U[n][s])) / np.max(np.abs(new.U[n][s]))
+            assert d <= 2 * tol, (n, s, d)
     # the shared columns stay identical across the blocks
     for n in range(order):
         if L[n]:
