@@ -383,6 +383,11 @@ concpd_status concpd_profile_read(concpd_ctx ctx, double* ms_pass1, double* ms_p
  *                            (and the register path of 16-bit storage) runs
  *                            unfused whatever the value; default 1 when pass 1
  *                            has at most two wavefronts per SIMD, else 0.
+ *   CONCPD_OPT_FUSE_LRA      1: the compressed sweep (Algorithm 2) runs the
+ *                            core update beside C_1 and the step matrix of
+ *                            mode n beside the W refresh of mode n - 1 (ten
+ *                            launches instead of thirteen); bit-identical to
+ *                            the unfused sweep; default 1.
  * Synchronises.  Errors: EINVAL (unknown option or value), EHIP. */
 typedef enum concpd_option {
     CONCPD_OPT_GRAPH_SWEEPS = 1,
@@ -390,7 +395,8 @@ typedef enum concpd_option {
     CONCPD_OPT_K2_ROWS = 3,
     CONCPD_OPT_P1_SPLIT = 4,
     CONCPD_OPT_P1_DMA = 5,
-    CONCPD_OPT_FUSE = 6
+    CONCPD_OPT_FUSE = 6,
+    CONCPD_OPT_FUSE_LRA = 7
 } concpd_option;
 concpd_status concpd_set_option(concpd_ctx ctx, int32_t option, int64_t value);
 concpd_status concpd_get_option(concpd_ctx ctx, int32_t option, int64_t* value);

@@ -75,7 +75,7 @@ class Tuning(ctypes.Structure):
 
 STATIC_WORKSPACE_BYTES = 32 << 20   # CONCPD_STATIC_WORKSPACE_BYTES of concpd.h
 
-OPT_GRAPH_SWEEPS, OPT_OVERLAP, OPT_K2_ROWS, OPT_P1_SPLIT, OPT_P1_DMA, OPT_FUSE = 1, 2, 3, 4, 5, 6
+OPT_GRAPH_SWEEPS, OPT_OVERLAP, OPT_K2_ROWS, OPT_P1_SPLIT, OPT_P1_DMA, OPT_FUSE, OPT_FUSE_LRA = 1, 2, 3, 4, 5, 6, 7
 
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libconcpd.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["runtime.cpp", "k_small.hip", "k_mttkrp.hip", "k_update.hip",
-           "k_misc.hip", "k_lra.hip", "k_grad.hip", "k_als.hip", "k_fused.hip", "k_nway.hip"]
+           "k_misc.hip", "k_lra.hip", "k_grad.hip", "k_als.hip", "k_fused.hip", "k_nway.hip", "k_lra_fused.hip"]
 ARCH = os.environ.get("CONCPD_ARCH", "gfx950")
 FLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-x", "hip",

@@ -150,6 +150,10 @@ void launch_grad(const Geo* g, const StateP<T>& st, int S, int R, int Rq, const 
 // LDS of the core-contraction kernel: G slice, two W factors, phase partials.
 inline size_t lra_c_lds_bytes(int Jmax, int Rq) { return sizeof(double) * ((size_t)Jmax * Jmax + 2 * (size_t)Jmax * Rq + 256); }
 template <typename T> void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int Rq, int n, hipStream_t q);
+// the compressed sweep's fused launches: core update + C_1; step matrix of
+// mode n + the W refresh of mode n - 1
+template <typename T> void launch_core_lrac(const Geo* g, const StateP<T>& st, int S, int R, int Jmax, int Rq, int extrap, hipStream_t q);
+template <typename T> void launch_prep_lraw(const Geo* g, const StateP<T>& st, int S, int R, int Jmax, int Rq, int n, hipStream_t q);
 void launch_sum_parts(const double* part, int np, double* out, hipStream_t q);
 void launch_empty(hipStream_t q);
 void launch_pad_copy(const void* src, int src_dtype, void* dst, int dst_dtype, long long rows, int I3, int ld, hipStream_t q);

@@ -582,6 +582,7 @@ struct concpd_ctx_s {
     int p1dma = 0, p1dma_ok = 0;   // pass 1 by LDS DMA (in use / possible)
     int fuse = 0;                  // R x R work fused into the launches of independent passes
     int fuse_dflt = 0;             // its default (pass 1 with few wavefronts per SIMD)
+    int fuse_lra = 1;              // the compressed sweep's fused launches (default on)
     int static_dev = -1;           // device whose static workspace this context holds (-1: none)
     std::vector<hipEvent_t> ev1, ev2;  // begin/end pairs of timed pass launches
     void drop_graph() {
@@ -734,6 +735,20 @@ void run_sweep_lra(concpd_ctx c, const StateP<T>& st) {
     hipStream_t q = c->q;
     const ItemU* itu[3];
     for (int n = 0; n < 3; ++n) itu[n] = (const ItemU*)(c->ws + c->lay.itu[n]);
+    if (c->fuse_lra) {
+        // the R x R work beside the lra work it does not depend on: ten launches
+        cpd::launch_core_lrac<T>(g, st, S, R, J, c->Rq, extrap, q);
+        for (int n = 0; n < 3; ++n) {
+            if (n > 0) {
+                cpd::launch_prep_lraw<T>(g, st, S, R, J, c->Rq, n, q);
+                cpd::launch_lra_c<T>(g, st, S, J, c->Rq, n, q);
+            }
+            cpd::launch_update<T>(g, st, itu[n], (int)c->lists.u[n].size(), n, R, extrap, c->lists.lds_rows[n], 1, q);
+        }
+        cpd::launch_lra_w<T>(g, st, S, J, 2, 0, 0, q);
+        cpd::launch_finish<T>(g, st, S, R, q);
+        return;
+    }
     cpd::launch_core<T>(g, st, S, R, extrap, q);
     for (int n = 0; n < 3; ++n) {
         if (n > 0) cpd::launch_prep<T>(g, st, S, R, n, q);
@@ -1978,6 +1993,11 @@ concpd_status concpd_set_option(concpd_ctx c, int32_t option, int64_t value) {
         if (value != c->fuse) c->drop_graph();
         c->fuse = (int)value;
         return CONCPD_OK;
+    case CONCPD_OPT_FUSE_LRA:
+        if (value != 0 && value != 1) return fail(CONCPD_EINVAL, "fuse_lra %lld not 0 or 1", (long long)value);
+        if (value != c->fuse_lra) c->drop_graph();
+        c->fuse_lra = (int)value;
+        return CONCPD_OK;
     case CONCPD_OPT_P1_SPLIT: {
         if (value != 0 && value != 1 && value != 2 && value != 4)
             return fail(CONCPD_EINVAL, "pass-1 split %lld not 0, 1, 2 or 4", (long long)value);
@@ -2018,6 +2038,7 @@ concpd_status concpd_get_option(concpd_ctx c, int32_t option, int64_t* value) {
     case CONCPD_OPT_P1_SPLIT: *value = c->lists.p1_split; return CONCPD_OK;
     case CONCPD_OPT_P1_DMA: *value = c->p1dma; return CONCPD_OK;
     case CONCPD_OPT_FUSE: *value = c->fuse; return CONCPD_OK;
+    case CONCPD_OPT_FUSE_LRA: *value = c->fuse_lra; return CONCPD_OK;
     default: return fail(CONCPD_EINVAL, "unknown option %d", option);
     }
 }

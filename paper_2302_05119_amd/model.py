@@ -266,7 +266,8 @@ class CoupledCP:
 
     # -- launch options (batching form) -------------------------------------
     _OPTS = {"graph_sweeps": _lib.OPT_GRAPH_SWEEPS, "overlap": _lib.OPT_OVERLAP, "k2_rows": _lib.OPT_K2_ROWS,
-             "p1_split": _lib.OPT_P1_SPLIT, "p1_dma": _lib.OPT_P1_DMA, "fuse": _lib.OPT_FUSE}
+             "p1_split": _lib.OPT_P1_SPLIT, "p1_dma": _lib.OPT_P1_DMA, "fuse": _lib.OPT_FUSE,
+             "fuse_lra": _lib.OPT_FUSE_LRA}
 
     def set_option(self, name: str, value: int) -> None:
         check(self._lib.concpd_set_option(self.ctx, self._OPTS[name], int(value)))

@@ -306,3 +306,33 @@ def test_full_size_c5_compression_and_fit(dev):
     assert st["k"] == 200 and not st["nonfinite"]
     assert st["fit"] > 0.95
     assert 0.80 <= gf <= 0.85
+
+
+@pytest.mark.parametrize("R,L,ranks", [(6, (3, 0, 2), (8, 7, 9)), (20, (8, 0, 0), (22, 21, 20)), (40, (40, 0, 0), (40, 40, 40))])
+def test_lra_fused_launches_bit_identical_to_unfused(dev, R, L, ranks):
+    # the compressed sweep with the R x R work sharing launches (core + C_1,
+    # step matrix n + W refresh of mode n - 1) against thirteen separate
+    # launches: the same device code on the same data, bit for bit
+    say(f"[lra fuse] R={R} L={L} ranks={ranks}")
+    P = synth.coupled_problem([(44, 40, 42), (44, 41, 42), (44, 40, 42)], R, L, 15.0, 931 + R, dtype=np.float32)
+    U0, lam0 = synth.uniform_init(P.dims, R, L, 932 + R)
+    a = make_model(P, U0, lam0, dev, ranks)
+    b = make_model(P, U0, lam0, dev, ranks)
+    a.lra_compress()
+    b.lra_compress()
+    assert a.get_option("fuse_lra") == 1
+    b.set_option("fuse_lra", 0)
+    assert b.get_option("fuse_lra") == 0
+    for it in range(3):
+        sa, sb = a.lra_step(5), b.lra_step(5)
+        say(f"   after {5 * (it + 1)}: F {sa['F']:.12e} / {sb['F']:.12e}")
+        assert sa["F"] == sb["F"] and sa["k"] == sb["k"] and sa["restarts"] == sb["restarts"]
+    for s in range(P.S):
+        np.testing.assert_array_equal(a.lam(s), b.lam(s))
+        for n in range(3):
+            np.testing.assert_array_equal(a.factor(n, s), b.factor(n, s))
+    # and the fused sweep replayed from a graph
+    a.set_option("graph_sweeps", 2)
+    b.set_option("fuse_lra", 1)
+    sa, sb = a.lra_step(4), b.lra_step(4)
+    assert sa["F"] == sb["F"]
