@@ -136,6 +136,10 @@ template <typename T> void launch_update(const Geo* g, const StateP<T>& st, cons
 template <typename T> void launch_nw_kr(const Geo* g, const StateP<T>& st, int S, int half, int slot, long long maxrows, int Rq, int check_stop, hipStream_t q);
 template <typename T> void launch_nw_pass(const Geo* g, const StateP<T>& st, const ItemNW* items, int nitems, int half, int Rq, int check_stop, hipStream_t q);
 template <typename T> void launch_nw_contract(const Geo* g, const StateP<T>& st, int S, int n, int lo_slot, int maxI, int Rq, int check_stop, hipStream_t q);
+// the order-N sweep's fused launches: core update + pass A's Khatri-Rao
+// operand; step matrix of mode n + the contraction of mode n
+template <typename T> void launch_nw_core_kr(const Geo* g, const StateP<T>& st, int S, int R, int extrap, long long maxB, int Rq, hipStream_t q);
+template <typename T> void launch_nw_prep_contract(const Geo* g, const StateP<T>& st, int S, int R, int n, int maxI, int Rq, hipStream_t q);
 template <typename T> void launch_extract_k(const Geo* g, const StateP<T>& st, int s, int n, int I, int R, T* out, int ld_out, int lra, hipStream_t q);
 template <typename T> void launch_resid(const Geo* g, const StateP<T>& st, const void* M, int dtype, int s, int I1, double* part, hipStream_t q);
 void launch_sqnorm(const void* src, int dtype, long long n, double* out, double* part, int npart, hipStream_t q);

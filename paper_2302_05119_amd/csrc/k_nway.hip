@@ -24,22 +24,23 @@
 // Khatri-Rao rows of a 16-deep chunk are staged in LDS so that lane class
 // l % 4 reads its columns 4t + l % 4 as one contiguous run.
 #include "mttkrp_kernels.h"
+#include "small_dev.h"
 
 namespace cpd {
 
 // Khatri-Rao operand of one half: rows o (multi-index over the half's modes,
 // last fastest), columns r < Rq; product of FP64 factor values, rounded once.
+// (st remapped; workgroup wg of nwg covers entries wg*256 + t, step nwg*256)
 template <typename T>
-__global__ __launch_bounds__(256) void k_nw_kr(const Geo* __restrict__ g, StateP<T> st, int half, int slot, int check_stop) {
-    if (check_stop && st.ctrl->stop) return;
-    apply_rot(st);
-    const int s = blockIdx.y, N = g->N, h = g->nh, Rq = g->Rq;
+__device__ __forceinline__ void nw_kr_part(const Geo* __restrict__ g, const StateP<T>& st, int half, int slot, int s, int wg,
+                                           int nwg) {
+    const int N = g->N, h = g->nh, Rq = g->Rq;
     // half 0: the operand of pass A (modes h..N-1), half 1: of pass B (modes 0..h-1)
     const int m0 = half ? 0 : h, m1 = half ? h : N;
     const long long rows = half ? g->nwA[s] : g->nwB[s];
     const T* U = pick3(st.U, slot);
     T* out = st.part + g->kroff[s];
-    for (long long e = blockIdx.x * 256LL + threadIdx.x; e < rows * Rq; e += (long long)gridDim.x * 256) {
+    for (long long e = wg * 256LL + threadIdx.x; e < rows * Rq; e += (long long)nwg * 256) {
         const int r = (int)(e % Rq);
         long long x = e / Rq;
         double p = 1.0;
@@ -51,6 +52,13 @@ __global__ __launch_bounds__(256) void k_nw_kr(const Geo* __restrict__ g, StateP
         }
         out[e] = (T)p;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nw_kr(const Geo* __restrict__ g, StateP<T> st, int half, int slot, int check_stop) {
+    if (check_stop && st.ctrl->stop) return;
+    apply_rot(st);
+    nw_kr_part<T>(g, st, half, slot, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // One pass (HALF 0: A, HALF 1: B); one wavefront per item (64 outputs of one
@@ -158,13 +166,9 @@ __global__ __launch_bounds__(256) void k_nw_pass(const Geo* __restrict__ g, Stat
 // factors of the half), then thread r adds the J stripe sums in stripe order;
 // FP64 throughout, rounded once into the plain K buffer.
 template <typename T>
-__global__ __launch_bounds__(256) void k_nw_contract(const Geo* __restrict__ g, StateP<T> st, int n, int lo_slot,
-                                                     int check_stop) {
-    if (check_stop && st.ctrl->stop) return;
-    const int s = blockIdx.y, i = blockIdx.x;
+__device__ __forceinline__ void nw_contract_row(const Geo* __restrict__ g, const StateP<T>& st, int n, int lo_slot, int s, int i) {
     const int In = g->I[s][n];
     if (i >= In) return;   // uniform over the workgroup
-    apply_rot(st);
     const int N = g->N, h = g->nh, Rq = g->Rq, R = g->R, tid = threadIdx.x;
     const int J = 256 / Rq, r = tid % Rq, j = tid / Rq;
     const int half = n >= h;
@@ -211,6 +215,51 @@ __global__ __launch_bounds__(256) void k_nw_contract(const Geo* __restrict__ g, 
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_nw_contract(const Geo* __restrict__ g, StateP<T> st, int n, int lo_slot,
+                                                     int check_stop) {
+    if (check_stop && st.ctrl->stop) return;
+    apply_rot(st);
+    nw_contract_row<T>(g, st, n, lo_slot, blockIdx.y, blockIdx.x);
+}
+
+// The sweep's R x R work beside order-N work it does not depend on (the
+// first nsmall workgroups, S rounded up to a multiple of 8, take one block
+// each; the rest the other kernel's work): the core update beside the
+// Khatri-Rao operand of pass A (x_{k-1} factors), the step matrix of mode n
+// beside the contraction of mode n (both read the factors updated so far).
+template <int NM> struct NwFuseWaves { static constexpr int W = NM <= 32 ? 2 : 1; };
+
+template <typename T, int NM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NwFuseWaves<NM>::W))) void k_nw_core_kr(
+    const Geo* __restrict__ g, StateP<T> st, int extrapolate, int S, int nsmall, int krw) {
+    if (st.ctrl->stop) return;
+    apply_rot(st);
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
+    const int bid = blockIdx.x;
+    if (bid < nsmall) {
+        if (bid < S) core_block<T, NM>(g, st, bid, extrapolating(st.ctrl, extrapolate), smraw);
+        return;
+    }
+    const int b = bid - nsmall;
+    nw_kr_part<T>(g, st, 0, 1, b / krw, b % krw, krw);
+}
+
+template <typename T, int NM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NwFuseWaves<NM>::W))) void k_nw_prep_contract(
+    const Geo* __restrict__ g, StateP<T> st, int n, int S, int nsmall, int maxI) {
+    if (st.ctrl->stop) return;
+    apply_rot(st);
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
+    const int bid = blockIdx.x;
+    if (bid < nsmall) {
+        if (bid < S) prep_block<T, NM>(g, st, bid, n, smraw);
+        return;
+    }
+    const int b = bid - nsmall;
+    nw_contract_row<T>(g, st, n, 0, b / maxI, b % maxI);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -255,10 +304,47 @@ void launch_nw_contract(const Geo* g, const StateP<T>& st, int S, int n, int lo_
     hipLaunchKernelGGL(k_nw_contract<T>, dim3(maxI, S), dim3(256), 0, q, g, st, n, lo_slot, check_stop);
 }
 
+static int nw_small_wgs(int S) { return (S + 7) & ~7; }
+
+template <typename T>
+void launch_nw_core_kr(const Geo* g, const StateP<T>& st, int S, int R, int extrap, long long maxB, int Rq, hipStream_t q) {
+    const int ns = nw_small_wgs(S);
+    const int krw = (int)grid_x(maxB * Rq);
+    const dim3 grid(ns + krw * S);
+    const size_t lds = eig_lds_bytes(R);
+#define CPD_NCK(NMV) hipLaunchKernelGGL((k_nw_core_kr<T, NMV>), grid, dim3(256), lds, q, g, st, extrap, S, ns, krw)
+    switch (nmax_class(R)) {
+    case 16: CPD_NCK(16); break;
+    case 24: CPD_NCK(24); break;
+    case 32: CPD_NCK(32); break;
+    case 48: CPD_NCK(48); break;
+    default: CPD_NCK(64); break;
+    }
+#undef CPD_NCK
+}
+
+template <typename T>
+void launch_nw_prep_contract(const Geo* g, const StateP<T>& st, int S, int R, int n, int maxI, int Rq, hipStream_t q) {
+    const int ns = nw_small_wgs(S);
+    const dim3 grid(ns + maxI * S);
+    const size_t lds = prep_lds_bytes<T>(R, Rq);
+#define CPD_NPC(NMV) hipLaunchKernelGGL((k_nw_prep_contract<T, NMV>), grid, dim3(256), lds, q, g, st, n, S, ns, maxI)
+    switch (nmax_class(R)) {
+    case 16: CPD_NPC(16); break;
+    case 24: CPD_NPC(24); break;
+    case 32: CPD_NPC(32); break;
+    case 48: CPD_NPC(48); break;
+    default: CPD_NPC(64); break;
+    }
+#undef CPD_NPC
+}
+
 #define CPD_INST_NW(T)                                                                                                    \
     template void launch_nw_kr<T>(const Geo*, const StateP<T>&, int, int, int, long long, int, int, hipStream_t);       \
     template void launch_nw_pass<T>(const Geo*, const StateP<T>&, const ItemNW*, int, int, int, int, hipStream_t);      \
-    template void launch_nw_contract<T>(const Geo*, const StateP<T>&, int, int, int, int, int, int, hipStream_t);
+    template void launch_nw_contract<T>(const Geo*, const StateP<T>&, int, int, int, int, int, int, hipStream_t);    \
+    template void launch_nw_core_kr<T>(const Geo*, const StateP<T>&, int, int, int, long long, int, hipStream_t);    \
+    template void launch_nw_prep_contract<T>(const Geo*, const StateP<T>&, int, int, int, int, int, hipStream_t);
 CPD_INST_NW(float)
 CPD_INST_NW(double)
 

@@ -783,16 +783,17 @@ void run_sweep_nw(concpd_ctx c, const StateP<T>& st) {
     nw_extents(c, &maxA, &maxB, &maxI);
     const ItemNW* ita = (const ItemNW*)(c->ws + c->lay.itna);
     const ItemNW* itb = (const ItemNW*)(c->ws + c->lay.itnb);
-    cpd::launch_core<T>(g, st, S, R, extrap, q);
-    cpd::launch_nw_kr<T>(g, st, S, 0, 1, maxB, Rq, 1, q);
+    // the core update beside pass A's Khatri-Rao operand, each mode's step
+    // matrix beside its contraction (independent work, one launch each)
+    cpd::launch_nw_core_kr<T>(g, st, S, R, extrap, maxB, Rq, q);
     cpd::launch_nw_pass<T>(g, st, ita, (int)c->lists.na.size(), 0, Rq, 1, q);
     for (int n = 0; n < N; ++n) {
         if (n == h) {
             cpd::launch_nw_kr<T>(g, st, S, 1, 0, maxA, Rq, 1, q);
             cpd::launch_nw_pass<T>(g, st, itb, (int)c->lists.nb.size(), 1, Rq, 1, q);
         }
-        if (n > 0) cpd::launch_prep<T>(g, st, S, R, n, q);
-        cpd::launch_nw_contract<T>(g, st, S, n, 0, maxI, Rq, 1, q);
+        if (n > 0) cpd::launch_nw_prep_contract<T>(g, st, S, R, n, maxI, Rq, q);
+        else cpd::launch_nw_contract<T>(g, st, S, n, 0, maxI, Rq, 1, q);
         cpd::launch_update<T>(g, st, (const ItemU*)(c->ws + c->lay.itu[n]), (int)c->lists.u[n].size(), n, R, extrap,
                               c->lists.lds_rows[n], 2, q);
     }
