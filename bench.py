@@ -146,10 +146,11 @@ def lra_leg(steps: int, warmup: int, dense_steps: int = 30, name: str = LRA_WORK
     t3 = time.perf_counter()
     st = m.stats()
     from paper_2302_05119_amd import launch_floor
-    fl = launch_floor(13)   # kernels per compressed sweep
+    nk = 10 if m.get_option("fuse_lra") else 13   # kernels per compressed sweep
+    fl = launch_floor(nk)
     return {"workload": name, "compression": compress, **extra, "compress_s": t1 - t0,
             "iter_per_s": (st["k"] - k0) / (t3 - t2),
-            "launch_floor": {"kernels_per_sweep": 13, "graph_us": fl["graph_us"], "direct_us": fl["direct_us"]},
+            "launch_floor": {"kernels_per_sweep": nk, "graph_us": fl["graph_us"], "direct_us": fl["direct_us"]},
             "dense_iter_per_s_same_blocks": dense_rate, "dense_passes_same_blocks": dense_passes, "sweeps": steps,
             "warmup": warmup, "fit_compressed": st["fit"], "global_fit": m.global_fit(), "iterations": st["k"],
             "restarts": st["restarts"]}
