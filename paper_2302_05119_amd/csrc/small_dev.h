@@ -643,7 +643,7 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
 // added in fixed order through LDS (lds: 256 + 256 doubles).  Only the upper
 // triangle is formed and mirrored.  lout / lbout (optional, LDS): copies of V
 // (row stride R) and b for the caller.
-template <typename T>
+template <typename T, int GB = 8>
 __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R, int Rq, double* __restrict__ out,
                                            const T* __restrict__ K, double* __restrict__ bout, char* lds,
                                            double* __restrict__ lout = nullptr, double* __restrict__ lbout = nullptr) {
@@ -658,11 +658,12 @@ __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R
     for (int p = 0; p < 10; ++p) acc[p] = (v4d){0.0, 0.0, 0.0, 0.0};
     // row steps of 4 rows, wave w takes steps w, w+4, ...; batches of GB steps
     // with every global load of the batch in flight (clamped addresses,
-    // zeros outside the factor)
-    constexpr int GB = 8;
+    // zeros outside the factor), held in the storage type; the kernels that
+    // run the Gram alone take 16 steps a batch, those that share registers
+    // with other work 8
     const int nsteps = (I + 3) >> 2;
     for (int sb = wv; sb < nsteps; sb += 4 * GB) {
-        double u[GB][4];
+        T u[GB][4];
 #pragma unroll
         for (int q = 0; q < GB; ++q) {
             const int row = 4 * (sb + 4 * q) + lk;
@@ -670,8 +671,8 @@ __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int col = 16 * t + li;
-                const double v = (double)U[(long long)rc * Rq + min(col, R - 1)];
-                u[q][t] = (t < nt && row < I && col < R) ? v : 0.0;
+                const T v = U[(long long)rc * Rq + min(col, R - 1)];
+                u[q][t] = (t < nt && row < I && col < R) ? v : (T)0;
             }
         }
 #pragma unroll
@@ -681,24 +682,26 @@ __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R
             for (int ta = 0; ta < 4; ++ta)
 #pragma unroll
                 for (int tb = ta; tb < 4; ++tb, ++p)
-                    if (tb < nt) acc[p] = mfma64(u[q][ta], u[q][tb], acc[p]);
+                    if (tb < nt) acc[p] = mfma64((double)u[q][ta], (double)u[q][tb], acc[p]);
         }
     }
-    // b = colsum(K ⊛ U): column c = lane, rows of phase wave, 8 rows in flight
+    // b = colsum(K ⊛ U): column c = lane, rows of phase wave in ascending
+    // order, 32 rows (64 loads) in flight
     double bacc = 0.0;
     if (K != nullptr) {
+        constexpr int BB = 32;
         const int lc = min(lane, R - 1);
-        for (int i0 = wv; i0 < I; i0 += 32) {
-            double kv[8], uv[8];
+        for (int i0 = wv; i0 < I; i0 += 4 * BB) {
+            T kv[BB], uv[BB];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < BB; ++q) {
                 const long long o = (long long)min(i0 + 4 * q, I - 1) * Rq + lc;
-                kv[q] = (double)K[o];
-                uv[q] = (double)U[o];
+                kv[q] = K[o];
+                uv[q] = U[o];
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (i0 + 4 * q < I) bacc = fma(kv[q], uv[q], bacc);
+            for (int q = 0; q < BB; ++q)
+                if (i0 + 4 * q < I) bacc = fma((double)kv[q], (double)uv[q], bacc);
         }
         bpart[wv * 64 + lane] = bacc;
     }
