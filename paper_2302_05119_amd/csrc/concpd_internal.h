@@ -151,8 +151,8 @@ template <typename T> void launch_lra_w(const Geo* g, const StateP<T>& st, int S
 template <typename T>
 void launch_grad(const Geo* g, const StateP<T>& st, int S, int R, int Rq, const int* In, int L0, int L1, int L2,
                  double* const* glam, double* Fblk, T* const* gU0, T* const* gU1, T* const* gU2, int coupled, hipStream_t q);
-// LDS of the core-contraction kernel: G slice, two W factors, phase partials.
-inline size_t lra_c_lds_bytes(int Jmax, int Rq) { return sizeof(double) * ((size_t)Jmax * Jmax + 2 * (size_t)Jmax * Rq + 256); }
+// LDS of the core-contraction kernel: G slice, two W factors, per-tile partial sums.
+inline size_t lra_c_lds_bytes(int Jmax, int Rq) { return sizeof(double) * ((size_t)Jmax * Jmax + 2 * (size_t)Jmax * Rq + 1024); }
 template <typename T> void launch_lra_c(const Geo* g, const StateP<T>& st, int S, int Jmax, int Rq, int n, hipStream_t q);
 // the compressed sweep's fused launches: core update + C_1; step matrix of
 // mode n + the W refresh of mode n - 1

@@ -45,9 +45,12 @@ __device__ __forceinline__ void lra_w_item(const Geo* __restrict__ g, const Stat
 
 // C_n^(s)[jn][c] = sum_{ja, jb} G_(n)[jn][(ja, jb)] W_a[ja][c] W_b[jb][c], where
 // (a, b) are the other two modes (W of modes before n from slot 0, after n
-// from slot 1), row jn of block s: the G slice of jn and both W factors are
-// staged in LDS (sm: lra_c_lds_bytes), then T[ja][c] = sum_jb G[ja][jb]
-// W_b[jb][c] and C = sum_ja W_a[ja][c] T[ja][c] run from LDS.
+// from slot 1), row jn of block s.  The G slice of jn and both W factors are
+// staged in LDS (sm: lra_c_lds_bytes); T = G_slice W_b (Ja x Rq) runs on the
+// FP64 matrix cores in 16 x 16 tiles (v_mfma_f64_16x16x4f64, wavefront w
+// takes tiles w, w + 4, ...), and C[c] = sum_ja W_a[ja][c] T[ja][c] is formed
+// from the accumulators: per lane over its four rows, then over the four lane
+// groups and the row tiles in fixed order through LDS.
 template <typename T>
 __device__ __forceinline__ void lra_c_item(const Geo* __restrict__ g, const StateP<T>& st, int n, int s, int jn, double* sm) {
     const int r2 = st.ctrl->rot2;
@@ -64,7 +67,7 @@ __device__ __forceinline__ void lra_c_item(const Geo* __restrict__ g, const Stat
     double* gs = sm;                       // [Ja][Jb]
     double* wa = gs + Ja * Jb;             // [Ja][Rq]
     double* wb = wa + Ja * Rq;             // [Jb][Rq]
-    double* tp = wb + Jb * Rq;             // [4][64] phase partials
+    double* part = wb + Jb * Rq;           // [row tile][lane group][64]
     const int tid = threadIdx.x;
     for (int e = tid; e < Ja * Jb; e += 256) {
         const int ja = e / Jb, jb = e % Jb;
@@ -77,28 +80,37 @@ __device__ __forceinline__ void lra_c_item(const Geo* __restrict__ g, const Stat
     for (int e = tid; e < Ja * Rq; e += 256) wa[e] = Wa[e];
     for (int e = tid; e < Jb * Rq; e += 256) wb[e] = Wb[e];
     __syncthreads();
-    const int c = tid & 63, ph = tid >> 6;
-    double acc = 0.0;
-    if (c < R) {
-        for (int ja = ph; ja < Ja; ja += 4) {
-            const double* grow = gs + ja * Jb;
-            double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
-            int jb = 0;
-            for (; jb + 3 < Jb; jb += 4) {
-                t0 = fma(grow[jb], wb[jb * Rq + c], t0);
-                t1 = fma(grow[jb + 1], wb[(jb + 1) * Rq + c], t1);
-                t2 = fma(grow[jb + 2], wb[(jb + 2) * Rq + c], t2);
-                t3 = fma(grow[jb + 3], wb[(jb + 3) * Rq + c], t3);
-            }
-            for (; jb < Jb; ++jb) t0 = fma(grow[jb], wb[jb * Rq + c], t0);
-            acc = fma(wa[ja * Rq + c], (t0 + t1) + (t2 + t3), acc);
+    const int lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int nta = (Ja + 15) >> 4, ntc = (Rq + 15) >> 4;
+    for (int tile = wv; tile < nta * ntc; tile += 4) {
+        const int ta = tile / ntc, tc = tile % ntc;
+        const int row = 16 * ta + li, col = 16 * tc + li;
+        v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
+        // lane l: A[l % 16][l / 16] = G_slice[row][k], B[l / 16][l % 16] = W_b[k][col]
+        for (int k0 = 0; k0 < Jb; k0 += 4) {
+            const int k = k0 + lk;
+            const double a = (row < Ja && k < Jb) ? gs[row * Jb + k] : 0.0;
+            const double b = (k < Jb && col < Rq) ? wb[k * Rq + col] : 0.0;
+            acc = mfma64(a, b, acc);
         }
+        // register v holds T[16 ta + 4 v + l / 16][16 tc + l % 16]
+        double p = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ja = 16 * ta + 4 * v + lk;
+            if (ja < Ja && col < Rq) p = fma(wa[ja * Rq + col], acc[v], p);
+        }
+        part[(ta * 4 + lk) * 64 + col] = p;
     }
-    tp[ph * 64 + c] = acc;
     __syncthreads();
-    if (tid < Rq)
-        st.lra[g->coff[s] + (long long)jn * Rq + tid] =
-            (tid < R) ? ((tp[tid] + tp[64 + tid]) + tp[128 + tid]) + tp[192 + tid] : 0.0;
+    if (tid < Rq) {
+        double c = 0.0;
+        if (tid < R)
+            for (int ta = 0; ta < nta; ++ta)
+                c += ((part[(ta * 4 + 0) * 64 + tid] + part[(ta * 4 + 1) * 64 + tid]) + part[(ta * 4 + 2) * 64 + tid]) +
+                     part[(ta * 4 + 3) * 64 + tid];
+        st.lra[g->coff[s] + (long long)jn * Rq + tid] = c;
+    }
 }
 
 }  // namespace cpd

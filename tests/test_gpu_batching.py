@@ -230,7 +230,7 @@ def test_full_size_c4_eeg_teacher_forced_fp32_and_bf16_fit():
     # 16 EEG-shaped blocks 64 x 60 x T_s, T_s in [200, 2000], R = 30, channel
     # and frequency factors fully shared, 5 dB
     name = "c4_eeg_bf16_16blocks_r30"
-    say("[c4 full] teacher-forced FP32 iteration; BF16 vs FP32 fit")
+    say("[c4 full] teacher-forced FP32 and BF16 iteration; BF16 vs FP32 fit")
     P = synth.make_workload(name)
     U0, lam0 = synth.workload_init(name, P)
     U0 = [[u.astype(np.float32).astype(np.float64) for u in per] for per in U0]
@@ -246,7 +246,15 @@ def test_full_size_c4_eeg_teacher_forced_fp32_and_bf16_fit():
             assert rel(m.factor(n, b), new.U[n][b]) <= 1e-5
     m.step(59)
     mb = model(P, U0, lam0, compute="bf16")
-    mb.step(60)
+    # the BF16 form's first iteration against the same oracle iteration: the
+    # per-step bound of the precision form (2e-2), on every block
+    sb1 = mb.step(1)
+    eb = max(rel(mb.factor(n, b), new.U[n][b]) for b in range(P.S) for n in range(3))
+    el = max(rel(mb.lam(b), new.lam[b]) for b in range(P.S))
+    say(f"   BF16 step: F gpu={sb1['F']:.10e} oracle={new.F:.10e}; worst factor {eb:.2e}, lambda {el:.2e}")
+    assert abs(sb1["F"] - new.F) / new.F <= 2e-2
+    assert eb <= 2e-2 and el <= 2e-2
+    mb.step(59)
     f32, fb = m.global_fit(), mb.global_fit()
     say(f"   60 iterations: global fit FP32 {f32:.6f}  BF16 {fb:.6f}")
     assert abs(f32 - fb) <= 1e-3
