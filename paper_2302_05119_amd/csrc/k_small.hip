@@ -76,7 +76,10 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     double* b = st.b[0] + s * Rq;
     double* V2l = (double*)(smraw + gram_lds_bytes<T>(Rq, 1));
     double* bl = V2l + RR;
-    block_gram<T, 16>(st.U[0] + g->uoff[N - 1][s], g->I[s][N - 1], R, Rq, V2, st.K3 + g->koff[s], b, smraw, V2l, bl);
+    if (g->I[s][N - 1] > 128)
+        block_gram<T, 16>(st.U[0] + g->uoff[N - 1][s], g->I[s][N - 1], R, Rq, V2, st.K3 + g->koff[s], b, smraw, V2l, bl);
+    else
+        block_gram<T, 8>(st.U[0] + g->uoff[N - 1][s], g->I[s][N - 1], R, Rq, V2, st.K3 + g->koff[s], b, smraw, V2l, bl);
     const double F = block_objective_pf<EP>(lam, v0, v1, V2l, bl, nrm_s, R);
     if (tid == 0) {
         store_agent(&st.Fblk[s], F);
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(256) void k_init_stats(const Geo* __restrict__ g, S
         block_gram<T, 16>(st.U[1] + g->uoff[m][s], g->I[s][m], R, Rq, st.V[1] + (m * S + s) * RR, nullptr, nullptr, smraw);
     double* V2 = st.V[1] + ((N - 1) * S + s) * RR;
     double* b = st.b[1] + s * Rq;
-    block_gram<T, 16>(st.U[1] + g->uoff[N - 1][s], g->I[s][N - 1], R, Rq, V2, st.K3 + g->koff[s], b, smraw);
+    block_gram<T, 16>(st.U[1] + g->uoff[N - 1][s], g->I[s][N - 1], R, Rq, V2, st.K3 + g->koff[s], b, smraw);   // once per fit
     __threadfence_block();
     __syncthreads();
     const double F = (N == 3) ? block_objective(st.lam[1] + s * Rq, st.V[1] + (0 * S + s) * RR, st.V[1] + (1 * S + s) * RR, V2,

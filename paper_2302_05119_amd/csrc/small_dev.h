@@ -659,8 +659,9 @@ __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R
     // row steps of 4 rows, wave w takes steps w, w+4, ...; batches of GB steps
     // with every global load of the batch in flight (clamped addresses,
     // zeros outside the factor), held in the storage type; the kernels that
-    // run the Gram alone take 16 steps a batch, those that share registers
-    // with other work 8
+    // run the Gram alone take 16 steps a batch on long factors (beyond 128
+    // rows; on short ones the clamped loads past the end would cost more than
+    // the round trips they save), those that share registers with other work 8
     const int nsteps = (I + 3) >> 2;
     for (int sb = wv; sb < nsteps; sb += 4 * GB) {
         T u[GB][4];
@@ -686,10 +687,10 @@ __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R
         }
     }
     // b = colsum(K ⊛ U): column c = lane, rows of phase wave in ascending
-    // order, 32 rows (64 loads) in flight
+    // order, 32 rows (64 loads) in flight with the deep batches, else 8
     double bacc = 0.0;
     if (K != nullptr) {
-        constexpr int BB = 32;
+        constexpr int BB = GB >= 16 ? 32 : 8;
         const int lc = min(lane, R - 1);
         for (int i0 = wv; i0 < I; i0 += 4 * BB) {
             T kv[BB], uv[BB];
