@@ -32,6 +32,7 @@ struct Ctrl {
     unsigned int counter_finish;   // arrival counters for last-workgroup reductions
     unsigned int counter_aux;
     int pad;
+    unsigned int blkcnt[CPD_MAXS]; // per-block arrival counters of the chunked finish
 };
 
 // Per-context geometry, resident in the workspace.
@@ -77,7 +78,13 @@ struct Geo {
     long long taoff[CPD_MAXS];    // pass-A partials: npa x A x Rq (in the Y region)
     long long tboff[CPD_MAXS];    // pass-B partials: npb x B x Rq (in the Y region)
     long long kroff[CPD_MAXS];    // Khatri-Rao operand: max(A, B) x Rq (in the part region)
+    // the finish over the last mode in chunks of CPD_FIN_ROWS rows: block s
+    // takes workgroups fin_c0[s] .. fin_c0[s] + fin_nc[s] - 1 of the launch
+    int fin_nc[CPD_MAXS];
+    int fin_c0[CPD_MAXS];
+    int fin_nwg;
 };
+#define CPD_FIN_ROWS 128
 
 // Device pointers of the iterate state.  Slot 0 = x_k being built,
 // slot 1 = x_{k-1}, slot 2 = x_{k-2}.
@@ -101,6 +108,7 @@ struct StateP {
     T* K1p;             // mode-1 partials
     T* K2;              // mode-2 MTTKRP
     double* lra;        // Tucker storage base (A, G, W, scratch)
+    double* fpart;      // partial Grams and data terms of the chunked finish: [chunk][R*R + Rq]
     Ctrl* ctrl;
 };
 
@@ -122,7 +130,7 @@ template <typename T> bool launch_core_pass1(const Geo* g, const StateP<T>& st, 
 template <typename T> bool launch_prep_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int R, int slot, int S, hipStream_t q);
 template <typename T> bool launch_prep_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int R, int slot, int mdtype, int maxI2, int S, hipStream_t q);
 template <typename T> void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, hipStream_t q);
-template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
+template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, int nwg, hipStream_t q);
 template <typename T> void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
 template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int P, int Rq, int slot, int mdtype, int dma, hipStream_t q);
 template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int mdtype, int maxI2, hipStream_t q);

@@ -24,17 +24,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 
 
 // After the last mode's update: Gram of U^(N), b (the data term (U^⊙)^T vec(M)
-// of eq. solapgG, reused by the next core update) and F^(s).  The last workgroup
-// sums F over the blocks in block order, applies the restart test of
-// Algorithm 1 and, for an accepted sweep, commits it: Lipschitz constants,
-// k, t, w_hat, the stopping rule and the slot rotation.
+// of eq. solapgG, reused by the next core update) and F^(s).  A block whose
+// last mode is longer than CPD_FIN_ROWS rows is split over workgroups of that
+// many rows: each hands its partial Gram and b to the block's last-arriving
+// workgroup (agent-scope stores, completion wait, arrival count), which adds
+// them in chunk order.  The last block to finish sums F over the blocks in
+// block order, applies the restart test of Algorithm 1 and, for an accepted
+// sweep, commits it: Lipschitz constants, k, t, w_hat, the stopping rule and
+// the slot rotation.
 template <typename T, int NMAX>
 __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, StateP<T> st) {
     Ctrl* c = st.ctrl;
     if (c->stop) return;
     apply_rot(st);
-    const int s = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int S = g->S, R = g->R, Rq = g->Rq, RR = R * R, N = g->N, NS = N * S;
+    // block and chunk of this workgroup (binary search over the chunk offsets)
+    int s = 0;
+    {
+        int lo = 0, hi = S - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (g->fin_c0[mid] <= (int)blockIdx.x) lo = mid;
+            else hi = mid - 1;
+        }
+        s = lo;
+    }
+    const int nc = g->fin_nc[s], chunk = blockIdx.x - g->fin_c0[s];
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     __shared__ int last;
     __shared__ double fb[CPD_MAXS], nb[CPD_MAXS];
@@ -76,15 +92,46 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
     double* b = st.b[0] + s * Rq;
     double* V2l = (double*)(smraw + gram_lds_bytes<T>(Rq, 1));
     double* bl = V2l + RR;
-    if (g->I[s][N - 1] > 128)
-        block_gram<T, 16>(st.U[0] + g->uoff[N - 1][s], g->I[s][N - 1], R, Rq, V2, st.K3 + g->koff[s], b, smraw, V2l, bl);
-    else
-        block_gram<T, 8>(st.U[0] + g->uoff[N - 1][s], g->I[s][N - 1], R, Rq, V2, st.K3 + g->koff[s], b, smraw, V2l, bl);
+    const int In = g->I[s][N - 1];
+    if (nc == 1) {
+        block_gram<T, 8>(st.U[0] + g->uoff[N - 1][s], In, R, Rq, V2, st.K3 + g->koff[s], b, smraw, V2l, bl);
+    } else {
+        // this chunk's rows: partial Gram and b into LDS, then to the block's
+        // partial slots
+        const int r0 = chunk * CPD_FIN_ROWS, nr = min(CPD_FIN_ROWS, In - r0);
+        block_gram<T, 8>(st.U[0] + g->uoff[N - 1][s] + (long long)r0 * Rq, nr, R, Rq, nullptr, st.K3 + g->koff[s] + (long long)r0 * Rq,
+                         nullptr, smraw, V2l, bl);
+        double* fp = st.fpart + (long long)blockIdx.x * (RR + Rq);
+        for (int e = tid; e < RR; e += 256) store_agent(&fp[e], V2l[e]);
+        if (tid < R) store_agent(&fp[RR + tid], bl[tid]);
+        wait_stores();
+        __syncthreads();
+        __shared__ int lastblk;
+        if (tid == 0) lastblk = (arrive_agent(&c->blkcnt[s]) == (unsigned)(nc - 1));
+        __syncthreads();
+        if (!lastblk) return;
+        if (tid == 0) c->blkcnt[s] = 0u;
+        // the block's Gram and b: the chunks' partials in chunk order
+        const double* fb0 = st.fpart + (long long)g->fin_c0[s] * (RR + Rq);
+        for (int e = tid; e < RR; e += 256) {
+            double a = 0.0;
+            for (int q = 0; q < nc; ++q) a += load_agent(&fb0[(long long)q * (RR + Rq) + e]);
+            V2l[e] = a;
+            V2[e] = a;
+        }
+        if (tid < R) {
+            double a = 0.0;
+            for (int q = 0; q < nc; ++q) a += load_agent(&fb0[(long long)q * (RR + Rq) + RR + tid]);
+            bl[tid] = a;
+            b[tid] = a;
+        }
+        __syncthreads();
+    }
     const double F = block_objective_pf<EP>(lam, v0, v1, V2l, bl, nrm_s, R);
     if (tid == 0) {
         store_agent(&st.Fblk[s], F);
         wait_stores();
-        last = (arrive_agent(&c->counter_finish) == (unsigned)(gridDim.x - 1));
+        last = (arrive_agent(&c->counter_finish) == (unsigned)(S - 1));
     }
     __syncthreads();
     if (!last) return;
@@ -242,9 +289,10 @@ void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, hipStre
 #undef CPD_PREP
 }
 template <typename T>
-void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q) {
+void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, int nwg, hipStream_t q) {
     const int Rq = (R + 3) / 4 * 4;
-#define CPD_FIN(N) hipLaunchKernelGGL((k_finish<T, N>), dim3(S), dim3(256), finish_lds_bytes<T>(R, Rq), q, g, st)
+    (void)S;
+#define CPD_FIN(N) hipLaunchKernelGGL((k_finish<T, N>), dim3(nwg), dim3(256), finish_lds_bytes<T>(R, Rq), q, g, st)
     CPD_NMAX_DISPATCH(R, CPD_FIN);
 #undef CPD_FIN
 }
@@ -263,7 +311,7 @@ void launch_spectral_norm(const double* mats, int n, int count, double* out, hip
 #define CPD_INST_SMALL(T)                                                                                  \
     template void launch_core<T>(const Geo*, const StateP<T>&, int, int, int, hipStream_t);               \
     template void launch_prep<T>(const Geo*, const StateP<T>&, int, int, int, hipStream_t);               \
-    template void launch_finish<T>(const Geo*, const StateP<T>&, int, int, hipStream_t);                  \
+    template void launch_finish<T>(const Geo*, const StateP<T>&, int, int, int, hipStream_t);             \
     template void launch_init_stats<T>(const Geo*, const StateP<T>&, int, int, hipStream_t);
 CPD_INST_SMALL(float)
 CPD_INST_SMALL(double)

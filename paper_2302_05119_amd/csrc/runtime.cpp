@@ -66,7 +66,7 @@ int operand_bytes(int dtype) { return dtype == CONCPD_F64 ? 8 : (dtype == CONCPD
 
 struct Layout {
     size_t geo, ctrl, U[3], lam[3], V[2], b[2], P, Ld_cur, Ld_prev, Lu_cur, Lu_prev, LC_prev, Fblk, normM2, normOrig, Y,
-        K3, part, K1p, K2, it1, it2, itk2, itu[CPD_MAXN], itna, itnb, scratch, shadow, lra, flag, total;
+        K3, part, K1p, K2, it1, it2, itk2, itu[CPD_MAXN], itna, itnb, scratch, shadow, lra, fpart, flag, total;
     // loss/gradient evaluation point (autograd form): factors, lambda, Grams,
     // b, step matrices, per-block F, control block, output pointer tables
     size_t gU, glam, gV, gb, gP, gF, gctrl, gptr;
@@ -397,6 +397,17 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
         g->nk2[s] = (int)((I1 + CPD_K2ROWS_DEFAULT - 1) / CPD_K2ROWS_DEFAULT);
         k2 += ((I1 + CPD_K2ROWS_MIN - 1) / CPD_K2ROWS_MIN) * I2 * Rq;   // room for the smallest chunk
     }
+    // the finish over the last mode in chunks of CPD_FIN_ROWS rows
+    {
+        int c0 = 0;
+        for (int s = 0; s < S; ++s) {
+            const long long In = c->dims[(size_t)N * s + N - 1];
+            g->fin_nc[s] = In > CPD_FIN_ROWS ? (int)((In + CPD_FIN_ROWS - 1) / CPD_FIN_ROWS) : 1;
+            g->fin_c0[s] = c0;
+            c0 += g->fin_nc[s];
+        }
+        g->fin_nwg = c0;
+    }
     P->uslot = u;
     P->ylen = y;
     P->klen = k;
@@ -441,6 +452,7 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
     for (int s = 0; s < S; ++s) scr = std::max<size_t>(scr, (size_t)c->dims[N * s]);
     P->scratch_len = scr;
     P->scratch = take(sizeof(double) * scr);
+    P->fpart = take(sizeof(double) * (size_t)g->fin_nwg * ((size_t)R * R + Rq));
     P->flag = take(sizeof(int) * 4);
     P->gU = take((size_t)u * P->esz);
     P->glam = take(sizeof(double) * S * Rq);
@@ -623,6 +635,7 @@ StateP<T> make_state(char* ws, const Layout& P) {
     st.K1p = (T*)(ws + P.K1p);
     st.K2 = (T*)(ws + P.K2);
     st.lra = (double*)(ws + P.lra);
+    st.fpart = (double*)(ws + P.fpart);
     st.ctrl = (Ctrl*)(ws + P.ctrl);
     return st;
 }
@@ -674,7 +687,7 @@ void run_sweep(concpd_ctx c, const StateP<T>& st) {
             c->ev2.push_back(e[3]);
         }
         cpd::launch_update<T>(g, st, itu[2], (int)c->lists.u[2].size(), 2, R, extrap, c->lists.lds_rows[2], 0, q);
-        cpd::launch_finish<T>(g, st, S, R, q);
+        cpd::launch_finish<T>(g, st, S, R, c->geo.fin_nwg, q);
         return;
     }
     // the second stream (if any) takes the small FP64 kernels
@@ -723,7 +736,7 @@ void run_sweep(concpd_ctx c, const StateP<T>& st) {
     }
     join(5);
     cpd::launch_update<T>(g, st, itu[2], (int)c->lists.u[2].size(), 2, R, extrap, c->lists.lds_rows[2], 0, q);
-    cpd::launch_finish<T>(g, st, S, R, q);
+    cpd::launch_finish<T>(g, st, S, R, c->geo.fin_nwg, q);
 }
 
 // The same sweep with the gradients taken from the Tucker form (Algorithm 2).
@@ -746,7 +759,7 @@ void run_sweep_lra(concpd_ctx c, const StateP<T>& st) {
             cpd::launch_update<T>(g, st, itu[n], (int)c->lists.u[n].size(), n, R, extrap, c->lists.lds_rows[n], 1, q);
         }
         cpd::launch_lra_w<T>(g, st, S, J, 2, 0, 0, q);
-        cpd::launch_finish<T>(g, st, S, R, q);
+        cpd::launch_finish<T>(g, st, S, R, c->geo.fin_nwg, q);
         return;
     }
     cpd::launch_core<T>(g, st, S, R, extrap, q);
@@ -756,7 +769,7 @@ void run_sweep_lra(concpd_ctx c, const StateP<T>& st) {
         cpd::launch_update<T>(g, st, itu[n], (int)c->lists.u[n].size(), n, R, extrap, c->lists.lds_rows[n], 1, q);
         cpd::launch_lra_w<T>(g, st, S, J, n, 0, 0, q);
     }
-    cpd::launch_finish<T>(g, st, S, R, q);
+    cpd::launch_finish<T>(g, st, S, R, c->geo.fin_nwg, q);
 }
 
 // Largest A_s, B_s and I_n of an order-N context (launch grids).
@@ -797,7 +810,7 @@ void run_sweep_nw(concpd_ctx c, const StateP<T>& st) {
         cpd::launch_update<T>(g, st, (const ItemU*)(c->ws + c->lay.itu[n]), (int)c->lists.u[n].size(), n, R, extrap,
                               c->lists.lds_rows[n], 2, q);
     }
-    cpd::launch_finish<T>(g, st, S, R, q);
+    cpd::launch_finish<T>(g, st, S, R, c->geo.fin_nwg, q);
 }
 
 // One sweep: either an accepted iteration, or an extrapolated sweep that the

@@ -722,8 +722,10 @@ __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R
                              part[(3 * 64 + l2) * 4 + v2];
             const int r = 16 * ta + 4 * v2 + (l2 >> 4), c = 16 * tb + (l2 & 15);
             if (r < R && c < R && (ta < tb || r <= c)) {
-                out[r * R + c] = d;
-                out[c * R + r] = d;
+                if (out) {
+                    out[r * R + c] = d;
+                    out[c * R + r] = d;
+                }
                 if (lout) {
                     lout[r * R + c] = d;
                     lout[c * R + r] = d;
@@ -733,7 +735,7 @@ __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R
     __syncthreads();
     if (K != nullptr && tid < R) {
         const double bb = ((bpart[tid] + bpart[64 + tid]) + bpart[128 + tid]) + bpart[192 + tid];
-        bout[tid] = bb;
+        if (bout) bout[tid] = bb;
         if (lbout) lbout[tid] = bb;
     }
     __syncthreads();
