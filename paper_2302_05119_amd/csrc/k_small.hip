@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
         // this chunk's rows: partial Gram and b into LDS, then to the block's
         // partial slots
         const int r0 = chunk * CPD_FIN_ROWS, nr = min(CPD_FIN_ROWS, In - r0);
-        block_gram<T, 8>(st.U[0] + g->uoff[N - 1][s] + (long long)r0 * Rq, nr, R, Rq, nullptr, st.K3 + g->koff[s] + (long long)r0 * Rq,
+        block_gram<T, 8, 32>(st.U[0] + g->uoff[N - 1][s] + (long long)r0 * Rq, nr, R, Rq, nullptr, st.K3 + g->koff[s] + (long long)r0 * Rq,
                          nullptr, smraw, V2l, bl);
         double* fp = st.fpart + (long long)blockIdx.x * (RR + Rq);
         for (int e = tid; e < RR; e += 256) store_agent(&fp[e], V2l[e]);

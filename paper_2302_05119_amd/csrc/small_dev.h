@@ -643,7 +643,7 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
 // added in fixed order through LDS (lds: 256 + 256 doubles).  Only the upper
 // triangle is formed and mirrored.  lout / lbout (optional, LDS): copies of V
 // (row stride R) and b for the caller.
-template <typename T, int GB = 8>
+template <typename T, int GB = 8, int BB = (GB >= 16 ? 32 : 8)>
 __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R, int Rq, double* __restrict__ out,
                                            const T* __restrict__ K, double* __restrict__ bout, char* lds,
                                            double* __restrict__ lout = nullptr, double* __restrict__ lbout = nullptr) {
@@ -687,10 +687,9 @@ __device__ __forceinline__ void block_gram(const T* __restrict__ U, int I, int R
         }
     }
     // b = colsum(K ⊛ U): column c = lane, rows of phase wave in ascending
-    // order, 32 rows (64 loads) in flight with the deep batches, else 8
+    // order, BB rows (2 BB loads) in flight: 32 with the deep batches, else 8
     double bacc = 0.0;
     if (K != nullptr) {
-        constexpr int BB = GB >= 16 ? 32 : 8;
         const int lc = min(lane, R - 1);
         for (int i0 = wv; i0 < I; i0 += 4 * BB) {
             T kv[BB], uv[BB];
