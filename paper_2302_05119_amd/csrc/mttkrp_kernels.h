@@ -320,9 +320,6 @@ __device__ __forceinline__ void load_cols(const float* __restrict__ p, float (&b
     }
 }
 
-#ifndef CPD_P1D_CBY
-#define CPD_P1D_CBY 32   // bytes of each tensor row per chunk
-#endif
 #ifndef CPD_P1D_NSTG
 #define CPD_P1D_NSTG 3   // LDS stages per wavefront (NSTG - 1 chunks in flight)
 #endif
@@ -330,14 +327,14 @@ template <typename TM, int RT>
 struct P1D {
     typedef typename Raw<TM>::type TR;
     static constexpr int NSTG = CPD_P1D_NSTG;
-    static constexpr int KC = CPD_P1D_CBY / (int)sizeof(TR);       // i3 values per chunk
-    static constexpr int NA = CPD_P1D_CBY / 16;                     // tensor DMAs per chunk
+    static constexpr int KC = 16;                                   // i3 values per chunk
+    static constexpr int NA = KC * (int)sizeof(TR) / 16;            // tensor DMAs per chunk
     static constexpr int UBY = KC * 4 * RT * 4;                     // U3 bytes per chunk (FP32 factors)
     static constexpr int NUF = UBY / 1024;                          // full U3 DMAs
     static constexpr int NUL = (UBY % 1024) / 16;                   // lanes of the last, partial one
     static constexpr int NU = NUF + (NUL > 0 ? 1 : 0);              // U3 DMAs per chunk
-    static constexpr int ABY = 64 * CPD_P1D_CBY;                    // tensor bytes per chunk
-    static constexpr int CBYTES = CPD_P1D_CBY;                      // bytes of a row per chunk
+    static constexpr int CBYTES = KC * (int)sizeof(TR);             // bytes of a row per chunk
+    static constexpr int ABY = 64 * CBYTES;                         // tensor bytes per chunk
     static constexpr int STG = ABY + UBY;                           // one stage (16-byte multiple)
     static constexpr int RING = NSTG * STG;                         // one wavefront's ring
     static constexpr int WAVE = RING > RT * 1024 ? RING : RT * 1024; // its LDS (ring, or P > 1 partials)
