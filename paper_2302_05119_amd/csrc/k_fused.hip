@@ -28,8 +28,17 @@ template <> struct FuseWaves<float, 24> { static constexpr int W = 3; };
 
 template <int RT> struct FuseNM { static constexpr int NM = nmax_class(4 * RT); };
 
+// Wavefronts per SIMD of the core update + pass 1 launch: the core code sets
+// the register count, and with it the occupancy of the pass wavefronts.  Up to
+// R = 20 on an FP32 tensor three fit, with a few core values spilled (C2's
+// fused launch: 28 -> 24.5 us); wider tiles, FP64 and the 16-bit DMA path
+// (its BF16 operand split) keep two.
+template <typename TM, int RT> struct FusePass1Waves {
+    static constexpr int W = (std::is_same<TM, float>::value && RT <= 5) ? 3 : 2;
+};
+
 template <typename TM, typename T, int RT, int DMA>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_core_pass1(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusePass1Waves<TM, RT>::W))) void k_core_pass1(
     const Geo* __restrict__ g, StateP<T> st, const ItemP1* __restrict__ items, int nitems, int P, int slot, int extrapolate,
     int S, int nsmall) {
     if (st.ctrl->stop) return;
