@@ -111,19 +111,39 @@ __global__ __launch_bounds__(256) void k_finish(const Geo* __restrict__ g, State
         __syncthreads();
         if (!lastblk) return;
         if (tid == 0) c->blkcnt[s] = 0u;
-        // the block's Gram and b: the chunks' partials in chunk order
+        // the block's Gram and b: the chunks' partials added in chunk order,
+        // QB chunks of loads in flight per step (clamped addresses); thread e
+        // holds Gram entries e, e + 256, ... and entry RR + e of b (e < R)
         const double* fb0 = st.fpart + (long long)g->fin_c0[s] * (RR + Rq);
-        for (int e = tid; e < RR; e += 256) {
-            double a = 0.0;
-            for (int q = 0; q < nc; ++q) a += load_agent(&fb0[(long long)q * (RR + Rq) + e]);
-            V2l[e] = a;
-            V2[e] = a;
+        constexpr int EG = EP + 1, QB = EP <= 4 ? 8 : 4;
+        double a[EG];
+#pragma unroll
+        for (int p = 0; p < EG; ++p) a[p] = 0.0;
+        for (int q0 = 0; q0 < nc; q0 += QB) {
+            double v[EG][QB];
+#pragma unroll
+            for (int p = 0; p < EG; ++p) {
+                const int e = (p < EP) ? min(tid + 256 * p, RR - 1) : RR + min(tid, R - 1);
+#pragma unroll
+                for (int j = 0; j < QB; ++j) v[p][j] = load_agent(&fb0[(long long)min(q0 + j, nc - 1) * (RR + Rq) + e]);
+            }
+#pragma unroll
+            for (int p = 0; p < EG; ++p)
+#pragma unroll
+                for (int j = 0; j < QB; ++j)
+                    if (q0 + j < nc) a[p] += v[p][j];
+        }
+#pragma unroll
+        for (int p = 0; p < EP; ++p) {
+            const int e = tid + 256 * p;
+            if (e < RR) {
+                V2l[e] = a[p];
+                V2[e] = a[p];
+            }
         }
         if (tid < R) {
-            double a = 0.0;
-            for (int q = 0; q < nc; ++q) a += load_agent(&fb0[(long long)q * (RR + Rq) + RR + tid]);
-            bl[tid] = a;
-            b[tid] = a;
+            bl[tid] = a[EP];
+            b[tid] = a[EP];
         }
         __syncthreads();
     }
