@@ -51,7 +51,8 @@ struct Geo {
     long long yoff[CPD_MAXS];     // Y^(s) = M^(s) x_3 U^(3,s): I1 x I2 x Rq
     long long koff[CPD_MAXS];     // K^(3,s) buffer (I3 x Rq)
     long long poff[CPD_MAXS];     // mode-3 MTTKRP partials: nchunk x I3 x Rq
-    int nchunk[CPD_MAXS];
+    int nchunk[CPD_MAXS];         // ceil(I1 / (4 p2spw))
+    int p2spw;                    // i1 slabs per pass-2 wavefront (a chunk is 4 p2spw slabs)
     long long aoff[3][CPD_MAXS];  // Tucker bases A_n^(s): I_n x J_n (double)
     long long goff[CPD_MAXS];     // Tucker cores G^(s): J1 x J2 x J3 (double), i3 fastest
     long long woff[3][CPD_MAXS];  // W_n^(s) = A_n^T U^(n): J_n x Rq (double)
@@ -114,7 +115,7 @@ struct StateP {
 
 // Work items of the grouped kernels (host-built lists, one entry per workgroup).
 struct ItemP1 { int s, i1, rg, pad; };              // pass 1: block (< 0: empty), slab, 64-row group
-struct ItemP2 { int s, chunk, q0, pad; };           // pass 2: block, 4-slab chunk, i3 start
+struct ItemP2 { int s, chunk, q0, pad; };           // pass 2: block, chunk of 4 p2spw slabs, i3 start
 // update: rows [row0, row0+nrows) of blocks [s0, s0+ns) (ns > 0, columns
 // individual), or of the -ns blocks of the mode's coupling group (ns < 0)
 struct ItemU  { int s0, ns, row0, nrows; }; 
@@ -128,12 +129,12 @@ template <typename T> void launch_core(const Geo* g, const StateP<T>& st, int S,
 // fused launches (R x R work beside independent MTTKRP work); false when R > 32
 template <typename T> bool launch_core_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int P, int R, int slot, int mdtype, int dma, int extrap, int S, hipStream_t q);
 template <typename T> bool launch_prep_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int R, int slot, int S, hipStream_t q);
-template <typename T> bool launch_prep_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int R, int slot, int mdtype, int maxI2, int S, hipStream_t q);
+template <typename T> bool launch_prep_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int R, int slot, int mdtype, int maxI2, int spw, int S, hipStream_t q);
 template <typename T> void launch_prep(const Geo* g, const StateP<T>& st, int S, int R, int n, hipStream_t q);
 template <typename T> void launch_finish(const Geo* g, const StateP<T>& st, int S, int R, int nwg, hipStream_t q);
 template <typename T> void launch_init_stats(const Geo* g, const StateP<T>& st, int S, int R, hipStream_t q);
 template <typename T> void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int nitems, int P, int Rq, int slot, int mdtype, int dma, hipStream_t q);
-template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int mdtype, int maxI2, hipStream_t q);
+template <typename T> void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int mdtype, int maxI2, int spw, hipStream_t q);
 template <typename T> void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitems, int slot, hipStream_t q);
 // ksrc: 0 the order-3 pass outputs, 1 the Tucker form, 2 the plain K buffer (order N > 3)
 template <typename T> void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int nitems, int n, int R, int extrap, int lds_rows, int ksrc, hipStream_t q);

@@ -178,8 +178,9 @@ static void prep_pass2_disp(int R, int maxI2, dim3 grid, hipStream_t q, const Ge
 
 template <typename T>
 bool launch_prep_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int R, int slot, int mdtype, int maxI2,
-                       int S, hipStream_t q) {
-    if (R > 32 || nitems <= 0) return false;
+                       int spw, int S, hipStream_t q) {
+    // one i1 slab per wavefront only (the fused launch shares its registers)
+    if (R > 32 || nitems <= 0 || spw != 1) return false;
     const int ns = small_wgs(S);
     const dim3 grid(ns + nitems);
     if constexpr (std::is_same<T, double>::value) {
@@ -196,7 +197,7 @@ bool launch_prep_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, i
     template bool launch_core_pass1<T>(const Geo*, const StateP<T>&, const ItemP1*, int, int, int, int, int, int, int, int, \
                                        hipStream_t);                                                                       \
     template bool launch_prep_k2<T>(const Geo*, const StateP<T>&, const ItemK2*, int, int, int, int, hipStream_t);          \
-    template bool launch_prep_pass2<T>(const Geo*, const StateP<T>&, const ItemP2*, int, int, int, int, int, int, hipStream_t);
+    template bool launch_prep_pass2<T>(const Geo*, const StateP<T>&, const ItemP2*, int, int, int, int, int, int, int, hipStream_t);
 CPD_INST_FUSED(float)
 CPD_INST_FUSED(double)
 

@@ -32,11 +32,11 @@ static void pass1d_rt(int RT, dim3 grid, hipStream_t q, const Geo* g, const Stat
     }
 #undef CPD_P1D
 }
-template <typename TM, typename T, bool BLDS>
+template <typename TM, typename T, bool BLDS, int SPW>
 static void pass2_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g, const StateP<T>& st, const ItemP2* items,
                      int slot) {
 #define CPD_P2(RTV) \
-    case RTV: hipLaunchKernelGGL((k_pass2<TM, T, RTV, BLDS>), grid, dim3(256), lds, q, g, st, items, slot); break;
+    case RTV: hipLaunchKernelGGL((k_pass2<TM, T, RTV, BLDS, SPW>), grid, dim3(256), lds, q, g, st, items, slot); break;
     switch (RT) {
         CPD_P2(1) CPD_P2(2) CPD_P2(3) CPD_P2(4) CPD_P2(5) CPD_P2(6) CPD_P2(7) CPD_P2(8)
         CPD_P2(9) CPD_P2(10) CPD_P2(11) CPD_P2(12) CPD_P2(13) CPD_P2(14) CPD_P2(15) CPD_P2(16)
@@ -45,13 +45,22 @@ static void pass2_rt(int RT, dim3 grid, size_t lds, hipStream_t q, const Geo* g,
 #undef CPD_P2
 }
 
+// spw: i1 slabs per wavefront, as the context's work list was built (two
+// only on FP32/16-bit tensors)
 template <typename TM, typename T>
-static void pass2_dispatch(int Rq, dim3 grid, int maxI2, hipStream_t q, const Geo* g, const StateP<T>& st,
+static void pass2_dispatch(int Rq, dim3 grid, int maxI2, int spw, hipStream_t q, const Geo* g, const StateP<T>& st,
                            const ItemP2* items, int slot) {
     bool blds = true;
     const size_t lds = pass2_lds<TM>(Rq, maxI2, &blds);
-    if (blds) pass2_rt<TM, T, true>(Rq / 4, grid, lds, q, g, st, items, slot);
-    else pass2_rt<TM, T, false>(Rq / 4, grid, lds, q, g, st, items, slot);
+    if constexpr (!std::is_same<T, double>::value) {
+        if (spw == 2) {
+            if (blds) pass2_rt<TM, T, true, 2>(Rq / 4, grid, lds, q, g, st, items, slot);
+            else pass2_rt<TM, T, false, 2>(Rq / 4, grid, lds, q, g, st, items, slot);
+            return;
+        }
+    }
+    if (blds) pass2_rt<TM, T, true, 1>(Rq / 4, grid, lds, q, g, st, items, slot);
+    else pass2_rt<TM, T, false, 1>(Rq / 4, grid, lds, q, g, st, items, slot);
 }
 
 template <typename T>
@@ -78,15 +87,15 @@ void launch_pass1(const Geo* g, const StateP<T>& st, const ItemP1* items, int ni
 
 template <typename T>
 void launch_pass2(const Geo* g, const StateP<T>& st, const ItemP2* items, int nitems, int Rq, int slot, int mdtype, int maxI2,
-                  hipStream_t q) {
+                  int spw, hipStream_t q) {
     if (nitems <= 0) return;
     const dim3 grid(nitems);
     if constexpr (std::is_same<T, double>::value) {
-        pass2_dispatch<double, double>(Rq, grid, maxI2, q, g, st, items, slot);
+        pass2_dispatch<double, double>(Rq, grid, maxI2, spw, q, g, st, items, slot);
     } else {
-        if (mdtype == 1) pass2_dispatch<float, float>(Rq, grid, maxI2, q, g, st, items, slot);
-        else if (mdtype == 2) pass2_dispatch<__hip_bfloat16, float>(Rq, grid, maxI2, q, g, st, items, slot);
-        else pass2_dispatch<__half, float>(Rq, grid, maxI2, q, g, st, items, slot);
+        if (mdtype == 1) pass2_dispatch<float, float>(Rq, grid, maxI2, spw, q, g, st, items, slot);
+        else if (mdtype == 2) pass2_dispatch<__hip_bfloat16, float>(Rq, grid, maxI2, spw, q, g, st, items, slot);
+        else pass2_dispatch<__half, float>(Rq, grid, maxI2, spw, q, g, st, items, slot);
     }
 }
 
@@ -98,8 +107,8 @@ void launch_k2(const Geo* g, const StateP<T>& st, const ItemK2* items, int nitem
 
 template void launch_pass1<float>(const Geo*, const StateP<float>&, const ItemP1*, int, int, int, int, int, int, hipStream_t);
 template void launch_pass1<double>(const Geo*, const StateP<double>&, const ItemP1*, int, int, int, int, int, int, hipStream_t);
-template void launch_pass2<float>(const Geo*, const StateP<float>&, const ItemP2*, int, int, int, int, int, hipStream_t);
-template void launch_pass2<double>(const Geo*, const StateP<double>&, const ItemP2*, int, int, int, int, int, hipStream_t);
+template void launch_pass2<float>(const Geo*, const StateP<float>&, const ItemP2*, int, int, int, int, int, int, hipStream_t);
+template void launch_pass2<double>(const Geo*, const StateP<double>&, const ItemP2*, int, int, int, int, int, int, hipStream_t);
 template void launch_k2<float>(const Geo*, const StateP<float>&, const ItemK2*, int, int, hipStream_t);
 template void launch_k2<double>(const Geo*, const StateP<double>&, const ItemK2*, int, int, hipStream_t);
 

@@ -566,7 +566,7 @@ constexpr int p2_chunk_rows() {
     return (32768 / (4 * RTP * (int)sizeof(TA))) / 16 * 16;
 }
 
-template <typename TM, typename T, int RT, bool BLDS>
+template <typename TM, typename T, int RT, bool BLDS, int SPW = 1>
 __device__ __forceinline__ void pass2_item(const Geo* __restrict__ g, StateP<T> st, const ItemP2* __restrict__ items,
                                                int slot, int bid) {
     typedef typename AccType<TM>::type TA;
@@ -575,162 +575,183 @@ __device__ __forceinline__ void pass2_item(const Geo* __restrict__ g, StateP<T> 
     const int s = it.s, chunk = it.chunk, q0 = it.q0;
     const int I1 = g->I[s][0], I2 = g->I[s][1], I3 = g->I[s][2], Rq = g->Rq;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i1 = chunk * 4 + wave;
     const int i3 = q0 + lane;
     const bool valid = i3 < I3;
     TA* sm = (TA*)smraw;
     constexpr int VA = 16 / (int)sizeof(TA);          // operand elements per 16-byte LDS read
     constexpr int RTP = (RT + VA - 1) / VA * VA;      // padded operand run per lane
     const CPD_GLOBAL T* __restrict__ U2g = gptr(pick3(st.U, slot) + g->uoff[1][s]);
-    // U1 row of this slab (the scale of the mode-3 partial), loaded now
-    TA u1v[RT];
-    {
-        const CPD_GLOBAL T* __restrict__ U1 =
-            gptr(pick3(st.U, slot) + g->uoff[0][s] + (long long)min(i1, I1 - 1) * Rq + (lane & 3));
-#pragma unroll
-        for (int t = 0; t < RT; ++t) u1v[t] = (TA)U1[4 * t];
-    }
-    Acc4<TA> z[RT];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) z[t].zero();
-    constexpr int NB = 16;
-    // the first NB rows of the slab are requested before the U2 staging, so
-    // their latency overlaps it (clamped, always valid addresses; zeros
-    // outside the slab)
     typedef typename Raw<TM>::type TR;
-    const bool live = i1 < I1;
     const long long ldm = g->mld[s];   // operand row stride (>= I3)
-    const CPD_GLOBAL TR* __restrict__ Mp =
-        gptr((const TR*)g->M[s] + (long long)min(i1, I1 - 1) * I2 * ldm + (valid ? i3 : 0));
-    TA cur[NB], nxt[NB];
+    // a chunk is 4 SPW slabs of i1 (SPW is the context's p2spw); wavefront w
+    // takes slabs 4 (SPW chunk + k) + w, k < SPW, one after another, and adds
+    // their scaled partials in k order (U2 is staged once when it fits LDS
+    // whole)
+    constexpr int spw = SPW;
+    Acc4<TA> z[RT];
+    TA zt[RT][4];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const TA v = cvt<TA, TM>(Mp[(long long)min(j, I2 - 1) * ldm]);
-        cur[j] = (live && valid && j < I2) ? v : (TA)0;
-    }
-    // U2 rows [c0, c1) transposed into LDS so that lane l's operands
-    // U2[i2][4t + l%4], t < RT, are one contiguous run: [rows][4][RTP]
-    // (eight loads per thread in flight per step, clamped addresses)
-    auto stage_u2 = [&](int c0, int c1) {
-        const int nu = (c1 - c0) * Rq;
-        const CPD_GLOBAL T* __restrict__ src = U2g + (long long)c0 * Rq;
-        for (int e0 = threadIdx.x; e0 < nu; e0 += 256 * 8) {
-            T v[8];
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = src[min(e0 + 256 * j, nu - 1)];
+        for (int v = 0; v < 4; ++v) zt[t][v] = (TA)0;
+    for (int k = 0; k < spw; ++k) {
+        const int i1 = (chunk * spw + k) * 4 + wave;
+        const bool restage = !BLDS || k == 0;
+        // U1 row of this slab (the scale of the mode-3 partial), loaded now
+        TA u1v[RT];
+        {
+            const CPD_GLOBAL T* __restrict__ U1 =
+                gptr(pick3(st.U, slot) + g->uoff[0][s] + (long long)min(i1, I1 - 1) * Rq + (lane & 3));
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int e = e0 + 256 * j;
-                if (e < nu) {
-                    const int r = e / Rq, c = e % Rq;
-                    sm[(r * 4 + (c & 3)) * RTP + (c >> 2)] = (TA)v[j];
-                }
-            }
+            for (int t = 0; t < RT; ++t) u1v[t] = (TA)U1[4 * t];
         }
-    };
-    constexpr int CHR = BLDS ? (1 << 30) : p2_chunk_rows<TA, RT>();
-    static_assert(CHR % NB == 0, "U2 chunks must hold whole NB-row groups");
-    if constexpr (std::is_same<TM, __hip_bfloat16>::value) {
-        // BF16 matrix cores: four consecutive i2 rows of a lane's tensor column
-        // form the A operand of v_mfma_f32_4x4x4_16b_bf16; U2 is staged as hi
-        // and lo BF16 parts, [group of 4 rows][lane class j][tile t][4 rows]
-        // (column 4t + j), rows past I2 zero.  Tensor loads are never masked
-        // (clamped addresses, finite values): a row past I2 meets zero U2
-        // operands, and a lane past I3 only feeds its own output row, which is
-        // never stored
-        unsigned short cb[NB], nb[NB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) cb[j] = Mp[(long long)min(j, I2 - 1) * ldm];
-        unsigned short* hb = (unsigned short*)smraw;
-        for (int c0 = 0; c0 < I2; c0 += CHR) {
-            const int c1 = min(I2, c0 + CHR), nr = c1 - c0, nr4 = (nr + 3) & ~3;
-            unsigned short* lb = hb + nr4 * Rq;
-            __syncthreads();
-            {
-                const int nu = nr4 * Rq;
-                const CPD_GLOBAL T* __restrict__ src = U2g + (long long)c0 * Rq;
-                for (int e0 = threadIdx.x; e0 < nu; e0 += 256 * 8) {
-                    T v[8];
+        for (int t = 0; t < RT; ++t) z[t].zero();
+        constexpr int NB = 16;
+        // the first NB rows of the slab are requested before the U2 staging, so
+        // their latency overlaps it (clamped, always valid addresses; zeros
+        // outside the slab)
+        const bool live = i1 < I1;
+        const CPD_GLOBAL TR* __restrict__ Mp =
+            gptr((const TR*)g->M[s] + (long long)min(i1, I1 - 1) * I2 * ldm + (valid ? i3 : 0));
+        TA cur[NB], nxt[NB];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) v[j] = src[min(e0 + 256 * j, nr * Rq - 1)];
+        for (int j = 0; j < NB; ++j) {
+            const TA v = cvt<TA, TM>(Mp[(long long)min(j, I2 - 1) * ldm]);
+            cur[j] = (live && valid && j < I2) ? v : (TA)0;
+        }
+        // U2 rows [c0, c1) transposed into LDS so that lane l's operands
+        // U2[i2][4t + l%4], t < RT, are one contiguous run: [rows][4][RTP]
+        // (eight loads per thread in flight per step, clamped addresses)
+        auto stage_u2 = [&](int c0, int c1) {
+            const int nu = (c1 - c0) * Rq;
+            const CPD_GLOBAL T* __restrict__ src = U2g + (long long)c0 * Rq;
+            for (int e0 = threadIdx.x; e0 < nu; e0 += 256 * 8) {
+                T v[8];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int e = e0 + 256 * j;
-                        if (e < nu) {
-                            const int r = e / Rq, c = e % Rq;
-                            const int o = (((r >> 2) * 4 + (c & 3)) * RT + (c >> 2)) * 4 + (r & 3);
-                            unsigned short h = 0, l = 0;
-                            if (r < nr) split_bf16((float)v[j], h, l);
-                            hb[o] = h;
-                            lb[o] = l;
-                        }
+                for (int j = 0; j < 8; ++j) v[j] = src[min(e0 + 256 * j, nu - 1)];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int e = e0 + 256 * j;
+                    if (e < nu) {
+                        const int r = e / Rq, c = e % Rq;
+                        sm[(r * 4 + (c & 3)) * RTP + (c >> 2)] = (TA)v[j];
                     }
                 }
             }
-            __syncthreads();
+        };
+        constexpr int CHR = BLDS ? (1 << 30) : p2_chunk_rows<TA, RT>();
+        static_assert(CHR % NB == 0, "U2 chunks must hold whole NB-row groups");
+        if constexpr (std::is_same<TM, __hip_bfloat16>::value) {
+            // BF16 matrix cores: four consecutive i2 rows of a lane's tensor column
+            // form the A operand of v_mfma_f32_4x4x4_16b_bf16; U2 is staged as hi
+            // and lo BF16 parts, [group of 4 rows][lane class j][tile t][4 rows]
+            // (column 4t + j), rows past I2 zero.  Tensor loads are never masked
+            // (clamped addresses, finite values): a row past I2 meets zero U2
+            // operands, and a lane past I3 only feeds its own output row, which is
+            // never stored
+            unsigned short cb[NB], nb[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) cb[j] = Mp[(long long)min(j, I2 - 1) * ldm];
+            unsigned short* hb = (unsigned short*)smraw;
+            for (int c0 = 0; c0 < I2; c0 += CHR) {
+                const int c1 = min(I2, c0 + CHR), nr = c1 - c0, nr4 = (nr + 3) & ~3;
+                unsigned short* lb = hb + nr4 * Rq;
+                if (restage) {
+                    __syncthreads();
+                    const int nu = nr4 * Rq;
+                    const CPD_GLOBAL T* __restrict__ src = U2g + (long long)c0 * Rq;
+                    for (int e0 = threadIdx.x; e0 < nu; e0 += 256 * 8) {
+                        T v[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) v[j] = src[min(e0 + 256 * j, nr * Rq - 1)];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int e = e0 + 256 * j;
+                            if (e < nu) {
+                                const int r = e / Rq, c = e % Rq;
+                                const int o = (((r >> 2) * 4 + (c & 3)) * RT + (c >> 2)) * 4 + (r & 3);
+                                unsigned short h = 0, l = 0;
+                                if (r < nr) split_bf16((float)v[j], h, l);
+                                hb[o] = h;
+                                lb[o] = l;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+                if (live) {
+                    for (int i2b = c0; i2b < c1; i2b += NB) {
+                        const int nb2 = i2b + NB;
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) nb[j] = Mp[(long long)min(nb2 + j, I2 - 1) * ldm];
+                        const int jm = min(NB, I2 - i2b);
+#pragma unroll
+                        for (int gg = 0; gg < NB / 4; ++gg) {
+                            if (4 * gg < jm) {
+                                v4i16 a;
+                                *(unsigned long long*)&a = (unsigned long long)cb[4 * gg] | ((unsigned long long)cb[4 * gg + 1] << 16) |
+                                                           ((unsigned long long)cb[4 * gg + 2] << 32) |
+                                                           ((unsigned long long)cb[4 * gg + 3] << 48);
+                                const int gk = (i2b - c0) / 4 + gg;
+                                const v4i16* bh = (const v4i16*)(hb + (gk * 4 + (lane & 3)) * RT * 4);
+                                const v4i16* bl = (const v4i16*)(lb + (gk * 4 + (lane & 3)) * RT * 4);
+#pragma unroll
+                                for (int t = 0; t < RT; ++t) {
+                                    z[t].mma_bf16(a, bh[t]);
+                                    z[t].mma_bf16(a, bl[t]);
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) cb[j] = nb[j];
+                    }
+                }
+            }
+        } else
+        for (int c0 = 0; c0 < I2; c0 += CHR) {
+            const int c1 = min(I2, c0 + CHR);
+            // every wavefront of the workgroup stages and waits (also those past I1)
+            if (restage) {
+                __syncthreads();
+                stage_u2(c0, c1);
+                __syncthreads();
+            }
             if (live) {
                 for (int i2b = c0; i2b < c1; i2b += NB) {
                     const int nb2 = i2b + NB;
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) nb[j] = Mp[(long long)min(nb2 + j, I2 - 1) * ldm];
+                    for (int j = 0; j < NB; ++j) {
+                        const TA v = cvt<TA, TM>(Mp[(long long)min(nb2 + j, I2 - 1) * ldm]);
+                        nxt[j] = (valid && nb2 + j < I2) ? v : (TA)0;
+                    }
                     const int jm = min(NB, I2 - i2b);
 #pragma unroll
-                    for (int gg = 0; gg < NB / 4; ++gg) {
-                        if (4 * gg < jm) {
-                            v4i16 a;
-                            *(unsigned long long*)&a = (unsigned long long)cb[4 * gg] | ((unsigned long long)cb[4 * gg + 1] << 16) |
-                                                       ((unsigned long long)cb[4 * gg + 2] << 32) |
-                                                       ((unsigned long long)cb[4 * gg + 3] << 48);
-                            const int gk = (i2b - c0) / 4 + gg;
-                            const v4i16* bh = (const v4i16*)(hb + (gk * 4 + (lane & 3)) * RT * 4);
-                            const v4i16* bl = (const v4i16*)(lb + (gk * 4 + (lane & 3)) * RT * 4);
+                    for (int j = 0; j < NB; ++j) {
+                        if (j < jm) {
+                            const TA* ur = sm + ((i2b - c0 + j) * 4 + (lane & 3)) * RTP;
+                            TA bb[RTP];
 #pragma unroll
-                            for (int t = 0; t < RT; ++t) {
-                                z[t].mma_bf16(a, bh[t]);
-                                z[t].mma_bf16(a, bl[t]);
-                            }
+                            for (int v = 0; v < RTP / VA; ++v) *(u32x4*)&bb[v * VA] = *(const u32x4*)(ur + v * VA);
+#pragma unroll
+                            for (int t = 0; t < RT; ++t) z[t].mma(cur[j], bb[t]);
                         }
                     }
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) cb[j] = nb[j];
+                    for (int j = 0; j < NB; ++j) cur[j] = nxt[j];
                 }
             }
         }
-    } else
-    for (int c0 = 0; c0 < I2; c0 += CHR) {
-        const int c1 = min(I2, c0 + CHR);
-        // every wavefront of the workgroup stages and waits (also those past I1)
-        __syncthreads();
-        stage_u2(c0, c1);
-        __syncthreads();
         if (live) {
-            for (int i2b = c0; i2b < c1; i2b += NB) {
-                const int nb2 = i2b + NB;
 #pragma unroll
-                for (int j = 0; j < NB; ++j) {
-                    const TA v = cvt<TA, TM>(Mp[(long long)min(nb2 + j, I2 - 1) * ldm]);
-                    nxt[j] = (valid && nb2 + j < I2) ? v : (TA)0;
-                }
-                const int jm = min(NB, I2 - i2b);
-#pragma unroll
-                for (int j = 0; j < NB; ++j) {
-                    if (j < jm) {
-                        const TA* ur = sm + ((i2b - c0 + j) * 4 + (lane & 3)) * RTP;
-                        TA bb[RTP];
-#pragma unroll
-                        for (int v = 0; v < RTP / VA; ++v) *(u32x4*)&bb[v * VA] = *(const u32x4*)(ur + v * VA);
-#pragma unroll
-                        for (int t = 0; t < RT; ++t) z[t].mma(cur[j], bb[t]);
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < NB; ++j) cur[j] = nxt[j];
-            }
+            for (int t = 0; t < RT; ++t) z[t].scale(u1v[t]);
         }
-    }
-    if (live) {
+        if constexpr (SPW > 1) {
 #pragma unroll
-        for (int t = 0; t < RT; ++t) z[t].scale(u1v[t]);
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) zt[t][v] += z[t].get(v);
+        }
     }
     __syncthreads();
     TA* red = sm;  // [4 waves][64][Rq]
@@ -738,7 +759,7 @@ __device__ __forceinline__ void pass2_item(const Geo* __restrict__ g, StateP<T> 
     for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            red[(wave * 64 + 4 * (lane >> 2) + v) * Rq + 4 * t + (lane & 3)] = z[t].get(v);
+            red[(wave * 64 + 4 * (lane >> 2) + v) * Rq + 4 * t + (lane & 3)] = SPW > 1 ? zt[t][v] : z[t].get(v);
     __syncthreads();
     const int nq = min(64, I3 - q0);
     CPD_GLOBAL T* __restrict__ out = gptr_w(st.part + g->poff[s] + ((long long)chunk * I3 + q0) * Rq);
@@ -750,11 +771,11 @@ __device__ __forceinline__ void pass2_item(const Geo* __restrict__ g, StateP<T> 
     }
 }
 
-template <typename TM, typename T, int RT, bool BLDS>
+template <typename TM, typename T, int RT, bool BLDS, int SPW>
 __global__ __launch_bounds__(256) void k_pass2(const Geo* __restrict__ g, StateP<T> st, const ItemP2* __restrict__ items, int slot) {
     if (st.ctrl->stop) return;
     apply_rot(st);
-    pass2_item<TM, T, RT, BLDS>(g, st, items, slot, blockIdx.x);
+    pass2_item<TM, T, RT, BLDS, SPW>(g, st, items, slot, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

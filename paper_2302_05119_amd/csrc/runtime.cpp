@@ -242,6 +242,25 @@ void nw_plan(const concpd_config* c, NwPlan* P) {
     }
 }
 
+// i1 slabs per pass-2 wavefront (a pass-2 workgroup takes 4 p2_slabs slabs):
+// two when that still leaves at least 2048 workgroups (eight per compute
+// unit) and every block's U^(2) is short enough to be staged once (I2 <= 128),
+// which halves the mode-3 partials and the U^(2) staging per tensor byte; else
+// one (always one for FP64 operands).  CONCPD_P2_SLABS=1 or 2 overrides the
+// choice (measurements).
+int p2_slabs(const concpd_config* c) {
+    if (c->order != 3 || c->compute_dtype == CONCPD_F64) return 1;
+    const char* ev = getenv("CONCPD_P2_SLABS");
+    if (ev && (ev[0] == '1' || ev[0] == '2') && ev[1] == 0) return ev[0] - '0';
+    long long wg = 0;
+    for (int s = 0; s < c->num_blocks; ++s) {
+        const long long I1 = c->dims[3 * s], I2 = c->dims[3 * s + 1], I3 = c->dims[3 * s + 2];
+        if (I2 > 128) return 1;
+        wg += ((I1 + 7) / 8) * ((I3 + 63) / 64);
+    }
+    return wg >= 2048 ? 2 : 1;
+}
+
 void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAULT, int p1split = 0) {
     const int S = c->num_blocks, R = c->rank, Rq = (R + 3) / 4 * 4, N = c->order;
     L->p1.clear();
@@ -266,6 +285,7 @@ void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAU
         xcd_order(L->nb, 4);
     }
     // the two-pass MTTKRP work lists exist at order 3 only
+    const int spw = p2_slabs(c);
     for (int s = 0; s < S && N == 3; ++s) {
         const int I1 = (int)c->dims[3 * s], I2 = (int)c->dims[3 * s + 1], I3 = (int)c->dims[3 * s + 2];
         L->maxI2 = std::max(L->maxI2, I2);
@@ -273,7 +293,7 @@ void build_lists(const concpd_config* c, Lists* L, int k2rows = CPD_K2ROWS_DEFAU
             for (long long c0 = 0; c0 < (long long)I2 * Rq; c0 += 256) L->k2.push_back({s, (int)c0, ch, 0});
         for (int i1 = 0; i1 < I1; ++i1)
             for (int rg = 0; rg * 64 < I2; ++rg) L->p1.push_back({s, i1, rg, 0});
-        for (int ch = 0; ch * 4 < I1; ++ch)
+        for (int ch = 0; ch * 4 * spw < I1; ++ch)
             for (int q0 = 0; q0 < I3; q0 += 64) L->p2.push_back({s, ch, q0, 0});
     }
     // pass 1: the smallest split P of i3 over wavefronts that gives at least
@@ -380,6 +400,7 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
             p += std::max(W.A[s], W.B[s]) * Rq;
         }
     }
+    g->p2spw = p2_slabs(c);
     for (int s = 0; s < S && N == 3; ++s) {
         const long long I1 = c->dims[3 * s], I2 = c->dims[3 * s + 1], I3 = c->dims[3 * s + 2];
         for (int n = 0; n < 3; ++n) g->I[s][n] = (int)c->dims[3 * s + n];
@@ -387,7 +408,7 @@ void plan(const concpd_config* c, const Lists& L, Layout* P, Geo* g) {
         y += I1 * I2 * Rq;
         g->koff[s] = k;
         k += I3 * Rq;
-        g->nchunk[s] = (int)((I1 + 3) / 4);
+        g->nchunk[s] = (int)((I1 + 4 * g->p2spw - 1) / (4 * g->p2spw));
         g->poff[s] = p;
         p += g->nchunk[s] * I3 * Rq;
         g->nrg[s] = (int)((I2 + 63) / 64);
@@ -675,9 +696,9 @@ void run_sweep(concpd_ctx c, const StateP<T>& st) {
         cpd::launch_update<T>(g, st, itu[1], (int)c->lists.u[1].size(), 1, R, extrap, c->lists.lds_rows[1], 0, q);
         if (prof) (void)hipEventRecord(e[2], q);
         for (int rep = 0; rep < (prof ? CPD_PROF_REPS : 1); ++rep)
-            if (!cpd::launch_prep_pass2<T>(g, st, it2, (int)c->lists.p2.size(), R, 0, c->mdtype, c->lists.maxI2, S, q)) {
+            if (!cpd::launch_prep_pass2<T>(g, st, it2, (int)c->lists.p2.size(), R, 0, c->mdtype, c->lists.maxI2, c->geo.p2spw, S, q)) {
                 cpd::launch_prep<T>(g, st, S, R, 2, q);
-                cpd::launch_pass2<T>(g, st, it2, (int)c->lists.p2.size(), Rq, 0, c->mdtype, c->lists.maxI2, q);
+                cpd::launch_pass2<T>(g, st, it2, (int)c->lists.p2.size(), Rq, 0, c->mdtype, c->lists.maxI2, c->geo.p2spw, q);
             }
         if (prof) {
             (void)hipEventRecord(e[3], q);
@@ -726,7 +747,7 @@ void run_sweep(concpd_ctx c, const StateP<T>& st) {
     cpd::launch_prep<T>(g, st, S, R, 2, qa);
     if (prof) (void)hipEventRecord(e[2], q);
     for (int rep = 0; rep < (prof ? CPD_PROF_REPS : 1); ++rep)
-        cpd::launch_pass2<T>(g, st, it2, (int)c->lists.p2.size(), Rq, 0, c->mdtype, c->lists.maxI2, q);
+        cpd::launch_pass2<T>(g, st, it2, (int)c->lists.p2.size(), Rq, 0, c->mdtype, c->lists.maxI2, c->geo.p2spw, q);
     if (prof) {
         (void)hipEventRecord(e[3], q);
         c->ev1.push_back(e[0]);
@@ -886,7 +907,7 @@ void recompute_stats(concpd_ctx c, const StateP<T>& st) {
         return;
     }
     const ItemP2* it2 = (const ItemP2*)(c->ws + c->lay.it2);
-    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
+    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->geo.p2spw, c->q);
     for (int s = 0; s < c->S; ++s)
         cpd::launch_extract_k<T>(c->dgeo, st, s, 2, (int)c->dims[3 * s + 2], c->R, st.K3 + c->geo.koff[s], c->Rq, 0, c->q);
     cpd::launch_init_stats<T>(c->dgeo, st, c->S, c->R, c->q);
@@ -1017,7 +1038,7 @@ void debug_passes(concpd_ctx c, const StateP<T>& st) {
     const ItemK2* itk = (const ItemK2*)(c->ws + c->lay.itk2);
     cpd::launch_pass1<T>(c->dgeo, st, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->p1dma, c->q);
     cpd::launch_k2<T>(c->dgeo, st, itk, (int)c->lists.k2.size(), 1, c->q);
-    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
+    cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->geo.p2spw, c->q);
 }
 
 // Loss and gradients at a caller-given point (autograd form): the point is
@@ -1067,7 +1088,7 @@ concpd_status loss_grad_t(concpd_ctx c, const StateP<T>& st, const void* const* 
     const ItemK2* itk = (const ItemK2*)(c->ws + P.itk2);
     cpd::launch_pass1<T>(c->dgeo, sg, it1, (int)c->lists.p1.size(), c->lists.p1_split, c->Rq, 1, c->mdtype, c->p1dma, c->q);
     cpd::launch_k2<T>(c->dgeo, sg, itk, (int)c->lists.k2.size(), 0, c->q);
-    cpd::launch_pass2<T>(c->dgeo, sg, it2, (int)c->lists.p2.size(), c->Rq, 0, c->mdtype, c->lists.maxI2, c->q);
+    cpd::launch_pass2<T>(c->dgeo, sg, it2, (int)c->lists.p2.size(), c->Rq, 0, c->mdtype, c->lists.maxI2, c->geo.p2spw, c->q);
     for (int s = 0; s < c->S; ++s)
         cpd::launch_extract_k<T>(c->dgeo, sg, s, 2, (int)c->dims[3 * s + 2], c->R, sg.K3 + c->geo.koff[s], c->Rq, 0, c->q);
     int In[3] = {1, 1, 1};
@@ -1140,7 +1161,7 @@ concpd_status als_fit_all(concpd_ctx c, const StateP<T>& st, int R, double eps, 
         cpd::launch_als_chol(c->dgeo, S, R, 1, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 1, Imax[1], act, Lfac, c->q);
         cpd::launch_als_gram<T>(c->dgeo, st, S, R, 1, act, V, c->q);
-        cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->q);
+        cpd::launch_pass2<T>(c->dgeo, st, it2, (int)c->lists.p2.size(), c->Rq, 1, c->mdtype, c->lists.maxI2, c->geo.p2spw, c->q);
         k3_sum();
         cpd::launch_als_chol(c->dgeo, S, R, 2, act, V, Lfac, bad, c->q);
         cpd::launch_als_solve<T>(c->dgeo, st, S, R, 2, Imax[2], act, Lfac, c->q);
