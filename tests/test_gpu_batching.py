@@ -134,6 +134,28 @@ def test_p1_dma_and_register_paths_match_oracle(compute, tol):
             assert abs(s["F"] - ref.F) / ref.F <= tol and e <= 10 * tol
 
 
+@pytest.mark.parametrize("compute,tol", [("f32", 1e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("dims", [[(33, 45, 100), (33, 70, 57), (33, 45, 100)], [(17, 800, 30), (17, 45, 77)]])
+def test_pass2_slab_counts_match_oracle(compute, tol, dims, monkeypatch):
+    # one or two i1 slabs per pass-2 wavefront (forced at context creation):
+    # ragged slab chunks (I1 = 33 and 17 against chunks of 4 and 8 slabs),
+    # ragged i3 tiles, and (second case) a U^(2) too long for LDS, which the
+    # two-slab kernel restages for each slab
+    say(f"[options] pass-2 slabs per wavefront, compute={compute}, dims={dims}")
+    L = (3, 0, 0)
+    P = synth.coupled_problem(dims, 8, L, 10.0, 861)
+    U0, lam0 = synth.uniform_init(P.dims, 8, L, 862)
+    ref = apg.run(DenseData(P.tensors), U0, lam0, Options(L=L), iters=2)
+    S = len(dims)
+    for slabs in ("1", "2"):
+        monkeypatch.setenv("CONCPD_P2_SLABS", slabs)
+        m = model(P, U0, lam0, compute=compute)
+        s = m.step(2)
+        e = max(rel(m.factor(n, b), ref.U[n][b]) for n in range(3) for b in range(S))
+        say(f"   slabs={slabs} F={s['F']:.10e} oracle={ref.F:.10e} max factor err={e:.2e}")
+        assert abs(s["F"] - ref.F) / ref.F <= tol and e <= 10 * tol
+
+
 def test_profiled_sweeps_leave_the_iterate_unchanged():
     # profiling repeats each MTTKRP pass back to back; the iterate must match
     # an unprofiled twin bit for bit
