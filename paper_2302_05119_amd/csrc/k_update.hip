@@ -16,8 +16,11 @@
 
 namespace cpd {
 
-template <typename T, int KSRC>
-__global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, StateP<T> st, const ItemU* __restrict__ items,
+// BS threads per workgroup: 256, or 512 / 1024 when an item holds more
+// elements (a row of a coupling group over many blocks), so that each thread
+// takes one element and its chain of loads runs once
+template <typename T, int KSRC, int BS>
+__global__ __launch_bounds__(BS) void k_update(const Geo* __restrict__ g, StateP<T> st, const ItemU* __restrict__ items,
                                                 int n, int extrapolate) {
     const Ctrl* c = st.ctrl;
     if (c->stop) return;
@@ -42,7 +45,7 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
     const double wC = (Ln > 0) ? extrap_weight(extrapolate, what, st.LC_prev[n], LC, dw) : 0.0;
 
     // extrapolated point
-    for (int e = tid; e < tot; e += 256) {
+    for (int e = tid; e < tot; e += BS) {
         const int sl = e / (nrows * R), rem = e % (nrows * R), rr = rem / R, col = rem % R;
         const int s = cg ? blk[sl] : s0 + sl;
         const long long off = g->uoff[n][s] + (long long)(row0 + rr) * Rq + col;
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
     }
     __syncthreads();
     // gradient; individual columns are projected here
-    for (int e = tid; e < tot; e += 256) {
+    for (int e = tid; e < tot; e += BS) {
         const int sl = e / (nrows * R), rem = e % (nrows * R), rr = rem / R, col = rem % R;
         const int s = cg ? blk[sl] : s0 + sl, i = row0 + rr;
         const double* P = st.P + (long long)s * RR;
@@ -88,7 +91,7 @@ __global__ __launch_bounds__(256) void k_update(const Geo* __restrict__ g, State
     if (Ln == 0) return;
     __syncthreads();
     // shared columns: sum the block gradients in block order
-    for (int e = tid; e < nrows * Ln; e += 256) {
+    for (int e = tid; e < nrows * Ln; e += BS) {
         const int rr = e / Ln, col = e % Ln, i = row0 + rr;
         double gsum = 0.0;
         for (int sl = 0; sl < ns; ++sl) gsum += gc[(sl * nrows + rr) * Ln + col];
@@ -137,8 +140,15 @@ void launch_update(const Geo* g, const StateP<T>& st, const ItemU* items, int ni
     const size_t lds = sizeof(double) * (size_t)lds_rows * (size_t)(2 * R);
     const int ks = ksrc == 2 ? KSRC_PLAIN
                              : (ksrc == 1 ? KSRC_LRA0 + n : (n == 0 ? KSRC_K1P : (n == 1 ? KSRC_K2 : KSRC_PART)));
-#define CPD_UPD(KS) \
-    case KS: hipLaunchKernelGGL((k_update<T, KS>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap); break;
+    // lds_rows * R is the largest item's element count
+    const long long tot = (long long)lds_rows * R;
+    const int bs = tot <= 256 ? 256 : tot <= 512 ? 512 : 1024;
+#define CPD_UPD(KS)                                                                                                       \
+    case KS:                                                                                                              \
+        if (bs == 256) hipLaunchKernelGGL((k_update<T, KS, 256>), dim3(nitems), dim3(256), lds, q, g, st, items, n, extrap);   \
+        else if (bs == 512) hipLaunchKernelGGL((k_update<T, KS, 512>), dim3(nitems), dim3(512), lds, q, g, st, items, n, extrap); \
+        else hipLaunchKernelGGL((k_update<T, KS, 1024>), dim3(nitems), dim3(1024), lds, q, g, st, items, n, extrap);          \
+        break;
     switch (ks) {
         CPD_UPD(KSRC_K1P) CPD_UPD(KSRC_K2) CPD_UPD(KSRC_PART) CPD_UPD(KSRC_LRA0) CPD_UPD(KSRC_LRA1) CPD_UPD(KSRC_LRA2)
         CPD_UPD(KSRC_PLAIN)
