@@ -112,6 +112,7 @@ def lra_leg(steps: int, warmup: int, dense_steps: int = 30, name: str = LRA_WORK
     # the plain path on the same blocks, for comparison (then the lra path
     # continues from the same starting point)
     dense = CoupledCP(tens, w["R"], w["L"], compute="f32", init_U=U0, init_lambda=lam0)
+    dense_tuning = dense.autotune(5)   # the plain path at its best launch configuration
     dense.step(3)
     kd0 = dense.stats()["k"]
     torch.cuda.synchronize()
@@ -151,7 +152,8 @@ def lra_leg(steps: int, warmup: int, dense_steps: int = 30, name: str = LRA_WORK
     return {"workload": name, "compression": compress, **extra, "compress_s": t1 - t0,
             "iter_per_s": (st["k"] - k0) / (t3 - t2),
             "launch_floor": {"kernels_per_sweep": nk, "graph_us": fl["graph_us"], "direct_us": fl["direct_us"]},
-            "dense_iter_per_s_same_blocks": dense_rate, "dense_passes_same_blocks": dense_passes, "sweeps": steps,
+            "dense_iter_per_s_same_blocks": dense_rate, "dense_passes_same_blocks": dense_passes,
+            "dense_tuning": dense_tuning, "sweeps": steps,
             "warmup": warmup, "fit_compressed": st["fit"], "global_fit": m.global_fit(), "iterations": st["k"],
             "restarts": st["restarts"]}
 
