@@ -542,16 +542,20 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
                     ++ta;
                 }
                 const int tb = ta + rem;
-                v4d acc = {0.0, 0.0, 0.0, 0.0};
                 // all operand loads of the tile in flight; rows past NP read
-                // row NP-1 and are zeroed
+                // row NP-1 and are zeroed.  Four accumulators by k-step mod 4
+                // (independent matrix-core chains), added in a fixed order
+                v4d ac[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) ac[j] = (v4d){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int k0 = 0; k0 < NPM; k0 += 4) {
                     const double* rk = Sa + min(k0 + lk, NP - 1) * lp;
                     const double a = rk[16 * ta + li], b = rk[16 * tb + li];
                     const bool ok = k0 < NP;
-                    acc = mfma64(ok ? a : 0.0, ok ? b : 0.0, acc);
+                    ac[(k0 >> 2) & 3] = mfma64(ok ? a : 0.0, ok ? b : 0.0, ac[(k0 >> 2) & 3]);
                 }
+                const v4d acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * ta + 4 * v + lk, c = 16 * tb + li;
