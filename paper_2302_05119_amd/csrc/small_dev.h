@@ -571,7 +571,7 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
             double* t = Sa;
             Sa = Sb;
             Sb = t;
-            if (it >= 5 && (it & 3) == 1) {
+            if (it >= 4 && (it < 8 || (it & 1))) {
                 // x = S 1 (column sums; S is exactly symmetric), y = A x, and
                 // the bounds over the support, on the first wavefront
                 if (wave == 0) {
