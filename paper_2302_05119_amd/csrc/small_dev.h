@@ -407,7 +407,7 @@ __device__ __forceinline__ bool wg_lmax_vsq(const double* __restrict__ A, int n,
                 es = wave_max_i32(ex);
                 if (es == INT_MIN) es = 0;
                 wave_sync();
-                if (it >= 4 && (it < 8 || (it & 1))) {
+                if (it >= 3 && (it < 8 || (it & 1))) {
                     // x = S 1 (row sums; S is exactly symmetric), y = A x, and
                     // the Collatz-Wielandt bounds over the support
                     const double* rs = Sb + min(lane, NPM - 1) * LP;
@@ -571,7 +571,7 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
             double* t = Sa;
             Sa = Sb;
             Sb = t;
-            if (it >= 4 && (it < 8 || (it & 1))) {
+            if (it >= 3 && (it < 8 || (it & 1))) {
                 // x = S 1 (column sums; S is exactly symmetric), y = A x, and
                 // the bounds over the support, on the first wavefront
                 if (wave == 0) {
