@@ -571,6 +571,9 @@ __device__ __forceinline__ double wg_lmax_nonneg(const double* __restrict__ A, i
             double* t = Sa;
             Sa = Sb;
             Sb = t;
+            // the bounds after squarings 4..8, then after every second one
+            // (the matrices of a sweep have a wide gap above the second
+            // eigenvalue, so most pass after four or five squarings)
             if (it >= 3 && (it < 8 || (it & 1))) {
                 // x = S 1 (column sums; S is exactly symmetric), y = A x, and
                 // the bounds over the support, on the first wavefront
